@@ -1,0 +1,13 @@
+"""CPU oracle for recursive bilinear fast matrix multiplication (arXiv 1507.00687).
+
+TEST INFRASTRUCTURE ONLY: a plain, slow, obviously correct CPU implementation of what the
+GPU path computes, used as the parity reference.  Only the test suite, the smoke check and
+the CPU-baseline leg of the benchmark may import it; the product library never does, and
+the two share no code.
+
+Parity pins (tests/test_oracle_*.py) tie it to the paper: Brent equations in exact
+arithmetic, Table 1 quantities, the stability vectors of Examples 4.2 and 4.3, exact
+agreement with integer matrix products, the worked scaling examples 6.1-6.5, the closed
+form of Lemma D.5 and the invariants of Lemma D.1.  Parity unpinned: the per-level (node)
+scaling reading and the distributions of the scaling study (their figure data is absent).
+"""
