@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark: effective TFLOP/s (2mkn/t) of recursive fast matrix multiplication on one
+MI355X, beside the classical GEMM built from the same kernel template, with the max-norm
+relative error of both against the long-double CPU reference.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--algo winograd] [--depth 2]
+                    [--n 8192] [--precision f64] [--scaling none] [--dist uniform01]
+
+Prints one JSON line.  A step is one fastmm_gemm call (scaling reductions, fused leaf
+products, W-combination) on inputs already resident in HBM.  The leaf-product kernel's
+average duration comes from HIP events the library records on its launch stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "effective TFLOP/s (2mkn/t) and max-norm rel error vs FP64 oracle, fast vs classical"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500.0, "f16x3": 2500.0,
+               "bf16x6": 2500.0}
+PRODUCTS = {"f64": 1, "f32": 1, "bf16": 1, "f16": 1, "bf16x3": 3, "f16x3": 3, "bf16x6": 6}
+HBM_PEAK_GBS = 8000.0
+ORACLE_NAME = {"strassen": "strassen", "winograd": "winograd", "f323": "f323", "f332": "f332", "f233": "f233",
+               "f442": "f442", "f424": "f424", "f244": "f244", "laderman333": "laderman333"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--algo", default="winograd")
+    ap.add_argument("--depth", type=int, default=2)
+    ap.add_argument("--cutoff", type=int, default=256)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--precision", default="f64")
+    ap.add_argument("--scaling", default="none")
+    ap.add_argument("--scaling-steps", type=int, default=2)
+    ap.add_argument("--dist", default="uniform01")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--err-rows", type=int, default=16)
+    ap.add_argument("--cpu-n", type=int, default=2048, help="size of the oracle timing sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-classical", action="store_true")
+    return ap.parse_args()
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "capi.cpp", "launch.h", "devtypes.h"):
+        with open(os.path.join(ROOT, "paper_1507_00687_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per leaf-kernel launch from committed rocprofv3 counter runs, if they were
+    taken with the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(workload)
+    except Exception:
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline_leg(args, A, B, rows):
+    """Everything that touches the CPU oracle: the long-double reference rows for the error
+    figures, and the oracle's own fast multiplication timed on a bounded sample."""
+    import numpy as np
+
+    from oracle import coeffs as C
+    from oracle import fastmm_oracle as O
+    from synth import make_pair
+
+    A64 = A.astype(np.float64)
+    B64 = B.astype(np.float64)
+    ref = O.reference_rows(A64, B64, rows)
+    out = {"ref": ref}
+    if not args.no_cpu:
+        n = args.cpu_n
+        As, Bs = make_pair(args.dist, args.seed, n, n, n, dtype=np.float64)
+        alg = C.get(ORACLE_NAME[args.algo]) if args.algo in ORACLE_NAME else None
+        t0 = time.perf_counter()
+        if alg is None or args.depth == 0:
+            O.classical(As, Bs)
+        else:
+            O.fast(As, Bs, alg, args.depth, min(args.cutoff, max(1, n // (2 ** args.depth))))
+        dt = time.perf_counter() - t0
+        out["cpu"] = {"value": 2.0 * n ** 3 / dt / 1e12, "unit": "TFLOP/s", "cores": O.num_threads(),
+                      "kind": "oracle",
+                      "sample": f"oracle fast FP64 ({args.algo}, depth {args.depth}) on one {n}^3 product "
+                                f"of the same distribution, {dt:.2f} s; plain C classical leaves, "
+                                f"sequential summation"}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1507_00687_amd as F
+    from synth import make_pair
+
+    torch.cuda.set_device(0)
+    n = args.n
+    m = k = n
+    dt_np = np.float64 if args.precision == "f64" else np.float32
+    A, B = make_pair(args.dist, args.seed, m, k, n, dtype=dt_np)
+    tA = torch.from_numpy(A).cuda()
+    tB = torch.from_numpy(B).cuda()
+    plan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
+                  precision=args.precision)
+    L, Mp, Kp, Np = plan.shape(m, k, n)
+    ws = torch.empty(max(plan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
+    Cf = torch.empty((m, n), dtype=tA.dtype, device="cuda")
+    run_fast = lambda: F.fastmm_gemm(plan, tA, tB, C=Cf, workspace=ws)
+
+    classical = None
+    if not args.no_classical:
+        cplan = F.Plan("classical", 0, 1, scaling=args.scaling, steps=args.scaling_steps, precision=args.precision)
+        cws = torch.empty(max(cplan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
+        Cc = torch.empty((m, n), dtype=tA.dtype, device="cuda")
+        run_cls = lambda: F.fastmm_gemm(cplan, tA, tB, C=Cc, workspace=cws)
+        ms_cls = time_steps(run_cls, args.steps, args.warmup)
+        classical = {"ms_per_step": ms_cls, "value": 2.0 * m * k * n / (ms_cls * 1e-3) / 1e12}
+
+    # timed region: K steps between device synchronisations (one GPU: no barrier needed)
+    ms = time_steps(run_fast, args.steps, args.warmup)
+    value = 2.0 * m * k * n / (ms * 1e-3) / 1e12
+
+    # leaf-kernel duration from the library's HIP events (same stream as the launches)
+    F.fastmm_profile_enable(True)
+    F.fastmm_profile_read()
+    for _ in range(args.steps):
+        run_fast()
+    prof = F.fastmm_profile_read()
+    F.fastmm_profile_enable(False)
+    calls = max(prof["calls"], 1)
+    leaf_ms = prof["leaf_ms"] / calls
+    info = F.fastmm_algo_info(args.algo)
+    nleaves = info["R"] ** L if args.algo != "classical" else 1
+    mb, kb, nb = Mp // info["M0"] ** L, Kp // info["K0"] ** L, Np // info["N0"] ** L
+    flops_per_launch = 2.0 * mb * kb * nb * nleaves * PRODUCTS[args.precision]
+    achieved = flops_per_launch / (leaf_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    workload = (f"{args.algo} L={args.depth} cutoff={args.cutoff} n={n} {args.precision} {args.dist} "
+                f"scaling={args.scaling}")
+
+    # errors on sampled rows against the long-double reference (oracle leg)
+    rows = np.unique(np.linspace(0, m - 1, args.err_rows).astype(np.int64))
+    Cf_rows = Cf[torch.from_numpy(rows).cuda()].cpu().numpy()
+    leg = cpu_baseline_leg(args, A, B, rows)
+    ref = leg["ref"]
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    den = float(np.max(np.abs(A64))) * float(np.max(np.abs(B64)))
+    err_fast = float(np.max(np.abs(Cf_rows.astype(np.longdouble) - ref))) / den
+    err = {"fast": err_fast, "rows_sampled": int(len(rows)), "reference": "long double classical (oracle)"}
+    if classical is not None:
+        Cc_rows = Cc[torch.from_numpy(rows).cuda()].cpu().numpy()
+        err["classical"] = float(np.max(np.abs(Cc_rows.astype(np.longdouble) - ref))) / den
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": workload, "algo": args.algo, "depth": args.depth, "levels_used": L,
+                   "cutoff": args.cutoff, "m": m, "k": k, "n": n, "padded": [Mp, Kp, Np],
+                   "precision": args.precision, "scaling": args.scaling, "dist": args.dist},
+        "classical": classical,
+        "speedup_vs_classical": (classical["ms_per_step"] / ms) if classical else None,
+        "error": err,
+        "phases_ms": {"scaling": prof["scaling_ms"] / calls, "leaf": leaf_ms, "combine": prof["combine_ms"] / calls},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": load_traffic(workload),
+                     "kernel": "leaf_kernel", "flops_per_launch": flops_per_launch},
+        "cpu_baseline": leg.get("cpu"),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

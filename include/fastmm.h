@@ -1,0 +1,189 @@
+/*
+ * fastmm.h -- C ABI of the MI355X (gfx950) fast matrix multiplication library.
+ *
+ * The library computes C = A B (A is m x k, B is k x n) by a recursive bilinear algorithm
+ * <M0,K0,N0;R> given by coefficient matrices [U, V, W] (section 3.1, eq. (1)): at every
+ * recursion level it forms S_r = sum_i U_ir A_i and T_r = sum_j V_jr B_j, multiplies the R
+ * pairs recursively and accumulates C_k = sum_r W_kr M_r (section 3.2, eq. (2)); after L
+ * levels the leaves use the classical algorithm.  Dimensions that are not multiples of
+ * M0^L, K0^L, N0^L are zero-padded (section 3.2); padding is virtual (masked loads).
+ * Optional diagonal scaling before the multiplication: outside scaling (Algorithm 1),
+ * inside scaling (Algorithm 2) and repeated outside-inside scaling (Algorithm 3), with every
+ * factor rounded to a power of two so that applying and removing it is exact (section 6).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are dense, row-major, in device memory (HBM of the current HIP device), with
+ *    leading dimensions in elements.  The element type follows the plan's precision:
+ *    FASTMM_F64 -> double; every other precision -> float (FP32 in and out).
+ *  - The caller owns A, B, C and the workspace; the library never frees or retains them.
+ *    The library owns plans and their device-side task tables (allocated once per plan and
+ *    problem shape, released by fastmm_plan_destroy).
+ *  - Calls are stream-ordered on `stream` (a hipStream_t; NULL = the default stream) and do
+ *    not synchronise the device, except the first call of a plan at a new recursion depth
+ *    on a device, which uploads that depth's task table (a blocking copy).
+ *  - Argument errors are detected on the host before any launch; nothing is launched then.
+ *    HIP errors map to FASTMM_EHIP.  fastmm_last_error() returns a message for the last
+ *    failing call on the calling thread.  The library never aborts or exits.
+ *  - Non-finite inputs are not errors; they propagate as IEEE arithmetic does.
+ */
+#ifndef FASTMM_H
+#define FASTMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FASTMM_OK = 0,
+    FASTMM_EINVAL = -1,      /* bad argument (null pointer, negative size, bad enum) */
+    FASTMM_EBRENT = -2,      /* registered [U,V,W] fails the Brent equations */
+    FASTMM_ESHAPE = -3,      /* inconsistent leading dimensions */
+    FASTMM_ENOMEM = -4,      /* host or device allocation of plan tables failed */
+    FASTMM_EHIP = -5,        /* a HIP runtime call or kernel launch failed */
+    FASTMM_EUNSUPPORTED = -6,/* combination not implemented (message says which) */
+    FASTMM_EALIAS = -7,      /* C overlaps A or B */
+    FASTMM_EWORKSPACE = -8   /* workspace missing or smaller than fastmm_workspace_size */
+} fastmm_status;
+
+/* Built-in algorithms.  Coefficients follow the paper's appendices (Appendix A Strassen,
+ * Appendix B <3,2,3;15>, Appendix C <4,4,2;26>) with rows relabelled to the stated index
+ * convention (A and B blocks column-major, C blocks row-major; section 3.1), their cyclic
+ * rotations (Appendices B and C), Winograd's variant of Strassen's algorithm and
+ * Laderman's rank-23 <3,3,3> rule (literature; not printed in the paper). */
+typedef enum {
+    FASTMM_ALGO_CLASSICAL = 0, /* <1,1,1;1>: L levels of it are the classical algorithm */
+    FASTMM_ALGO_STRASSEN = 1,  /* <2,2,2;7> */
+    FASTMM_ALGO_WINOGRAD = 2,  /* <2,2,2;7>, Winograd's variant */
+    FASTMM_ALGO_F323 = 3,      /* <3,2,3;15> */
+    FASTMM_ALGO_F332 = 4,      /* <3,3,2;15> = [W,U,V] of <3,2,3> */
+    FASTMM_ALGO_F233 = 5,      /* <2,3,3;15> = [V,W,U] of <3,2,3> */
+    FASTMM_ALGO_F442 = 6,      /* <4,4,2;26> */
+    FASTMM_ALGO_F424 = 7,      /* <4,2,4;26> = [V,W,U] of <4,4,2> */
+    FASTMM_ALGO_F244 = 8,      /* <2,4,4;26> = [W,U,V] of <4,4,2> */
+    FASTMM_ALGO_LADERMAN333 = 9,/* <3,3,3;23> */
+    FASTMM_ALGO_USER0 = 64     /* first id handed out by fastmm_algo_register */
+} fastmm_algo;
+
+/* Scaling procedures of section 6.  Every factor is rounded to a power of two:
+ * outside factors to the smallest power of two >= the row/column max-abs, inside factors
+ * to 2^j with j the nearest integer to log2(max_j|B'_kj| / max_i|A'_ik|)/2 (ties to even).
+ * All-zero rows/columns get factor 1. */
+typedef enum {
+    FASTMM_SCALE_NONE = 0,
+    FASTMM_SCALE_OUTSIDE = 1,  /* Algorithm 1: one O step */
+    FASTMM_SCALE_INSIDE = 2,   /* Algorithm 2: one I step */
+    FASTMM_SCALE_OUT_IN = 3,   /* O step then I step */
+    FASTMM_SCALE_IN_OUT = 4,   /* I step then O step */
+    FASTMM_SCALE_REPEATED = 5  /* Algorithm 3: `steps` alternating steps starting with O */
+} fastmm_scale_mode;
+
+/* Arithmetic of the leaf products.  FP32 accumulation everywhere except FASTMM_F64. */
+typedef enum {
+    FASTMM_F64 = 0,    /* double in/out; v_mfma_f64_16x16x4f64 leaves */
+    FASTMM_F32 = 1,    /* float in/out; v_mfma_f32_16x16x4f32 leaves */
+    FASTMM_BF16 = 2,   /* float in/out; operands rounded to bf16 (1 product) */
+    FASTMM_F16 = 3,    /* float in/out; operands rounded to fp16 (1 product) */
+    FASTMM_BF16X3 = 4, /* float in/out; x = hi + lo in bf16, hi*hi + hi*lo + lo*hi */
+    FASTMM_F16X3 = 5,  /* float in/out; x = hi + lo in fp16, hi*hi + hi*lo + lo*hi */
+    FASTMM_BF16X6 = 6  /* float in/out; three bf16 limbs, the six products of order <= 2 */
+} fastmm_precision;
+
+typedef struct {
+    int mode;   /* fastmm_scale_mode */
+    int steps;  /* number of O/I steps for FASTMM_SCALE_REPEATED (>= 1) */
+    double tau; /* > 0: stop early by the test of Theorem 6.5, applied to every step after
+                   the first O step on the unrounded factors; evaluated on the device (the
+                   remaining steps become no-ops), no host synchronisation; 0: run all steps */
+} fastmm_scaling;
+
+typedef struct fastmm_plan_s *fastmm_plan_t;
+
+/* ---- algorithms ------------------------------------------------------------------- */
+
+/* Register a user algorithm <M0,K0,N0;R>: num_U (M0K0 x R), num_V (K0N0 x R), num_W
+ * (M0N0 x R), row-major int64 numerators over the common denominator 2^log2_den
+ * (0 <= log2_den <= 30).  Index conventions of section 3.1.  The Brent equations are
+ * checked exactly; FASTMM_EBRENT if they fail.  *algo_out receives the new id. */
+fastmm_status fastmm_algo_register(int M0, int K0, int N0, int R, const int64_t *num_U,
+                                   const int64_t *num_V, const int64_t *num_W, int log2_den,
+                                   int *algo_out);
+
+/* Dimensions and principal quantities (section 4.1: nnz, Q of Definition 4.1, E of
+ * Definition 4.2) of an algorithm.  Any output pointer may be NULL. */
+fastmm_status fastmm_algo_info(int algo, int *M0, int *K0, int *N0, int *R, int *nnz,
+                               double *Q, double *E);
+
+/* Copy the algorithm's coefficients as doubles into host arrays U (M0K0 x R), V (K0N0 x R),
+ * W (M0N0 x R), row-major.  Any pointer may be NULL. */
+fastmm_status fastmm_algo_coeffs(int algo, double *U, double *V, double *W);
+
+/* ---- plans ------------------------------------------------------------------------ */
+
+/* Create a plan: `depth` recursion levels of `algo` (fewer when a child dimension would
+ * drop below `cutoff`: recursion continues while levels remain and ceil(dim / base^l) >=
+ * cutoff for all three dimensions), the scaling procedure (NULL = none) and the leaf
+ * precision.  depth >= 0, cutoff >= 1. */
+fastmm_status fastmm_plan_create(fastmm_plan_t *out, int algo, int depth, int cutoff,
+                                 const fastmm_scaling *scaling, int precision);
+
+fastmm_status fastmm_plan_destroy(fastmm_plan_t plan);
+
+/* Levels the plan uses for an m x k by k x n product, and the padded sizes. */
+fastmm_status fastmm_plan_shape(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n,
+                                int *levels, int64_t *Mp, int64_t *Kp, int64_t *Np);
+
+/* Device workspace bytes fastmm_gemm needs for this shape. */
+fastmm_status fastmm_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n,
+                                    size_t *bytes);
+
+/* ---- multiplication ---------------------------------------------------------------- */
+
+/* C = A B with contiguous row-major operands (lda = k, ldb = n, ldc = n).  m, k, n >= 0;
+ * a zero m or n is a no-op, a zero k writes zeros.  `workspace` is device memory of at least
+ * fastmm_workspace_size bytes (may be NULL when that size is 0).  C must not overlap A or B
+ * (FASTMM_EALIAS).  `stream` is a hipStream_t (NULL = default stream). */
+fastmm_status fastmm_gemm(fastmm_plan_t plan, const void *A, const void *B, void *C, int64_t m,
+                          int64_t k, int64_t n, void *workspace, size_t ws_bytes, void *stream);
+
+/* As fastmm_gemm with leading dimensions and transposition flags: op(A) is m x k and
+ * op(B) is k x n, where op(X) = X^T when the flag is nonzero (X then stored k x m, resp.
+ * n x k, row-major with its own leading dimension).  Used by the backward pass. */
+fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int transA,
+                             const void *B, int64_t ldb, int transB, void *C, int64_t ldc,
+                             int64_t m, int64_t k, int64_t n, void *workspace, size_t ws_bytes,
+                             void *stream);
+
+/* ---- scaling vectors (the reductions of Algorithms 1-3, exposed for verification) ---- */
+
+/* Run the plan's scaling steps on A (m x k) and B (k x n) and write the power-of-two
+ * exponents of the cumulative factors to device int32 arrays: ea (m) for D_A, eb (n) for
+ * D_B, ep (k) for the product of the inside factors, so that the scaled operands are
+ * A' = diag(2^-ea) A diag(2^ep) and B' = diag(2^-ep) B diag(2^-eb).  Needs the workspace of
+ * fastmm_workspace_size. */
+fastmm_status fastmm_scaling_exponents(fastmm_plan_t plan, const void *A, const void *B,
+                                       int64_t m, int64_t k, int64_t n, int32_t *ea,
+                                       int32_t *eb, int32_t *ep, void *workspace,
+                                       size_t ws_bytes, void *stream);
+
+/* ---- diagnostics ------------------------------------------------------------------- */
+
+/* Phase timing for measurement: while enabled (nonzero), every fastmm_gemm / gemm_ex call
+ * on the calling thread records HIP events on its stream around its three phases (scaling
+ * reductions, leaf products, W-combination).  fastmm_profile_read synchronises on the last
+ * recorded events and returns the summed milliseconds of each phase and the number of
+ * calls since the last read (then resets).  Any output pointer may be NULL. */
+fastmm_status fastmm_profile_enable(int enable);
+fastmm_status fastmm_profile_read(double *ms_scaling, double *ms_leaf, double *ms_combine, int *calls);
+
+const char *fastmm_strerror(fastmm_status status);
+const char *fastmm_last_error(void);
+int fastmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTMM_H */

@@ -1,0 +1,653 @@
+// C ABI of the library: argument checking, the recursion planner (levels, padding, the
+// composite leaf task tables of eq. (2)), the scaling schedule of Algorithms 1-3 and the
+// launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "devtypes.h"
+#include "fastmm.h"
+#include "fastmm_internal.h"
+#include "launch.h"
+
+namespace fastmm {
+
+namespace {
+thread_local std::string g_last_error;
+
+// Phase timing (fastmm_profile_enable): events recorded around each phase of each call.
+struct PhaseEvents {
+    hipEvent_t ev[4];
+};
+struct Profiler {
+    bool on = false;
+    std::vector<PhaseEvents> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[3] = {0, 0, 0};
+    int calls = 0;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+};
+thread_local Profiler g_prof;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+
+fastmm_status fail(fastmm_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+fastmm_status hip_fail(hipError_t e, const char *what) {
+    return fail(FASTMM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device copy of the composite task tables for L levels of one algorithm.  They depend only
+// on the algorithm and L (block sizes are launch arguments), so a plan caches one per L.
+struct Tables {
+    int L = 0;
+    int nleaves = 0;
+    int MB = 1, KB = 1, NB = 1;  // M0^L, K0^L, N0^L blocks per dimension
+    LeafEntry *leaves = nullptr;
+    SrcEntry *asrc = nullptr;
+    SrcEntry *bsrc = nullptr;
+    BlockDests *bdest = nullptr;
+    DestEntry *dest = nullptr;
+    int device = -1;
+    ~Tables() {
+        if (device >= 0) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(device);
+            (void)hipFree(leaves);
+            (void)hipFree(asrc);
+            (void)hipFree(bsrc);
+            (void)hipFree(bdest);
+            (void)hipFree(dest);
+            (void)hipSetDevice(cur);
+        }
+    }
+};
+
+struct HostTables {
+    std::vector<LeafEntry> leaves;
+    std::vector<SrcEntry> asrc, bsrc;
+    std::vector<BlockDests> bdest;
+    std::vector<DestEntry> dest;
+    int MB = 1, KB = 1, NB = 1;
+};
+
+// Nonzeros of column r of a coefficient matrix: (row, numerator).
+std::vector<std::vector<std::pair<int, int64_t>>> col_nonzeros(const std::vector<int64_t> &X, int rows, int R) {
+    std::vector<std::vector<std::pair<int, int64_t>>> nz(R);
+    for (int r = 0; r < R; ++r)
+        for (int i = 0; i < rows; ++i)
+            if (X[(size_t)i * R + r] != 0) nz[r].push_back({i, X[(size_t)i * R + r]});
+    return nz;
+}
+
+const size_t kMaxTableEntries = size_t(1) << 24;
+
+// Unroll L levels of the rule into the composite leaf list (eq. (ST_exact)): leaf
+// r = (r_1..r_L) has A sources prod_l U[i_l, r_l] A_(i_1..i_L), B sources likewise, and
+// contributes prod_l W[k_l, r_l] M_r to output block (k_1..k_L).  Level 1 is the most
+// significant digit of every composite block coordinate.
+bool build_tables(const Algo &a, int L, HostTables &ht, std::string &err) {
+    const int M0 = a.M0, K0 = a.K0, N0 = a.N0, R = a.R;
+    ht.MB = ht.KB = ht.NB = 1;
+    for (int l = 0; l < L; ++l) ht.MB *= M0, ht.KB *= K0, ht.NB *= N0;
+    const auto Unz = col_nonzeros(a.U, M0 * K0, R);
+    const auto Vnz = col_nonzeros(a.V, K0 * N0, R);
+    const auto Wnz = col_nonzeros(a.W, M0 * N0, R);
+    std::vector<std::vector<DestEntry>> per_block((size_t)ht.MB * ht.NB);
+    int64_t nleaves_all = 1;
+    for (int l = 0; l < L; ++l) nleaves_all *= R;
+    if (nleaves_all > (int64_t)1 << 22) {
+        err = "too many leaves";
+        return false;
+    }
+    std::vector<int> r(L, 0);
+    for (int64_t leaf_all = 0; leaf_all < nleaves_all; ++leaf_all) {
+        {  // odometer: r[0] most significant
+            int64_t x = leaf_all;
+            for (int l = L - 1; l >= 0; --l) r[l] = (int)(x % R), x /= R;
+        }
+        bool zero = false;
+        for (int l = 0; l < L; ++l)
+            if (Unz[r[l]].empty() || Vnz[r[l]].empty() || Wnz[r[l]].empty()) zero = true;
+        if (zero) continue;  // this product never reaches C
+        const int leaf = (int)ht.leaves.size();
+        LeafEntry le{(int32_t)ht.asrc.size(), 0, (int32_t)ht.bsrc.size(), 0};
+        // cartesian products over levels of the per-level nonzero lists
+        auto expand = [&](const std::vector<std::vector<std::pair<int, int64_t>>> &nz, int den, int rowsz,
+                          int colsz_base, bool is_c, std::vector<SrcEntry> *out_src) {
+            std::vector<int> idx(L, 0);
+            while (true) {
+                int64_t br = 0, bc = 0;
+                double coef = 1.0;
+                for (int l = 0; l < L; ++l) {
+                    const auto &e = nz[r[l]][idx[l]];
+                    int p, q;
+                    if (is_c) {  // row-major single index over M0 x N0
+                        p = e.first / N0, q = e.first % N0;
+                    } else {  // column-major single index over rowsz x colsz_base
+                        p = e.first % rowsz, q = e.first / rowsz;
+                    }
+                    br = br * rowsz + p;
+                    bc = bc * colsz_base + q;
+                    coef *= std::ldexp((double)e.second, -den);
+                }
+                if (is_c) {
+                    per_block[(size_t)br * ht.NB + bc].push_back({(int32_t)leaf, (float)coef});
+                } else {
+                    out_src->push_back({(int32_t)br, (int32_t)bc, (float)coef, 0});
+                }
+                int l = L - 1;
+                while (l >= 0 && ++idx[l] == (int)nz[r[l]].size()) idx[l] = 0, --l;
+                if (l < 0) break;
+            }
+        };
+        expand(Unz, a.den_U, M0, K0, false, &ht.asrc);
+        expand(Vnz, a.den_V, K0, N0, false, &ht.bsrc);
+        expand(Wnz, a.den_W, M0, N0, true, nullptr);
+        le.a_count = (int32_t)(ht.asrc.size() - le.a_begin);
+        le.b_count = (int32_t)(ht.bsrc.size() - le.b_begin);
+        ht.leaves.push_back(le);
+        if (ht.asrc.size() + ht.bsrc.size() > kMaxTableEntries) {
+            err = "task table too large for this algorithm and depth";
+            return false;
+        }
+    }
+    ht.bdest.resize(per_block.size());
+    for (size_t b = 0; b < per_block.size(); ++b) {
+        ht.bdest[b] = {(int32_t)ht.dest.size(), (int32_t)per_block[b].size()};
+        ht.dest.insert(ht.dest.end(), per_block[b].begin(), per_block[b].end());
+    }
+    return true;
+}
+
+template <typename X>
+hipError_t upload(X **dst, const std::vector<X> &src) {
+    *dst = nullptr;
+    size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(X);
+    hipError_t e = hipMalloc((void **)dst, bytes);
+    if (e != hipSuccess) return e;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(X), hipMemcpyHostToDevice);
+    return e;
+}
+
+struct Shape {
+    int L;
+    int64_t Mp, Kp, Np, mb, kb, nb;
+};
+
+}  // namespace
+}  // namespace fastmm
+
+struct fastmm_plan_s {
+    int algo = 0;
+    int depth = 0;
+    int cutoff = 1;
+    fastmm_scaling sc{0, 0, 0.0};
+    int prec = FASTMM_F64;
+    std::mutex mu;
+    std::map<std::pair<int, int>, std::unique_ptr<fastmm::Tables>> tables;  // (L, device)
+};
+
+namespace fastmm {
+namespace {
+
+const Algo &plan_algo(const fastmm_plan_s *p) { return *algo_get(p->algo); }
+
+Shape shape_of(const fastmm_plan_s *p, int64_t m, int64_t k, int64_t n) {
+    const Algo &a = plan_algo(p);
+    Shape s{0, m, k, n, m, k, n};
+    // Recurse while levels remain and every child dimension ceil(dim / base^l) >= cutoff.
+    int64_t pm = 1, pk = 1, pn = 1;
+    int L = 0;
+    if (a.M0 * a.K0 * a.N0 > 1) {
+        for (int l = 0; l < p->depth; ++l) {
+            pm *= a.M0, pk *= a.K0, pn *= a.N0;
+            if ((m + pm - 1) / pm < p->cutoff || (k + pk - 1) / pk < p->cutoff || (n + pn - 1) / pn < p->cutoff) {
+                pm /= a.M0, pk /= a.K0, pn /= a.N0;
+                break;
+            }
+            ++L;
+        }
+    }
+    s.L = L;
+    s.Mp = (m + pm - 1) / pm * pm;
+    s.Kp = (k + pk - 1) / pk * pk;
+    s.Np = (n + pn - 1) / pn * pn;
+    s.mb = s.Mp / pm, s.kb = s.Kp / pk, s.nb = s.Np / pn;
+    return s;
+}
+
+int leaf_count(const Algo &a, int L) {
+    // Leaves whose columns of U, V and W are all nonzero (the others are dropped).
+    int live = 0;
+    for (int r = 0; r < a.R; ++r) {
+        bool u = false, v = false, w = false;
+        for (int i = 0; i < a.M0 * a.K0; ++i) u |= a.U[(size_t)i * a.R + r] != 0;
+        for (int j = 0; j < a.K0 * a.N0; ++j) v |= a.V[(size_t)j * a.R + r] != 0;
+        for (int k2 = 0; k2 < a.M0 * a.N0; ++k2) w |= a.W[(size_t)k2 * a.R + r] != 0;
+        live += (u && v && w);
+    }
+    int64_t c = 1;
+    for (int l = 0; l < L; ++l) c *= live;
+    return (int)c;
+}
+
+size_t elem_size(int prec) { return prec == FASTMM_F64 ? 8 : 4; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace layout: [ea m][ep k][eb n][flags 2] int32 | [maxA max(m,k)][maxB max(k,n)] elems |
+// [leaf products nleaves * mb * nb] elems.
+struct WsLayout {
+    size_t ea, ep, eb, flags, maxA, maxB, leaves, total;
+};
+
+WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n) {
+    WsLayout w{};
+    const size_t es = elem_size(p->prec);
+    size_t off = 0;
+    if (p->sc.mode != FASTMM_SCALE_NONE) {
+        w.ea = off, off = align256(off + 4 * (size_t)m);
+        w.ep = off, off = align256(off + 4 * (size_t)k);
+        w.eb = off, off = align256(off + 4 * (size_t)n);
+        w.flags = off, off = align256(off + 16);
+        w.maxA = off, off = align256(off + es * (size_t)std::max(m, k));
+        w.maxB = off, off = align256(off + es * (size_t)std::max(k, n));
+    }
+    w.leaves = off;
+    if (s.L > 0) off = align256(off + es * (size_t)leaf_count(plan_algo(p), s.L) * s.mb * s.nb);
+    w.total = off;
+    return w;
+}
+
+std::string schedule_of(const fastmm_scaling &sc) {
+    switch (sc.mode) {
+        case FASTMM_SCALE_NONE: return "";
+        case FASTMM_SCALE_OUTSIDE: return "O";
+        case FASTMM_SCALE_INSIDE: return "I";
+        case FASTMM_SCALE_OUT_IN: return "OI";
+        case FASTMM_SCALE_IN_OUT: return "IO";
+        case FASTMM_SCALE_REPEATED: {
+            std::string s;
+            for (int t = 0; t < sc.steps; ++t) s += (t % 2 == 0) ? 'O' : 'I';
+            return s;
+        }
+    }
+    return "";
+}
+
+fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(p->mu);
+    auto key = std::make_pair(L, dev);
+    auto it = p->tables.find(key);
+    if (it != p->tables.end()) {
+        *out = it->second.get();
+        return FASTMM_OK;
+    }
+    HostTables ht;
+    std::string err;
+    if (!build_tables(plan_algo(p), L, ht, err)) return fail(FASTMM_EUNSUPPORTED, err);
+    std::unique_ptr<Tables> t(new Tables());
+    t->L = L;
+    t->nleaves = (int)ht.leaves.size();
+    t->MB = ht.MB, t->KB = ht.KB, t->NB = ht.NB;
+    t->device = dev;
+    if ((e = upload(&t->leaves, ht.leaves)) != hipSuccess || (e = upload(&t->asrc, ht.asrc)) != hipSuccess ||
+        (e = upload(&t->bsrc, ht.bsrc)) != hipSuccess || (e = upload(&t->bdest, ht.bdest)) != hipSuccess ||
+        (e = upload(&t->dest, ht.dest)) != hipSuccess)
+        return hip_fail(e, "uploading task tables");
+    *out = t.get();
+    p->tables[key] = std::move(t);
+    return FASTMM_OK;
+}
+
+bool ranges_overlap(const void *a, size_t abytes, const void *b, size_t bbytes) {
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+size_t span_bytes(int64_t rows, int64_t cols, int64_t ld, size_t es) {
+    if (rows <= 0 || cols <= 0) return 0;
+    return ((size_t)(rows - 1) * (size_t)ld + (size_t)cols) * es;
+}
+
+// Scaling steps on op(A), op(B); leaves the exponents in the workspace.
+fastmm_status run_scaling(fastmm_plan_s *p, const void *A, int64_t lda, int transA, const void *B, int64_t ldb,
+                          int transB, int64_t m, int64_t k, int64_t n, char *ws, const WsLayout &w, hipStream_t st,
+                          ScaleExps *exps) {
+    *exps = ScaleExps{nullptr, nullptr, nullptr};
+    if (p->sc.mode == FASTMM_SCALE_NONE) return FASTMM_OK;
+    int32_t *ea = (int32_t *)(ws + w.ea), *ep = (int32_t *)(ws + w.ep), *eb = (int32_t *)(ws + w.eb);
+    int32_t *flags = (int32_t *)(ws + w.flags);
+    hipError_t e;
+    if ((e = launch_fill_i32(ea, m, 0, st)) != hipSuccess || (e = launch_fill_i32(ep, k, 0, st)) != hipSuccess ||
+        (e = launch_fill_i32(eb, n, 0, st)) != hipSuccess || (e = launch_fill_i32(flags, 4, 0, st)) != hipSuccess)
+        return hip_fail(e, "scaling init");
+    const std::string sched = schedule_of(p->sc);
+    bool seen_o = false;
+    for (char kind : sched) {
+        ScaleStep S;
+        S.elem = p->prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
+        S.kind = kind;
+        S.A = A, S.B = B, S.lda = lda, S.ldb = ldb, S.transA = transA, S.transB = transB;
+        S.m = m, S.k = k, S.n = n;
+        S.ea = ea, S.ep = ep, S.eb = eb;
+        S.maxA = ws + w.maxA, S.maxB = ws + w.maxB;
+        S.flags = flags;
+        S.tau = p->sc.tau;
+        // The stopping test of Theorem 6.5 applies to every step after the first O step.
+        S.test = (p->sc.tau > 0.0 && seen_o) ? 1 : 0;
+        if (kind == 'O') seen_o = true;
+        if ((e = launch_scale_step(S, st)) != hipSuccess) return hip_fail(e, "scaling step");
+    }
+    *exps = ScaleExps{ea, ep, eb};
+    return FASTMM_OK;
+}
+
+fastmm_status check_plan(fastmm_plan_t p) {
+    if (!p) return fail(FASTMM_EINVAL, "null plan");
+    return FASTMM_OK;
+}
+
+}  // namespace
+}  // namespace fastmm
+
+using namespace fastmm;
+
+extern "C" {
+
+int fastmm_version(void) { return 1; }
+
+const char *fastmm_strerror(fastmm_status s) {
+    switch (s) {
+        case FASTMM_OK: return "ok";
+        case FASTMM_EINVAL: return "invalid argument";
+        case FASTMM_EBRENT: return "coefficients fail the Brent equations";
+        case FASTMM_ESHAPE: return "inconsistent shape or leading dimension";
+        case FASTMM_ENOMEM: return "out of memory";
+        case FASTMM_EHIP: return "HIP runtime error";
+        case FASTMM_EUNSUPPORTED: return "unsupported combination";
+        case FASTMM_EALIAS: return "output overlaps an input";
+        case FASTMM_EWORKSPACE: return "workspace too small";
+    }
+    return "unknown status";
+}
+
+const char *fastmm_last_error(void) { return g_last_error.c_str(); }
+
+fastmm_status fastmm_profile_enable(int enable) {
+    g_prof.on = enable != 0;
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_profile_read(double *ms_scaling, double *ms_leaf, double *ms_combine, int *calls) {
+    for (PhaseEvents &pe : g_prof.pending) {
+        hipError_t e = hipEventSynchronize(pe.ev[3]);
+        if (e != hipSuccess) return hip_fail(e, "profile sync");
+        for (int ph = 0; ph < 3; ++ph) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pe.ev[ph], pe.ev[ph + 1]) == hipSuccess) g_prof.ms[ph] += t;
+        }
+        for (int i = 0; i < 4; ++i) g_prof.pool.push_back(pe.ev[i]);
+        ++g_prof.calls;
+    }
+    g_prof.pending.clear();
+    if (ms_scaling) *ms_scaling = g_prof.ms[0];
+    if (ms_leaf) *ms_leaf = g_prof.ms[1];
+    if (ms_combine) *ms_combine = g_prof.ms[2];
+    if (calls) *calls = g_prof.calls;
+    g_prof.ms[0] = g_prof.ms[1] = g_prof.ms[2] = 0;
+    g_prof.calls = 0;
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_algo_register(int M0, int K0, int N0, int R, const int64_t *num_U, const int64_t *num_V,
+                                   const int64_t *num_W, int log2_den, int *algo_out) {
+    if (M0 < 1 || K0 < 1 || N0 < 1 || R < 1 || M0 > 16 || K0 > 16 || N0 > 16 || R > 4096 || !num_U || !num_V ||
+        !num_W || !algo_out || log2_den < 0 || log2_den > 30)
+        return fail(FASTMM_EINVAL, "fastmm_algo_register: bad arguments");
+    Algo a;
+    a.name = "user";
+    a.M0 = M0, a.K0 = K0, a.N0 = N0, a.R = R;
+    a.U.assign(num_U, num_U + (size_t)M0 * K0 * R);
+    a.V.assign(num_V, num_V + (size_t)K0 * N0 * R);
+    a.W.assign(num_W, num_W + (size_t)M0 * N0 * R);
+    a.den_U = a.den_V = a.den_W = log2_den;
+    for (int64_t x : a.U) if (x > (1 << 20) || x < -(1 << 20)) return fail(FASTMM_EINVAL, "coefficient too large");
+    for (int64_t x : a.V) if (x > (1 << 20) || x < -(1 << 20)) return fail(FASTMM_EINVAL, "coefficient too large");
+    for (int64_t x : a.W) if (x > (1 << 20) || x < -(1 << 20)) return fail(FASTMM_EINVAL, "coefficient too large");
+    if (brent_violations(a) != 0) return fail(FASTMM_EBRENT, "registered algorithm fails the Brent equations");
+    const int id = algo_register(std::move(a));
+    if (id < 0) return fail(FASTMM_ENOMEM, "algorithm registry full");
+    *algo_out = id;
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_algo_info(int algo, int *M0, int *K0, int *N0, int *R, int *nnz, double *Q, double *E) {
+    const Algo *a = algo_get(algo);
+    if (!a) return fail(FASTMM_EINVAL, "unknown algorithm id");
+    const Quantities q = quantities(*a);
+    if (M0) *M0 = a->M0;
+    if (K0) *K0 = a->K0;
+    if (N0) *N0 = a->N0;
+    if (R) *R = a->R;
+    if (nnz) *nnz = q.nnz;
+    if (Q) *Q = q.Q;
+    if (E) *E = q.E;
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_algo_coeffs(int algo, double *U, double *V, double *W) {
+    const Algo *a = algo_get(algo);
+    if (!a) return fail(FASTMM_EINVAL, "unknown algorithm id");
+    for (int i = 0; U && i < a->M0 * a->K0; ++i)
+        for (int r = 0; r < a->R; ++r) U[(size_t)i * a->R + r] = a->u(i, r);
+    for (int j = 0; V && j < a->K0 * a->N0; ++j)
+        for (int r = 0; r < a->R; ++r) V[(size_t)j * a->R + r] = a->v(j, r);
+    for (int k = 0; W && k < a->M0 * a->N0; ++k)
+        for (int r = 0; r < a->R; ++r) W[(size_t)k * a->R + r] = a->w(k, r);
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_plan_create(fastmm_plan_t *out, int algo, int depth, int cutoff, const fastmm_scaling *scaling,
+                                 int precision) {
+    if (!out) return fail(FASTMM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!algo_get(algo)) return fail(FASTMM_EINVAL, "unknown algorithm id");
+    if (depth < 0 || depth > 8) return fail(FASTMM_EINVAL, "depth must be in [0, 8]");
+    if (cutoff < 1) return fail(FASTMM_EINVAL, "cutoff must be >= 1");
+    if (precision < FASTMM_F64 || precision > FASTMM_BF16X6) return fail(FASTMM_EINVAL, "unknown precision");
+    if (precision != FASTMM_F64 && precision != FASTMM_F32)
+        return fail(FASTMM_EUNSUPPORTED, "precision not implemented yet");
+    fastmm_scaling sc{FASTMM_SCALE_NONE, 0, 0.0};
+    if (scaling) {
+        sc = *scaling;
+        if (sc.mode < FASTMM_SCALE_NONE || sc.mode > FASTMM_SCALE_REPEATED)
+            return fail(FASTMM_EINVAL, "unknown scaling mode");
+        if (sc.mode == FASTMM_SCALE_REPEATED && (sc.steps < 1 || sc.steps > 256))
+            return fail(FASTMM_EINVAL, "repeated scaling needs 1 <= steps <= 256");
+        if (!(sc.tau >= 0.0) || std::isinf(sc.tau)) return fail(FASTMM_EINVAL, "tau must be finite and >= 0");
+    }
+    fastmm_plan_s *p = new (std::nothrow) fastmm_plan_s();
+    if (!p) return fail(FASTMM_ENOMEM, "plan allocation");
+    p->algo = algo;
+    p->depth = depth;
+    p->cutoff = cutoff;
+    p->sc = sc;
+    p->prec = precision;
+    *out = p;
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_plan_destroy(fastmm_plan_t plan) {
+    delete plan;
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_plan_shape(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, int *levels, int64_t *Mp,
+                                int64_t *Kp, int64_t *Np) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    if (m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "negative size");
+    const Shape s = shape_of(plan, m, k, n);
+    if (levels) *levels = s.L;
+    if (Mp) *Mp = s.Mp;
+    if (Kp) *Kp = s.Kp;
+    if (Np) *Np = s.Np;
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, size_t *bytes) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    if (!bytes || m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "bad arguments");
+    const Shape s = shape_of(plan, m, k, n);
+    *bytes = ws_layout(plan, s, m, k, n).total;
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int transA, const void *B, int64_t ldb,
+                             int transB, void *C, int64_t ldc, int64_t m, int64_t k, int64_t n, void *workspace,
+                             size_t ws_bytes, void *stream) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    if (m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "negative size");
+    if (m == 0 || n == 0) return FASTMM_OK;
+    if (!C) return fail(FASTMM_EINVAL, "null C");
+    if (ldc < n) return fail(FASTMM_ESHAPE, "ldc < n");
+    const size_t es = elem_size(plan->prec);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cbytes = span_bytes(m, n, ldc, es);
+    if (k == 0) {
+        hipError_t e = launch_zero_elems(plan->prec == FASTMM_F64 ? Elem::F64 : Elem::F32, C, ldc, m, n, st);
+        return e == hipSuccess ? FASTMM_OK : hip_fail(e, "zero fill");
+    }
+    if (!A || !B) return fail(FASTMM_EINVAL, "null A or B");
+    // op(A) is m x k: stored m x k (lda >= k) or k x m (lda >= m); likewise op(B).
+    if (lda < (transA ? m : k)) return fail(FASTMM_ESHAPE, "lda too small");
+    if (ldb < (transB ? k : n)) return fail(FASTMM_ESHAPE, "ldb too small");
+    const size_t abytes = transA ? span_bytes(k, m, lda, es) : span_bytes(m, k, lda, es);
+    const size_t bbytes = transB ? span_bytes(n, k, ldb, es) : span_bytes(k, n, ldb, es);
+    if (ranges_overlap(C, cbytes, A, abytes) || ranges_overlap(C, cbytes, B, bbytes))
+        return fail(FASTMM_EALIAS, "C overlaps A or B");
+    const Shape s = shape_of(plan, m, k, n);
+    const WsLayout w = ws_layout(plan, s, m, k, n);
+    if (w.total > 0 && (workspace == nullptr || ws_bytes < w.total))
+        return fail(FASTMM_EWORKSPACE, "workspace of " + std::to_string(w.total) + " bytes required");
+    if (w.total > 0 && ((uintptr_t)workspace & 255) != 0) return fail(FASTMM_EINVAL, "workspace must be 256-byte aligned");
+    if (((uintptr_t)A % es) || ((uintptr_t)B % es) || ((uintptr_t)C % es))
+        return fail(FASTMM_EINVAL, "misaligned operand");
+    Tables *tab = nullptr;
+    fastmm_status stt = get_tables(plan, s.L, &tab);
+    if (stt != FASTMM_OK) return stt;
+    char *ws = (char *)workspace;
+    PhaseEvents pe{};
+    const bool prof = g_prof.on;
+    if (prof) {
+        for (int i = 0; i < 4; ++i) pe.ev[i] = g_prof.get();
+        (void)hipEventRecord(pe.ev[0], st);
+    }
+    struct Finish {  // records the remaining phase marks on every exit path
+        bool prof;
+        PhaseEvents *pe;
+        hipStream_t st;
+        int next = 1;
+        void mark() {
+            if (prof && next < 4) (void)hipEventRecord(pe->ev[next++], st);
+        }
+        ~Finish() {
+            if (!prof) return;
+            while (next < 4) (void)hipEventRecord(pe->ev[next++], st);
+            g_prof.pending.push_back(*pe);
+        }
+    } fin{prof, &pe, st};
+    ScaleExps exps;
+    stt = run_scaling(plan, A, lda, transA, B, ldb, transB, m, k, n, ws, w, st, &exps);
+    fin.mark();
+    if (stt != FASTMM_OK) return stt;
+    const Elem el = plan->prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
+    LeafLaunch L;
+    L.elem = el;
+    L.prec = plan->prec;
+    L.A = A, L.B = B;
+    L.lda = lda, L.ldb = ldb;
+    L.transA = transA ? 1 : 0, L.transB = transB ? 1 : 0;
+    L.m = m, L.k = k, L.n = n;
+    L.mb = s.mb, L.kb = s.kb, L.nb = s.nb;
+    L.nleaves = tab->nleaves;
+    L.leaves = tab->leaves, L.asrc = tab->asrc, L.bsrc = tab->bsrc;
+    L.sc = exps;
+    hipError_t e;
+    if (s.L == 0) {
+        L.out = C, L.ldo = ldc, L.leaf_stride = 0, L.direct = 1;
+        e = launch_leaf(L, st);
+        fin.mark();
+        if (e != hipSuccess) return hip_fail(e, "leaf kernel");
+        return FASTMM_OK;
+    }
+    L.out = ws + w.leaves, L.ldo = s.nb, L.leaf_stride = s.mb * s.nb, L.direct = 0;
+    e = launch_leaf(L, st);
+    fin.mark();
+    if (e != hipSuccess) return hip_fail(e, "leaf kernel");
+    CombineLaunch Cb;
+    Cb.elem = el;
+    Cb.M = ws + w.leaves;
+    Cb.leaf_stride = s.mb * s.nb;
+    Cb.C = C, Cb.ldc = ldc, Cb.m = m, Cb.n = n, Cb.mb = s.mb, Cb.nb = s.nb;
+    Cb.NB = tab->NB;
+    Cb.bdest = tab->bdest, Cb.dest = tab->dest;
+    Cb.sc = exps;
+    if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_gemm(fastmm_plan_t plan, const void *A, const void *B, void *C, int64_t m, int64_t k, int64_t n,
+                          void *workspace, size_t ws_bytes, void *stream) {
+    return fastmm_gemm_ex(plan, A, k, 0, B, n, 0, C, n, m, k, n, workspace, ws_bytes, stream);
+}
+
+fastmm_status fastmm_scaling_exponents(fastmm_plan_t plan, const void *A, const void *B, int64_t m, int64_t k,
+                                       int64_t n, int32_t *ea, int32_t *eb, int32_t *ep, void *workspace,
+                                       size_t ws_bytes, void *stream) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    if (m <= 0 || k <= 0 || n <= 0 || !A || !B || !ea || !eb || !ep) return fail(FASTMM_EINVAL, "bad arguments");
+    if (plan->sc.mode == FASTMM_SCALE_NONE) return fail(FASTMM_EINVAL, "plan has no scaling");
+    const Shape s = shape_of(plan, m, k, n);
+    const WsLayout w = ws_layout(plan, s, m, k, n);
+    if (workspace == nullptr || ws_bytes < w.total) return fail(FASTMM_EWORKSPACE, "workspace too small");
+    if (((uintptr_t)workspace & 255) != 0) return fail(FASTMM_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    ScaleExps exps;
+    fastmm_status stt = run_scaling(plan, A, k, 0, B, n, 0, m, k, n, (char *)workspace, w, st, &exps);
+    if (stt != FASTMM_OK) return stt;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ea, exps.ea, 4 * (size_t)m, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(eb, exps.eb, 4 * (size_t)n, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(ep, exps.ep, 4 * (size_t)k, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return hip_fail(e, "copying exponents");
+    return FASTMM_OK;
+}
+
+}  // extern "C"

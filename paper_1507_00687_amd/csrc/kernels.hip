@@ -1,0 +1,532 @@
+// Device kernels for gfx950 (CDNA4): scaling-vector reductions, the fused leaf-product
+// GEMM (S/T formation folded into the tile loads, MFMA leaf product) and the W-combination.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "devtypes.h"
+#include "launch.h"
+
+namespace fastmm {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;  // 4 wave64 per work-group
+constexpr int kXcds = 8;       // MI355X: 8 XCDs, work-groups dispatched round-robin
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef d4_t acc_t;
+    // D(16x16) += A(16x4) B(4x16); lane l holds A[l%16][l/16], B[l/16][l%16],
+    // D[4*(l/16)+v][l%16] in element v.
+    __device__ static inline acc_t op(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<float> {
+    typedef f4_t acc_t;
+    __device__ static inline acc_t op(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+__device__ inline double ldexp_t(double x, int e) { return ldexp(x, e); }
+__device__ inline float ldexp_t(float x, int e) { return ldexpf(x, e); }
+
+// Block id remap so that consecutive logical tiles land on the same XCD (each XCD has its
+// own L2): hardware places block b on XCD b % 8.  Bijective for any grid size.
+__device__ inline int64_t xcd_remap(int64_t b, int64_t G) {
+    const int64_t x = b % kXcds, j = b / kXcds;
+    const int64_t per = G / kXcds, rem = G % kXcds;
+    const int64_t base = (x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+    return base + j;
+}
+
+template <typename T>
+struct LeafArgs {
+    const T *A;
+    const T *B;
+    T *out;
+    int64_t lda, ldb, ldo;
+    int64_t m, k, n;
+    int64_t mb, kb, nb;
+    int64_t leaf_stride;
+    int tiles_m, tiles_n;
+    const LeafEntry *leaves;
+    const SrcEntry *asrc;
+    const SrcEntry *bsrc;
+    ScaleExps sc;
+};
+
+// One BMxBN tile of one leaf product.  2x2 waves, each owning a (BM/2)x(BN/2) sub-tile made
+// of 16x16 MFMA blocks.  Per K step of BK: every thread forms BM*BK/256 elements of the S
+// tile as the sequential sum over the leaf's A sources of coef * (scaled) element, and the
+// same for T, stores them to LDS (k-major), then the waves run BK/4 MFMA steps.
+template <typename T, int BM, int BN, int BK, bool TA, bool TB, bool SCALED, bool DIRECT>
+__global__ __launch_bounds__(kThreads) void leaf_kernel(LeafArgs<T> p) {
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int EA = BM * BK / kThreads, EB = BK * BN / kThreads;
+    static_assert(EA * kThreads == BM * BK && EB * kThreads == BK * BN, "tile/threads");
+    __shared__ T As[BK][BM + 1];
+    __shared__ T Bs[BK][BN + 1];
+
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
+    const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int leaf = (int)(bid / tiles);
+    const int64_t rem = bid - (int64_t)leaf * tiles;
+    const int64_t tm = rem / p.tiles_n, tn = rem - tm * p.tiles_n;
+    const LeafEntry le = p.leaves[leaf];
+
+    typename Mfma<T>::acc_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = typename Mfma<T>::acc_t{};
+
+    for (int64_t k0 = 0; k0 < p.kb; k0 += BK) {
+        T ra[EA], rb[EB];
+        // ---- S tile: sum_src coef * A'(src block)
+#pragma unroll
+        for (int s = 0; s < EA; ++s) ra[s] = T(0);
+        for (int q = 0; q < le.a_count; ++q) {
+            const SrcEntry se = p.asrc[le.a_begin + q];
+            const T c = (T)se.coef;
+#pragma unroll
+            for (int s = 0; s < EA; ++s) {
+                const int e = t + kThreads * s;
+                const int row = TA ? (e % BM) : (e / BK);
+                const int kk = TA ? (e / BM) : (e % BK);
+                const int64_t x = tm * BM + row, y = k0 + kk;
+                const int64_t gr = (int64_t)se.br * p.mb + x, gc = (int64_t)se.bc * p.kb + y;
+                T v = T(0);
+                if (x < p.mb && y < p.kb && gr < p.m && gc < p.k) {
+                    v = TA ? p.A[gc * p.lda + gr] : p.A[gr * p.lda + gc];
+                    if (SCALED) v = ldexp_t(v, p.sc.ep[gc] - p.sc.ea[gr]);
+                }
+                const T term = c * v;
+                ra[s] = (q == 0) ? term : ra[s] + term;
+            }
+        }
+        // ---- T tile: sum_src coef * B'(src block)
+#pragma unroll
+        for (int s = 0; s < EB; ++s) rb[s] = T(0);
+        for (int q = 0; q < le.b_count; ++q) {
+            const SrcEntry se = p.bsrc[le.b_begin + q];
+            const T c = (T)se.coef;
+#pragma unroll
+            for (int s = 0; s < EB; ++s) {
+                const int e = t + kThreads * s;
+                const int kk = TB ? (e % BK) : (e / BN);
+                const int col = TB ? (e / BK) : (e % BN);
+                const int64_t y = k0 + kk, z = tn * BN + col;
+                const int64_t gr = (int64_t)se.br * p.kb + y, gc = (int64_t)se.bc * p.nb + z;
+                T v = T(0);
+                if (y < p.kb && z < p.nb && gr < p.k && gc < p.n) {
+                    v = TB ? p.B[gc * p.ldb + gr] : p.B[gr * p.ldb + gc];
+                    if (SCALED) v = ldexp_t(v, -p.sc.ep[gr] - p.sc.eb[gc]);
+                }
+                const T term = c * v;
+                rb[s] = (q == 0) ? term : rb[s] + term;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < EA; ++s) {
+            const int e = t + kThreads * s;
+            const int row = TA ? (e % BM) : (e / BK);
+            const int kk = TA ? (e / BM) : (e % BK);
+            As[kk][row] = ra[s];
+        }
+#pragma unroll
+        for (int s = 0; s < EB; ++s) {
+            const int e = t + kThreads * s;
+            const int kk = TB ? (e % BK) : (e / BN);
+            const int col = TB ? (e / BK) : (e % BN);
+            Bs[kk][col] = rb[s];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            T a[TM], b[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = As[ks + (lane >> 4)][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b[j] = Bs[ks + (lane >> 4)][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::op(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+
+    // ---- epilogue
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = tm * BM + wm * WM + i * 16 + 4 * (lane >> 4) + v;
+                const int64_t col = tn * BN + wn * WN + j * 16 + (lane & 15);
+                T val = acc[i][j][v];
+                if (DIRECT) {
+                    if (row < p.m && col < p.n) {
+                        if (SCALED) val = ldexp_t(val, p.sc.ea[row] + p.sc.eb[col]);
+                        p.out[row * p.ldo + col] = val;
+                    }
+                } else {
+                    if (row < p.mb && col < p.nb) p.out[(int64_t)leaf * p.leaf_stride + row * p.ldo + col] = val;
+                }
+            }
+}
+
+template <typename T>
+struct CombineArgs {
+    const T *M;
+    int64_t leaf_stride;
+    T *C;
+    int64_t ldc, m, n, mb, nb;
+    int NB;
+    const BlockDests *bdest;
+    const DestEntry *dest;
+    ScaleExps sc;
+};
+
+// C(i, j) = 2^(ea_i + eb_j) * sum_q coef_q * M_{leaf_q}(i mod mb, j mod nb), summed in list
+// order.  One thread per output element; every element is written once.
+template <typename T, bool SCALED>
+__global__ __launch_bounds__(kThreads) void combine_kernel(CombineArgs<T> p) {
+    const int64_t col = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (col >= p.n) return;
+    const int64_t S = col / p.nb, y = col - S * p.nb;
+    for (int64_t row = blockIdx.y; row < p.m; row += gridDim.y) {
+        const int64_t P = row / p.mb, x = row - P * p.mb;
+        const BlockDests bd = p.bdest[P * p.NB + S];
+        T acc = T(0);
+        for (int q = 0; q < bd.count; ++q) {
+            const DestEntry de = p.dest[bd.begin + q];
+            const T term = (T)de.coef * p.M[(int64_t)de.leaf * p.leaf_stride + x * p.nb + y];
+            acc = (q == 0) ? term : acc + term;
+        }
+        if (SCALED) acc = ldexp_t(acc, p.sc.ea[row] + p.sc.eb[col]);
+        p.C[row * p.ldc + col] = acc;
+    }
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int64_t count, int32_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+template <typename T>
+__global__ void zero_kernel(T *C, int64_t ldc, int64_t m, int64_t n) {
+    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= n) return;
+    for (int64_t row = blockIdx.y; row < m; row += gridDim.y) C[row * ldc + col] = T(0);
+}
+
+// ------------------------------------------------------------------ scaling reductions
+template <typename T>
+struct Bits;
+template <>
+struct Bits<double> {
+    typedef unsigned long long u;
+    __device__ static u of(double x) { return (u)__double_as_longlong(x); }
+};
+template <>
+struct Bits<float> {
+    typedef unsigned int u;
+    __device__ static u of(float x) { return (u)__float_as_uint(x); }
+};
+
+// max that keeps NaN once seen (so a NaN row/column gets the neutral factor 1)
+template <typename T>
+__device__ inline T nanmax(T a, T b) {
+    return (b > a || b != b) ? b : a;
+}
+
+// out[r] = max_c |X(r,c)| * 2^(sr*er[r] + sc*ec[c]) over a stored row-major R x C matrix
+// whose rows are contiguous.  One wave per row.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void rowmax_kernel(const T *X, int64_t ld, int64_t R, int64_t C,
+                                                           const int32_t *er, int sr, const int32_t *ec, int sc,
+                                                           T *out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (r >= R) return;
+    const int rexp = sr * er[r];
+    T mx = T(0);
+    for (int64_t c = lane; c < C; c += 64) {
+        const T v = ldexp_t(fabs(X[r * ld + c]), rexp + sc * ec[c]);
+        mx = nanmax(mx, v);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = nanmax(mx, (T)__shfl_xor(mx, off, 64));
+    if (lane == 0) out[r] = mx;
+}
+
+// out[c] = max_r |X(r,c)| * 2^(sr*er[r] + sc*ec[c]); each block covers 256 columns and a
+// chunk of rows, partial maxima merged with an unsigned atomic max on the IEEE bit pattern
+// (order-independent, so the result is deterministic).  `out` must start at +0.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void colmax_kernel(const T *X, int64_t ld, int64_t R, int64_t C,
+                                                           const int32_t *er, int sr, const int32_t *ec, int sc,
+                                                           int64_t rows_per_block, T *out) {
+    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (c >= C) return;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
+    const int64_t r1 = r0 + rows_per_block < R ? r0 + rows_per_block : R;
+    const int cexp = sc * ec[c];
+    T mx = T(0);
+    for (int64_t r = r0; r < r1; ++r) mx = nanmax(mx, ldexp_t(fabs(X[r * ld + c]), cexp + sr * er[r]));
+    atomicMax(reinterpret_cast<typename Bits<T>::u *>(out + c), Bits<T>::of(mx));
+}
+
+template <typename T>
+__global__ void zero_elems_kernel(T *p, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = T(0);
+}
+
+template <typename T>
+__device__ inline bool finite_pos(T x) {
+    return x > T(0) && x < T(INFINITY);  // false for NaN
+}
+
+// Smallest e with x <= 2^e, for finite x > 0.
+template <typename T>
+__device__ inline int ceil_log2(T x) {
+    int e;
+    const T f = frexp(x, &e);
+    return (f == T(0.5)) ? e - 1 : e;
+}
+
+// Nearest integer to log2(b/a)/2, ties to even, for finite a, b > 0 (exact: mantissas of b
+// and a compared directly).
+template <typename T>
+__device__ inline int half_log2_ratio(T b, T a) {
+    int eb, ea;
+    const T fb = frexp(b, &eb), fa = frexp(a, &ea);
+    const int d = eb - ea;
+    if ((d & 1) == 0) return d / 2;  // d even: log2(b/a) in (d-1, d+1)
+    const int lo = (d - 1) >> 1, hi = lo + 1;
+    if (fb < fa) return lo;
+    if (fb > fa) return hi;
+    return (lo & 1) == 0 ? lo : hi;
+}
+
+// O-step finalisation: e[i] += ceil_log2(max[i]) where the max is finite and positive.
+// Stopping test (tau > 0): fail unless every unrounded factor max[i] >= thr.
+template <typename T>
+__global__ void o_finalize_kernel(const T *mx, int64_t count, int32_t *e, const int32_t *flags, int32_t *fail,
+                                  int test, double thr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (flags[0] != 0 || i >= count) return;  // flags[0]: iteration already stopped
+    const T v = mx[i];
+    if (finite_pos(v)) {
+        e[i] += ceil_log2(v);
+        if (test && (double)v < thr) atomicOr(fail, 1);
+    }
+}
+
+// I-step finalisation: e[k] += nearest integer to log2(bmax/amax)/2.  Stopping test: fail
+// unless every unrounded factor sqrt(bmax/amax) lies in [lo, hi].
+template <typename T>
+__global__ void i_finalize_kernel(const T *amax, const T *bmax, int64_t count, int32_t *e, const int32_t *flags,
+                                  int32_t *fail, int test, double lo, double hi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (flags[0] != 0 || i >= count) return;
+    const T a = amax[i], b = bmax[i];
+    if (finite_pos(a) && finite_pos(b)) {
+        e[i] += half_log2_ratio(b, a);
+        if (test) {
+            const double pe = sqrt((double)b / (double)a);
+            if (pe < lo || pe > hi) atomicOr(fail, 1);
+        }
+    }
+}
+
+// After a tested step: stop the iteration if no factor failed; reset the fail flag.
+__global__ void stop_update_kernel(int32_t *flags) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (flags[0] == 0 && flags[1] == 0) flags[0] = 1;
+        flags[1] = 0;
+    }
+}
+
+template <typename T, int BM, int BN, int BK, bool TA, bool TB>
+hipError_t leaf_go(const LeafLaunch &L, hipStream_t s) {
+    LeafArgs<T> a;
+    a.A = (const T *)L.A;
+    a.B = (const T *)L.B;
+    a.out = (T *)L.out;
+    a.lda = L.lda, a.ldb = L.ldb, a.ldo = L.ldo;
+    a.m = L.m, a.k = L.k, a.n = L.n;
+    a.mb = L.mb, a.kb = L.kb, a.nb = L.nb;
+    a.leaf_stride = L.leaf_stride;
+    a.tiles_m = (int)((L.mb + BM - 1) / BM);
+    a.tiles_n = (int)((L.nb + BN - 1) / BN);
+    a.leaves = L.leaves, a.asrc = L.asrc, a.bsrc = L.bsrc;
+    a.sc = L.sc;
+    const int64_t blocks = (int64_t)a.tiles_m * a.tiles_n * L.nleaves;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const bool scaled = L.sc.ea != nullptr;
+    dim3 grid((unsigned)blocks), block(kThreads);
+    if (L.direct) {
+        if (scaled) hipLaunchKernelGGL((leaf_kernel<T, BM, BN, BK, TA, TB, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((leaf_kernel<T, BM, BN, BK, TA, TB, false, true>), grid, block, 0, s, a);
+    } else {
+        if (scaled) hipLaunchKernelGGL((leaf_kernel<T, BM, BN, BK, TA, TB, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((leaf_kernel<T, BM, BN, BK, TA, TB, false, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int BM, int BN, int BK>
+hipError_t leaf_trans(const LeafLaunch &L, hipStream_t s) {
+    if (L.transA) {
+        if (L.transB) return leaf_go<T, BM, BN, BK, true, true>(L, s);
+        return leaf_go<T, BM, BN, BK, true, false>(L, s);
+    }
+    if (L.transB) return leaf_go<T, BM, BN, BK, false, true>(L, s);
+    return leaf_go<T, BM, BN, BK, false, false>(L, s);
+}
+
+template <typename T>
+hipError_t combine_go(const CombineLaunch &L, hipStream_t s) {
+    CombineArgs<T> a;
+    a.M = (const T *)L.M;
+    a.leaf_stride = L.leaf_stride;
+    a.C = (T *)L.C;
+    a.ldc = L.ldc, a.m = L.m, a.n = L.n, a.mb = L.mb, a.nb = L.nb;
+    a.NB = L.NB;
+    a.bdest = L.bdest, a.dest = L.dest, a.sc = L.sc;
+    if (L.m <= 0 || L.n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)(L.m < 65535 ? L.m : 65535));
+    if (L.sc.ea) hipLaunchKernelGGL((combine_kernel<T, true>), grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((combine_kernel<T, false>), grid, dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+inline unsigned grid1d(int64_t count, int per) {
+    int64_t g = (count + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > 65535) g = 65535;
+    return (unsigned)g;
+}
+
+// Logical reductions over op(X) where op(X) is R x C; the stored matrix is row-major with
+// contiguous rows (trans == 0) or op(X) = stored^T (trans != 0).
+template <typename T>
+hipError_t reduce_rows(const T *X, int64_t ld, int trans, int64_t R, int64_t C, const int32_t *er, int sr,
+                       const int32_t *ec, int sc, T *out, hipStream_t s) {
+    if (R <= 0) return hipSuccess;
+    if (!trans) {
+        hipLaunchKernelGGL(rowmax_kernel<T>, dim3((unsigned)((R + 3) / 4)), dim3(kThreads), 0, s, X, ld, R, C, er,
+                           sr, ec, sc, out);
+    } else {
+        // rows of op(X) are columns of the stored C x R matrix
+        hipLaunchKernelGGL(zero_elems_kernel<T>, dim3(grid1d(R, kThreads)), dim3(kThreads), 0, s, out, R);
+        const int64_t rpb = 64;
+        dim3 grid((unsigned)((R + kThreads - 1) / kThreads), (unsigned)((C + rpb - 1) / rpb));
+        hipLaunchKernelGGL(colmax_kernel<T>, grid, dim3(kThreads), 0, s, X, ld, C, R, ec, sc, er, sr, rpb, out);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t reduce_cols(const T *X, int64_t ld, int trans, int64_t R, int64_t C, const int32_t *er, int sr,
+                       const int32_t *ec, int sc, T *out, hipStream_t s) {
+    if (C <= 0) return hipSuccess;
+    if (!trans) {
+        hipLaunchKernelGGL(zero_elems_kernel<T>, dim3(grid1d(C, kThreads)), dim3(kThreads), 0, s, out, C);
+        const int64_t rpb = 64;
+        dim3 grid((unsigned)((C + kThreads - 1) / kThreads), (unsigned)((R + rpb - 1) / rpb));
+        hipLaunchKernelGGL(colmax_kernel<T>, grid, dim3(kThreads), 0, s, X, ld, R, C, er, sr, ec, sc, rpb, out);
+    } else {
+        hipLaunchKernelGGL(rowmax_kernel<T>, dim3((unsigned)((C + 3) / 4)), dim3(kThreads), 0, s, X, ld, C, R, ec,
+                           sc, er, sr, out);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t scale_step_t(const ScaleStep &S, hipStream_t s) {
+    const T *A = (const T *)S.A;
+    const T *B = (const T *)S.B;
+    T *mA = (T *)S.maxA;
+    T *mB = (T *)S.maxB;
+    hipError_t err;
+    // Note: the reductions run even after an early stop; the finalisers are guarded by the
+    // stop flag, so the exponents no longer change.
+    if (S.kind == 'O') {
+        // rows of A' = diag(2^-ea) A diag(2^ep): max over k of |A_ik| 2^(ep_k - ea_i)
+        err = reduce_rows<T>(A, S.lda, S.transA, S.m, S.k, S.ea, -1, S.ep, +1, mA, s);
+        if (err != hipSuccess) return err;
+        // columns of B' = diag(2^-ep) B diag(2^-eb)
+        err = reduce_cols<T>(B, S.ldb, S.transB, S.k, S.n, S.ep, -1, S.eb, -1, mB, s);
+        if (err != hipSuccess) return err;
+        const double thr = S.test ? std::pow(1.0 + S.tau, -0.5) : 0.0;
+        hipLaunchKernelGGL(o_finalize_kernel<T>, dim3(grid1d(S.m, kThreads)), dim3(kThreads), 0, s, mA, S.m,
+                           S.ea, S.flags, S.flags + 1, S.test, thr);
+        hipLaunchKernelGGL(o_finalize_kernel<T>, dim3(grid1d(S.n, kThreads)), dim3(kThreads), 0, s, mB, S.n,
+                           S.eb, S.flags, S.flags + 1, S.test, thr);
+    } else {
+        // columns of A' and rows of B'
+        err = reduce_cols<T>(A, S.lda, S.transA, S.m, S.k, S.ea, -1, S.ep, +1, mA, s);
+        if (err != hipSuccess) return err;
+        err = reduce_rows<T>(B, S.ldb, S.transB, S.k, S.n, S.ep, -1, S.eb, -1, mB, s);
+        if (err != hipSuccess) return err;
+        const double lo = S.test ? std::pow(1.0 + S.tau, -0.25) : 0.0;
+        const double hi = S.test ? std::pow(1.0 + S.tau, 0.25) : 0.0;
+        hipLaunchKernelGGL(i_finalize_kernel<T>, dim3(grid1d(S.k, kThreads)), dim3(kThreads), 0, s, mA, mB, S.k,
+                           S.ep, S.flags, S.flags + 1, S.test, lo, hi);
+    }
+    if (S.test) hipLaunchKernelGGL(stop_update_kernel, dim3(1), dim3(64), 0, s, S.flags);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_leaf(const LeafLaunch &L, hipStream_t s) {
+    if (L.elem == Elem::F64) return leaf_trans<double, 64, 64, 16>(L, s);
+    return leaf_trans<float, 128, 128, 16>(L, s);
+}
+
+hipError_t launch_combine(const CombineLaunch &L, hipStream_t s) {
+    if (L.elem == Elem::F64) return combine_go<double>(L, s);
+    return combine_go<float>(L, s);
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid1d(count, kThreads)), dim3(kThreads), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_elems(Elem e, void *C, int64_t ldc, int64_t m, int64_t n, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)(m < 65535 ? m : 65535));
+    if (e == Elem::F64) hipLaunchKernelGGL(zero_kernel<double>, grid, dim3(kThreads), 0, s, (double *)C, ldc, m, n);
+    else hipLaunchKernelGGL(zero_kernel<float>, grid, dim3(kThreads), 0, s, (float *)C, ldc, m, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_step(const ScaleStep &S, hipStream_t s) {
+    if (S.elem == Elem::F64) return scale_step_t<double>(S, s);
+    return scale_step_t<float>(S, s);
+}
+
+}  // namespace fastmm

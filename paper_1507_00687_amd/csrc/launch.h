@@ -1,0 +1,79 @@
+// Host-side launchers of the device kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "devtypes.h"
+
+namespace fastmm {
+
+// Element type tag of a launch.
+enum class Elem { F64, F32 };
+
+// Leaf-product launch: every work-group computes one BMxBN tile of one leaf product
+// M_r = S_r T_r, forming the S_r / T_r tiles from their source blocks while loading them
+// (coefficients and scaling exponents applied in registers), and writes the tile either to
+// the leaf workspace (direct == 0) or, for a single classical leaf, straight to C with the
+// outside-scaling factors applied (direct == 1).
+struct LeafLaunch {
+    Elem elem;
+    int prec;  // fastmm_precision
+    const void *A;
+    const void *B;
+    void *out;
+    int64_t lda, ldb, ldo;
+    int transA, transB;
+    int64_t m, k, n;
+    int64_t mb, kb, nb;
+    int64_t leaf_stride;
+    int nleaves;
+    const LeafEntry *leaves;
+    const SrcEntry *asrc;
+    const SrcEntry *bsrc;
+    ScaleExps sc;
+    int direct;
+};
+
+// W-combination: C_block(P,S) = sum over its DestEntry list of coef * M_leaf, then
+// multiplied by 2^(ea_i + eb_j); writes every C element exactly once.
+struct CombineLaunch {
+    Elem elem;
+    const void *M;  // leaf workspace
+    int64_t leaf_stride;
+    void *C;
+    int64_t ldc;
+    int64_t m, n, mb, nb;
+    int NB;  // blocks per row of the output block grid (N0^L)
+    const BlockDests *bdest;
+    const DestEntry *dest;
+    ScaleExps sc;
+};
+
+// Scaling-step reductions (Algorithms 1-3).  `kind` 'O' or 'I'.  Operands are op(A) (m x k)
+// and op(B) (k x n).  `maxA`, `maxB` hold (m | k) and (k | n) maxima scratch of the element
+// type; `exps` are updated in place; `flags` are two int32 (stop, fail) for the optional
+// stopping test (tau > 0).
+struct ScaleStep {
+    Elem elem;
+    char kind;
+    const void *A;
+    const void *B;
+    int64_t lda, ldb;
+    int transA, transB;
+    int64_t m, k, n;
+    int32_t *ea, *ep, *eb;
+    void *maxA, *maxB;
+    int32_t *flags;
+    double tau;
+    int test;  // apply the stopping test at this step
+};
+
+hipError_t launch_leaf(const LeafLaunch &L, hipStream_t s);
+hipError_t launch_combine(const CombineLaunch &L, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
+hipError_t launch_zero_elems(Elem e, void *C, int64_t ldc, int64_t m, int64_t n, hipStream_t s);
+hipError_t launch_scale_step(const ScaleStep &S, hipStream_t s);
+
+}  // namespace fastmm

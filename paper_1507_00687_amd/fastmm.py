@@ -1,0 +1,257 @@
+"""Thin Python binding of the fastmm C ABI (include/fastmm.h).
+
+Argument marshalling only: every step of the multiplication runs in the HIP kernels of
+libfastmm.so.  PyTorch provides device memory (tensors, the caching allocator for the
+workspace) and the current stream.  If the shared library is missing the import of this
+module still works, but every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastmm.so")
+
+FASTMM_OK = 0
+
+ALGOS = {
+    "classical": 0,
+    "strassen": 1,
+    "winograd": 2,
+    "f323": 3,
+    "f332": 4,
+    "f233": 5,
+    "f442": 6,
+    "f424": 7,
+    "f244": 8,
+    "laderman333": 9,
+}
+SCALE_MODES = {"none": 0, "outside": 1, "inside": 2, "out_in": 3, "in_out": 4, "repeated": 5}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4, "f16x3": 5, "bf16x6": 6}
+
+
+class FastmmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fastmm error {status}: {msg}")
+        self.status = status
+
+
+class _Scaling(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("steps", ctypes.c_int), ("tau", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libfastmm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1507_00687_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64, vp, sz = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+        pi32, pi64, pd = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+        L.fastmm_algo_register.argtypes = [i32, i32, i32, i32, pi64, pi64, pi64, i32, pi32]
+        L.fastmm_algo_info.argtypes = [i32, pi32, pi32, pi32, pi32, pi32, pd, pd]
+        L.fastmm_algo_coeffs.argtypes = [i32, pd, pd, pd]
+        L.fastmm_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(_Scaling), i32]
+        L.fastmm_plan_destroy.argtypes = [vp]
+        L.fastmm_plan_shape.argtypes = [vp, i64, i64, i64, pi32, pi64, pi64, pi64]
+        L.fastmm_workspace_size.argtypes = [vp, i64, i64, i64, ctypes.POINTER(sz)]
+        L.fastmm_gemm.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
+        L.fastmm_gemm_ex.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64, i64, i64, i64, vp, sz, vp]
+        L.fastmm_scaling_exponents.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp, vp, sz, vp]
+        L.fastmm_profile_enable.argtypes = [i32]
+        L.fastmm_profile_read.argtypes = [pd, pd, pd, pi32]
+        L.fastmm_strerror.argtypes = [i32]
+        L.fastmm_strerror.restype = ctypes.c_char_p
+        L.fastmm_last_error.restype = ctypes.c_char_p
+        for name in ("fastmm_algo_register", "fastmm_algo_info", "fastmm_algo_coeffs", "fastmm_plan_create",
+                     "fastmm_plan_destroy", "fastmm_plan_shape", "fastmm_workspace_size", "fastmm_gemm",
+                     "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != FASTMM_OK:
+        L = lib()
+        msg = L.fastmm_last_error().decode() or L.fastmm_strerror(status).decode()
+        raise FastmmError(status, msg)
+
+
+def _id(table: dict, key) -> int:
+    return table[key] if isinstance(key, str) else int(key)
+
+
+# --------------------------------------------------------------------------- algorithms
+def fastmm_algo_info(algo) -> dict:
+    vals = [ctypes.c_int() for _ in range(5)]
+    Q, E = ctypes.c_double(), ctypes.c_double()
+    _check(lib().fastmm_algo_info(_id(ALGOS, algo), *[ctypes.byref(v) for v in vals], ctypes.byref(Q),
+                                  ctypes.byref(E)))
+    M0, K0, N0, R, nnz = (v.value for v in vals)
+    return {"M0": M0, "K0": K0, "N0": N0, "R": R, "nnz": nnz, "Q": Q.value, "E": E.value}
+
+
+def fastmm_algo_coeffs(algo):
+    import numpy as np
+
+    info = fastmm_algo_info(algo)
+    M0, K0, N0, R = info["M0"], info["K0"], info["N0"], info["R"]
+    U = np.zeros((M0 * K0, R))
+    V = np.zeros((K0 * N0, R))
+    W = np.zeros((M0 * N0, R))
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(lib().fastmm_algo_coeffs(_id(ALGOS, algo), U.ctypes.data_as(P), V.ctypes.data_as(P),
+                                    W.ctypes.data_as(P)))
+    return U, V, W
+
+
+def fastmm_algo_register(M0, K0, N0, R, num_U, num_V, num_W, log2_den=0) -> int:
+    import numpy as np
+
+    arrs = [np.ascontiguousarray(x, dtype=np.int64) for x in (num_U, num_V, num_W)]
+    out = ctypes.c_int()
+    P = ctypes.POINTER(ctypes.c_int64)
+    _check(lib().fastmm_algo_register(M0, K0, N0, R, *[a.ctypes.data_as(P) for a in arrs], log2_den,
+                                      ctypes.byref(out)))
+    return out.value
+
+
+# --------------------------------------------------------------------------------- plans
+class Plan:
+    """A fastmm plan: algorithm, recursion depth, cutoff, scaling procedure, precision."""
+
+    def __init__(self, algo="strassen", depth: int = 1, cutoff: int = 1, scaling: str = "none",
+                 steps: int = 2, tau: float = 0.0, precision: str = "f64"):
+        self.algo, self.depth, self.cutoff = algo, depth, cutoff
+        self.scaling, self.steps, self.tau, self.precision = scaling, steps, tau, precision
+        self._h = ctypes.c_void_p()
+        sc = _Scaling(_id(SCALE_MODES, scaling), steps, tau)
+        _check(lib().fastmm_plan_create(ctypes.byref(self._h), _id(ALGOS, algo), depth, cutoff, ctypes.byref(sc),
+                                        _id(PRECISIONS, precision)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def shape(self, m: int, k: int, n: int) -> Tuple[int, int, int, int]:
+        L = ctypes.c_int()
+        Mp, Kp, Np = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fastmm_plan_shape(self._h, m, k, n, ctypes.byref(L), ctypes.byref(Mp), ctypes.byref(Kp),
+                                       ctypes.byref(Np)))
+        return L.value, Mp.value, Kp.value, Np.value
+
+    def workspace_size(self, m: int, k: int, n: int) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().fastmm_workspace_size(self._h, m, k, n, ctypes.byref(b)))
+        return b.value
+
+    @property
+    def dtype(self):
+        import torch
+
+        return torch.float64 if self.precision == "f64" else torch.float32
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.fastmm_plan_destroy(h)
+            self._h = ctypes.c_void_p()
+
+
+# ------------------------------------------------------------------------ multiplication
+def _stream_ptr(stream) -> int:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _workspace(plan: Plan, m, k, n, device, workspace):
+    import torch
+
+    need = plan.workspace_size(m, k, n)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+    return workspace, need
+
+
+def fastmm_gemm(plan: Plan, A, B, C=None, workspace=None, stream=None):
+    """C = A @ B on the GPU (A: m x k, B: k x n, contiguous row-major CUDA tensors)."""
+    import torch
+
+    m, k = A.shape
+    k2, n = B.shape
+    if k != k2:
+        raise ValueError("inner dimensions differ")
+    if A.dtype != plan.dtype or B.dtype != plan.dtype:
+        raise TypeError(f"plan precision {plan.precision} takes {plan.dtype} operands")
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("operands must be on the GPU")
+    A = A.contiguous()
+    B = B.contiguous()
+    if C is None:
+        C = torch.empty((m, n), dtype=plan.dtype, device=A.device)
+    ws, need = _workspace(plan, m, k, n, A.device, workspace)
+    _check(lib().fastmm_gemm(plan.handle, A.data_ptr(), B.data_ptr(), C.data_ptr(), m, k, n, ws.data_ptr(),
+                             ws.numel(), _stream_ptr(stream)))
+    return C
+
+
+def fastmm_gemm_ex(plan: Plan, A, transA: bool, B, transB: bool, C=None, workspace=None, stream=None):
+    """C = op(A) @ op(B) with op(X) = X.T when the flag is set (X stored row-major)."""
+    import torch
+
+    m, k = (A.shape[1], A.shape[0]) if transA else (A.shape[0], A.shape[1])
+    kb, n = (B.shape[1], B.shape[0]) if transB else (B.shape[0], B.shape[1])
+    if k != kb:
+        raise ValueError("inner dimensions differ")
+    if A.stride(1) != 1 or B.stride(1) != 1:
+        raise ValueError("operands need contiguous rows")
+    if C is None:
+        C = torch.empty((m, n), dtype=plan.dtype, device=A.device)
+    ws, need = _workspace(plan, m, k, n, A.device, workspace)
+    _check(lib().fastmm_gemm_ex(plan.handle, A.data_ptr(), A.stride(0), int(bool(transA)), B.data_ptr(),
+                                B.stride(0), int(bool(transB)), C.data_ptr(), C.stride(0), m, k, n, ws.data_ptr(),
+                                ws.numel(), _stream_ptr(stream)))
+    return C
+
+
+def fastmm_scaling_exponents(plan: Plan, A, B, workspace=None, stream=None):
+    """Power-of-two exponents (ea, eb, ep) of the plan's scaling of (A, B), int32 tensors."""
+    import torch
+
+    m, k = A.shape
+    n = B.shape[1]
+    ea = torch.empty(m, dtype=torch.int32, device=A.device)
+    eb = torch.empty(n, dtype=torch.int32, device=A.device)
+    ep = torch.empty(k, dtype=torch.int32, device=A.device)
+    ws, need = _workspace(plan, m, k, n, A.device, workspace)
+    _check(lib().fastmm_scaling_exponents(plan.handle, A.contiguous().data_ptr(), B.contiguous().data_ptr(), m, k,
+                                          n, ea.data_ptr(), eb.data_ptr(), ep.data_ptr(), ws.data_ptr(),
+                                          ws.numel(), _stream_ptr(stream)))
+    return ea, eb, ep
+
+
+def fastmm_profile_enable(enable: bool = True) -> None:
+    _check(lib().fastmm_profile_enable(int(bool(enable))))
+
+
+def fastmm_profile_read() -> dict:
+    """Summed milliseconds per phase of the profiled calls since the last read."""
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n = ctypes.c_int()
+    _check(lib().fastmm_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(n)))
+    return {"scaling_ms": a.value, "leaf_ms": b.value, "combine_ms": c.value, "calls": n.value}
+
+
+def matmul(A, B, plan: Optional[Plan] = None, **plan_kwargs):
+    """Convenience: C = A @ B through a (new or given) plan."""
+    plan = plan or Plan(**plan_kwargs)
+    return fastmm_gemm(plan, A, B)

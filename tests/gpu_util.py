@@ -1,0 +1,50 @@
+"""Helpers for the GPU parity tests: move seeded host inputs to the device, run the library
+through its C ABI (the thin binding), and compare with the oracle."""
+import numpy as np
+
+from oracle import coeffs as C
+from oracle import fastmm_oracle as O
+
+ORACLE_ALGO = {
+    "classical": None, "strassen": "strassen", "winograd": "winograd", "f323": "f323", "f332": "f332",
+    "f233": "f233", "f442": "f442", "f424": "f424", "f244": "f244", "laderman333": "laderman333",
+}
+
+UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
+
+
+def np_dtype(precision):
+    return np.float64 if precision == "f64" else np.float32
+
+
+def run_gpu(plan, A, B, transA=False, transB=False):
+    """Run fastmm on host arrays A, B (already in the plan's dtype); returns a host array."""
+    import torch
+
+    import paper_1507_00687_amd as F
+
+    tA = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    tB = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    if transA or transB:
+        Cg = F.fastmm_gemm_ex(plan, tA, transA, tB, transB)
+    else:
+        Cg = F.fastmm_gemm(plan, tA, tB)
+    torch.cuda.synchronize()
+    return Cg.cpu().numpy()
+
+
+def oracle_fast(name, A, B, depth, cutoff):
+    if ORACLE_ALGO[name] is None or depth == 0:
+        return O.classical(A, B)
+    return O.fast(A, B, C.get(ORACLE_ALGO[name]), depth, cutoff)
+
+
+def theorem_bound(name, m, k, n, depth, cutoff, u):
+    """Theorem 4.1 for the levels the plan actually uses (K = padded inner dimension)."""
+    if ORACLE_ALGO[name] is None:
+        return k * k * u
+    a = C.get(ORACLE_ALGO[name])
+    q = C.quantities(a)
+    L = O.effective_depth(m, k, n, [(a.M0, a.K0, a.N0)] * depth, cutoff)
+    Kp = O.padded_dims(m, k, n, [(a.M0, a.K0, a.N0)] * L)[1]
+    return O.thm41_bound(Kp, a.K0, L, q.Q, q.E, u)

@@ -1,0 +1,119 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol, and its host-side
+logic (coefficient tables, quantities, planning rules, argument checks) agrees with the oracle.
+No GPU compute is called here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import coeffs as C
+from oracle import fastmm_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastmm.h")
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_1507_00687_amd as F
+
+    if not os.path.exists(F.fastmm.LIB_PATH):
+        from paper_1507_00687_amd import build
+
+        build.build()
+    return F
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:fastmm_status|const char|int)\s*\*?\s*(fastmm_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol(F):
+    names = declared_functions()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(F.fastmm.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+ORACLE_NAME = {
+    "strassen": "strassen", "winograd": "winograd", "f323": "f323", "f332": "f332", "f233": "f233",
+    "f442": "f442", "f424": "f424", "f244": "f244", "laderman333": "laderman333",
+}
+
+
+@pytest.mark.parametrize("name", sorted(ORACLE_NAME))
+def test_library_tables_equal_oracle_tables(F, name):
+    # Two independent transcriptions of the same rule must agree entry for entry.
+    U, V, W = F.fastmm_algo_coeffs(name)
+    Uo, Vo, Wo = C.get(ORACLE_NAME[name]).as_float()
+    assert np.array_equal(U, Uo) and np.array_equal(V, Vo) and np.array_equal(W, Wo)
+    info = F.fastmm_algo_info(name)
+    q = C.quantities(C.get(ORACLE_NAME[name]))
+    assert (info["nnz"], info["Q"], info["E"]) == (q.nnz, float(q.Q), float(q.E))
+
+
+@pytest.mark.parametrize("name,depth,cutoff,shape", [
+    ("strassen", 2, 64, (256, 256, 256)),
+    ("strassen", 3, 64, (256, 256, 256)),
+    ("f323", 3, 256, (4096, 4096, 4096)),
+    ("f424", 2, 1, (37, 29, 41)),
+    ("laderman333", 2, 1, (100, 1, 7)),
+    ("winograd", 4, 1, (1, 1, 1)),
+])
+def test_plan_shape_matches_oracle_rules(F, name, depth, cutoff, shape):
+    p = F.Plan(name, depth, cutoff)
+    a = C.get(ORACLE_NAME[name])
+    L = O.effective_depth(*shape, [(a.M0, a.K0, a.N0)] * depth, cutoff)
+    pads = O.padded_dims(*shape, [(a.M0, a.K0, a.N0)] * L)
+    assert p.shape(*shape) == (L, *pads)
+
+
+def test_register_rejects_non_brent(F):
+    a = C.strassen()
+    U = np.array([[int(x) for x in r] for r in a.U])
+    V = np.array([[int(x) for x in r] for r in a.V])
+    W = np.array([[int(x) for x in r] for r in a.W])
+    new_id = F.fastmm_algo_register(2, 2, 2, 7, U, V, W, 0)
+    assert new_id >= 64
+    assert F.fastmm_algo_info(new_id)["E"] == 12.0
+    W2 = W.copy()
+    W2[0, 0] = -W2[0, 0]
+    with pytest.raises(F.FastmmError) as ei:
+        F.fastmm_algo_register(2, 2, 2, 7, U, V, W2, 0)
+    assert ei.value.status == -2  # FASTMM_EBRENT
+    # the printed (unrelabelled) Strassen table is rejected as well
+    sp = C.strassen_as_printed()
+    with pytest.raises(F.FastmmError):
+        F.fastmm_algo_register(2, 2, 2, 7, *[np.array([[int(x) for x in r] for r in M]) for M in (sp.U, sp.V, sp.W)], 0)
+
+
+def test_plan_argument_errors(F):
+    with pytest.raises(F.FastmmError):
+        F.Plan("strassen", -1)
+    with pytest.raises(F.FastmmError):
+        F.Plan("strassen", 1, cutoff=0)
+    with pytest.raises(F.FastmmError):
+        F.Plan(77, 1)
+    with pytest.raises(F.FastmmError):
+        F.Plan("strassen", 1, scaling="repeated", steps=0)
+
+
+def test_gemm_argument_errors_before_launch(F):
+    lib = F.lib()
+    p = F.Plan("strassen", 1)
+    # null plan, negative sizes, bad leading dims, aliasing: all rejected on the host
+    assert lib.fastmm_gemm(None, 8, 8, 8, 4, 4, 4, None, 0, None) == -1
+    assert lib.fastmm_gemm(p.handle, 8, 8, 8, -1, 4, 4, None, 0, None) == -1
+    assert lib.fastmm_gemm_ex(p.handle, 8, 2, 0, 8, 4, 0, 4096, 4, 4, 4, 4, None, 0, None) == -3
+    base = 1 << 20
+    # C overlapping A
+    assert lib.fastmm_gemm(p.handle, base, base + 100000, base + 64, 4, 4, 4, None, 0, None) in (-7, -8)
+    # workspace too small (shape needs one at depth 1)
+    assert p.workspace_size(64, 64, 64) > 0
+    assert lib.fastmm_gemm(p.handle, base, base + 100000, base + 200000, 64, 64, 64, None, 0, None) == -8
+    # empty products are no-ops
+    assert lib.fastmm_gemm(p.handle, 0, 0, 0, 0, 5, 5, None, 0, None) == 0

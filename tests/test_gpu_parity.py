@@ -1,0 +1,189 @@
+"""GPU parity tests: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars:
+  * integer inputs: bit-exact against the exact product (every intermediate is an integer
+    below 2^24 resp. 2^53, so both FP32 and FP64 arithmetic are exact);
+  * floating point: max-norm error ||C^ - C_ref|| / (||A|| ||B||) against the long-double
+    reference within the stated tolerances (1e-13 FP64, 5e-5 FP32) on N(0,1) inputs, within
+    the Theorem 4.1 bound always, and within 4x the oracle's own error for the same algorithm
+    and depth (different summation order, same method);
+  * scaling exponents: bit-exact against the oracle's power-of-two factors.
+"""
+import numpy as np
+import pytest
+
+from oracle import coeffs as C
+from oracle import fastmm_oracle as O
+from synth import make_pair
+from tests.gpu_util import np_dtype, oracle_fast, run_gpu, theorem_bound, UNIT_ROUNDOFF
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-13, "f32": 5e-5}
+
+
+def _plan(name, depth, cutoff=1, precision="f64", **kw):
+    import paper_1507_00687_amd as F
+
+    return F.Plan(name, depth, cutoff, precision=precision, **kw)
+
+
+def _exact(A, B):
+    return (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,depth,shape", [
+    ("strassen", 2, (256, 256, 256)),
+    ("winograd", 2, (256, 256, 256)),
+    ("f323", 2, (200, 150, 190)),
+    ("f332", 1, (99, 120, 64)),
+    ("f424", 1, (160, 96, 200)),
+    ("f442", 1, (128, 128, 96)),
+    ("laderman333", 2, (135, 100, 81)),
+    ("classical", 0, (300, 129, 257)),
+    ("strassen", 3, (333, 300, 271)),
+])
+def test_integer_inputs_bit_exact(precision, name, depth, shape):
+    print(f"\n[int] {name} L={depth} {shape} {precision}", flush=True)
+    A, B = make_pair("int8", 0, *shape, dtype=np_dtype(precision))
+    got = run_gpu(_plan(name, depth, 1, precision), A, B)
+    assert np.array_equal(got.astype(np.float64), _exact(A, B))
+
+
+def test_config1_strassen_depth2_cutoff64_n256():
+    # Strassen <2,2,2;7>, depth 2, cutoff 64, n = 256, FP64: integers {-8..8} bit-exact and
+    # U[0,1) within the stated tolerance classes.
+    p = _plan("strassen", 2, 64, "f64")
+    assert p.shape(256, 256, 256)[0] == 2
+    for seed in range(5):
+        A, B = make_pair("int8", seed, 256, 256, 256)
+        assert np.array_equal(run_gpu(p, A, B), _exact(A, B))
+    for seed in range(5):
+        A, B = make_pair("uniform01", seed, 256, 256, 256)
+        ref = O.reference_rows(A, B)
+        err = O.normwise_error(run_gpu(p, A, B), ref, A, B)
+        err_or = O.normwise_error(O.fast(A, B, C.strassen(), 2, 64), ref, A, B)
+        assert err <= theorem_bound("strassen", 256, 256, 256, 2, 64, 2.0 ** -53)
+        assert err <= 4 * err_or
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("dist", ["normal", "uniform01"])
+@pytest.mark.parametrize("name,depth,shape", [
+    ("strassen", 2, (256, 256, 256)),
+    ("winograd", 2, (250, 260, 270)),
+    ("f323", 2, (198, 200, 180)),
+    ("f424", 2, (256, 128, 256)),
+    ("laderman333", 1, (243, 243, 243)),
+])
+def test_float_error_against_oracle(precision, dist, name, depth, shape):
+    print(f"\n[float] {name} L={depth} {shape} {precision} {dist}", flush=True)
+    A, B = make_pair(dist, 1, *shape, dtype=np_dtype(precision))
+    got = run_gpu(_plan(name, depth, 1, precision), A, B)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ref = O.reference_rows(A64, B64)
+    err = O.normwise_error(got, ref, A64, B64)
+    u = UNIT_ROUNDOFF[precision]
+    assert err <= theorem_bound(name, *shape, depth, 1, u)
+    err_or = O.normwise_error(oracle_fast(name, A, B, depth, 1), ref, A64, B64)
+    assert err <= 4 * err_or + 4 * u
+    if dist == "normal":
+        assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 7, 1), (5, 1, 9), (65, 3, 64), (2, 2, 2), (17, 64, 1)])
+def test_small_and_degenerate_shapes(shape):
+    A, B = make_pair("int8", 4, *shape)
+    for depth in (1, 2):
+        got = run_gpu(_plan("strassen", depth, 1, "f64"), A, B)
+        assert np.array_equal(got, _exact(A, B))
+
+
+def test_empty_inputs():
+    import torch
+
+    import paper_1507_00687_amd as F
+
+    p = _plan("strassen", 1)
+    A = torch.zeros((0, 5), dtype=torch.float64, device="cuda")
+    B = torch.zeros((5, 4), dtype=torch.float64, device="cuda")
+    assert F.fastmm_gemm(p, A, B).shape == (0, 4)
+    A = torch.ones((3, 0), dtype=torch.float64, device="cuda")
+    B = torch.ones((0, 4), dtype=torch.float64, device="cuda")
+    C0 = torch.full((3, 4), 7.0, dtype=torch.float64, device="cuda")
+    F.fastmm_gemm(p, A, B, C=C0)
+    assert torch.count_nonzero(C0).item() == 0
+
+
+@pytest.mark.parametrize("transA,transB", [(True, False), (False, True), (True, True)])
+def test_transposed_operands(transA, transB):
+    m, k, n = 130, 96, 70
+    A, B = make_pair("int8", 5, m, k, n)
+    As = np.ascontiguousarray(A.T) if transA else A
+    Bs = np.ascontiguousarray(B.T) if transB else B
+    got = run_gpu(_plan("f323", 2, 1, "f64"), As, Bs, transA, transB)
+    assert np.array_equal(got, _exact(A, B))
+
+
+def test_deterministic_repeat():
+    A, B = make_pair("normal", 9, 300, 280, 260, dtype=np.float32)
+    p = _plan("f424", 2, 1, "f32")
+    assert np.array_equal(run_gpu(p, A, B), run_gpu(p, A, B))
+
+
+MODES = {"outside": "O", "inside": "I", "out_in": "OI", "in_out": "IO"}
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("mode,steps", [("outside", 1), ("inside", 1), ("out_in", 2), ("in_out", 2),
+                                        ("repeated", 4), ("repeated", 7)])
+def test_scaling_exponents_bit_exact(precision, mode, steps):
+    import torch
+
+    import paper_1507_00687_amd as F
+
+    A, B = make_pair("badly_scaled", 2, 96, 130, 70, dtype=np_dtype(precision))
+    p = _plan("strassen", 1, 1, precision, scaling=mode, steps=steps)
+    ea, eb, ep = F.fastmm_scaling_exponents(p, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+    sched = MODES.get(mode) or O.schedule_for("repeated", steps)
+    sc = O.scale(A.astype(np.float64), B.astype(np.float64), sched, pow2=True)
+    assert np.array_equal(ea.cpu().numpy(), np.log2(sc.r).astype(np.int32))
+    assert np.array_equal(eb.cpu().numpy(), np.log2(sc.s).astype(np.int32))
+    assert np.array_equal(ep.cpu().numpy(), np.log2(sc.p).astype(np.int32))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("mode", ["none", "outside", "repeated"])
+def test_scaled_gemm_against_scaled_oracle(precision, mode):
+    A, B = make_pair("badly_scaled", 3, 128, 128, 128, dtype=np_dtype(precision))
+    got = run_gpu(_plan("strassen", 2, 1, precision, scaling=mode, steps=4), A, B)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ref = O.reference_rows(A64, B64)
+    sched = {"none": "", "outside": "O", "repeated": "OIOI"}[mode]
+    sc = O.scale(A64, B64, sched, pow2=True)
+    # Error of the scaled computation, measured as Proposition 6.3 states it: relative to
+    # r_i s_j ||A'|| ||B'|| entry by entry.
+    bound_mat = np.outer(sc.r, sc.s) * O.maxabs(sc.A) * O.maxabs(sc.B)
+    rel = np.max(np.abs(got.astype(np.longdouble) - ref) / bound_mat)
+    u = UNIT_ROUNDOFF[precision]
+    assert float(rel) <= theorem_bound("strassen", 128, 128, 128, 2, 1, u)
+    Cor = O.scaled_fast(A64.astype(np_dtype(precision)), B64.astype(np_dtype(precision)), C.strassen(), 2,
+                        mode=mode if mode != "repeated" else "repeated", steps=4)
+    rel_or = np.max(np.abs(Cor.astype(np.longdouble) - ref) / bound_mat)
+    assert float(rel) <= 4 * float(rel_or) + 4 * u
+
+
+def test_scaling_with_tau_stops_early_like_oracle():
+    import torch
+
+    import paper_1507_00687_amd as F
+
+    A, B = make_pair("badly_scaled", 6, 64, 80, 72)
+    for tau in (1.0, 0.05):
+        p = _plan("strassen", 1, 1, "f64", scaling="repeated", steps=40, tau=tau)
+        ea, eb, ep = F.fastmm_scaling_exponents(p, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+        sc = O.scale(A, B, O.schedule_for("repeated", 40), tau=tau, pow2=True)
+        assert np.array_equal(ea.cpu().numpy(), np.log2(sc.r).astype(np.int32))
+        assert np.array_equal(ep.cpu().numpy(), np.log2(sc.p).astype(np.int32))
+        assert np.array_equal(eb.cpu().numpy(), np.log2(sc.s).astype(np.int32))
