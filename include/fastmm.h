@@ -156,6 +156,19 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
                              int64_t m, int64_t k, int64_t n, void *workspace, size_t ws_bytes,
                              void *stream);
 
+/* Export the composite task table the plan uses at `levels` recursion levels (host memory,
+ * for inspection and testing).  counts[0..4] receive the number of leaves, A-source
+ * entries, B-source entries, output blocks and output contributions.  Arrays may be NULL
+ * (call once with NULLs to size them):
+ *   leaves  4 int32 per leaf: first A entry, A count, first B entry, B count;
+ *   asrc    2 int32 per entry (block row, block column) with acoef its coefficient
+ *           (the product over levels of U entries, eq. (ST_exact)); bsrc / bcoef likewise;
+ *   bdest   2 int32 per output block (row-major over the M0^L x N0^L block grid): first
+ *           contribution, count; dest_leaf / dest_coef: leaf index and product of W entries. */
+fastmm_status fastmm_task_table(fastmm_plan_t plan, int levels, int64_t counts[5], int32_t *leaves,
+                                int32_t *asrc, double *acoef, int32_t *bsrc, double *bcoef,
+                                int32_t *bdest, int32_t *dest_leaf, double *dest_coef);
+
 /* ---- scaling vectors (the reductions of Algorithms 1-3, exposed for verification) ---- */
 
 /* Run the plan's scaling steps on A (m x k) and B (k x n) and write the power-of-two

@@ -17,6 +17,7 @@ from .fastmm import (  # noqa: F401
     fastmm_profile_enable,
     fastmm_profile_read,
     fastmm_scaling_exponents,
+    fastmm_task_table,
     lib,
     matmul,
 )

@@ -628,6 +628,39 @@ fastmm_status fastmm_gemm(fastmm_plan_t plan, const void *A, const void *B, void
     return fastmm_gemm_ex(plan, A, k, 0, B, n, 0, C, n, m, k, n, workspace, ws_bytes, stream);
 }
 
+fastmm_status fastmm_task_table(fastmm_plan_t plan, int levels, int64_t counts[5], int32_t *leaves, int32_t *asrc,
+                                double *acoef, int32_t *bsrc, double *bcoef, int32_t *bdest, int32_t *dest_leaf,
+                                double *dest_coef) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    if (levels < 0 || levels > 8 || !counts) return fail(FASTMM_EINVAL, "bad arguments");
+    HostTables ht;
+    std::string err;
+    if (!build_tables(plan_algo(plan), levels, ht, err)) return fail(FASTMM_EUNSUPPORTED, err);
+    counts[0] = (int64_t)ht.leaves.size();
+    counts[1] = (int64_t)ht.asrc.size();
+    counts[2] = (int64_t)ht.bsrc.size();
+    counts[3] = (int64_t)ht.bdest.size();
+    counts[4] = (int64_t)ht.dest.size();
+    for (size_t i = 0; leaves && i < ht.leaves.size(); ++i) {
+        leaves[4 * i] = ht.leaves[i].a_begin, leaves[4 * i + 1] = ht.leaves[i].a_count;
+        leaves[4 * i + 2] = ht.leaves[i].b_begin, leaves[4 * i + 3] = ht.leaves[i].b_count;
+    }
+    for (size_t i = 0; i < ht.asrc.size(); ++i) {
+        if (asrc) asrc[2 * i] = ht.asrc[i].br, asrc[2 * i + 1] = ht.asrc[i].bc;
+        if (acoef) acoef[i] = ht.asrc[i].coef;
+    }
+    for (size_t i = 0; i < ht.bsrc.size(); ++i) {
+        if (bsrc) bsrc[2 * i] = ht.bsrc[i].br, bsrc[2 * i + 1] = ht.bsrc[i].bc;
+        if (bcoef) bcoef[i] = ht.bsrc[i].coef;
+    }
+    for (size_t i = 0; bdest && i < ht.bdest.size(); ++i) bdest[2 * i] = ht.bdest[i].begin, bdest[2 * i + 1] = ht.bdest[i].count;
+    for (size_t i = 0; i < ht.dest.size(); ++i) {
+        if (dest_leaf) dest_leaf[i] = ht.dest[i].leaf;
+        if (dest_coef) dest_coef[i] = ht.dest[i].coef;
+    }
+    return FASTMM_OK;
+}
+
 fastmm_status fastmm_scaling_exponents(fastmm_plan_t plan, const void *A, const void *B, int64_t m, int64_t k,
                                        int64_t n, int32_t *ea, int32_t *eb, int32_t *ep, void *workspace,
                                        size_t ws_bytes, void *stream) {

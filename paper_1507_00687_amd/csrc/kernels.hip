@@ -19,14 +19,16 @@ constexpr int kXcds = 8;       // MI355X: 8 XCDs, work-groups dispatched round-r
 
 template <typename T>
 struct Mfma;
+// D(16x16) += A(16x4) B(4x16) with lane l holding A[l%16][l/16] and B[l/16][l%16].
+// Row of accumulator element v in lane l (column l%16): (l/16) + 4v for the f64 form,
+// 4(l/16) + v for the f32 form (checked on the device).
 template <>
 struct Mfma<double> {
     typedef d4_t acc_t;
-    // D(16x16) += A(16x4) B(4x16); lane l holds A[l%16][l/16], B[l/16][l%16],
-    // D[4*(l/16)+v][l%16] in element v.
     __device__ static inline acc_t op(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 template <>
 struct Mfma<float> {
@@ -34,6 +36,7 @@ struct Mfma<float> {
     __device__ static inline acc_t op(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
 __device__ inline double ldexp_t(double x, int e) { return ldexp(x, e); }
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void leaf_kernel(LeafArgs<T> p) {
         for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t row = tm * BM + wm * WM + i * 16 + 4 * (lane >> 4) + v;
+                const int64_t row = tm * BM + wm * WM + i * 16 + Mfma<T>::row(lane, v);
                 const int64_t col = tn * BN + wn * WN + j * 16 + (lane & 15);
                 T val = acc[i][j][v];
                 if (DIRECT) {

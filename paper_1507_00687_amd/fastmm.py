@@ -49,6 +49,12 @@ def lib() -> ctypes.CDLL:
     """The loaded libfastmm.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch first: its HIP runtime (libamdhip64.so, SONAME libamdhip64.so.7) must be the
+        # one in the process before libfastmm.so is loaded, so that the library's dependency on
+        # libamdhip64.so.7 binds to it.  Loading libfastmm.so first would pull in a second
+        # HIP/HSA runtime from /opt/rocm next to torch's, and the two contend for the device.
+        import torch  # noqa: F401
+
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1507_00687_amd.build")
         L = ctypes.CDLL(LIB_PATH)
@@ -64,6 +70,7 @@ def lib() -> ctypes.CDLL:
         L.fastmm_gemm.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
         L.fastmm_gemm_ex.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64, i64, i64, i64, vp, sz, vp]
         L.fastmm_scaling_exponents.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp, vp, sz, vp]
+        L.fastmm_task_table.argtypes = [vp, i32, pi64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.fastmm_profile_enable.argtypes = [i32]
         L.fastmm_profile_read.argtypes = [pd, pd, pd, pi32]
         L.fastmm_strerror.argtypes = [i32]
@@ -71,7 +78,7 @@ def lib() -> ctypes.CDLL:
         L.fastmm_last_error.restype = ctypes.c_char_p
         for name in ("fastmm_algo_register", "fastmm_algo_info", "fastmm_algo_coeffs", "fastmm_plan_create",
                      "fastmm_plan_destroy", "fastmm_plan_shape", "fastmm_workspace_size", "fastmm_gemm",
-                     "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read"):
+                     "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read", "fastmm_task_table"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -237,6 +244,25 @@ def fastmm_scaling_exponents(plan: Plan, A, B, workspace=None, stream=None):
                                           n, ea.data_ptr(), eb.data_ptr(), ep.data_ptr(), ws.data_ptr(),
                                           ws.numel(), _stream_ptr(stream)))
     return ea, eb, ep
+
+
+def fastmm_task_table(plan: "Plan", levels: int) -> dict:
+    """The composite leaf task table of `plan` at `levels` levels, as numpy arrays."""
+    import numpy as np
+
+    counts = (ctypes.c_int64 * 5)()
+    _check(lib().fastmm_task_table(plan.handle, levels, counts, *([None] * 8)))
+    nl, na, nb, nblk, nd = list(counts)
+    out = {
+        "leaves": np.zeros((nl, 4), np.int32), "asrc": np.zeros((na, 2), np.int32), "acoef": np.zeros(na),
+        "bsrc": np.zeros((nb, 2), np.int32), "bcoef": np.zeros(nb), "bdest": np.zeros((nblk, 2), np.int32),
+        "dest_leaf": np.zeros(nd, np.int32), "dest_coef": np.zeros(nd),
+    }
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().fastmm_task_table(plan.handle, levels, counts, ptr(out["leaves"]), ptr(out["asrc"]),
+                                   ptr(out["acoef"]), ptr(out["bsrc"]), ptr(out["bcoef"]), ptr(out["bdest"]),
+                                   ptr(out["dest_leaf"]), ptr(out["dest_coef"])))
+    return out
 
 
 def fastmm_profile_enable(enable: bool = True) -> None:

@@ -27,3 +27,11 @@ def oracle_mod():
     from oracle import fastmm_oracle
 
     return fastmm_oracle
+
+
+def pytest_runtest_logreport(report):
+    # Print a failing test's report at once: a later crash of the process would otherwise
+    # lose the summary that pytest prints at the end of the session.
+    if report.failed and report.when in ("setup", "call"):
+        text = getattr(report, "longreprtext", "") or ""
+        print(f"\n---- {report.nodeid} failed ----\n{text[-2500:]}\n", flush=True)

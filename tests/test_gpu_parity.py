@@ -187,3 +187,26 @@ def test_scaling_with_tau_stops_early_like_oracle():
         assert np.array_equal(ea.cpu().numpy(), np.log2(sc.r).astype(np.int32))
         assert np.array_equal(ep.cpu().numpy(), np.log2(sc.p).astype(np.int32))
         assert np.array_equal(eb.cpu().numpy(), np.log2(sc.s).astype(np.int32))
+
+
+def test_library_loaded_before_torch_in_fresh_process():
+    # Regression: creating a plan (which loads libfastmm.so) before torch is imported must
+    # still bind the library to torch's HIP runtime.
+    import subprocess
+    import sys
+
+    code = (
+        "import numpy as np, paper_1507_00687_amd as F\n"
+        "p = F.Plan('strassen', 1, 1, precision='f64')\n"
+        "import torch\n"
+        "A = torch.ones((64, 64), dtype=torch.float64, device='cuda')\n"
+        "C = F.fastmm_gemm(p, A, A)\n"
+        "torch.cuda.synchronize()\n"
+        "assert float(C.sum()) == 64.0 ** 3\n"
+        "print('ok')\n"
+    )
+    import os
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0 and "ok" in out.stdout, out.stderr[-2000:]
