@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=2048, help="size of the oracle timing sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classical", action="store_true")
+    ap.add_argument("--torch-ref", action="store_true",
+                    help="also time torch.matmul (vendor BLAS) on the same operands, as context")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device copy of this many MiB (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
 
 
@@ -68,7 +72,7 @@ def time_steps(fn, steps, warmup):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("kernels.hip", "capi.cpp", "launch.h", "devtypes.h"):
+    for name in ("kernels.hip", "leaf_mfma.hip", "leaf_split.hip", "capi.cpp", "launch.h", "devtypes.h"):
         with open(os.path.join(ROOT, "paper_1507_00687_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -177,6 +181,17 @@ def main():
     workload = (f"{args.algo} L={args.depth} cutoff={args.cutoff} n={n} {args.precision} {args.dist} "
                 f"scaling={args.scaling}")
 
+    torch_ref = None
+    if args.torch_ref:
+        ms_t = time_steps(lambda: torch.matmul(tA, tB), args.steps, args.warmup)
+        torch_ref = {"ms_per_step": ms_t, "value": 2.0 * m * k * n / (ms_t * 1e-3) / 1e12}
+    if args.calib_copy_mb > 0:
+        nbytes = args.calib_copy_mb << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
     # errors on sampled rows against the long-double reference (oracle leg)
     rows = np.unique(np.linspace(0, m - 1, args.err_rows).astype(np.int64))
     Cf_rows = Cf[torch.from_numpy(rows).cuda()].cpu().numpy()
@@ -207,6 +222,7 @@ def main():
                    "cutoff": args.cutoff, "m": m, "k": k, "n": n, "padded": [Mp, Kp, Np],
                    "precision": args.precision, "scaling": args.scaling, "dist": args.dist},
         "classical": classical,
+        "torch_matmul": torch_ref,
         "speedup_vs_classical": (classical["ms_per_step"] / ms) if classical else None,
         "error": err,
         "phases_ms": {"scaling": prof["scaling_ms"] / calls, "leaf": leaf_ms, "combine": prof["combine_ms"] / calls},

@@ -256,12 +256,17 @@ int leaf_count(const Algo &a, int L) {
 
 size_t elem_size(int prec) { return prec == FASTMM_F64 ? 8 : 4; }
 
+bool is_split(int prec) { return prec >= FASTMM_BF16 && prec <= FASTMM_BF16X6; }
+
+int64_t round4(int64_t x) { return (x + 3) / 4 * 4; }
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace layout: [ea m][ep k][eb n][flags 2] int32 | [maxA max(m,k)][maxB max(k,n)] elems |
+// split precisions: [A copy m x k][B^T n x k] floats (row stride round4(k)) |
 // [leaf products nleaves * mb * nb] elems.
 struct WsLayout {
-    size_t ea, ep, eb, flags, maxA, maxB, leaves, total;
+    size_t ea, ep, eb, flags, maxA, maxB, at, bt, leaves, total;
 };
 
 WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n) {
@@ -275,6 +280,10 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
         w.flags = off, off = align256(off + 16);
         w.maxA = off, off = align256(off + es * (size_t)std::max(m, k));
         w.maxB = off, off = align256(off + es * (size_t)std::max(k, n));
+    }
+    if (is_split(p->prec)) {
+        w.at = off, off = align256(off + 4 * (size_t)m * round4(k));
+        w.bt = off, off = align256(off + 4 * (size_t)n * round4(k));
     }
     w.leaves = off;
     if (s.L > 0) off = align256(off + es * (size_t)leaf_count(plan_algo(p), s.L) * s.mb * s.nb);
@@ -482,8 +491,6 @@ fastmm_status fastmm_plan_create(fastmm_plan_t *out, int algo, int depth, int cu
     if (depth < 0 || depth > 8) return fail(FASTMM_EINVAL, "depth must be in [0, 8]");
     if (cutoff < 1) return fail(FASTMM_EINVAL, "cutoff must be >= 1");
     if (precision < FASTMM_F64 || precision > FASTMM_BF16X6) return fail(FASTMM_EINVAL, "unknown precision");
-    if (precision != FASTMM_F64 && precision != FASTMM_F32)
-        return fail(FASTMM_EUNSUPPORTED, "precision not implemented yet");
     fastmm_scaling sc{FASTMM_SCALE_NONE, 0, 0.0};
     if (scaling) {
         sc = *scaling;
@@ -600,15 +607,35 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     L.leaves = tab->leaves, L.asrc = tab->asrc, L.bsrc = tab->bsrc;
     L.sc = exps;
     hipError_t e;
+    // Split precisions read both operands with k contiguous: A as m x k, B as its transpose
+    // n x k; operands stored the other way round are transposed into the workspace first.
+    const float *Bt = nullptr;
+    int64_t ldbt = 0;
+    if (is_split(plan->prec)) {
+        if (transA) {
+            e = launch_transpose_f32((const float *)A, lda, k, m, (float *)(ws + w.at), round4(k), st);
+            if (e != hipSuccess) return hip_fail(e, "transpose kernel");
+            L.A = ws + w.at, L.lda = round4(k), L.transA = 0;
+        }
+        if (transB) {
+            Bt = (const float *)B, ldbt = ldb;
+        } else {
+            e = launch_transpose_f32((const float *)B, ldb, k, n, (float *)(ws + w.bt), round4(k), st);
+            if (e != hipSuccess) return hip_fail(e, "transpose kernel");
+            Bt = (const float *)(ws + w.bt), ldbt = round4(k);
+        }
+        L.transB = 0;
+    }
+    auto leaf_launch = [&]() { return is_split(plan->prec) ? launch_leaf_split(L, Bt, ldbt, st) : launch_leaf(L, st); };
     if (s.L == 0) {
         L.out = C, L.ldo = ldc, L.leaf_stride = 0, L.direct = 1;
-        e = launch_leaf(L, st);
+        e = leaf_launch();
         fin.mark();
         if (e != hipSuccess) return hip_fail(e, "leaf kernel");
         return FASTMM_OK;
     }
     L.out = ws + w.leaves, L.ldo = s.nb, L.leaf_stride = s.mb * s.nb, L.direct = 0;
-    e = launch_leaf(L, st);
+    e = leaf_launch();
     fin.mark();
     if (e != hipSuccess) return hip_fail(e, "leaf kernel");
     CombineLaunch Cb;

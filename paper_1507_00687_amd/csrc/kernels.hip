@@ -504,6 +504,7 @@ hipError_t scale_step_t(const ScaleStep &S, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_leaf(const LeafLaunch &L, hipStream_t s) {
+    if (!L.transA && !L.transB) return launch_leaf_pipelined(L, s);
     if (L.elem == Elem::F64) return leaf_trans<double, 64, 64, 16>(L, s);
     return leaf_trans<float, 128, 128, 16>(L, s);
 }

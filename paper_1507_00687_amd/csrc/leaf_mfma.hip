@@ -1,0 +1,398 @@
+// Pipelined fused leaf-product kernel for row-major (non-transposed) operands: FP64 via
+// v_mfma_f64_16x16x4f64 and FP32 via v_mfma_f32_16x16x4f32.
+//
+// Each work-group computes one 128x128 tile of one leaf product M_r = S_r T_r of eq. (2).
+// The S_r / T_r tiles are never stored in HBM: at every K step each thread loads its part of
+// every source block of the leaf (16-byte vector loads on interior tiles), applies the
+// power-of-two scaling exponents and the composite coefficient, sums the sources in table
+// order and writes the result to LDS.  LDS is double-buffered and the global loads of step
+// k+1 (the first two sources) are issued before the MFMA work of step k, so their latency is
+// hidden behind the matrix cores; further sources of a high fan-in leaf are loaded after it.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "devtypes.h"
+#include "launch.h"
+
+namespace fastmm {
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int kNT = 256;
+constexpr int kXcd = 8;
+
+template <typename T>
+struct Core;
+
+// D(16x16) += A(16x4) B(4x16): lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// accumulator element v of lane l is D[row(l, v)][l%16].
+template <>
+struct Core<double> {
+    typedef d4v acc_t;
+    typedef double2 vec_t;
+    static constexpr int VEC = 2, BK = 16, OCC = 1;
+    __device__ static acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+    __device__ static double scale(double x, int e) { return ldexp(x, e); }
+};
+template <>
+struct Core<float> {
+    typedef f4v acc_t;
+    typedef float4 vec_t;
+    static constexpr int VEC = 4, BK = 32, OCC = 2;
+    __device__ static acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+    __device__ static float scale(float x, int e) { return ldexpf(x, e); }
+};
+
+template <typename T>
+struct PArgs {
+    const T *A;
+    const T *B;
+    T *out;
+    int64_t lda, ldb, ldo;
+    int64_t m, k, n;
+    int64_t mb, kb, nb;
+    int64_t leaf_stride;
+    int tiles_m, tiles_n;
+    const LeafEntry *leaves;
+    const SrcEntry *asrc;
+    const SrcEntry *bsrc;
+    ScaleExps sc;
+    int vec_a, vec_b;  // 16-byte loads allowed (alignment of pointers, ld and block sizes)
+};
+
+__device__ inline int64_t xcd_remap_tile(int64_t b, int64_t G) {
+    const int64_t x = b % kXcd, j = b / kXcd;
+    const int64_t per = G / kXcd, rem = G % kXcd;
+    return ((x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + j;
+}
+
+template <typename T, bool SCALED, bool DIRECT>
+__global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T> p) {
+    typedef Core<T> C;
+    constexpr int BM = 128, BN = 128, BK = C::BK, VEC = C::VEC;
+    constexpr int TPRA = BK / VEC, RPPA = kNT / TPRA, NPA = BM / RPPA;  // A: threads/row, rows/pass
+    constexpr int TPRB = BN / VEC, KPPB = kNT / TPRB, NPB = BK / KPPB;  // B: threads/k-row, k-rows/pass
+    constexpr int LDA_S = BK + 1;   // odd row stride: conflict-free column reads of A
+    constexpr int LDB_S = BN + 16;  // k-rows of B land on different bank groups
+    constexpr int WM = 64, WN = 64, TM = WM / 16, TN = WN / 16;
+    static_assert(NPA * RPPA == BM && NPB * KPPB == BK, "tile shape");
+
+    __shared__ T As[2][BM * LDA_S];
+    __shared__ __attribute__((aligned(16))) T Bs[2][BK * LDB_S];
+
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    // Work-group-uniform values are moved to scalar registers explicitly, so that branches on
+    // the leaf's source counts stay scalar branches.
+    const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
+    const int bid = __builtin_amdgcn_readfirstlane((int)xcd_remap_tile(blockIdx.x, gridDim.x));
+    const int leaf = __builtin_amdgcn_readfirstlane((int)(bid / tiles));
+    const int rem = __builtin_amdgcn_readfirstlane((int)(bid - (int64_t)leaf * tiles));
+    const int64_t tm = __builtin_amdgcn_readfirstlane(rem / p.tiles_n);
+    const int64_t tn = __builtin_amdgcn_readfirstlane(rem - (int)tm * p.tiles_n);
+    LeafEntry le = p.leaves[leaf];
+    le.a_begin = __builtin_amdgcn_readfirstlane(le.a_begin);
+    le.a_count = __builtin_amdgcn_readfirstlane(le.a_count);
+    le.b_begin = __builtin_amdgcn_readfirstlane(le.b_begin);
+    le.b_count = __builtin_amdgcn_readfirstlane(le.b_count);
+
+    const int ra = t / TPRA, ka = (t % TPRA) * VEC;   // A: row within pass, k offset
+    const int kbr = t / TPRB, cb = (t % TPRB) * VEC;  // B: k-row within pass, column offset
+
+    // Load (with zero fill outside the operand and outside the leaf block) the thread's part
+    // of one source block of A at K offset k0; values scaled by 2^(ep_col - ea_row).  Loads
+    // outside the operand read the (valid) operand base instead and are replaced by zero, so
+    // the loads themselves never branch; only the uniform interior/edge choice does.
+    auto load_a = [&](const SrcEntry &se, int64_t k0, T (&v)[NPA][VEC]) {
+        const int64_t row0 = (int64_t)se.br * p.mb + tm * BM;  // operand row of tile row 0
+        const int64_t col0 = (int64_t)se.bc * p.kb + k0 + ka;  // operand column of this thread
+        const bool full = p.vec_a && (k0 + BK <= p.kb) && ((int64_t)se.bc * p.kb + k0 + BK <= p.k);
+        if (full) {
+#pragma unroll
+            for (int pa = 0; pa < NPA; ++pa) {
+                const int r = pa * RPPA + ra;
+                const bool rok = (tm * BM + r < p.mb) && (row0 + r < p.m);
+                const T *src = rok ? p.A + (row0 + r) * p.lda + col0 : p.A;
+                const typename C::vec_t x =
+                    *reinterpret_cast<const typename C::vec_t *>(__builtin_assume_aligned(src, 16));
+                const T *xs = reinterpret_cast<const T *>(&x);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[pa][e] = rok ? xs[e] : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int pa = 0; pa < NPA; ++pa) {
+                const int r = pa * RPPA + ra;
+                const bool rok = (tm * BM + r < p.mb) && (row0 + r < p.m);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const bool ok = rok && (k0 + ka + e < p.kb) && (col0 + e < p.k);
+                    const T x = *(ok ? p.A + (row0 + r) * p.lda + col0 + e : p.A);
+                    v[pa][e] = ok ? x : T(0);
+                }
+            }
+        }
+        if (SCALED) {
+#pragma unroll
+            for (int pa = 0; pa < NPA; ++pa) {
+                const int r = pa * RPPA + ra;
+                const bool rok = (tm * BM + r < p.mb) && (row0 + r < p.m);
+                const int er = p.sc.ea[rok ? row0 + r : 0];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const bool cok = col0 + e < p.k;
+                    const int ec = p.sc.ep[cok ? col0 + e : 0];
+                    v[pa][e] = C::scale(v[pa][e], ec - er);
+                }
+            }
+        }
+    };
+    auto load_b = [&](const SrcEntry &se, int64_t k0, T (&v)[NPB][VEC]) {
+        const int64_t row0 = (int64_t)se.br * p.kb + k0;           // operand row of k-row 0
+        const int64_t col0 = (int64_t)se.bc * p.nb + tn * BN + cb;  // operand column
+        const bool cfull = (tn * BN + cb + VEC <= p.nb) && (col0 + VEC <= p.n);
+        const bool full = p.vec_b && (tn * BN + BN <= p.nb) && ((int64_t)se.bc * p.nb + tn * BN + BN <= p.n);
+        if (full) {
+#pragma unroll
+            for (int pb = 0; pb < NPB; ++pb) {
+                const int kr = pb * KPPB + kbr;
+                const bool rok = (k0 + kr < p.kb) && (row0 + kr < p.k);
+                const T *src = rok ? p.B + (row0 + kr) * p.ldb + col0 : p.B;
+                const typename C::vec_t x =
+                    *reinterpret_cast<const typename C::vec_t *>(__builtin_assume_aligned(src, 16));
+                const T *xs = reinterpret_cast<const T *>(&x);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[pb][e] = rok ? xs[e] : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int pb = 0; pb < NPB; ++pb) {
+                const int kr = pb * KPPB + kbr;
+                const bool rok = (k0 + kr < p.kb) && (row0 + kr < p.k);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const bool ok = rok && (cfull || ((tn * BN + cb + e < p.nb) && (col0 + e < p.n)));
+                    const T x = *(ok ? p.B + (row0 + kr) * p.ldb + col0 + e : p.B);
+                    v[pb][e] = ok ? x : T(0);
+                }
+            }
+        }
+        if (SCALED) {
+#pragma unroll
+            for (int pb = 0; pb < NPB; ++pb) {
+                const int kr = pb * KPPB + kbr;
+                const bool rok = (k0 + kr < p.kb) && (row0 + kr < p.k);
+                const int er = p.sc.ep[rok ? row0 + kr : 0];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const bool cok = col0 + e < p.n;
+                    const int ec = p.sc.eb[cok ? col0 + e : 0];
+                    v[pb][e] = C::scale(v[pb][e], -er - ec);
+                }
+            }
+        }
+    };
+
+    T sa[NPA][VEC], sb[NPB][VEC];   // summed S / T parts of the next stage
+    T xa0[NPA][VEC], xb0[NPB][VEC];  // raw loads of source 0
+    T xa1[NPA][VEC], xb1[NPB][VEC];  // raw loads of source 1
+
+    // S/T part of the stage at k0: sources >= first, added to sa/sb (first == 0: assign)
+    auto gather_rest = [&](int64_t k0, int first) {
+        for (int q = first; q < le.a_count; ++q) {
+            const SrcEntry se = p.asrc[le.a_begin + q];
+            const T c = (T)se.coef;
+            load_a(se, k0, xa0);
+#pragma unroll
+            for (int i = 0; i < NPA; ++i)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) sa[i][e] = (q == 0) ? c * xa0[i][e] : sa[i][e] + c * xa0[i][e];
+        }
+        for (int q = first; q < le.b_count; ++q) {
+            const SrcEntry se = p.bsrc[le.b_begin + q];
+            const T c = (T)se.coef;
+            load_b(se, k0, xb0);
+#pragma unroll
+            for (int i = 0; i < NPB; ++i)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) sb[i][e] = (q == 0) ? c * xb0[i][e] : sb[i][e] + c * xb0[i][e];
+        }
+    };
+    // Issue the raw loads of sources 0 and 1 (those exist) of the stage at k0.
+    auto prefetch = [&](int64_t k0) {
+        load_a(p.asrc[le.a_begin], k0, xa0);
+        if (le.a_count > 1) load_a(p.asrc[le.a_begin + 1], k0, xa1);
+        load_b(p.bsrc[le.b_begin], k0, xb0);
+        if (le.b_count > 1) load_b(p.bsrc[le.b_begin + 1], k0, xb1);
+    };
+    // Combine the prefetched sources (in source order) and gather the remaining ones.
+    auto finish = [&](int64_t k0) {
+        const T ca0 = (T)p.asrc[le.a_begin].coef, cb0 = (T)p.bsrc[le.b_begin].coef;
+#pragma unroll
+        for (int i = 0; i < NPA; ++i)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) sa[i][e] = ca0 * xa0[i][e];
+#pragma unroll
+        for (int i = 0; i < NPB; ++i)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) sb[i][e] = cb0 * xb0[i][e];
+        if (le.a_count > 1) {
+            const T c = (T)p.asrc[le.a_begin + 1].coef;
+#pragma unroll
+            for (int i = 0; i < NPA; ++i)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) sa[i][e] = sa[i][e] + c * xa1[i][e];
+        }
+        if (le.b_count > 1) {
+            const T c = (T)p.bsrc[le.b_begin + 1].coef;
+#pragma unroll
+            for (int i = 0; i < NPB; ++i)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) sb[i][e] = sb[i][e] + c * xb1[i][e];
+        }
+        if (le.a_count > 2 || le.b_count > 2) {
+            // remaining sources (their latency is not hidden)
+            for (int q = 2; q < le.a_count; ++q) {
+                const SrcEntry se = p.asrc[le.a_begin + q];
+                const T c = (T)se.coef;
+                load_a(se, k0, xa0);
+#pragma unroll
+                for (int i = 0; i < NPA; ++i)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) sa[i][e] = sa[i][e] + c * xa0[i][e];
+            }
+            for (int q = 2; q < le.b_count; ++q) {
+                const SrcEntry se = p.bsrc[le.b_begin + q];
+                const T c = (T)se.coef;
+                load_b(se, k0, xb0);
+#pragma unroll
+                for (int i = 0; i < NPB; ++i)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) sb[i][e] = sb[i][e] + c * xb0[i][e];
+            }
+        }
+    };
+    auto store = [&](int s) {
+#pragma unroll
+        for (int pa = 0; pa < NPA; ++pa)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) As[s][(pa * RPPA + ra) * LDA_S + ka + e] = sa[pa][e];
+#pragma unroll
+        for (int pb = 0; pb < NPB; ++pb) {
+            typename C::vec_t x;
+            if constexpr (VEC == 2) {
+                x.x = sb[pb][0], x.y = sb[pb][1];
+            } else {
+                x.x = sb[pb][0], x.y = sb[pb][1], x.z = sb[pb][2], x.w = sb[pb][3];
+            }
+            *reinterpret_cast<typename C::vec_t *>(&Bs[s][(pb * KPPB + kbr) * LDB_S + cb]) = x;
+        }
+    };
+
+    typename C::acc_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = typename C::acc_t{};
+
+    const int64_t nk = (p.kb + BK - 1) / BK;
+    gather_rest(0, 0);
+    store(0);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        const bool more = kt + 1 < nk;
+        if (more) prefetch((kt + 1) * BK);
+        const T *as = As[cur];
+        const T *bs = Bs[cur];
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            T a[TM], b[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = as[(wm * WM + i * 16 + (lane & 15)) * LDA_S + ks + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b[j] = bs[(ks + (lane >> 4)) * LDB_S + wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = C::mma(a[i], b[j], acc[i][j]);
+            // Half-way through the MFMA work: combine the prefetched sources of the next stage
+            // and write them to the other LDS buffer (last read before the previous barrier),
+            // so the VALU and LDS work overlaps the matrix cores.
+            if (ks == BK / 2 - 4 && more) {
+                finish((kt + 1) * BK);
+                store(cur ^ 1);
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = tm * BM + wm * WM + i * 16 + C::row(lane, v);
+                const int64_t col = tn * BN + wn * WN + j * 16 + (lane & 15);
+                T val = acc[i][j][v];
+                if (DIRECT) {
+                    if (row < p.m && col < p.n) {
+                        if (SCALED) val = C::scale(val, p.sc.ea[row] + p.sc.eb[col]);
+                        p.out[row * p.ldo + col] = val;
+                    }
+                } else {
+                    if (row < p.mb && col < p.nb) p.out[(int64_t)leaf * p.leaf_stride + row * p.ldo + col] = val;
+                }
+            }
+}
+
+template <typename T>
+hipError_t go(const LeafLaunch &L, hipStream_t s) {
+    PArgs<T> a;
+    a.A = (const T *)L.A;
+    a.B = (const T *)L.B;
+    a.out = (T *)L.out;
+    a.lda = L.lda, a.ldb = L.ldb, a.ldo = L.ldo;
+    a.m = L.m, a.k = L.k, a.n = L.n;
+    a.mb = L.mb, a.kb = L.kb, a.nb = L.nb;
+    a.leaf_stride = L.leaf_stride;
+    a.tiles_m = (int)((L.mb + 127) / 128);
+    a.tiles_n = (int)((L.nb + 127) / 128);
+    a.leaves = L.leaves, a.asrc = L.asrc, a.bsrc = L.bsrc;
+    a.sc = L.sc;
+    constexpr int VEC = Core<T>::VEC;
+    a.vec_a = ((uintptr_t)L.A % 16 == 0) && (L.lda % VEC == 0) && (L.kb % VEC == 0);
+    a.vec_b = ((uintptr_t)L.B % 16 == 0) && (L.ldb % VEC == 0) && (L.nb % VEC == 0);
+    const int64_t blocks = (int64_t)a.tiles_m * a.tiles_n * L.nleaves;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const bool scaled = L.sc.ea != nullptr;
+    dim3 grid((unsigned)blocks), block(kNT);
+    if (L.direct) {
+        if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, true>), grid, block, 0, s, a);
+    } else {
+        if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_leaf_pipelined(const LeafLaunch &L, hipStream_t s) {
+    if (L.elem == Elem::F64) return go<double>(L, s);
+    return go<float>(L, s);
+}
+
+}  // namespace fastmm

@@ -11,6 +11,7 @@ ORACLE_ALGO = {
 }
 
 UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
+SPLIT_PRECISIONS = ("bf16", "f16", "bf16x3", "f16x3", "bf16x6")
 
 
 def np_dtype(precision):
