@@ -37,17 +37,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--algo", default="winograd")
-    ap.add_argument("--depth", type=int, default=2)
+    ap.add_argument("--algo", default="strassen")
+    ap.add_argument("--depth", type=int, default=1)
     ap.add_argument("--cutoff", type=int, default=256)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--precision", default="f64")
+    ap.add_argument("--precision", default="f32")
     ap.add_argument("--scaling", default="none")
     ap.add_argument("--scaling-steps", type=int, default=2)
-    ap.add_argument("--dist", default="uniform01")
+    ap.add_argument("--dist", default="normal")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--err-rows", type=int, default=16)
-    ap.add_argument("--cpu-n", type=int, default=2048, help="size of the oracle timing sample")
+    ap.add_argument("--cpu-n", type=int, default=4096, help="size of the oracle timing sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classical", action="store_true")
     ap.add_argument("--torch-ref", action="store_true",
@@ -70,15 +70,17 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps * 1e3
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for name in ("kernels.hip", "leaf_mfma.hip", "leaf_split.hip", "capi.cpp", "launch.h", "devtypes.h"):
-        with open(os.path.join(ROOT, "paper_1507_00687_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+LEAF_SOURCE = {"f64": "leaf_mfma.hip", "f32": "leaf_mfma.hip"}  # split precisions: leaf_split.hip
 
 
-def load_traffic(workload: str):
+def kernel_source_hash(precision: str) -> str:
+    """Hash of the source file of the leaf kernel that serves `precision`."""
+    name = LEAF_SOURCE.get(precision, "leaf_split.hip")
+    with open(os.path.join(ROOT, "paper_1507_00687_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str, precision: str):
     """HBM bytes per leaf-kernel launch from committed rocprofv3 counter runs, if they were
     taken with the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -88,7 +90,7 @@ def load_traffic(workload: str):
         rec = json.load(open(path)).get(workload)
     except Exception:
         return None
-    if not rec or rec.get("source_hash") != kernel_source_hash():
+    if not rec or rec.get("source_hash") != kernel_source_hash(precision):
         return None
     return rec.get("bytes_per_launch")
 
@@ -227,7 +229,7 @@ def main():
         "error": err,
         "phases_ms": {"scaling": prof["scaling_ms"] / calls, "leaf": leaf_ms, "combine": prof["combine_ms"] / calls},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": load_traffic(workload),
+                     "frac": achieved / peak, "traffic": load_traffic(workload, args.precision),
                      "kernel": "leaf_kernel", "flops_per_launch": flops_per_launch},
         "cpu_baseline": leg.get("cpu"),
     }

@@ -103,8 +103,13 @@ __global__ __launch_bounds__(kNT, 1) void fmm_leaf_split(SArgs p) {
     const int bid = __builtin_amdgcn_readfirstlane((int)remap_xcd(blockIdx.x, gridDim.x));
     const int leaf = __builtin_amdgcn_readfirstlane((int)(bid / tiles));
     const int rem = __builtin_amdgcn_readfirstlane((int)(bid - (int64_t)leaf * tiles));
-    const int64_t tm = __builtin_amdgcn_readfirstlane(rem / p.tiles_n);
-    const int64_t tn = __builtin_amdgcn_readfirstlane(rem - (int)tm * p.tiles_n);
+    // Grouped tile order: 8 tile-rows at a time, column by column inside the group, so the
+    // work-groups resident on one XCD share A row panels and B column panels in its L2.
+    const int grp = rem / (8 * p.tiles_n);
+    const int gsz = min(8, p.tiles_m - grp * 8);
+    const int gidx = rem - grp * 8 * p.tiles_n;
+    const int64_t tm = __builtin_amdgcn_readfirstlane(grp * 8 + gidx % gsz);
+    const int64_t tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
     LeafEntry le = p.leaves[leaf];
     le.a_begin = __builtin_amdgcn_readfirstlane(le.a_begin);
     le.a_count = __builtin_amdgcn_readfirstlane(le.a_count);
