@@ -169,6 +169,21 @@ fastmm_status fastmm_task_table(fastmm_plan_t plan, int levels, int64_t counts[5
                                 int32_t *asrc, double *acoef, int32_t *bsrc, double *bcoef,
                                 int32_t *bdest, int32_t *dest_leaf, double *dest_coef);
 
+/* ---- differentiation ----------------------------------------------------------------- */
+
+/* Gradients of a loss through C = A B: dA = G B^T and dB = A^T G for G = dLoss/dC (m x n),
+ * computed by the same recursion with the cyclic rotations of the plan's rule (the rotation
+ * rule stated with Appendices B and C): dA^T = B G^T is a <K0,N0,M0> product, done by
+ * [V,W,U]; dB^T = G^T A is a <N0,M0,K0> product, done by [W,U,V]; each result is transposed
+ * into place.  Same depth, cutoff, scaling and precision as the plan.  A (m x k), B (k x n),
+ * G (m x n) are contiguous row-major inputs; dA (m x k) and dB (k x n) outputs, either may be
+ * NULL to skip it.  Workspace: fastmm_backward_workspace_size bytes. */
+fastmm_status fastmm_backward_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n,
+                                             size_t *bytes);
+fastmm_status fastmm_gemm_backward(fastmm_plan_t plan, const void *A, const void *B, const void *G,
+                                   void *dA, void *dB, int64_t m, int64_t k, int64_t n,
+                                   void *workspace, size_t ws_bytes, void *stream);
+
 /* ---- scaling vectors (the reductions of Algorithms 1-3, exposed for verification) ---- */
 
 /* Run the plan's scaling steps on A (m x k) and B (k x n) and write the power-of-two

@@ -3,6 +3,7 @@
 The computation runs in libfastmm.so (hand-written HIP kernels for gfx950) behind the C ABI
 declared in include/fastmm.h; this package is a thin binding over it.
 """
+from .autograd import FastMatmulFn, fast_matmul  # noqa: F401
 from .fastmm import (  # noqa: F401
     ALGOS,
     PRECISIONS,
@@ -13,6 +14,7 @@ from .fastmm import (  # noqa: F401
     fastmm_algo_info,
     fastmm_algo_register,
     fastmm_gemm,
+    fastmm_gemm_backward,
     fastmm_gemm_ex,
     fastmm_profile_enable,
     fastmm_profile_read,

@@ -13,6 +13,7 @@
 // literature.  Every table is checked against the Brent equations when the registry is built.
 #include <cmath>
 #include <cstdlib>
+#include <map>
 #include <mutex>
 
 #include "fastmm_internal.h"
@@ -272,6 +273,7 @@ struct Registry {
     std::mutex mu;
     std::vector<Algo> builtin;  // index = fastmm_algo id
     std::vector<Algo> user;     // id = FASTMM_ALGO_USER0 + index
+    std::map<std::pair<int, int>, int> rotations;  // (id, times) -> id of the rotated rule
     bool ok = false;
     Registry() {
         builtin.resize(10);
@@ -358,13 +360,36 @@ const Algo *algo_get(int id) {
     return nullptr;
 }
 
-int algo_register(Algo &&a) {
-    Registry &reg = registry();
-    std::lock_guard<std::mutex> g(reg.mu);
+namespace {
+int register_locked(Registry &reg, Algo &&a) {
     reg.user.reserve(256);  // keep pointers handed out by algo_get stable
     if (reg.user.size() >= 256) return -1;
     reg.user.push_back(std::move(a));
     return FASTMM_ALGO_USER0 + (int)reg.user.size() - 1;
+}
+}  // namespace
+
+int algo_register(Algo &&a) {
+    Registry &reg = registry();
+    std::lock_guard<std::mutex> g(reg.mu);
+    return register_locked(reg, std::move(a));
+}
+
+int algo_rotated(int id, int times) {
+    times = ((times % 3) + 3) % 3;
+    if (times == 0) return id;
+    const Algo *a = algo_get(id);
+    if (!a) return -1;
+    Registry &reg = registry();
+    std::lock_guard<std::mutex> g(reg.mu);
+    auto it = reg.rotations.find({id, times});
+    if (it != reg.rotations.end()) return it->second;
+    Algo r = rotate(*a, "rotation");
+    if (times == 2) r = rotate(r, "rotation");
+    if (brent_violations(r) != 0) return -1;
+    const int nid = register_locked(reg, std::move(r));
+    if (nid >= 0) reg.rotations[{id, times}] = nid;
+    return nid;
 }
 
 }  // namespace fastmm

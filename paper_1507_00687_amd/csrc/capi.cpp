@@ -208,6 +208,8 @@ struct fastmm_plan_s {
     int prec = FASTMM_F64;
     std::mutex mu;
     std::map<std::pair<int, int>, std::unique_ptr<fastmm::Tables>> tables;  // (L, device)
+    // Sub-plans with the rotated rules, made on first use by the backward pass.
+    std::unique_ptr<fastmm_plan_s> rot[3];
 };
 
 namespace fastmm {
@@ -653,6 +655,77 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
 fastmm_status fastmm_gemm(fastmm_plan_t plan, const void *A, const void *B, void *C, int64_t m, int64_t k, int64_t n,
                           void *workspace, size_t ws_bytes, void *stream) {
     return fastmm_gemm_ex(plan, A, k, 0, B, n, 0, C, n, m, k, n, workspace, ws_bytes, stream);
+}
+
+namespace fastmm {
+namespace {
+// Sub-plan of `p` whose rule is the rotation of p's rule applied `times` times.
+fastmm_status rotated_plan(fastmm_plan_s *p, int times, fastmm_plan_s **out) {
+    std::lock_guard<std::mutex> g(p->mu);
+    if (!p->rot[times]) {
+        const int id = algo_rotated(p->algo, times);
+        if (id < 0) return fail(FASTMM_EUNSUPPORTED, "cannot rotate the plan's rule");
+        std::unique_ptr<fastmm_plan_s> q(new (std::nothrow) fastmm_plan_s());
+        if (!q) return fail(FASTMM_ENOMEM, "plan allocation");
+        q->algo = id, q->depth = p->depth, q->cutoff = p->cutoff, q->sc = p->sc, q->prec = p->prec;
+        p->rot[times] = std::move(q);
+    }
+    *out = p->rot[times].get();
+    return FASTMM_OK;
+}
+}  // namespace
+}  // namespace fastmm
+
+fastmm_status fastmm_backward_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, size_t *bytes) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    if (!bytes || m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "bad arguments");
+    fastmm_plan_s *ra = nullptr, *rb = nullptr;
+    fastmm_status st;
+    if ((st = rotated_plan(plan, 2, &ra)) != FASTMM_OK || (st = rotated_plan(plan, 1, &rb)) != FASTMM_OK) return st;
+    size_t wa = 0, wb = 0;
+    if ((st = fastmm_workspace_size(ra, k, n, m, &wa)) != FASTMM_OK) return st;  // dA^T = B G^T
+    if ((st = fastmm_workspace_size(rb, n, m, k, &wb)) != FASTMM_OK) return st;  // dB^T = G^T A
+    const size_t es = elem_size(plan->prec);
+    *bytes = align256(es * (size_t)std::max(k * m, n * k)) + std::max(wa, wb);
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_gemm_backward(fastmm_plan_t plan, const void *A, const void *B, const void *G, void *dA,
+                                   void *dB, int64_t m, int64_t k, int64_t n, void *workspace, size_t ws_bytes,
+                                   void *stream) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    if (m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "negative size");
+    if ((dA && (!G || !B)) || (dB && (!G || !A))) return fail(FASTMM_EINVAL, "null input");
+    if (m == 0 || k == 0) return FASTMM_OK;
+    size_t need = 0;
+    fastmm_status st = fastmm_backward_workspace_size(plan, m, k, n, &need);
+    if (st != FASTMM_OK) return st;
+    if (workspace == nullptr || ws_bytes < need) return fail(FASTMM_EWORKSPACE, "backward workspace too small");
+    if (((uintptr_t)workspace & 255) != 0) return fail(FASTMM_EINVAL, "workspace must be 256-byte aligned");
+    const size_t es = elem_size(plan->prec);
+    const Elem el = plan->prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
+    char *tmp = (char *)workspace;
+    const size_t tmp_bytes = align256(es * (size_t)std::max(k * m, n * k));
+    char *ws = tmp + tmp_bytes;
+    const size_t wsb = ws_bytes - tmp_bytes;
+    hipStream_t s = (hipStream_t)stream;
+    fastmm_plan_s *ra = nullptr, *rb = nullptr;
+    if ((st = rotated_plan(plan, 2, &ra)) != FASTMM_OK || (st = rotated_plan(plan, 1, &rb)) != FASTMM_OK) return st;
+    if (dA) {
+        // dA^T (k x m) = B (k x n) * G^T, G stored m x n
+        st = fastmm_gemm_ex(ra, B, n, 0, G, n, 1, tmp, m, k, n, m, ws, wsb, stream);
+        if (st != FASTMM_OK) return st;
+        hipError_t e = launch_transpose(el, tmp, m, k, m, dA, k, s);
+        if (e != hipSuccess) return hip_fail(e, "transpose kernel");
+    }
+    if (dB && n > 0) {
+        // dB^T (n x k) = G^T (n x m) * A (m x k)
+        st = fastmm_gemm_ex(rb, G, n, 1, A, k, 0, tmp, k, n, m, k, ws, wsb, stream);
+        if (st != FASTMM_OK) return st;
+        hipError_t e = launch_transpose(el, tmp, k, n, k, dB, n, s);
+        if (e != hipSuccess) return hip_fail(e, "transpose kernel");
+    }
+    return FASTMM_OK;
 }
 
 fastmm_status fastmm_task_table(fastmm_plan_t plan, int levels, int64_t counts[5], int32_t *leaves, int32_t *asrc,

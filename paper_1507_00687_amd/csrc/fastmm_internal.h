@@ -26,6 +26,9 @@ struct Algo {
 // Registry access; returns nullptr for an unknown id.
 const Algo *algo_get(int id);
 int algo_register(Algo &&a);  // returns the new id
+// Id of the cyclic rotation of rule `id` applied `times` times: once gives [W,U,V] (a rule for
+// <N0,M0,K0>), twice [V,W,U] (<K0,N0,M0>).  Registered on first use; -1 on failure.
+int algo_rotated(int id, int times);
 // Number of (a, b, c) index triples violating the Brent equations under the convention
 // A, B column-major and C row-major (exact integer arithmetic).
 long brent_violations(const Algo &a);

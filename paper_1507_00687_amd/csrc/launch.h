@@ -79,6 +79,8 @@ hipError_t launch_leaf_split(const LeafLaunch &L, const float *Bt, int64_t ldbt,
 // out (C x R) = in^T for a row-major R x C FP32 matrix.
 hipError_t launch_transpose_f32(const float *in, int64_t ldi, int64_t R, int64_t C, float *out, int64_t ldo,
                                 hipStream_t s);
+hipError_t launch_transpose(Elem e, const void *in, int64_t ldi, int64_t R, int64_t C, void *out, int64_t ldo,
+                            hipStream_t s);
 hipError_t launch_combine(const CombineLaunch &L, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
 hipError_t launch_zero_elems(Elem e, void *C, int64_t ldc, int64_t m, int64_t n, hipStream_t s);

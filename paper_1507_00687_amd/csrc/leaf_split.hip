@@ -316,9 +316,10 @@ __global__ __launch_bounds__(kNT, 1) void fmm_leaf_split(SArgs p) {
 }
 
 // out (C x R, row-major ldo) = in^T where in is R x C row-major (ldi); 32x32 tiles via LDS.
-__global__ __launch_bounds__(256) void transpose_kernel(const float *in, int64_t ldi, int64_t R, int64_t C,
-                                                        float *out, int64_t ldo) {
-    __shared__ float tile[32][33];
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(const T *in, int64_t ldi, int64_t R, int64_t C, T *out,
+                                                        int64_t ldo) {
+    __shared__ T tile[32][33];
     const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
 #pragma unroll
@@ -354,7 +355,18 @@ hipError_t launch_transpose_f32(const float *in, int64_t ldi, int64_t R, int64_t
     if (R <= 0 || C <= 0) return hipSuccess;
     if ((C + 31) / 32 > 0x7fffffffLL || (R + 31) / 32 > 65535) return hipErrorInvalidValue;
     dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32));
-    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, in, ldi, R, C, out, ldo);
+    hipLaunchKernelGGL(transpose_kernel<float>, grid, dim3(256), 0, s, in, ldi, R, C, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(Elem e, const void *in, int64_t ldi, int64_t R, int64_t C, void *out, int64_t ldo,
+                            hipStream_t s) {
+    if (e == Elem::F32) return launch_transpose_f32((const float *)in, ldi, R, C, (float *)out, ldo, s);
+    if (R <= 0 || C <= 0) return hipSuccess;
+    if ((C + 31) / 32 > 0x7fffffffLL || (R + 31) / 32 > 65535) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32));
+    hipLaunchKernelGGL(transpose_kernel<double>, grid, dim3(256), 0, s, (const double *)in, ldi, R, C,
+                       (double *)out, ldo);
     return hipGetLastError();
 }
 

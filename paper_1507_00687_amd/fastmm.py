@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
         L.fastmm_gemm_ex.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64, i64, i64, i64, vp, sz, vp]
         L.fastmm_scaling_exponents.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp, vp, sz, vp]
         L.fastmm_task_table.argtypes = [vp, i32, pi64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fastmm_backward_workspace_size.argtypes = [vp, i64, i64, i64, ctypes.POINTER(sz)]
+        L.fastmm_gemm_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
         L.fastmm_profile_enable.argtypes = [i32]
         L.fastmm_profile_read.argtypes = [pd, pd, pd, pi32]
         L.fastmm_strerror.argtypes = [i32]
@@ -78,7 +80,8 @@ def lib() -> ctypes.CDLL:
         L.fastmm_last_error.restype = ctypes.c_char_p
         for name in ("fastmm_algo_register", "fastmm_algo_info", "fastmm_algo_coeffs", "fastmm_plan_create",
                      "fastmm_plan_destroy", "fastmm_plan_shape", "fastmm_workspace_size", "fastmm_gemm",
-                     "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read", "fastmm_task_table"):
+                     "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read", "fastmm_task_table",
+                     "fastmm_backward_workspace_size", "fastmm_gemm_backward"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -228,6 +231,27 @@ def fastmm_gemm_ex(plan: Plan, A, transA: bool, B, transB: bool, C=None, workspa
                                 B.stride(0), int(bool(transB)), C.data_ptr(), C.stride(0), m, k, n, ws.data_ptr(),
                                 ws.numel(), _stream_ptr(stream)))
     return C
+
+
+def fastmm_gemm_backward(plan: Plan, A, B, G, need_dA: bool = True, need_dB: bool = True, workspace=None,
+                         stream=None):
+    """(dA, dB) = (G B^T, A^T G) through the rotated fast algorithms (None where not needed)."""
+    import torch
+
+    m, k = A.shape
+    n = B.shape[1]
+    A, B, G = A.contiguous(), B.contiguous(), G.contiguous()
+    dA = torch.empty((m, k), dtype=plan.dtype, device=A.device) if need_dA else None
+    dB = torch.empty((k, n), dtype=plan.dtype, device=A.device) if need_dB else None
+    b = ctypes.c_size_t()
+    _check(lib().fastmm_backward_workspace_size(plan.handle, m, k, n, ctypes.byref(b)))
+    if workspace is None:
+        workspace = torch.empty(max(b.value, 1), dtype=torch.uint8, device=A.device)
+    _check(lib().fastmm_gemm_backward(plan.handle, A.data_ptr(), B.data_ptr(), G.data_ptr(),
+                                      dA.data_ptr() if dA is not None else None,
+                                      dB.data_ptr() if dB is not None else None, m, k, n, workspace.data_ptr(),
+                                      workspace.numel(), _stream_ptr(stream)))
+    return dA, dB
 
 
 def fastmm_scaling_exponents(plan: Plan, A, B, workspace=None, stream=None):
