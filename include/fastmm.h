@@ -169,6 +169,30 @@ fastmm_status fastmm_task_table(fastmm_plan_t plan, int levels, int64_t counts[5
                                 int32_t *asrc, double *acoef, int32_t *bsrc, double *bcoef,
                                 int32_t *bdest, int32_t *dest_leaf, double *dest_coef);
 
+/* ---- batches ---------------------------------------------------------------------- */
+
+/* One product of a batch: C = A B with contiguous row-major A (m x k), B (k x n), C (m x n). */
+typedef struct {
+    const void *A;
+    const void *B;
+    void *C;
+    int64_t m, k, n;
+} fastmm_problem;
+
+/* Workspace bytes for fastmm_gemm_batched with these plans and problems. */
+fastmm_status fastmm_batched_workspace_size(const fastmm_plan_t *plans, const fastmm_problem *probs,
+                                            int count, size_t *bytes);
+
+/* Multiply `count` independent problems, problem i with plans[i] (its own rule, depth,
+ * cutoff and scaling; all plans must share one precision, FASTMM_F64 or FASTMM_F32).  Each
+ * problem's scaling steps run first; then ONE persistent launch computes the leaf tiles of all
+ * problems (work items ordered by problem, largest inner dimension first, assigned to
+ * work-groups round-robin: deterministic), then the W-combinations.  Outputs must not overlap
+ * any input.  The per-call descriptor table is copied from host memory into the workspace
+ * (a staged copy). */
+fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_problem *probs, int count,
+                                  void *workspace, size_t ws_bytes, void *stream);
+
 /* ---- differentiation ----------------------------------------------------------------- */
 
 /* Gradients of a loss through C = A B: dA = G B^T and dB = A^T G for G = dLoss/dC (m x n),

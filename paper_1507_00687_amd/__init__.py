@@ -15,6 +15,7 @@ from .fastmm import (  # noqa: F401
     fastmm_algo_register,
     fastmm_gemm,
     fastmm_gemm_backward,
+    fastmm_gemm_batched,
     fastmm_gemm_ex,
     fastmm_profile_enable,
     fastmm_profile_read,

@@ -3,6 +3,7 @@
 // launch sequence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -675,6 +676,190 @@ fastmm_status rotated_plan(fastmm_plan_s *p, int times, fastmm_plan_s **out) {
 }
 }  // namespace
 }  // namespace fastmm
+
+namespace fastmm {
+namespace {
+struct BatchLayout {
+    std::vector<size_t> ws_off, ws_size;
+    size_t descs = 0, first = 0, direct = 0, total = 0;
+};
+
+fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem *probs, int count, BatchLayout &bl) {
+    if (count < 0 || (count > 0 && (!plans || !probs))) return fail(FASTMM_EINVAL, "bad batch arguments");
+    if (count > 65536) return fail(FASTMM_EINVAL, "batch too large");
+    size_t off = 0;
+    int prec = -1;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i]) return fail(FASTMM_EINVAL, "null plan in batch");
+        if (prec < 0) prec = plans[i]->prec;
+        if (plans[i]->prec != prec) return fail(FASTMM_EUNSUPPORTED, "batched plans must share one precision");
+        if (prec != FASTMM_F64 && prec != FASTMM_F32)
+            return fail(FASTMM_EUNSUPPORTED, "batched launch supports FP64 and FP32 leaves");
+        const fastmm_problem &q = probs[i];
+        if (q.m < 0 || q.k < 0 || q.n < 0) return fail(FASTMM_EINVAL, "negative size in batch");
+        const Shape s = shape_of(plans[i], q.m, q.k, q.n);
+        const size_t w = ws_layout(plans[i], s, q.m, q.k, q.n).total;
+        bl.ws_off.push_back(off);
+        bl.ws_size.push_back(w);
+        off = align256(off + w);
+    }
+    const Elem el = prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
+    bl.descs = off, off = align256(off + leaf_desc_bytes(el) * (size_t)std::max(count, 1));
+    bl.first = off, off = align256(off + 8 * (size_t)(count + 1));
+    bl.direct = off, off = align256(off + 4 * (size_t)std::max(count, 1));
+    bl.total = off;
+    return FASTMM_OK;
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+}  // namespace
+}  // namespace fastmm
+
+fastmm_status fastmm_batched_workspace_size(const fastmm_plan_t *plans, const fastmm_problem *probs, int count,
+                                            size_t *bytes) {
+    if (!bytes) return fail(FASTMM_EINVAL, "null output");
+    BatchLayout bl;
+    fastmm_status st = batch_layout(plans, probs, count, bl);
+    if (st == FASTMM_OK) *bytes = bl.total;
+    return st;
+}
+
+fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_problem *probs, int count, void *workspace,
+                                  size_t ws_bytes, void *stream) {
+    BatchLayout bl;
+    fastmm_status st = batch_layout(plans, probs, count, bl);
+    if (st != FASTMM_OK) return st;
+    if (count == 0) return FASTMM_OK;
+    if (workspace == nullptr || ws_bytes < bl.total) return fail(FASTMM_EWORKSPACE, "batch workspace too small");
+    if (((uintptr_t)workspace & 255) != 0) return fail(FASTMM_EINVAL, "workspace must be 256-byte aligned");
+    const Elem el = plans[0]->prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
+    const size_t es = elem_size(plans[0]->prec);
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    // validate every problem before launching anything
+    for (int i = 0; i < count; ++i) {
+        const fastmm_problem &q = probs[i];
+        if (q.m == 0 || q.n == 0) continue;
+        if (!q.C || (q.k > 0 && (!q.A || !q.B))) return fail(FASTMM_EINVAL, "null operand in batch");
+        const size_t cb = span_bytes(q.m, q.n, q.n, es);
+        for (int j = 0; j < count; ++j) {
+            const fastmm_problem &r = probs[j];
+            if (r.k > 0 && (ranges_overlap(q.C, cb, r.A, span_bytes(r.m, r.k, r.k, es)) ||
+                            ranges_overlap(q.C, cb, r.B, span_bytes(r.k, r.n, r.n, es))))
+                return fail(FASTMM_EALIAS, "a batch output overlaps an input");
+            if (j != i && r.m > 0 && r.n > 0 && ranges_overlap(q.C, cb, r.C, span_bytes(r.m, r.n, r.n, es)))
+                return fail(FASTMM_EALIAS, "batch outputs overlap");
+        }
+        if (((uintptr_t)q.A % es) || ((uintptr_t)q.B % es) || ((uintptr_t)q.C % es))
+            return fail(FASTMM_EINVAL, "misaligned operand in batch");
+    }
+    struct Item {
+        int idx;
+        int64_t kb;
+        std::vector<char> desc;
+        int direct;
+        int64_t tiles;
+        CombineLaunch cb;
+        bool combine;
+    };
+    std::vector<Item> items;
+    hipError_t e;
+    for (int i = 0; i < count; ++i) {
+        const fastmm_problem &q = probs[i];
+        fastmm_plan_s *p = plans[i];
+        if (q.m == 0 || q.n == 0) continue;
+        if (q.k == 0) {
+            if ((e = launch_zero_elems(el, q.C, q.n, q.m, q.n, s)) != hipSuccess) return hip_fail(e, "zero fill");
+            continue;
+        }
+        const Shape sh = shape_of(p, q.m, q.k, q.n);
+        const WsLayout w = ws_layout(p, sh, q.m, q.k, q.n);
+        char *pws = ws + bl.ws_off[i];
+        Tables *tab = nullptr;
+        if ((st = get_tables(p, sh.L, &tab)) != FASTMM_OK) return st;
+        ScaleExps exps;
+        if ((st = run_scaling(p, q.A, q.k, 0, q.B, q.n, 0, q.m, q.k, q.n, pws, w, s, &exps)) != FASTMM_OK) return st;
+        LeafLaunch L;
+        L.elem = el;
+        L.prec = p->prec;
+        L.A = q.A, L.B = q.B, L.lda = q.k, L.ldb = q.n, L.transA = 0, L.transB = 0;
+        L.m = q.m, L.k = q.k, L.n = q.n, L.mb = sh.mb, L.kb = sh.kb, L.nb = sh.nb;
+        L.nleaves = tab->nleaves;
+        L.leaves = tab->leaves, L.asrc = tab->asrc, L.bsrc = tab->bsrc;
+        L.sc = exps;
+        Item it;
+        it.idx = i;
+        it.kb = sh.kb;
+        it.combine = sh.L > 0;
+        if (sh.L == 0) {
+            L.out = q.C, L.ldo = q.n, L.leaf_stride = 0, L.direct = 1;
+        } else {
+            L.out = pws + w.leaves, L.ldo = sh.nb, L.leaf_stride = sh.mb * sh.nb, L.direct = 0;
+            CombineLaunch &c = it.cb;
+            c.elem = el;
+            c.M = pws + w.leaves;
+            c.leaf_stride = sh.mb * sh.nb;
+            c.C = q.C, c.ldc = q.n, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
+            c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
+        }
+        it.direct = L.direct;
+        it.desc.resize(leaf_desc_bytes(el));
+        it.tiles = leaf_desc_build(L, it.desc.data());
+        items.push_back(std::move(it));
+    }
+    // largest inner dimension first: the longest work items start earliest
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.kb > b.kb; });
+    // Host staging of the descriptor table: kept per thread until the copies of the previous
+    // batched call on this thread have completed (an event marks them), so the stream never
+    // has to be synchronised.
+    thread_local struct Staging {
+        std::vector<char> descs;
+        std::vector<int64_t> first;
+        std::vector<int> direct;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    } stg;
+    if (stg.pending && (e = hipEventSynchronize(stg.done)) != hipSuccess) return hip_fail(e, "staging wait");
+    stg.pending = false;
+    const size_t db = leaf_desc_bytes(el);
+    stg.descs.assign(db * std::max<size_t>(items.size(), 1), 0);
+    stg.first.assign(items.size() + 1, 0);
+    stg.direct.assign(std::max<size_t>(items.size(), 1), 0);
+    for (size_t i = 0; i < items.size(); ++i) {
+        std::memcpy(stg.descs.data() + i * db, items[i].desc.data(), db);
+        stg.first[i + 1] = stg.first[i] + items[i].tiles;
+        stg.direct[i] = items[i].direct;
+    }
+    const int64_t total = stg.first.back();
+    if (total > 0) {
+        if (!stg.done && (e = hipEventCreateWithFlags(&stg.done, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "staging event");
+        if ((e = hipMemcpyAsync(ws + bl.descs, stg.descs.data(), db * items.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(ws + bl.first, stg.first.data(), 8 * stg.first.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(ws + bl.direct, stg.direct.data(), 4 * items.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_fail(e, "uploading batch descriptors");
+        if ((e = hipEventRecord(stg.done, s)) != hipSuccess) return hip_fail(e, "staging event");
+        stg.pending = true;
+        const int64_t slots = (int64_t)device_cus() * leaf_blocks_per_cu(el);
+        const int grid = (int)std::min<int64_t>(total, slots);
+        if ((e = launch_leaf_batched(el, ws + bl.descs, (const int64_t *)(ws + bl.first), (const int *)(ws + bl.direct),
+                                     (int)items.size(), total, grid, s)) != hipSuccess)
+            return hip_fail(e, "batched leaf kernel");
+    }
+    for (const Item &it : items)
+        if (it.combine && (e = launch_combine(it.cb, s)) != hipSuccess) return hip_fail(e, "combine kernel");
+    return FASTMM_OK;
+}
 
 fastmm_status fastmm_backward_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, size_t *bytes) {
     if (check_plan(plan)) return FASTMM_EINVAL;

@@ -73,6 +73,16 @@ struct ScaleStep {
 hipError_t launch_leaf(const LeafLaunch &L, hipStream_t s);
 // Pipelined 128x128-tile version for row-major (non-transposed) operands.
 hipError_t launch_leaf_pipelined(const LeafLaunch &L, hipStream_t s);
+// Batched persistent version (row-major operands, FP64/FP32): leaf_desc_build writes the
+// device descriptor of one problem's launch to `dst` (leaf_desc_bytes(e) bytes, host memory)
+// and returns its number of work items; launch_leaf_batched runs `total` items of `count`
+// problems (descriptors, item prefix offsets first[count+1] and direct flags in device memory)
+// on `grid` persistent work-groups.
+size_t leaf_desc_bytes(Elem e);
+int64_t leaf_desc_build(const LeafLaunch &L, void *dst);
+hipError_t launch_leaf_batched(Elem e, const void *descs, const int64_t *first, const int *direct, int count,
+                               int64_t total, int grid, hipStream_t s);
+int leaf_blocks_per_cu(Elem e);
 // Split-precision (bf16 / fp16 limb) version: FP32 A (m x k, row-major, L.A / L.lda) and the
 // transpose of B (n x k, row-major); L.prec selects the limb format and count.
 hipError_t launch_leaf_split(const LeafLaunch &L, const float *Bt, int64_t ldbt, hipStream_t s);

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 
 #include "devtypes.h"
 #include "launch.h"
@@ -75,35 +76,34 @@ __device__ inline int64_t xcd_remap_tile(int64_t b, int64_t G) {
     return ((x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + j;
 }
 
+template <typename T>
+struct Tile {
+    typedef Core<T> C;
+    static constexpr int BM = 128, BN = 128, BK = C::BK, VEC = C::VEC;
+    static constexpr int LDA_S = BK + 1;   // odd row stride: conflict-free column reads of A
+    static constexpr int LDB_S = BN + 16;  // k-rows of B land on different bank groups
+    struct Smem {
+        T As[2][BM * LDA_S];
+        __attribute__((aligned(16))) T Bs[2][BK * LDB_S];
+    };
+};
+
+// One 128x128 output tile (tile row tm, tile column tn) of leaf `leaf` of the problem p.
 template <typename T, bool SCALED, bool DIRECT>
-__global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T> p) {
+__device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t tm, int64_t tn,
+                                          typename Tile<T>::Smem &sm) {
     typedef Core<T> C;
     constexpr int BM = 128, BN = 128, BK = C::BK, VEC = C::VEC;
     constexpr int TPRA = BK / VEC, RPPA = kNT / TPRA, NPA = BM / RPPA;  // A: threads/row, rows/pass
     constexpr int TPRB = BN / VEC, KPPB = kNT / TPRB, NPB = BK / KPPB;  // B: threads/k-row, k-rows/pass
-    constexpr int LDA_S = BK + 1;   // odd row stride: conflict-free column reads of A
-    constexpr int LDB_S = BN + 16;  // k-rows of B land on different bank groups
+    constexpr int LDA_S = Tile<T>::LDA_S, LDB_S = Tile<T>::LDB_S;
     constexpr int WM = 64, WN = 64, TM = WM / 16, TN = WN / 16;
     static_assert(NPA * RPPA == BM && NPB * KPPB == BK, "tile shape");
-
-    __shared__ T As[2][BM * LDA_S];
-    __shared__ __attribute__((aligned(16))) T Bs[2][BK * LDB_S];
+    auto &As = sm.As;
+    auto &Bs = sm.Bs;
 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    // Work-group-uniform values are moved to scalar registers explicitly, so that branches on
-    // the leaf's source counts stay scalar branches.
-    const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
-    const int bid = __builtin_amdgcn_readfirstlane((int)xcd_remap_tile(blockIdx.x, gridDim.x));
-    const int leaf = __builtin_amdgcn_readfirstlane((int)(bid / tiles));
-    const int rem = __builtin_amdgcn_readfirstlane((int)(bid - (int64_t)leaf * tiles));
-    // Grouped tile order: 8 tile-rows at a time, column by column inside the group, so the
-    // work-groups resident on one XCD share A row panels and B column panels in its L2.
-    const int grp = rem / (8 * p.tiles_n);
-    const int gsz = min(8, p.tiles_m - grp * 8);
-    const int gidx = rem - grp * 8 * p.tiles_n;
-    const int64_t tm = __builtin_amdgcn_readfirstlane(grp * 8 + gidx % gsz);
-    const int64_t tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
     LeafEntry le = p.leaves[leaf];
     le.a_begin = __builtin_amdgcn_readfirstlane(le.a_begin);
     le.a_count = __builtin_amdgcn_readfirstlane(le.a_count);
@@ -361,6 +361,62 @@ __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T>
             }
 }
 
+// Work-group-uniform values are moved to scalar registers explicitly, so that branches on the
+// leaf's source counts stay scalar branches.  Tiles run in groups of 8 tile-rows, column by
+// column inside a group, so the work-groups resident on one XCD share A row panels and B
+// column panels in its L2.
+__device__ __forceinline__ void tile_coords(int rem, int tiles_m, int tiles_n, int64_t &tm, int64_t &tn) {
+    const int grp = rem / (8 * tiles_n);
+    const int gsz = min(8, tiles_m - grp * 8);
+    const int gidx = rem - grp * 8 * tiles_n;
+    tm = __builtin_amdgcn_readfirstlane(grp * 8 + gidx % gsz);
+    tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
+}
+
+template <typename T, bool SCALED, bool DIRECT>
+__global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T> p) {
+    __shared__ typename Tile<T>::Smem sm;
+    const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
+    const int bid = __builtin_amdgcn_readfirstlane((int)xcd_remap_tile(blockIdx.x, gridDim.x));
+    const int leaf = __builtin_amdgcn_readfirstlane((int)(bid / tiles));
+    const int rem = __builtin_amdgcn_readfirstlane((int)(bid - (int64_t)leaf * tiles));
+    int64_t tm, tn;
+    tile_coords(rem, p.tiles_m, p.tiles_n, tm, tn);
+    leaf_tile<T, SCALED, DIRECT>(p, leaf, tm, tn, sm);
+}
+
+// Persistent batched launch over several problems (each with its own plan tables): work item
+// w (in [0, total)) belongs to the problem q with first[q] <= w < first[q+1], ordered by the
+// host (largest K first); work-group g processes items g, g + G, g + 2G, ... in order, so the
+// assignment is static and the results deterministic.
+template <typename T>
+__global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_batched(const PArgs<T> *probs, const int64_t *first,
+                                                                     const int *direct, int count, int64_t total) {
+    __shared__ typename Tile<T>::Smem sm;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        int q = 0;
+        while (q + 1 < count && first[q + 1] <= w) ++q;
+        q = __builtin_amdgcn_readfirstlane(q);
+        const PArgs<T> &p = probs[q];
+        const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
+        const int64_t local = w - first[q];
+        const int leaf = __builtin_amdgcn_readfirstlane((int)(local / tiles));
+        const int rem = __builtin_amdgcn_readfirstlane((int)(local - (int64_t)leaf * tiles));
+        int64_t tm, tn;
+        tile_coords(rem, p.tiles_m, p.tiles_n, tm, tn);
+        const bool scaled = p.sc.ea != nullptr, dir = direct[q] != 0;
+        if (scaled) {
+            if (dir) leaf_tile<T, true, true>(p, leaf, tm, tn, sm);
+            else leaf_tile<T, true, false>(p, leaf, tm, tn, sm);
+        } else {
+            if (dir) leaf_tile<T, false, true>(p, leaf, tm, tn, sm);
+            else leaf_tile<T, false, false>(p, leaf, tm, tn, sm);
+        }
+        __syncthreads();  // the next item reuses the LDS buffers
+    }
+}
+
+
 template <typename T>
 hipError_t go(const LeafLaunch &L, hipStream_t s) {
     PArgs<T> a;
@@ -393,7 +449,54 @@ hipError_t go(const LeafLaunch &L, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T>
+PArgs<T> make_args(const LeafLaunch &L) {
+    PArgs<T> a;
+    a.A = (const T *)L.A;
+    a.B = (const T *)L.B;
+    a.out = (T *)L.out;
+    a.lda = L.lda, a.ldb = L.ldb, a.ldo = L.ldo;
+    a.m = L.m, a.k = L.k, a.n = L.n;
+    a.mb = L.mb, a.kb = L.kb, a.nb = L.nb;
+    a.leaf_stride = L.leaf_stride;
+    a.tiles_m = (int)((L.mb + 127) / 128);
+    a.tiles_n = (int)((L.nb + 127) / 128);
+    a.leaves = L.leaves, a.asrc = L.asrc, a.bsrc = L.bsrc;
+    a.sc = L.sc;
+    constexpr int VEC = Core<T>::VEC;
+    a.vec_a = ((uintptr_t)L.A % 16 == 0) && (L.lda % VEC == 0) && (L.kb % VEC == 0);
+    a.vec_b = ((uintptr_t)L.B % 16 == 0) && (L.ldb % VEC == 0) && (L.nb % VEC == 0);
+    return a;
+}
+
 }  // namespace
+
+size_t leaf_desc_bytes(Elem e) { return e == Elem::F64 ? sizeof(PArgs<double>) : sizeof(PArgs<float>); }
+
+int64_t leaf_desc_build(const LeafLaunch &L, void *dst) {
+    if (L.elem == Elem::F64) {
+        const PArgs<double> a = make_args<double>(L);
+        std::memcpy(dst, &a, sizeof(a));
+        return (int64_t)a.tiles_m * a.tiles_n * L.nleaves;
+    }
+    const PArgs<float> a = make_args<float>(L);
+    std::memcpy(dst, &a, sizeof(a));
+    return (int64_t)a.tiles_m * a.tiles_n * L.nleaves;
+}
+
+hipError_t launch_leaf_batched(Elem e, const void *descs, const int64_t *first, const int *direct, int count,
+                               int64_t total, int grid, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    if (e == Elem::F64)
+        hipLaunchKernelGGL(fmm_leaf_batched<double>, dim3(grid), dim3(kNT), 0, s, (const PArgs<double> *)descs, first,
+                           direct, count, total);
+    else
+        hipLaunchKernelGGL(fmm_leaf_batched<float>, dim3(grid), dim3(kNT), 0, s, (const PArgs<float> *)descs, first,
+                           direct, count, total);
+    return hipGetLastError();
+}
+
+int leaf_blocks_per_cu(Elem e) { return e == Elem::F64 ? Core<double>::OCC : Core<float>::OCC; }
 
 hipError_t launch_leaf_pipelined(const LeafLaunch &L, hipStream_t s) {
     if (L.elem == Elem::F64) return go<double>(L, s);

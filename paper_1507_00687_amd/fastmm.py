@@ -38,6 +38,11 @@ class FastmmError(RuntimeError):
         self.status = status
 
 
+class _Problem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p), ("m", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("n", ctypes.c_int64)]
+
+
 class _Scaling(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("steps", ctypes.c_int), ("tau", ctypes.c_double)]
 
@@ -71,6 +76,9 @@ def lib() -> ctypes.CDLL:
         L.fastmm_gemm_ex.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64, i64, i64, i64, vp, sz, vp]
         L.fastmm_scaling_exponents.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp, vp, sz, vp]
         L.fastmm_task_table.argtypes = [vp, i32, pi64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fastmm_batched_workspace_size.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Problem), i32,
+                                                     ctypes.POINTER(sz)]
+        L.fastmm_gemm_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Problem), i32, vp, sz, vp]
         L.fastmm_backward_workspace_size.argtypes = [vp, i64, i64, i64, ctypes.POINTER(sz)]
         L.fastmm_gemm_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
         L.fastmm_profile_enable.argtypes = [i32]
@@ -81,7 +89,8 @@ def lib() -> ctypes.CDLL:
         for name in ("fastmm_algo_register", "fastmm_algo_info", "fastmm_algo_coeffs", "fastmm_plan_create",
                      "fastmm_plan_destroy", "fastmm_plan_shape", "fastmm_workspace_size", "fastmm_gemm",
                      "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read", "fastmm_task_table",
-                     "fastmm_backward_workspace_size", "fastmm_gemm_backward"):
+                     "fastmm_backward_workspace_size", "fastmm_gemm_backward", "fastmm_batched_workspace_size",
+                     "fastmm_gemm_batched"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -231,6 +240,34 @@ def fastmm_gemm_ex(plan: Plan, A, transA: bool, B, transB: bool, C=None, workspa
                                 B.stride(0), int(bool(transB)), C.data_ptr(), C.stride(0), m, k, n, ws.data_ptr(),
                                 ws.numel(), _stream_ptr(stream)))
     return C
+
+
+def fastmm_gemm_batched(plans, As, Bs, Cs=None, workspace=None, stream=None):
+    """C_i = A_i @ B_i for all i with plans[i]; one persistent leaf launch for the batch."""
+    import torch
+
+    count = len(As)
+    if not (len(Bs) == count and len(plans) == count):
+        raise ValueError("plans, As and Bs must have the same length")
+    As = [a.contiguous() for a in As]
+    Bs = [b.contiguous() for b in Bs]
+    if Cs is None:
+        Cs = [torch.empty((a.shape[0], b.shape[1]), dtype=a.dtype, device=a.device) for a, b in zip(As, Bs)]
+    probs = (_Problem * max(count, 1))()
+    for i, (a, b, c) in enumerate(zip(As, Bs, Cs)):
+        if a.shape[1] != b.shape[0]:
+            raise ValueError(f"problem {i}: inner dimensions differ")
+        if a.dtype != plans[i].dtype or b.dtype != plans[i].dtype:
+            raise TypeError(f"problem {i}: operands must be {plans[i].dtype}")
+        probs[i] = _Problem(a.data_ptr(), b.data_ptr(), c.data_ptr(), a.shape[0], a.shape[1], b.shape[1])
+    handles = (ctypes.c_void_p * max(count, 1))(*[p.handle.value for p in plans])
+    need = ctypes.c_size_t()
+    _check(lib().fastmm_batched_workspace_size(handles, probs, count, ctypes.byref(need)))
+    if workspace is None:
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=As[0].device if count else "cuda")
+    _check(lib().fastmm_gemm_batched(handles, probs, count, workspace.data_ptr(), workspace.numel(),
+                                     _stream_ptr(stream)))
+    return Cs
 
 
 def fastmm_gemm_backward(plan: Plan, A, B, G, need_dA: bool = True, need_dB: bool = True, workspace=None,

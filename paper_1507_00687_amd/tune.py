@@ -1,0 +1,129 @@
+"""Autotuner: choose a plan (rule, depth, cutoff) per problem shape by measuring on the GPU.
+
+Candidates are the built-in rules at depths 0..3 (depth 0 is the classical kernel).  A
+candidate is admitted only if its growth factor relative to classical -- the E^L term of
+Theorem 4.1 over the classical K0^L -- stays within `max_instability` (the relative
+instability (E/K0^2)^L of section 5.3 is the same quantity up to the inner dimension); the
+fastest admitted candidate wins.  Results are cached in a JSON file keyed by shape and
+precision, so tuning can resume.  The timing itself runs the product through libfastmm.so.
+"""
+from __future__ import annotations
+
+import json
+import os
+from dataclasses import asdict, dataclass
+from typing import Dict, Iterable, List, Optional, Tuple
+
+RULES = ("strassen", "winograd", "f323", "f332", "f233", "f424", "f442", "f244", "laderman333")
+
+
+@dataclass
+class Choice:
+    algo: str
+    depth: int
+    cutoff: int
+    ms: float
+    instability: float  # (E / K0^2)^L of the levels actually used (1 for classical)
+
+    def plan(self, precision: str, **kw):
+        from .fastmm import Plan
+
+        return Plan(self.algo, self.depth, self.cutoff, precision=precision, **kw)
+
+
+def relative_instability(algo: str, levels: int) -> float:
+    """(E / K0^2)^L: the factor by which the leading term of Theorem 4.1 exceeds classical's."""
+    from .fastmm import fastmm_algo_info
+
+    if algo == "classical" or levels == 0:
+        return 1.0
+    info = fastmm_algo_info(algo)
+    return (info["E"] / info["K0"] ** 2) ** levels
+
+
+def candidates(max_depth: int = 3, cutoffs: Iterable[int] = (256,)) -> List[Tuple[str, int, int]]:
+    out = [("classical", 0, 1)]
+    for a in RULES:
+        for d in range(1, max_depth + 1):
+            for c in cutoffs:
+                out.append((a, d, c))
+    return out
+
+
+def _time_plan(plan, A, B, C, ws, reps: int) -> float:
+    import torch
+
+    from .fastmm import fastmm_gemm
+
+    fastmm_gemm(plan, A, B, C=C, workspace=ws)  # warm-up (uploads the task table)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        start.record()
+        fastmm_gemm(plan, A, B, C=C, workspace=ws)
+        stop.record()
+        stop.synchronize()
+        times.append(start.elapsed_time(stop))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def _key(m, k, n, precision):
+    return f"{m}x{k}x{n}:{precision}"
+
+
+def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 3, cutoffs=(256,),
+               max_instability: float = float("inf"), reps: int = 3, A=None, B=None) -> Choice:
+    """Measure every admitted candidate on (m, k, n) and return the fastest."""
+    import torch
+
+    from .fastmm import Plan
+
+    dt = torch.float64 if precision == "f64" else torch.float32
+    gen = torch.Generator(device="cuda").manual_seed(1234)
+    if A is None:
+        A = torch.randn((m, k), dtype=dt, device="cuda", generator=gen)
+    if B is None:
+        B = torch.randn((k, n), dtype=dt, device="cuda", generator=gen)
+    C = torch.empty((m, n), dtype=dt, device="cuda")
+    best: Optional[Choice] = None
+    seen = set()
+    for algo, depth, cutoff in candidates(max_depth, cutoffs):
+        plan = Plan(algo, depth, cutoff, precision=precision)
+        levels = plan.shape(m, k, n)[0]
+        if (algo, levels) in seen or (levels == 0 and algo != "classical"):
+            continue  # same computation as a candidate already measured
+        seen.add((algo, levels))
+        inst = relative_instability(algo, levels)
+        if inst > max_instability:
+            continue
+        ws = torch.empty(max(plan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
+        ms = _time_plan(plan, A, B, C, ws, reps)
+        if best is None or ms < best.ms:
+            best = Choice(algo, depth if levels else 0, cutoff, ms, inst)
+    assert best is not None
+    return best
+
+
+def tune(shapes: Iterable[Tuple[int, int, int]], precision: str = "f32", cache: Optional[str] = None,
+         **kw) -> Dict[Tuple[int, int, int], Choice]:
+    """Tune every distinct shape (cached results are reused and new ones appended)."""
+    store = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            store = json.load(f)
+    out = {}
+    for (m, k, n) in dict.fromkeys(tuple(s) for s in shapes):
+        key = _key(m, k, n, precision)
+        if key in store:
+            out[(m, k, n)] = Choice(**store[key])
+            continue
+        ch = tune_shape(m, k, n, precision, **kw)
+        out[(m, k, n)] = ch
+        store[key] = asdict(ch)
+        if cache:
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(store, f, indent=1)
+            os.replace(tmp, cache)
+    return out

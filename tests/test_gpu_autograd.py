@@ -104,8 +104,9 @@ def test_torch_gradcheck():
 
     plan = F.Plan("strassen", 2, 1, precision="f64")
     # finite differences with step 1e-6 carry ~u |C| / 1e-6 ~ 1e-9 noise
-    A = torch.randn(9, 7, dtype=torch.float64, device="cuda").requires_grad_(True)
-    B = torch.randn(7, 11, dtype=torch.float64, device="cuda").requires_grad_(True)
+    An, Bn = make_pair("normal", 12, 9, 7, 11)
+    A = torch.from_numpy(An).cuda().requires_grad_(True)
+    B = torch.from_numpy(Bn).cuda().requires_grad_(True)
     assert torch.autograd.gradcheck(lambda a, b: F.fast_matmul(a, b, plan), (A, B), eps=1e-6, atol=1e-6, rtol=1e-5)
 
 
