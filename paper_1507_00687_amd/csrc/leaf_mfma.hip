@@ -68,6 +68,7 @@ struct PArgs {
     const SrcEntry *bsrc;
     ScaleExps sc;
     int vec_a, vec_b;  // 16-byte loads allowed (alignment of pointers, ld and block sizes)
+    int small_ld;      // a 128-row (or BK-row) panel of either operand spans < 2^31 bytes
 };
 
 __device__ inline int64_t xcd_remap_tile(int64_t b, int64_t G) {
@@ -112,6 +113,15 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
 
     const int ra = t / TPRA, ka = (t % TPRA) * VEC;   // A: row within pass, k offset
     const int kbr = t / TPRB, cb = (t % TPRB) * VEC;  // B: k-row within pass, column offset
+    // Byte offsets of the thread's vectors inside an interior tile: independent of the source
+    // block and of the K stage (valid when 128 rows of the operands span < 2^31 bytes).  Used
+    // for FP32 only: for FP64 the extra live offsets cost more than the address math they save.
+    constexpr bool kInterior = sizeof(T) == 4;
+    uint32_t voA[NPA], voB[NPB];
+#pragma unroll
+    for (int pa = 0; pa < NPA; ++pa) voA[pa] = (uint32_t)(((pa * RPPA + ra) * p.lda + ka) * sizeof(T));
+#pragma unroll
+    for (int pb = 0; pb < NPB; ++pb) voB[pb] = (uint32_t)(((pb * KPPB + kbr) * p.ldb + cb) * sizeof(T));
 
     // Load (with zero fill outside the operand and outside the leaf block) the thread's part
     // of one source block of A at K offset k0; values scaled by 2^(ep_col - ea_row).  Loads
@@ -121,7 +131,18 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
         const int64_t row0 = (int64_t)se.br * p.mb + tm * BM;  // operand row of tile row 0
         const int64_t col0 = (int64_t)se.bc * p.kb + k0 + ka;  // operand column of this thread
         const bool full = p.vec_a && (k0 + BK <= p.kb) && ((int64_t)se.bc * p.kb + k0 + BK <= p.k);
-        if (full) {
+        if (kInterior && full && (tm * BM + BM <= p.mb) && (row0 + BM <= p.m) && p.small_ld) {
+            // interior tile: a work-group-uniform base and the thread's fixed 32-bit offsets
+            const char *base = reinterpret_cast<const char *>(p.A + row0 * p.lda + (int64_t)se.bc * p.kb + k0);
+#pragma unroll
+            for (int pa = 0; pa < NPA; ++pa) {
+                const typename C::vec_t x = *reinterpret_cast<const typename C::vec_t *>(
+                    __builtin_assume_aligned(base + voA[pa], 16));
+                const T *xs = reinterpret_cast<const T *>(&x);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[pa][e] = xs[e];
+            }
+        } else if (full) {
 #pragma unroll
             for (int pa = 0; pa < NPA; ++pa) {
                 const int r = pa * RPPA + ra;
@@ -166,7 +187,18 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
         const int64_t col0 = (int64_t)se.bc * p.nb + tn * BN + cb;  // operand column
         const bool cfull = (tn * BN + cb + VEC <= p.nb) && (col0 + VEC <= p.n);
         const bool full = p.vec_b && (tn * BN + BN <= p.nb) && ((int64_t)se.bc * p.nb + tn * BN + BN <= p.n);
-        if (full) {
+        if (kInterior && full && (k0 + BK <= p.kb) && (row0 + BK <= p.k) && p.small_ld) {
+            // interior tile: a work-group-uniform base and the thread's fixed 32-bit offsets
+            const char *base = reinterpret_cast<const char *>(p.B + row0 * p.ldb + (int64_t)se.bc * p.nb + tn * BN);
+#pragma unroll
+            for (int pb = 0; pb < NPB; ++pb) {
+                const typename C::vec_t x = *reinterpret_cast<const typename C::vec_t *>(
+                    __builtin_assume_aligned(base + voB[pb], 16));
+                const T *xs = reinterpret_cast<const T *>(&x);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[pb][e] = xs[e];
+            }
+        } else if (full) {
 #pragma unroll
             for (int pb = 0; pb < NPB; ++pb) {
                 const int kr = pb * KPPB + kbr;
@@ -390,7 +422,7 @@ __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T>
 // host (largest K first); work-group g processes items g, g + G, g + 2G, ... in order, so the
 // assignment is static and the results deterministic.
 template <typename T>
-__global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_batched(const PArgs<T> *probs, const int64_t *first,
+__global__ __launch_bounds__(kNT, 1) void fmm_leaf_batched(const PArgs<T> *probs, const int64_t *first,
                                                                      const int *direct, int count, int64_t total) {
     __shared__ typename Tile<T>::Smem sm;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
@@ -418,38 +450,6 @@ __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_batched(const PArg
 
 
 template <typename T>
-hipError_t go(const LeafLaunch &L, hipStream_t s) {
-    PArgs<T> a;
-    a.A = (const T *)L.A;
-    a.B = (const T *)L.B;
-    a.out = (T *)L.out;
-    a.lda = L.lda, a.ldb = L.ldb, a.ldo = L.ldo;
-    a.m = L.m, a.k = L.k, a.n = L.n;
-    a.mb = L.mb, a.kb = L.kb, a.nb = L.nb;
-    a.leaf_stride = L.leaf_stride;
-    a.tiles_m = (int)((L.mb + 127) / 128);
-    a.tiles_n = (int)((L.nb + 127) / 128);
-    a.leaves = L.leaves, a.asrc = L.asrc, a.bsrc = L.bsrc;
-    a.sc = L.sc;
-    constexpr int VEC = Core<T>::VEC;
-    a.vec_a = ((uintptr_t)L.A % 16 == 0) && (L.lda % VEC == 0) && (L.kb % VEC == 0);
-    a.vec_b = ((uintptr_t)L.B % 16 == 0) && (L.ldb % VEC == 0) && (L.nb % VEC == 0);
-    const int64_t blocks = (int64_t)a.tiles_m * a.tiles_n * L.nleaves;
-    if (blocks <= 0) return hipSuccess;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    const bool scaled = L.sc.ea != nullptr;
-    dim3 grid((unsigned)blocks), block(kNT);
-    if (L.direct) {
-        if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, true>), grid, block, 0, s, a);
-    } else {
-        if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, false>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, false>), grid, block, 0, s, a);
-    }
-    return hipGetLastError();
-}
-
-template <typename T>
 PArgs<T> make_args(const LeafLaunch &L) {
     PArgs<T> a;
     a.A = (const T *)L.A;
@@ -466,8 +466,29 @@ PArgs<T> make_args(const LeafLaunch &L) {
     constexpr int VEC = Core<T>::VEC;
     a.vec_a = ((uintptr_t)L.A % 16 == 0) && (L.lda % VEC == 0) && (L.kb % VEC == 0);
     a.vec_b = ((uintptr_t)L.B % 16 == 0) && (L.ldb % VEC == 0) && (L.nb % VEC == 0);
+    a.small_ld = (128 * (L.lda + 8) * (int64_t)sizeof(T) < (int64_t(1) << 31)) &&
+                 (128 * (L.ldb + 8) * (int64_t)sizeof(T) < (int64_t(1) << 31));
     return a;
 }
+
+template <typename T>
+hipError_t go(const LeafLaunch &L, hipStream_t s) {
+    const PArgs<T> a = make_args<T>(L);
+    const int64_t blocks = (int64_t)a.tiles_m * a.tiles_n * L.nleaves;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const bool scaled = L.sc.ea != nullptr;
+    dim3 grid((unsigned)blocks), block(kNT);
+    if (L.direct) {
+        if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, true>), grid, block, 0, s, a);
+    } else {
+        if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 
 }  // namespace
 
@@ -496,7 +517,7 @@ hipError_t launch_leaf_batched(Elem e, const void *descs, const int64_t *first, 
     return hipGetLastError();
 }
 
-int leaf_blocks_per_cu(Elem e) { return e == Elem::F64 ? Core<double>::OCC : Core<float>::OCC; }
+int leaf_blocks_per_cu(Elem) { return 1; }  // the batched kernel holds all four tile variants
 
 hipError_t launch_leaf_pipelined(const LeafLaunch &L, hipStream_t s) {
     if (L.elem == Elem::F64) return go<double>(L, s);
