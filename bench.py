@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=4096, help="size of the oracle timing sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classical", action="store_true")
+    ap.add_argument("--no-fuse", action="store_true", help="force the leaf-products + W-combination path")
     ap.add_argument("--torch-ref", action="store_true",
                     help="also time torch.matmul (vendor BLAS) on the same operands, as context")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -70,19 +71,23 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps * 1e3
 
 
-LEAF_SOURCE = {"f64": "leaf_mfma.hip", "f32": "leaf_mfma.hip"}  # split precisions: leaf_split.hip
+def product_kernel(precision: str, path: str):
+    """(kernel name, source file) of the launch that computes the products."""
+    if path == "fused":
+        return "fmm_node222", "node_fused.hip"
+    if precision in ("f64", "f32"):
+        return "fmm_leaf_pipelined", "leaf_mfma.hip"
+    return "fmm_leaf_split", "leaf_split.hip"
 
 
-def kernel_source_hash(precision: str) -> str:
-    """Hash of the source file of the leaf kernel that serves `precision`."""
-    name = LEAF_SOURCE.get(precision, "leaf_split.hip")
-    with open(os.path.join(ROOT, "paper_1507_00687_amd", "csrc", name), "rb") as f:
+def kernel_source_hash(source: str) -> str:
+    with open(os.path.join(ROOT, "paper_1507_00687_amd", "csrc", source), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(workload: str, precision: str):
-    """HBM bytes per leaf-kernel launch from committed rocprofv3 counter runs, if they were
-    taken with the current kernel sources."""
+def load_traffic(workload: str, source: str):
+    """HBM bytes per product-kernel launch from committed rocprofv3 counter runs, if they were
+    taken with the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -90,7 +95,7 @@ def load_traffic(workload: str, precision: str):
         rec = json.load(open(path)).get(workload)
     except Exception:
         return None
-    if not rec or rec.get("source_hash") != kernel_source_hash(precision):
+    if not rec or rec.get("source") != source or rec.get("source_hash") != kernel_source_hash(source):
         return None
     return rec.get("bytes_per_launch")
 
@@ -146,8 +151,10 @@ def main():
     tA = torch.from_numpy(A).cuda()
     tB = torch.from_numpy(B).cuda()
     plan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
-                  precision=args.precision)
+                  precision=args.precision, fuse=not args.no_fuse)
     L, Mp, Kp, Np = plan.shape(m, k, n)
+    path = plan.path(m, k, n)
+    kname, ksource = product_kernel(args.precision, path)
     ws = torch.empty(max(plan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
     Cf = torch.empty((m, n), dtype=tA.dtype, device="cuda")
     run_fast = lambda: F.fastmm_gemm(plan, tA, tB, C=Cf, workspace=ws)
@@ -165,7 +172,7 @@ def main():
     ms = time_steps(run_fast, args.steps, args.warmup)
     value = 2.0 * m * k * n / (ms * 1e-3) / 1e12
 
-    # leaf-kernel duration from the library's HIP events (same stream as the launches)
+    # product-kernel duration from the library's HIP events (same stream as the launches)
     F.fastmm_profile_enable(True)
     F.fastmm_profile_read()
     for _ in range(args.steps):
@@ -181,7 +188,7 @@ def main():
     achieved = flops_per_launch / (leaf_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     workload = (f"{args.algo} L={args.depth} cutoff={args.cutoff} n={n} {args.precision} {args.dist} "
-                f"scaling={args.scaling}")
+                f"scaling={args.scaling} path={path}")
 
     torch_ref = None
     if args.torch_ref:
@@ -222,15 +229,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "algo": args.algo, "depth": args.depth, "levels_used": L,
                    "cutoff": args.cutoff, "m": m, "k": k, "n": n, "padded": [Mp, Kp, Np],
-                   "precision": args.precision, "scaling": args.scaling, "dist": args.dist},
+                   "precision": args.precision, "scaling": args.scaling, "dist": args.dist, "path": path},
         "classical": classical,
         "torch_matmul": torch_ref,
         "speedup_vs_classical": (classical["ms_per_step"] / ms) if classical else None,
         "error": err,
         "phases_ms": {"scaling": prof["scaling_ms"] / calls, "leaf": leaf_ms, "combine": prof["combine_ms"] / calls},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": load_traffic(workload, args.precision),
-                     "kernel": "leaf_kernel", "flops_per_launch": flops_per_launch},
+                     "frac": achieved / peak, "traffic": load_traffic(workload, ksource),
+                     "kernel": kname, "flops_per_launch": flops_per_launch},
         "cpu_baseline": leg.get("cpu"),
     }
     print(json.dumps(line), flush=True)

@@ -135,7 +135,28 @@ fastmm_status fastmm_plan_destroy(fastmm_plan_t plan);
 fastmm_status fastmm_plan_shape(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n,
                                 int *levels, int64_t *Mp, int64_t *Kp, int64_t *Np);
 
-/* Device workspace bytes fastmm_gemm needs for this shape. */
+/* Execution paths of one product (fastmm_plan_path). */
+typedef enum {
+    FASTMM_PATH_LEAF = 0,  /* one launch over all leaf products M_r = S_r T_r (S and T formed
+                              while loading, eq. (2)), then one W-combination launch */
+    FASTMM_PATH_FUSED = 1  /* the innermost level fused: each work-group forms S_r, T_r, the R
+                              products and the W-sums of eq. (1) for one tile of a node of the
+                              recursion; the outer L-1 levels as in the leaf path */
+} fastmm_path;
+
+/* Allow (enable != 0, the default) or forbid the fused path for this plan and the rotated
+ * sub-plans of its backward pass.  The fused path applies to FP64 and FP32 plans with at
+ * least one level, row-major (non-transposed) operands, and a <2,2,2;7> rule whose
+ * coefficients are all 0 or +-1 and whose sign pattern has a compiled kernel (Strassen's
+ * rule, Winograd's variant and their cyclic rotations).  Both paths give the same result in
+ * exact arithmetic; at one level with both operands in range they round identically. */
+fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int enable);
+
+/* The path (fastmm_path) fastmm_gemm_ex takes for this shape and these transposition flags. */
+fastmm_status fastmm_plan_path(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, int transA,
+                               int transB, int *path);
+
+/* Device workspace bytes fastmm_gemm needs for this shape (enough for either path). */
 fastmm_status fastmm_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n,
                                     size_t *bytes);
 

@@ -207,6 +207,7 @@ struct fastmm_plan_s {
     int cutoff = 1;
     fastmm_scaling sc{0, 0, 0.0};
     int prec = FASTMM_F64;
+    int fuse = 1;  // use the fused one-level kernel where it applies
     std::mutex mu;
     std::map<std::pair<int, int>, std::unique_ptr<fastmm::Tables>> tables;  // (L, device)
     // Sub-plans with the rotated rules, made on first use by the backward pass.
@@ -259,6 +260,27 @@ int leaf_count(const Algo &a, int L) {
 
 size_t elem_size(int prec) { return prec == FASTMM_F64 ? 8 : 4; }
 
+// Sign masks (U+, U-, V+, V-, W+, W-) of a <2,2,2;7> rule whose coefficients are all in
+// {0, +1, -1}: bit s*7+r is set where row s, column r holds +1 (resp. -1).  False otherwise.
+bool rule_masks_222(const Algo &a, uint32_t m[6]) {
+    if (a.M0 != 2 || a.K0 != 2 || a.N0 != 2 || a.R != 7) return false;
+    const std::vector<int64_t> *X[3] = {&a.U, &a.V, &a.W};
+    const int den[3] = {a.den_U, a.den_V, a.den_W};
+    for (int t = 0; t < 3; ++t) {
+        m[2 * t] = m[2 * t + 1] = 0;
+        for (int s = 0; s < 4; ++s)
+            for (int r = 0; r < 7; ++r) {
+                const int64_t v = (*X[t])[(size_t)s * 7 + r];
+                if (v == 0) continue;
+                if (den[t] != 0) return false;
+                if (v == 1) m[2 * t] |= 1u << (s * 7 + r);
+                else if (v == -1) m[2 * t + 1] |= 1u << (s * 7 + r);
+                else return false;
+            }
+    }
+    return true;
+}
+
 bool is_split(int prec) { return prec >= FASTMM_BF16 && prec <= FASTMM_BF16X6; }
 
 int64_t round4(int64_t x) { return (x + 3) / 4 * 4; }
@@ -292,6 +314,14 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
     if (s.L > 0) off = align256(off + es * (size_t)leaf_count(plan_algo(p), s.L) * s.mb * s.nb);
     w.total = off;
     return w;
+}
+
+// Whether a product takes the fused one-level kernel: FP64/FP32, at least one level, row-major
+// operands and a rule with a compiled sign pattern.
+bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, uint32_t masks[6]) {
+    if (!p->fuse || s.L < 1 || transA || transB) return false;
+    if (p->prec != FASTMM_F64 && p->prec != FASTMM_F32) return false;
+    return rule_masks_222(plan_algo(p), masks) && node222_supported(masks);
 }
 
 std::string schedule_of(const fastmm_scaling &sc) {
@@ -531,6 +561,25 @@ fastmm_status fastmm_plan_shape(fastmm_plan_t plan, int64_t m, int64_t k, int64_
     return FASTMM_OK;
 }
 
+fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int enable) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    std::lock_guard<std::mutex> g(plan->mu);
+    plan->fuse = enable ? 1 : 0;
+    for (auto &r : plan->rot)
+        if (r) r->fuse = plan->fuse;
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_plan_path(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, int transA, int transB,
+                               int *path) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    if (!path || m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "bad arguments");
+    const Shape s = shape_of(plan, m, k, n);
+    uint32_t masks[6];
+    *path = fused_path(plan, s, transA, transB, masks) ? FASTMM_PATH_FUSED : FASTMM_PATH_LEAF;
+    return FASTMM_OK;
+}
+
 fastmm_status fastmm_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, size_t *bytes) {
     if (check_plan(plan)) return FASTMM_EINVAL;
     if (!bytes || m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "bad arguments");
@@ -629,6 +678,42 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         }
         L.transB = 0;
     }
+    uint32_t masks[6];
+    if (fused_path(plan, s, transA, transB, masks)) {
+        // The innermost level runs fused; the L-1 outer levels supply the node operands and,
+        // for L >= 2, the W-combination of the node products.
+        Tables *outer = nullptr;
+        if ((stt = get_tables(plan, s.L - 1, &outer)) != FASTMM_OK) return stt;
+        NodeLaunch N;
+        N.elem = el;
+        N.A = A, N.B = B;
+        N.lda = lda, N.ldb = ldb;
+        N.m = m, N.k = k, N.n = n;
+        N.mb = s.mb, N.kb = s.kb, N.nb = s.nb;
+        N.nnodes = outer->nleaves;
+        N.outer = outer->leaves, N.asrc = outer->asrc, N.bsrc = outer->bsrc;
+        N.sc = exps;
+        for (int i = 0; i < 6; ++i) N.masks[i] = masks[i];
+        if (s.L == 1) {
+            N.out = C, N.ldo = ldc, N.node_stride = 0;
+        } else {
+            N.out = ws + w.leaves, N.ldo = 2 * s.nb, N.node_stride = 4 * s.mb * s.nb;
+        }
+        e = launch_node222(N, st);
+        fin.mark();
+        if (e != hipSuccess) return hip_fail(e, "fused node kernel");
+        if (s.L == 1) return FASTMM_OK;
+        CombineLaunch Cb;
+        Cb.elem = el;
+        Cb.M = ws + w.leaves;
+        Cb.leaf_stride = 4 * s.mb * s.nb;
+        Cb.C = C, Cb.ldc = ldc, Cb.m = m, Cb.n = n, Cb.mb = 2 * s.mb, Cb.nb = 2 * s.nb;
+        Cb.NB = outer->NB;
+        Cb.bdest = outer->bdest, Cb.dest = outer->dest;
+        Cb.sc = exps;
+        if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
+        return FASTMM_OK;
+    }
     auto leaf_launch = [&]() { return is_split(plan->prec) ? launch_leaf_split(L, Bt, ldbt, st) : launch_leaf(L, st); };
     if (s.L == 0) {
         L.out = C, L.ldo = ldc, L.leaf_stride = 0, L.direct = 1;
@@ -668,7 +753,7 @@ fastmm_status rotated_plan(fastmm_plan_s *p, int times, fastmm_plan_s **out) {
         if (id < 0) return fail(FASTMM_EUNSUPPORTED, "cannot rotate the plan's rule");
         std::unique_ptr<fastmm_plan_s> q(new (std::nothrow) fastmm_plan_s());
         if (!q) return fail(FASTMM_ENOMEM, "plan allocation");
-        q->algo = id, q->depth = p->depth, q->cutoff = p->cutoff, q->sc = p->sc, q->prec = p->prec;
+        q->algo = id, q->depth = p->depth, q->cutoff = p->cutoff, q->sc = p->sc, q->prec = p->prec, q->fuse = p->fuse;
         p->rot[times] = std::move(q);
     }
     *out = p->rot[times].get();
@@ -871,7 +956,7 @@ fastmm_status fastmm_backward_workspace_size(fastmm_plan_t plan, int64_t m, int6
     if ((st = fastmm_workspace_size(ra, k, n, m, &wa)) != FASTMM_OK) return st;  // dA^T = B G^T
     if ((st = fastmm_workspace_size(rb, n, m, k, &wb)) != FASTMM_OK) return st;  // dB^T = G^T A
     const size_t es = elem_size(plan->prec);
-    *bytes = align256(es * (size_t)std::max(k * m, n * k)) + std::max(wa, wb);
+    *bytes = align256(es * (size_t)std::max(k * m, n * k)) + align256(es * (size_t)n * m) + std::max(wa, wb);
     return FASTMM_OK;
 }
 
@@ -891,21 +976,29 @@ fastmm_status fastmm_gemm_backward(fastmm_plan_t plan, const void *A, const void
     const Elem el = plan->prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
     char *tmp = (char *)workspace;
     const size_t tmp_bytes = align256(es * (size_t)std::max(k * m, n * k));
-    char *ws = tmp + tmp_bytes;
-    const size_t wsb = ws_bytes - tmp_bytes;
+    char *gt = tmp + tmp_bytes;  // G^T (n x m), shared by both products
+    const size_t gt_bytes = align256(es * (size_t)n * m);
+    char *ws = gt + gt_bytes;
+    const size_t wsb = ws_bytes - tmp_bytes - gt_bytes;
     hipStream_t s = (hipStream_t)stream;
     fastmm_plan_s *ra = nullptr, *rb = nullptr;
     if ((st = rotated_plan(plan, 2, &ra)) != FASTMM_OK || (st = rotated_plan(plan, 1, &rb)) != FASTMM_OK) return st;
+    if (n > 0) {
+        // Both products read G transposed: materialise G^T once, so that they run on row-major
+        // operands (the pipelined and fused kernels).
+        hipError_t e = launch_transpose(el, G, n, m, n, gt, m, s);
+        if (e != hipSuccess) return hip_fail(e, "transpose kernel");
+    }
     if (dA) {
-        // dA^T (k x m) = B (k x n) * G^T, G stored m x n
-        st = fastmm_gemm_ex(ra, B, n, 0, G, n, 1, tmp, m, k, n, m, ws, wsb, stream);
+        // dA^T (k x m) = B (k x n) * G^T (n x m)
+        st = fastmm_gemm_ex(ra, B, n, 0, gt, m, 0, tmp, m, k, n, m, ws, wsb, stream);
         if (st != FASTMM_OK) return st;
         hipError_t e = launch_transpose(el, tmp, m, k, m, dA, k, s);
         if (e != hipSuccess) return hip_fail(e, "transpose kernel");
     }
     if (dB && n > 0) {
         // dB^T (n x k) = G^T (n x m) * A (m x k)
-        st = fastmm_gemm_ex(rb, G, n, 1, A, k, 0, tmp, k, n, m, k, ws, wsb, stream);
+        st = fastmm_gemm_ex(rb, gt, m, 0, A, k, 0, tmp, k, n, m, k, ws, wsb, stream);
         if (st != FASTMM_OK) return st;
         hipError_t e = launch_transpose(el, tmp, k, n, k, dB, n, s);
         if (e != hipSuccess) return hip_fail(e, "transpose kernel");

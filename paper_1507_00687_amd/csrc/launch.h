@@ -70,6 +70,34 @@ struct ScaleStep {
     int test;  // apply the stopping test at this step
 };
 
+// Fused one-level launch for <2,2,2;7> rules with coefficients in {0, +1, -1}: every
+// work-group computes one 64x64 tile position of the four output sub-blocks of one node (a
+// product of the outer L-1 levels, or the whole problem at depth 1), forming the node's
+// operands from its outer sources, the seven S_r / T_r fragments, the products and the W-sums
+// in one pass.  Sub-blocks are mb x kb (A) and kb x nb (B), i.e. the leaf blocks of the full
+// recursion; node operands are 2mb x 2kb and 2kb x 2nb.  node_stride == 0: single node, the
+// result goes to C (out / ldo) with the outside-scaling factors; otherwise node q's
+// 2mb x 2nb product goes to out + q * node_stride (row stride 2nb).
+struct NodeLaunch {
+    Elem elem;
+    const void *A;
+    const void *B;
+    void *out;
+    int64_t lda, ldb, ldo;
+    int64_t m, k, n;
+    int64_t mb, kb, nb;
+    int64_t node_stride;
+    int nnodes;
+    const LeafEntry *outer;
+    const SrcEntry *asrc;
+    const SrcEntry *bsrc;
+    ScaleExps sc;
+    uint32_t masks[6];  // (U+, U-, V+, V-, W+, W-): bit s*7+r marks coefficient +1 / -1
+};
+// Whether a compiled fused kernel exists for this sign pattern.
+bool node222_supported(const uint32_t masks[6]);
+hipError_t launch_node222(const NodeLaunch &L, hipStream_t s);
+
 hipError_t launch_leaf(const LeafLaunch &L, hipStream_t s);
 // Pipelined 128x128-tile version for row-major (non-transposed) operands.
 hipError_t launch_leaf_pipelined(const LeafLaunch &L, hipStream_t s);

@@ -72,6 +72,8 @@ def lib() -> ctypes.CDLL:
         L.fastmm_plan_destroy.argtypes = [vp]
         L.fastmm_plan_shape.argtypes = [vp, i64, i64, i64, pi32, pi64, pi64, pi64]
         L.fastmm_workspace_size.argtypes = [vp, i64, i64, i64, ctypes.POINTER(sz)]
+        L.fastmm_plan_set_fusion.argtypes = [vp, i32]
+        L.fastmm_plan_path.argtypes = [vp, i64, i64, i64, i32, i32, pi32]
         L.fastmm_gemm.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
         L.fastmm_gemm_ex.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64, i64, i64, i64, vp, sz, vp]
         L.fastmm_scaling_exponents.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp, vp, sz, vp]
@@ -90,7 +92,7 @@ def lib() -> ctypes.CDLL:
                      "fastmm_plan_destroy", "fastmm_plan_shape", "fastmm_workspace_size", "fastmm_gemm",
                      "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read", "fastmm_task_table",
                      "fastmm_backward_workspace_size", "fastmm_gemm_backward", "fastmm_batched_workspace_size",
-                     "fastmm_gemm_batched"):
+                     "fastmm_gemm_batched", "fastmm_plan_set_fusion", "fastmm_plan_path"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -147,13 +149,22 @@ class Plan:
     """A fastmm plan: algorithm, recursion depth, cutoff, scaling procedure, precision."""
 
     def __init__(self, algo="strassen", depth: int = 1, cutoff: int = 1, scaling: str = "none",
-                 steps: int = 2, tau: float = 0.0, precision: str = "f64"):
+                 steps: int = 2, tau: float = 0.0, precision: str = "f64", fuse: bool = True):
         self.algo, self.depth, self.cutoff = algo, depth, cutoff
         self.scaling, self.steps, self.tau, self.precision = scaling, steps, tau, precision
+        self.fuse = fuse
         self._h = ctypes.c_void_p()
         sc = _Scaling(_id(SCALE_MODES, scaling), steps, tau)
         _check(lib().fastmm_plan_create(ctypes.byref(self._h), _id(ALGOS, algo), depth, cutoff, ctypes.byref(sc),
                                         _id(PRECISIONS, precision)))
+        if not fuse:
+            _check(lib().fastmm_plan_set_fusion(self._h, 0))
+
+    def path(self, m: int, k: int, n: int, transA: bool = False, transB: bool = False) -> str:
+        """'fused' or 'leaf': the execution path of an m x k by k x n product."""
+        v = ctypes.c_int()
+        _check(lib().fastmm_plan_path(self._h, m, k, n, int(transA), int(transB), ctypes.byref(v)))
+        return "fused" if v.value == 1 else "leaf"
 
     @property
     def handle(self):

@@ -117,3 +117,42 @@ def test_gemm_argument_errors_before_launch(F):
     assert lib.fastmm_gemm(p.handle, base, base + 100000, base + 200000, 64, 64, 64, None, 0, None) == -8
     # empty products are no-ops
     assert lib.fastmm_gemm(p.handle, 0, 0, 0, 0, 5, 5, None, 0, None) == 0
+
+
+def _int_rows(M):
+    return np.array([[int(x) for x in r] for r in M], dtype=np.int64)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_fused_path_selection(F, precision):
+    P = lambda name, depth, cutoff=1, **kw: F.Plan(name, depth, cutoff, precision=precision, **kw)
+    assert P("strassen", 1).path(256, 256, 256) == "fused"
+    assert P("winograd", 3).path(300, 200, 100) == "fused"
+    assert P("strassen", 2).path(17, 300, 41) == "fused"
+    # transposed operands, no level, cutoff stopping at depth 0, other rules, fusion off
+    assert P("strassen", 1).path(256, 256, 256, transB=True) == "leaf"
+    assert P("strassen", 1).path(256, 256, 256, transA=True) == "leaf"
+    assert P("strassen", 0).path(256, 256, 256) == "leaf"
+    assert P("strassen", 2, 512).path(256, 256, 256) == "leaf"
+    assert P("f323", 1).path(300, 200, 300) == "leaf"
+    assert P("laderman333", 1).path(300, 300, 300) == "leaf"
+    assert P("strassen", 1, fuse=False).path(256, 256, 256) == "leaf"
+    assert F.Plan("strassen", 1, 1, precision="bf16x3").path(256, 256, 256) == "leaf"
+
+
+def test_fused_path_matches_rules_by_coefficients(F):
+    # Cyclic rotations (the rules of the backward pass) and user rules equal to a built-in
+    # one take the fused path; a rule with its products reordered does not.
+    for name in ("strassen", "winograd"):
+        a = C.get(name)
+        for t in range(3):
+            r = a
+            for _ in range(t):
+                r = C.rotate(r)
+            uid = F.fastmm_algo_register(2, 2, 2, 7, _int_rows(r.U), _int_rows(r.V), _int_rows(r.W), 0)
+            assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "fused", (name, t)
+    a = C.strassen()
+    perm = [1, 0, 2, 3, 4, 5, 6]
+    U, V, W = (_int_rows(M)[:, perm] for M in (a.U, a.V, a.W))
+    uid = F.fastmm_algo_register(2, 2, 2, 7, U, V, W, 0)
+    assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "leaf"
