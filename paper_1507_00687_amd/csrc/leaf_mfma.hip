@@ -81,11 +81,12 @@ template <typename T>
 struct Tile {
     typedef Core<T> C;
     static constexpr int BM = 128, BN = 128, BK = C::BK, VEC = C::VEC;
-    static constexpr int LDA_S = BK + 1;   // odd row stride: conflict-free column reads of A
-    static constexpr int LDB_S = BN + 16;  // k-rows of B land on different bank groups
+    // Both tiles are k-contiguous (B stored transposed), rows padded by 16 bytes: 16-byte
+    // reads of consecutive rows fall on distinct banks.
+    static constexpr int LDS_K = BK + 16 / (int)sizeof(T);
     struct Smem {
-        T As[2][BM * LDA_S];
-        __attribute__((aligned(16))) T Bs[2][BK * LDB_S];
+        __attribute__((aligned(16))) T As[2][BM * LDS_K];
+        __attribute__((aligned(16))) T Bs[2][BN * LDS_K];
     };
 };
 
@@ -96,10 +97,12 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
     typedef Core<T> C;
     constexpr int BM = 128, BN = 128, BK = C::BK, VEC = C::VEC;
     constexpr int TPRA = BK / VEC, RPPA = kNT / TPRA, NPA = BM / RPPA;  // A: threads/row, rows/pass
-    constexpr int TPRB = BN / VEC, KPPB = kNT / TPRB, NPB = BK / KPPB;  // B: threads/k-row, k-rows/pass
-    constexpr int LDA_S = Tile<T>::LDA_S, LDB_S = Tile<T>::LDB_S;
+    // B is loaded in VEC x VEC blocks (VEC k-rows by VEC columns, consecutive lanes on
+    // consecutive k-blocks) and written transposed, one 16-byte LDS write per column.
+    constexpr int KBV = BK / VEC, NBT = KBV * (BN / VEC) / kNT, NPB = NBT * VEC;  // B: blocks, rows
+    constexpr int LDS_K = Tile<T>::LDS_K;
     constexpr int WM = 64, WN = 64, TM = WM / 16, TN = WN / 16;
-    static_assert(NPA * RPPA == BM && NPB * KPPB == BK, "tile shape");
+    static_assert(NPA * RPPA == BM && NBT * kNT == KBV * (BN / VEC) && BK % 16 == 0, "tile shape");
     auto &As = sm.As;
     auto &Bs = sm.Bs;
 
@@ -112,7 +115,9 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
     le.b_count = __builtin_amdgcn_readfirstlane(le.b_count);
 
     const int ra = t / TPRA, ka = (t % TPRA) * VEC;   // A: row within pass, k offset
-    const int kbr = t / TPRB, cb = (t % TPRB) * VEC;  // B: k-row within pass, column offset
+    int kB[NBT], cB[NBT];  // B: the thread's blocks (k offset, column offset in the tile)
+#pragma unroll
+    for (int u = 0; u < NBT; ++u) kB[u] = ((t + kNT * u) % KBV) * VEC, cB[u] = ((t + kNT * u) / KBV) * VEC;
     // Byte offsets of the thread's vectors inside an interior tile: independent of the source
     // block and of the K stage (valid when 128 rows of the operands span < 2^31 bytes).  Used
     // for FP32 only: for FP64 the extra live offsets cost more than the address math they save.
@@ -121,7 +126,8 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
 #pragma unroll
     for (int pa = 0; pa < NPA; ++pa) voA[pa] = (uint32_t)(((pa * RPPA + ra) * p.lda + ka) * sizeof(T));
 #pragma unroll
-    for (int pb = 0; pb < NPB; ++pb) voB[pb] = (uint32_t)(((pb * KPPB + kbr) * p.ldb + cb) * sizeof(T));
+    for (int pb = 0; pb < NPB; ++pb)
+        voB[pb] = (uint32_t)(((kB[pb / VEC] + pb % VEC) * p.ldb + cB[pb / VEC]) * sizeof(T));
 
     // Load (with zero fill outside the operand and outside the leaf block) the thread's part
     // of one source block of A at K offset k0; values scaled by 2^(ep_col - ea_row).  Loads
@@ -182,14 +188,15 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
             }
         }
     };
+    // The thread's B blocks of one source block: row pb = u * VEC + vr of v holds k-row
+    // kB[u] + vr, columns cB[u] .. cB[u] + VEC - 1; values scaled by 2^(-ep_row - eb_col).
     auto load_b = [&](const SrcEntry &se, int64_t k0, T (&v)[NPB][VEC]) {
-        const int64_t row0 = (int64_t)se.br * p.kb + k0;           // operand row of k-row 0
-        const int64_t col0 = (int64_t)se.bc * p.nb + tn * BN + cb;  // operand column
-        const bool cfull = (tn * BN + cb + VEC <= p.nb) && (col0 + VEC <= p.n);
-        const bool full = p.vec_b && (tn * BN + BN <= p.nb) && ((int64_t)se.bc * p.nb + tn * BN + BN <= p.n);
+        const int64_t row0 = (int64_t)se.br * p.kb + k0;      // operand row of k-row 0
+        const int64_t colt = (int64_t)se.bc * p.nb + tn * BN;  // operand column of tile column 0
+        const bool full = p.vec_b && (tn * BN + BN <= p.nb) && (colt + BN <= p.n);
         if (kInterior && full && (k0 + BK <= p.kb) && (row0 + BK <= p.k) && p.small_ld) {
             // interior tile: a work-group-uniform base and the thread's fixed 32-bit offsets
-            const char *base = reinterpret_cast<const char *>(p.B + row0 * p.ldb + (int64_t)se.bc * p.nb + tn * BN);
+            const char *base = reinterpret_cast<const char *>(p.B + row0 * p.ldb + colt);
 #pragma unroll
             for (int pb = 0; pb < NPB; ++pb) {
                 const typename C::vec_t x = *reinterpret_cast<const typename C::vec_t *>(
@@ -201,9 +208,9 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
         } else if (full) {
 #pragma unroll
             for (int pb = 0; pb < NPB; ++pb) {
-                const int kr = pb * KPPB + kbr;
+                const int kr = kB[pb / VEC] + pb % VEC;
                 const bool rok = (k0 + kr < p.kb) && (row0 + kr < p.k);
-                const T *src = rok ? p.B + (row0 + kr) * p.ldb + col0 : p.B;
+                const T *src = rok ? p.B + (row0 + kr) * p.ldb + colt + cB[pb / VEC] : p.B;
                 const typename C::vec_t x =
                     *reinterpret_cast<const typename C::vec_t *>(__builtin_assume_aligned(src, 16));
                 const T *xs = reinterpret_cast<const T *>(&x);
@@ -213,12 +220,13 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
         } else {
 #pragma unroll
             for (int pb = 0; pb < NPB; ++pb) {
-                const int kr = pb * KPPB + kbr;
+                const int kr = kB[pb / VEC] + pb % VEC;
                 const bool rok = (k0 + kr < p.kb) && (row0 + kr < p.k);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    const bool ok = rok && (cfull || ((tn * BN + cb + e < p.nb) && (col0 + e < p.n)));
-                    const T x = *(ok ? p.B + (row0 + kr) * p.ldb + col0 + e : p.B);
+                    const int64_t cc = cB[pb / VEC] + e;
+                    const bool ok = rok && (tn * BN + cc < p.nb) && (colt + cc < p.n);
+                    const T x = *(ok ? p.B + (row0 + kr) * p.ldb + colt + cc : p.B);
                     v[pb][e] = ok ? x : T(0);
                 }
             }
@@ -226,13 +234,13 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
         if (SCALED) {
 #pragma unroll
             for (int pb = 0; pb < NPB; ++pb) {
-                const int kr = pb * KPPB + kbr;
+                const int kr = kB[pb / VEC] + pb % VEC;
                 const bool rok = (k0 + kr < p.kb) && (row0 + kr < p.k);
                 const int er = p.sc.ep[rok ? row0 + kr : 0];
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    const bool cok = col0 + e < p.n;
-                    const int ec = p.sc.eb[cok ? col0 + e : 0];
+                    const int64_t col = colt + cB[pb / VEC] + e;
+                    const int ec = p.sc.eb[col < p.n ? col : 0];
                     v[pb][e] = C::scale(v[pb][e], -er - ec);
                 }
             }
@@ -320,19 +328,23 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
     };
     auto store = [&](int s) {
 #pragma unroll
-        for (int pa = 0; pa < NPA; ++pa)
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) As[s][(pa * RPPA + ra) * LDA_S + ka + e] = sa[pa][e];
-#pragma unroll
-        for (int pb = 0; pb < NPB; ++pb) {
+        for (int pa = 0; pa < NPA; ++pa) {
             typename C::vec_t x;
-            if constexpr (VEC == 2) {
-                x.x = sb[pb][0], x.y = sb[pb][1];
-            } else {
-                x.x = sb[pb][0], x.y = sb[pb][1], x.z = sb[pb][2], x.w = sb[pb][3];
-            }
-            *reinterpret_cast<typename C::vec_t *>(&Bs[s][(pb * KPPB + kbr) * LDB_S + cb]) = x;
+            T *xs = reinterpret_cast<T *>(&x);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) xs[e] = sa[pa][e];
+            *reinterpret_cast<typename C::vec_t *>(&As[s][(pa * RPPA + ra) * LDS_K + ka]) = x;
         }
+#pragma unroll
+        for (int u = 0; u < NBT; ++u)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {  // column cB + e, k-rows kB .. kB + VEC - 1
+                typename C::vec_t x;
+                T *xs = reinterpret_cast<T *>(&x);
+#pragma unroll
+                for (int vr = 0; vr < VEC; ++vr) xs[vr] = sb[u * VEC + vr][e];
+                *reinterpret_cast<typename C::vec_t *>(&Bs[s][(cB[u] + e) * LDS_K + kB[u]]) = x;
+            }
     };
 
     typename C::acc_t acc[TM][TN];
@@ -351,23 +363,46 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
         if (more) prefetch((kt + 1) * BK);
         const T *as = As[cur];
         const T *bs = Bs[cur];
+        // Each 16-k chunk takes four MFMA steps; step j uses k = 4g + j of the chunk from lane
+        // group g = lane / 16, so a lane's operands for the four steps are 4 consecutive k of
+        // one tile row: 16-byte LDS reads.
+        const int g4 = 4 * (lane >> 4), l16 = lane & 15;
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 4) {
-            T a[TM], b[TN];
-#pragma unroll
-            for (int i = 0; i < TM; ++i) a[i] = as[(wm * WM + i * 16 + (lane & 15)) * LDA_S + ks + (lane >> 4)];
-#pragma unroll
-            for (int j = 0; j < TN; ++j) b[j] = bs[(ks + (lane >> 4)) * LDB_S + wn * WN + j * 16 + (lane & 15)];
+        for (int h = 0; h < BK / 16; ++h) {
+            T ea[TM][4], eb[TN][4];
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TN; ++j) acc[i][j] = C::mma(a[i], b[j], acc[i][j]);
-            // Half-way through the MFMA work: combine the prefetched sources of the next stage
-            // and write them to the other LDS buffer (last read before the previous barrier),
-            // so the VALU and LDS work overlaps the matrix cores.
-            if (ks == BK / 2 - 4 && more) {
-                finish((kt + 1) * BK);
-                store(cur ^ 1);
+                for (int c = 0; c < 4; c += VEC) {
+                    const typename C::vec_t x = *reinterpret_cast<const typename C::vec_t *>(
+                        &as[(wm * WM + i * 16 + l16) * LDS_K + 16 * h + g4 + c]);
+                    const T *xs = reinterpret_cast<const T *>(&x);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) ea[i][c + e] = xs[e];
+                }
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int c = 0; c < 4; c += VEC) {
+                    const typename C::vec_t x = *reinterpret_cast<const typename C::vec_t *>(
+                        &bs[(wn * WN + j * 16 + l16) * LDS_K + 16 * h + g4 + c]);
+                    const T *xs = reinterpret_cast<const T *>(&x);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) eb[j][c + e] = xs[e];
+                }
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) acc[i][j] = C::mma(ea[i][st], eb[j][st], acc[i][j]);
+                // Half-way through the MFMA work: combine the prefetched sources of the next
+                // stage and write them to the other LDS buffer (last read before the previous
+                // barrier), so the VALU and LDS work overlaps the matrix cores.
+                if (4 * h + st == BK / 8 - 1 && more) {
+                    finish((kt + 1) * BK);
+                    store(cur ^ 1);
+                }
             }
         }
         __syncthreads();

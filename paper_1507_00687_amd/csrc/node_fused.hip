@@ -2,7 +2,7 @@
 // Winograd's variant and their cyclic rotations), FP64 and FP32 on MFMA.
 //
 // The innermost recursion level is done entirely inside one launch.  A work-group owns one
-// 64x64 tile position (tm, tn) of the four output sub-blocks of one node of the recursion tree
+// 64x64 (FP32) or 64x32 (FP64) tile position (tm, tn) of the four output sub-blocks of one node of the recursion tree
 // (the node is the whole problem at depth 1; at depth L it is one of the R^(L-1) products of the
 // outer levels).  Per K stage it loads the matching tiles of the node's four A sub-blocks and
 // four B sub-blocks into LDS once -- each node operand being the sum of its outer-level sources,
@@ -38,7 +38,7 @@ template <>
 struct NCore<double> {
     typedef nd4 acc_t;
     typedef double2 vec_t;
-    static constexpr int VEC = 2, OCC = 1;
+    static constexpr int VEC = 2, OCC = 1, BK = 16, TN = 2;
     __device__ static acc_t mma(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -50,7 +50,7 @@ template <>
 struct NCore<float> {
     typedef nf4 acc_t;
     typedef float4 vec_t;
-    static constexpr int VEC = 4, OCC = 2;
+    static constexpr int VEC = 4, OCC = 2, BK = 16, TN = 2;
     __device__ static acc_t mma(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -73,7 +73,7 @@ struct NArgs {
     int64_t node_stride;  // elements between node products in the workspace
     ScaleExps sc;
     int vec_a, vec_b;  // 16-byte loads allowed (alignment of pointers, ld and block sizes)
-    int small_ld;      // 64 rows of A and 16 rows of B span < 2^31 bytes
+    int small_ld;      // a 64-row tile of A and a BK-row tile of B span < 2^31 bytes
 };
 
 // Coefficient of row s, column r of a {0, +1, -1} pattern.
@@ -108,15 +108,22 @@ template <typename T, bool SCALED, uint32_t UP, uint32_t UN, uint32_t VP, uint32
 __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
     typedef NCore<T> C;
     typedef typename C::vec_t vec_t;
-    constexpr int BM = 64, BN = 64, BK = 16, VEC = C::VEC;
+    constexpr int TM = 2, TN = C::TN;  // 16x16 MFMA blocks per wave and product
+    constexpr int BM = 32 * TM, BN = 32 * TN, BK = C::BK, VEC = C::VEC;
+    constexpr int KPL = BK / 4;  // consecutive k per lane group and stage
     constexpr int TPRA = BK / VEC, RPPA = kNT / TPRA, NPA = BM / RPPA;  // A: threads/row, rows/pass
-    constexpr int TPRB = BN / VEC, KPPB = kNT / TPRB, NPB = BK / KPPB;  // B: threads/k-row, k-rows/pass
-    constexpr int LDA_S = BK + 1, LDB_S = BN + 16;
-    constexpr int TM = 2, TN = 2;  // 16x16 MFMA blocks per wave and product (wave tile 32x32)
-    static_assert(NPA * RPPA == BM && NPB * KPPB == BK, "tile shape");
+    // B is loaded in VEC x VEC blocks (VEC k-rows by VEC columns) and stored transposed, one
+    // 16-byte LDS write per column; consecutive lanes take consecutive k-blocks, which keeps
+    // both the global reads (whole row segments) and the LDS writes free of conflicts.
+    constexpr int KBV = BK / VEC, CBV = BN / VEC, NBT = 4 * KBV * CBV / kNT;  // B: blocks per thread
+    // LDS tiles are k-contiguous for both operands (B stored transposed), rows padded to a
+    // 16-byte multiple that spreads consecutive rows over the banks.
+    constexpr int LDS_K = BK + 16 / (int)sizeof(T);
+    static_assert(NPA * RPPA == BM && NBT * kNT == 4 * KBV * CBV, "tile shape");
+    static_assert((LDS_K * sizeof(T)) % 16 == 0 && KPL % VEC == 0, "row alignment");
 
-    __shared__ T As[2][4][BM * LDA_S];
-    __shared__ __attribute__((aligned(16))) T Bs[2][4][BK * LDB_S];
+    __shared__ __attribute__((aligned(16))) T As[2][4][BM * LDS_K];
+    __shared__ __attribute__((aligned(16))) T Bs[2][4][BN * LDS_K];
 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -137,22 +144,44 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
     le.b_count = __builtin_amdgcn_readfirstlane(le.b_count);
 
     const int ra = t / TPRA, ka = (t % TPRA) * VEC;   // A: row within pass, k offset
-    const int kbr = t / TPRB, cb = (t % TPRB) * VEC;  // B: k-row within pass, column offset
+    int sB[NBT], kB[NBT], cB[NBT];  // B: the thread's blocks (sub-block, k offset, column offset)
+#pragma unroll
+    for (int u = 0; u < NBT; ++u) {
+        const int idx = t + kNT * u, b = idx % (KBV * CBV);
+        sB[u] = idx / (KBV * CBV), kB[u] = (b % KBV) * VEC, cB[u] = (b / KBV) * VEC;
+    }
     const int64_t mb2 = 2 * p.mb, kb2 = 2 * p.kb, nb2 = 2 * p.nb;
-    const bool a_rows_in = tm * BM + BM <= p.mb;
-    const bool b_cols_in = tn * BN + BN <= p.nb;
-    // byte offsets of the thread's vectors inside an interior tile (independent of the source,
-    // the sub-block and the K stage)
-    uint32_t voA[NPA], voB[NPB];
+
+    // Stages with k0 + BK <= kfast read whole tiles with vector loads and no bounds checks:
+    // every source tile of this work-group lies inside its sub-block and inside the operand.
+    int64_t kfast = (p.vec_a && p.vec_b && p.small_ld && tm * BM + BM <= p.mb && tn * BN + BN <= p.nb) ? p.kb : 0;
+    for (int q = 0; q < le.a_count && kfast > 0; ++q) {
+        const SrcEntry se = p.asrc[le.a_begin + q];
+        for (int s = 0; s < 4; ++s) {
+            if ((int64_t)se.br * mb2 + (s & 1) * p.mb + tm * BM + BM > p.m) kfast = 0;
+            kfast = min(kfast, p.k - ((int64_t)se.bc * kb2 + (s >> 1) * p.kb));
+        }
+    }
+    for (int q = 0; q < le.b_count && kfast > 0; ++q) {
+        const SrcEntry se = p.bsrc[le.b_begin + q];
+        for (int s = 0; s < 4; ++s) {
+            if ((int64_t)se.bc * nb2 + (s >> 1) * p.nb + tn * BN + BN > p.n) kfast = 0;
+            kfast = min(kfast, p.k - ((int64_t)se.br * kb2 + (s & 1) * p.kb));
+        }
+    }
+    kfast = __builtin_amdgcn_readfirstlane(kfast);
+    // byte offsets of the thread's vectors inside a tile (the same for every source, sub-block
+    // and K stage)
+    uint32_t voA[NPA], voB[NBT];
 #pragma unroll
     for (int pa = 0; pa < NPA; ++pa) voA[pa] = (uint32_t)(((pa * RPPA + ra) * p.lda + ka) * sizeof(T));
 #pragma unroll
-    for (int pb = 0; pb < NPB; ++pb) voB[pb] = (uint32_t)(((pb * KPPB + kbr) * p.ldb + cb) * sizeof(T));
+    for (int u = 0; u < NBT; ++u) voB[u] = (uint32_t)((kB[u] * p.ldb + cB[u]) * sizeof(T));
 
     // The thread's part of the A tiles of the four node sub-blocks at K offset k0: the sum over
     // the node's sources of coef * 2^(ep_col - ea_row) * A, zero outside A and the sub-block.
     auto load_a = [&](int64_t k0, T (&v)[4][NPA][VEC]) {
-        const bool k_in = k0 + BK <= p.kb;
+        const bool fast = k0 + BK <= kfast;
         for (int q = 0; q < le.a_count; ++q) {
             const SrcEntry se = p.asrc[le.a_begin + q];
             const T c = (T)se.coef;
@@ -161,7 +190,7 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
                 const int64_t row0 = (int64_t)se.br * mb2 + (s & 1) * p.mb + tm * BM;
                 const int64_t cbase = (int64_t)se.bc * kb2 + (s >> 1) * p.kb + k0;
                 T x[NPA][VEC];
-                if (p.vec_a && p.small_ld && k_in && a_rows_in && cbase + BK <= p.k && row0 + BM <= p.m) {
+                if (fast) {
                     const char *base = reinterpret_cast<const char *>(p.A + row0 * p.lda + cbase);
 #pragma unroll
                     for (int pa = 0; pa < NPA; ++pa) {
@@ -203,75 +232,85 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
             }
         }
     };
-    // Likewise for B: 2^(-ep_row - eb_col) * B.
-    auto load_b = [&](int64_t k0, T (&v)[4][NPB][VEC]) {
-        const bool k_in = k0 + BK <= p.kb;
+    // The thread's B blocks at K offset k0: the sum over the node's sources of
+    // coef * 2^(-ep_row - eb_col) * B, zero outside B and the sub-block.
+    auto load_b = [&](int64_t k0, T (&v)[NBT][VEC][VEC]) {
+        const bool fast = k0 + BK <= kfast;
         for (int q = 0; q < le.b_count; ++q) {
             const SrcEntry se = p.bsrc[le.b_begin + q];
             const T c = (T)se.coef;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int64_t row0 = (int64_t)se.br * kb2 + (s & 1) * p.kb + k0;
-                const int64_t cbase = (int64_t)se.bc * nb2 + (s >> 1) * p.nb + tn * BN;
-                T x[NPB][VEC];
-                if (p.vec_b && p.small_ld && k_in && b_cols_in && cbase + BN <= p.n && row0 + BK <= p.k) {
-                    const char *base = reinterpret_cast<const char *>(p.B + row0 * p.ldb + cbase);
+            for (int u = 0; u < NBT; ++u) {
+                const int sb = sB[u];
+                const int64_t row0 = (int64_t)se.br * kb2 + (sb & 1) * p.kb + k0;        // k-row of block row 0
+                const int64_t cbase = (int64_t)se.bc * nb2 + (sb >> 1) * p.nb + tn * BN;  // column of tile column 0
+                T x[VEC][VEC];
+                if (fast) {
+                    const char *base = reinterpret_cast<const char *>(p.B + row0 * p.ldb + cbase) + voB[u];
 #pragma unroll
-                    for (int pb = 0; pb < NPB; ++pb) {
-                        const vec_t w = *reinterpret_cast<const vec_t *>(__builtin_assume_aligned(base + voB[pb], 16));
+                    for (int vr = 0; vr < VEC; ++vr) {
+                        const vec_t w = *reinterpret_cast<const vec_t *>(
+                            __builtin_assume_aligned(base + (size_t)vr * p.ldb * sizeof(T), 16));
                         const T *ws = reinterpret_cast<const T *>(&w);
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) x[pb][e] = ws[e];
+                        for (int e = 0; e < VEC; ++e) x[vr][e] = ws[e];
                     }
                 } else {
 #pragma unroll
-                    for (int pb = 0; pb < NPB; ++pb) {
-                        const int kr = pb * KPPB + kbr;
+                    for (int vr = 0; vr < VEC; ++vr) {
+                        const int kr = kB[u] + vr;
                         const bool rok = (k0 + kr < p.kb) && (row0 + kr < p.k);
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) {
-                            const bool ok = rok && (tn * BN + cb + e < p.nb) && (cbase + cb + e < p.n);
-                            const T y = *(ok ? p.B + (row0 + kr) * p.ldb + cbase + cb + e : p.B);
-                            x[pb][e] = ok ? y : T(0);
+                            const int cc = cB[u] + e;
+                            const bool ok = rok && (tn * BN + cc < p.nb) && (cbase + cc < p.n);
+                            const T y = *(ok ? p.B + (row0 + kr) * p.ldb + cbase + cc : p.B);
+                            x[vr][e] = ok ? y : T(0);
                         }
                     }
                 }
                 if (SCALED) {
 #pragma unroll
-                    for (int pb = 0; pb < NPB; ++pb) {
-                        const int64_t row = row0 + pb * KPPB + kbr;
+                    for (int vr = 0; vr < VEC; ++vr) {
+                        const int64_t row = row0 + kB[u] + vr;
                         const int er = p.sc.ep[row < p.k ? row : 0];
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) {
-                            const int64_t col = cbase + cb + e;
-                            x[pb][e] = C::scale(x[pb][e], -er - p.sc.eb[col < p.n ? col : 0]);
+                            const int64_t col = cbase + cB[u] + e;
+                            x[vr][e] = C::scale(x[vr][e], -er - p.sc.eb[col < p.n ? col : 0]);
                         }
                     }
                 }
 #pragma unroll
-                for (int pb = 0; pb < NPB; ++pb)
+                for (int vr = 0; vr < VEC; ++vr)
 #pragma unroll
                     for (int e = 0; e < VEC; ++e)
-                        v[s][pb][e] = (q == 0) ? c * x[pb][e] : v[s][pb][e] + c * x[pb][e];
+                        v[u][vr][e] = (q == 0) ? c * x[vr][e] : v[u][vr][e] + c * x[vr][e];
             }
         }
     };
-    auto store = [&](int st, const T (&va)[4][NPA][VEC], const T (&vb)[4][NPB][VEC]) {
+    auto store = [&](int st, const T (&va)[4][NPA][VEC], const T (&vb)[NBT][VEC][VEC]) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
 #pragma unroll
-            for (int pa = 0; pa < NPA; ++pa)
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) As[st][s][(pa * RPPA + ra) * LDA_S + ka + e] = va[s][pa][e];
-#pragma unroll
-            for (int pb = 0; pb < NPB; ++pb) {
+            for (int pa = 0; pa < NPA; ++pa) {
                 vec_t x;
                 T *xs = reinterpret_cast<T *>(&x);
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) xs[e] = vb[s][pb][e];
-                *reinterpret_cast<vec_t *>(&Bs[st][s][(pb * KPPB + kbr) * LDB_S + cb]) = x;
+                for (int e = 0; e < VEC; ++e) xs[e] = va[s][pa][e];
+                *reinterpret_cast<vec_t *>(&As[st][s][(pa * RPPA + ra) * LDS_K + ka]) = x;
             }
         }
+#pragma unroll
+        for (int u = 0; u < NBT; ++u)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {  // column cB + e, k-rows kB .. kB + VEC - 1
+                vec_t x;
+                T *xs = reinterpret_cast<T *>(&x);
+#pragma unroll
+                for (int vr = 0; vr < VEC; ++vr) xs[vr] = vb[u][vr][e];
+                *reinterpret_cast<vec_t *>(&Bs[st][sB[u]][(cB[u] + e) * LDS_K + kB[u]]) = x;
+            }
     };
 
     typename C::acc_t acc[7][TM][TN];
@@ -282,12 +321,15 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
 #pragma unroll
             for (int j = 0; j < TN; ++j) acc[r][i][j] = typename C::acc_t{};
 
-    T va[4][NPA][VEC], vb[4][NPB][VEC];
+    T va[4][NPA][VEC], vb[NBT][VEC][VEC];
     const int64_t nk = (p.kb + BK - 1) / BK;
     load_a(0, va);
     load_b(0, vb);
     store(0, va, vb);
     __syncthreads();
+    // MFMA step j of a stage takes k = KPL g + j from lane group g = lane / 16, so each lane's
+    // operands for the KPL steps are KPL consecutive k of one tile row: 16-byte LDS reads.
+    const int g4 = KPL * (lane >> 4), l16 = lane & 15;
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int cur = (int)(kt & 1);
         const bool more = kt + 1 < nk;
@@ -296,29 +338,47 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
             load_b((kt + 1) * BK, vb);
         }
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 4) {
-            T ea[TM][4], eb[TN][4];  // this lane's element of each sub-block tile, per 16-block
+        for (int jh = 0; jh < KPL / VEC; ++jh) {
+            T ea[TM][4][VEC], eb[TN][4][VEC];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
 #pragma unroll
-                for (int i = 0; i < TM; ++i)
-                    ea[i][s] = As[cur][s][(wm * 32 + i * 16 + (lane & 15)) * LDA_S + ks + (lane >> 4)];
+                for (int i = 0; i < TM; ++i) {
+                    const vec_t w = *reinterpret_cast<const vec_t *>(
+                        &As[cur][s][(wm * 16 * TM + i * 16 + l16) * LDS_K + g4 + jh * VEC]);
+                    const T *ws = reinterpret_cast<const T *>(&w);
 #pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    eb[j][s] = Bs[cur][s][(ks + (lane >> 4)) * LDB_S + wn * 32 + j * 16 + (lane & 15)];
+                    for (int e = 0; e < VEC; ++e) ea[i][s][e] = ws[e];
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const vec_t w = *reinterpret_cast<const vec_t *>(
+                        &Bs[cur][s][(wn * 16 * TN + j * 16 + l16) * LDS_K + g4 + jh * VEC]);
+                    const T *ws = reinterpret_cast<const T *>(&w);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) eb[j][s][e] = ws[e];
+                }
             }
 #pragma unroll
-            for (int r = 0; r < 7; ++r) {
-                T a[TM], b[TN];
+            for (int e = 0; e < VEC; ++e)
 #pragma unroll
-                for (int i = 0; i < TM; ++i) a[i] = psum<UP, UN>(r, ea[i]);
+                for (int r = 0; r < 7; ++r) {
+                    T a[TM], b[TN];
 #pragma unroll
-                for (int j = 0; j < TN; ++j) b[j] = psum<VP, VN>(r, eb[j]);
+                    for (int i = 0; i < TM; ++i) {
+                        const T x[4] = {ea[i][0][e], ea[i][1][e], ea[i][2][e], ea[i][3][e]};
+                        a[i] = psum<UP, UN>(r, x);
+                    }
 #pragma unroll
-                for (int i = 0; i < TM; ++i)
+                    for (int j = 0; j < TN; ++j) {
+                        const T x[4] = {eb[j][0][e], eb[j][1][e], eb[j][2][e], eb[j][3][e]};
+                        b[j] = psum<VP, VN>(r, x);
+                    }
 #pragma unroll
-                    for (int j = 0; j < TN; ++j) acc[r][i][j] = C::mma(a[i], b[j], acc[r][i][j]);
-            }
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) acc[r][i][j] = C::mma(a[i], b[j], acc[r][i][j]);
+                }
         }
         if (more) store(cur ^ 1, va, vb);  // the other buffer was last read before the previous barrier
         __syncthreads();
@@ -347,8 +407,8 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
                         else val = (c > 0) ? val + mr[r] : val - mr[r];
                         first = false;
                     }
-                    const int64_t lr = tm * BM + wm * 32 + i * 16 + C::row(lane, v);  // inside the sub-block
-                    const int64_t lc = tn * BN + wn * 32 + j * 16 + (lane & 15);
+                    const int64_t lr = tm * BM + wm * 16 * TM + i * 16 + C::row(lane, v);  // inside the sub-block
+                    const int64_t lc = tn * BN + wn * 16 * TN + j * 16 + (lane & 15);
                     if (lr >= p.mb || lc >= p.nb) continue;
                     const int64_t row = rsub + lr, col = csub + lc;  // inside the node's output
                     if (p.node_stride == 0) {  // depth 1: the node is the whole product
@@ -393,8 +453,9 @@ hipError_t node_go(const NodeLaunch &L, hipStream_t s) {
     a.lda = L.lda, a.ldb = L.ldb, a.ldo = L.ldo;
     a.m = L.m, a.k = L.k, a.n = L.n;
     a.mb = L.mb, a.kb = L.kb, a.nb = L.nb;
+    constexpr int BN = 32 * NCore<T>::TN;
     a.tiles_m = (int)((L.mb + 63) / 64);
-    a.tiles_n = (int)((L.nb + 63) / 64);
+    a.tiles_n = (int)((L.nb + BN - 1) / BN);
     a.outer = L.outer, a.asrc = L.asrc, a.bsrc = L.bsrc;
     a.node_stride = L.node_stride;
     a.sc = L.sc;

@@ -49,7 +49,8 @@ def test_fused_integer_inputs_bit_exact(precision, name, depth, shape):
 @pytest.mark.parametrize("shape", [(256, 256, 256), (300, 200, 260)])
 def test_fused_equals_leaf_path_at_depth_one(precision, name, scaling, shape):
     # At one level both paths form each S_r, T_r element with the same operations in the same
-    # order, accumulate over k in the same MFMA sequence and sum the W terms in ascending r.
+    # order, run the same MFMA sequence over k (the same k-interleave in every 16-k chunk) and
+    # sum the W terms in ascending r: the results are bitwise equal.
     m, k, n = shape
     print(f"\n[fused=leaf] {name} {precision} {scaling} {shape}", flush=True)
     dist = "badly_scaled" if scaling != "none" else "normal"
