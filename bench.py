@@ -47,10 +47,11 @@ def parse():
     ap.add_argument("--dist", default="normal")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--err-rows", type=int, default=16)
-    ap.add_argument("--cpu-n", type=int, default=4096, help="size of the oracle timing sample")
+    ap.add_argument("--cpu-n", type=int, default=8192, help="size of the oracle timing sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classical", action="store_true")
-    ap.add_argument("--no-fuse", action="store_true", help="force the leaf-products + W-combination path")
+    ap.add_argument("--fuse", default="auto", choices=["auto", "off", "always"],
+                    help="fusion mode of the plan (off: leaf products + W-combination)")
     ap.add_argument("--torch-ref", action="store_true",
                     help="also time torch.matmul (vendor BLAS) on the same operands, as context")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -151,7 +152,7 @@ def main():
     tA = torch.from_numpy(A).cuda()
     tB = torch.from_numpy(B).cuda()
     plan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
-                  precision=args.precision, fuse=not args.no_fuse)
+                  precision=args.precision, fuse=args.fuse)
     L, Mp, Kp, Np = plan.shape(m, k, n)
     path = plan.path(m, k, n)
     kname, ksource = product_kernel(args.precision, path)

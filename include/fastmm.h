@@ -144,13 +144,21 @@ typedef enum {
                               recursion; the outer L-1 levels as in the leaf path */
 } fastmm_path;
 
-/* Allow (enable != 0, the default) or forbid the fused path for this plan and the rotated
- * sub-plans of its backward pass.  The fused path applies to FP64 and FP32 plans with at
- * least one level, row-major (non-transposed) operands, and a <2,2,2;7> rule whose
- * coefficients are all 0 or +-1 and whose sign pattern has a compiled kernel (Strassen's
- * rule, Winograd's variant and their cyclic rotations).  Both paths give the same result in
- * exact arithmetic; at one level with both operands in range they round identically. */
-fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int enable);
+/* Fusion modes (fastmm_plan_set_fusion). */
+typedef enum {
+    FASTMM_FUSE_OFF = 0,    /* always the leaf path */
+    FASTMM_FUSE_AUTO = 1,   /* the default: the fused path where it applies and is the faster one
+                               (FP32 from depth 1, FP64 from depth 2) */
+    FASTMM_FUSE_ALWAYS = 2  /* the fused path wherever it applies */
+} fastmm_fusion;
+
+/* Set the fusion mode (fastmm_fusion) of this plan and of the rotated sub-plans of its backward
+ * pass; FASTMM_EINVAL for an unknown mode.  The fused path applies to FP64 and FP32 plans with
+ * at least one level, row-major (non-transposed) operands, and a <2,2,2;7> rule whose
+ * coefficients are all 0 or +-1 and whose sign pattern has a compiled kernel (Strassen's rule,
+ * Winograd's variant and their cyclic rotations).  Both paths compute the same result in exact
+ * arithmetic; at depth 1 they round identically (bitwise equal results). */
+fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode);
 
 /* The path (fastmm_path) fastmm_gemm_ex takes for this shape and these transposition flags. */
 fastmm_status fastmm_plan_path(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, int transA,

@@ -207,7 +207,7 @@ struct fastmm_plan_s {
     int cutoff = 1;
     fastmm_scaling sc{0, 0, 0.0};
     int prec = FASTMM_F64;
-    int fuse = 1;  // use the fused one-level kernel where it applies
+    int fuse = FASTMM_FUSE_AUTO;  // fastmm_fusion
     std::mutex mu;
     std::map<std::pair<int, int>, std::unique_ptr<fastmm::Tables>> tables;  // (L, device)
     // Sub-plans with the rotated rules, made on first use by the backward pass.
@@ -317,10 +317,14 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
 }
 
 // Whether a product takes the fused one-level kernel: FP64/FP32, at least one level, row-major
-// operands and a rule with a compiled sign pattern.
+// operands and a rule with a compiled sign pattern.  FASTMM_FUSE_AUTO leaves FP64 at depth 1
+// on the leaf path, whose 128x128 tiles run faster there (measured on MI355X: 44 against 40
+// effective TFLOP/s for Strassen at n = 8192); from depth 2 on, saving the leaf products'
+// round trip through memory wins.
 bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, uint32_t masks[6]) {
-    if (!p->fuse || s.L < 1 || transA || transB) return false;
+    if (p->fuse == FASTMM_FUSE_OFF || s.L < 1 || transA || transB) return false;
     if (p->prec != FASTMM_F64 && p->prec != FASTMM_F32) return false;
+    if (p->fuse == FASTMM_FUSE_AUTO && p->prec == FASTMM_F64 && s.L < 2) return false;
     return rule_masks_222(plan_algo(p), masks) && node222_supported(masks);
 }
 
@@ -561,10 +565,11 @@ fastmm_status fastmm_plan_shape(fastmm_plan_t plan, int64_t m, int64_t k, int64_
     return FASTMM_OK;
 }
 
-fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int enable) {
+fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode) {
     if (check_plan(plan)) return FASTMM_EINVAL;
+    if (mode < FASTMM_FUSE_OFF || mode > FASTMM_FUSE_ALWAYS) return fail(FASTMM_EINVAL, "unknown fusion mode");
     std::lock_guard<std::mutex> g(plan->mu);
-    plan->fuse = enable ? 1 : 0;
+    plan->fuse = mode;
     for (auto &r : plan->rot)
         if (r) r->fuse = plan->fuse;
     return FASTMM_OK;

@@ -28,6 +28,7 @@ ALGOS = {
     "f244": 8,
     "laderman333": 9,
 }
+FUSION = {"off": 0, "auto": 1, "always": 2}
 SCALE_MODES = {"none": 0, "outside": 1, "inside": 2, "out_in": 3, "in_out": 4, "repeated": 5}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4, "f16x3": 5, "bf16x6": 6}
 
@@ -149,7 +150,7 @@ class Plan:
     """A fastmm plan: algorithm, recursion depth, cutoff, scaling procedure, precision."""
 
     def __init__(self, algo="strassen", depth: int = 1, cutoff: int = 1, scaling: str = "none",
-                 steps: int = 2, tau: float = 0.0, precision: str = "f64", fuse: bool = True):
+                 steps: int = 2, tau: float = 0.0, precision: str = "f64", fuse="auto"):
         self.algo, self.depth, self.cutoff = algo, depth, cutoff
         self.scaling, self.steps, self.tau, self.precision = scaling, steps, tau, precision
         self.fuse = fuse
@@ -157,8 +158,9 @@ class Plan:
         sc = _Scaling(_id(SCALE_MODES, scaling), steps, tau)
         _check(lib().fastmm_plan_create(ctypes.byref(self._h), _id(ALGOS, algo), depth, cutoff, ctypes.byref(sc),
                                         _id(PRECISIONS, precision)))
-        if not fuse:
-            _check(lib().fastmm_plan_set_fusion(self._h, 0))
+        mode = FUSION[fuse] if isinstance(fuse, str) else (FUSION["auto"] if fuse else FUSION["off"])
+        if mode != FUSION["auto"]:
+            _check(lib().fastmm_plan_set_fusion(self._h, mode))
 
     def path(self, m: int, k: int, n: int, transA: bool = False, transB: bool = False) -> str:
         """'fused' or 'leaf': the execution path of an m x k by k x n product."""

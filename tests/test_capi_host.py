@@ -126,7 +126,9 @@ def _int_rows(M):
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_fused_path_selection(F, precision):
     P = lambda name, depth, cutoff=1, **kw: F.Plan(name, depth, cutoff, precision=precision, **kw)
-    assert P("strassen", 1).path(256, 256, 256) == "fused"
+    # FP64 at depth 1 stays on the leaf path unless fusion is forced
+    assert P("strassen", 1).path(256, 256, 256) == ("fused" if precision == "f32" else "leaf")
+    assert P("strassen", 1, fuse="always").path(256, 256, 256) == "fused"
     assert P("winograd", 3).path(300, 200, 100) == "fused"
     assert P("strassen", 2).path(17, 300, 41) == "fused"
     # transposed operands, no level, cutoff stopping at depth 0, other rules, fusion off
@@ -136,7 +138,11 @@ def test_fused_path_selection(F, precision):
     assert P("strassen", 2, 512).path(256, 256, 256) == "leaf"
     assert P("f323", 1).path(300, 200, 300) == "leaf"
     assert P("laderman333", 1).path(300, 300, 300) == "leaf"
-    assert P("strassen", 1, fuse=False).path(256, 256, 256) == "leaf"
+    assert P("strassen", 2, fuse=False).path(256, 256, 256) == "leaf"
+    assert P("strassen", 2, fuse="off").path(256, 256, 256) == "leaf"
+    plan = P("strassen", 1)
+    with pytest.raises(F.FastmmError):
+        F.fastmm._check(F.fastmm.lib().fastmm_plan_set_fusion(plan.handle, 3))
     assert F.Plan("strassen", 1, 1, precision="bf16x3").path(256, 256, 256) == "leaf"
 
 
@@ -151,6 +157,7 @@ def test_fused_path_matches_rules_by_coefficients(F):
                 r = C.rotate(r)
             uid = F.fastmm_algo_register(2, 2, 2, 7, _int_rows(r.U), _int_rows(r.V), _int_rows(r.W), 0)
             assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "fused", (name, t)
+            assert F.Plan(uid, 2, 1, precision="f64").path(128, 128, 128) == "fused", (name, t)
     a = C.strassen()
     perm = [1, 0, 2, 3, 4, 5, 6]
     U, V, W = (_int_rows(M)[:, perm] for M in (a.U, a.V, a.W))

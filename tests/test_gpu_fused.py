@@ -23,7 +23,7 @@ SHAPES = [
 ]
 
 
-def _plan(name, depth, precision, fuse=True, scaling="none", cutoff=1):
+def _plan(name, depth, precision, fuse="always", scaling="none", cutoff=1):
     import paper_1507_00687_amd as F
 
     return F.Plan(name, depth, cutoff, precision=precision, scaling=scaling, fuse=fuse)
@@ -55,8 +55,8 @@ def test_fused_equals_leaf_path_at_depth_one(precision, name, scaling, shape):
     print(f"\n[fused=leaf] {name} {precision} {scaling} {shape}", flush=True)
     dist = "badly_scaled" if scaling != "none" else "normal"
     A, B = make_pair(dist, 11, m, k, n, dtype=np_dtype(precision))
-    Cf = run_gpu(_plan(name, 1, precision, True, scaling), A, B)
-    Cl = run_gpu(_plan(name, 1, precision, False, scaling), A, B)
+    Cf = run_gpu(_plan(name, 1, precision, "always", scaling), A, B)
+    Cl = run_gpu(_plan(name, 1, precision, "off", scaling), A, B)
     assert np.array_equal(Cf, Cl)
 
 
