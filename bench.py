@@ -78,7 +78,7 @@ def product_kernel(precision: str, path: str):
         return "fmm_node222", "node_fused.hip"
     if precision in ("f64", "f32"):
         return "fmm_leaf_pipelined", "leaf_mfma.hip"
-    return "fmm_leaf_split", "leaf_split.hip"
+    return "fmm_limb_gemm", "limb_gemm.hip"
 
 
 def kernel_source_hash(source: str) -> str:
@@ -235,7 +235,8 @@ def main():
         "torch_matmul": torch_ref,
         "speedup_vs_classical": (classical["ms_per_step"] / ms) if classical else None,
         "error": err,
-        "phases_ms": {"scaling": prof["scaling_ms"] / calls, "leaf": leaf_ms, "combine": prof["combine_ms"] / calls},
+        "phases_ms": {"scaling": prof["scaling_ms"] / calls, "form": prof["form_ms"] / calls, "leaf": leaf_ms,
+                      "combine": prof["combine_ms"] / calls},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": load_traffic(workload, ksource),
                      "kernel": kname, "flops_per_launch": flops_per_launch},

@@ -22,15 +22,17 @@ namespace fastmm {
 namespace {
 thread_local std::string g_last_error;
 
-// Phase timing (fastmm_profile_enable): events recorded around each phase of each call.
+// Phase timing (fastmm_profile_enable): events recorded around each phase of each call:
+// scaling, operand formation (split precisions), products, W-combination.
+constexpr int kPhases = 4;
 struct PhaseEvents {
-    hipEvent_t ev[4];
+    hipEvent_t ev[kPhases + 1];
 };
 struct Profiler {
     bool on = false;
     std::vector<PhaseEvents> pending;
     std::vector<hipEvent_t> pool;
-    double ms[3] = {0, 0, 0};
+    double ms[kPhases] = {0, 0, 0, 0};
     int calls = 0;
     hipEvent_t get() {
         if (!pool.empty()) {
@@ -283,15 +285,30 @@ bool rule_masks_222(const Algo &a, uint32_t m[6]) {
 
 bool is_split(int prec) { return prec >= FASTMM_BF16 && prec <= FASTMM_BF16X6; }
 
-int64_t round4(int64_t x) { return (x + 3) / 4 * 4; }
-
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Split-precision plane sizes: limbs per element, limb-GEMM tile rows, plane rows (A side,
+// B side) and plane row length, all padded to the GEMM and formation tiles.
+struct SplitDims {
+    int nl, bm;
+    int64_t mbp, nbp, kp;
+};
+
+int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+SplitDims split_dims(int prec, const Shape &s) {
+    SplitDims d;
+    d.nl = limb_count(prec);
+    d.bm = limb_gemm_bm(prec, s.mb);
+    d.mbp = round_up(s.mb, d.bm), d.nbp = round_up(s.nb, 128), d.kp = round_up(s.kb, 64);
+    return d;
+}
+
 // Workspace layout: [ea m][ep k][eb n][flags 2] int32 | [maxA max(m,k)][maxB max(k,n)] elems |
-// split precisions: [A copy m x k][B^T n x k] floats (row stride round4(k)) |
-// [leaf products nleaves * mb * nb] elems.
+// split precisions: [S limb planes][T^T limb planes] 16-bit | [leaf products nleaves * mb * nb]
+// elems.
 struct WsLayout {
-    size_t ea, ep, eb, flags, maxA, maxB, at, bt, leaves, total;
+    size_t ea, ep, eb, flags, maxA, maxB, sp, tp, leaves, total;
 };
 
 WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n) {
@@ -307,8 +324,10 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
         w.maxB = off, off = align256(off + es * (size_t)std::max(k, n));
     }
     if (is_split(p->prec)) {
-        w.at = off, off = align256(off + 4 * (size_t)m * round4(k));
-        w.bt = off, off = align256(off + 4 * (size_t)n * round4(k));
+        const SplitDims d = split_dims(p->prec, s);
+        const size_t nleaves = (size_t)leaf_count(plan_algo(p), s.L);
+        w.sp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.mbp * d.kp);
+        w.tp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.nbp * d.kp);
     }
     w.leaves = off;
     if (s.L > 0) off = align256(off + es * (size_t)leaf_count(plan_algo(p), s.L) * s.mb * s.nb);
@@ -451,23 +470,25 @@ fastmm_status fastmm_profile_enable(int enable) {
     return FASTMM_OK;
 }
 
-fastmm_status fastmm_profile_read(double *ms_scaling, double *ms_leaf, double *ms_combine, int *calls) {
+fastmm_status fastmm_profile_read(double *ms_scaling, double *ms_form, double *ms_leaf, double *ms_combine,
+                                  int *calls) {
     for (PhaseEvents &pe : g_prof.pending) {
-        hipError_t e = hipEventSynchronize(pe.ev[3]);
+        hipError_t e = hipEventSynchronize(pe.ev[kPhases]);
         if (e != hipSuccess) return hip_fail(e, "profile sync");
-        for (int ph = 0; ph < 3; ++ph) {
+        for (int ph = 0; ph < kPhases; ++ph) {
             float t = 0.f;
             if (hipEventElapsedTime(&t, pe.ev[ph], pe.ev[ph + 1]) == hipSuccess) g_prof.ms[ph] += t;
         }
-        for (int i = 0; i < 4; ++i) g_prof.pool.push_back(pe.ev[i]);
+        for (int i = 0; i <= kPhases; ++i) g_prof.pool.push_back(pe.ev[i]);
         ++g_prof.calls;
     }
     g_prof.pending.clear();
     if (ms_scaling) *ms_scaling = g_prof.ms[0];
-    if (ms_leaf) *ms_leaf = g_prof.ms[1];
-    if (ms_combine) *ms_combine = g_prof.ms[2];
+    if (ms_form) *ms_form = g_prof.ms[1];
+    if (ms_leaf) *ms_leaf = g_prof.ms[2];
+    if (ms_combine) *ms_combine = g_prof.ms[3];
     if (calls) *calls = g_prof.calls;
-    g_prof.ms[0] = g_prof.ms[1] = g_prof.ms[2] = 0;
+    for (double &x : g_prof.ms) x = 0;
     g_prof.calls = 0;
     return FASTMM_OK;
 }
@@ -630,7 +651,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     PhaseEvents pe{};
     const bool prof = g_prof.on;
     if (prof) {
-        for (int i = 0; i < 4; ++i) pe.ev[i] = g_prof.get();
+        for (int i = 0; i <= kPhases; ++i) pe.ev[i] = g_prof.get();
         (void)hipEventRecord(pe.ev[0], st);
     }
     struct Finish {  // records the remaining phase marks on every exit path
@@ -639,11 +660,11 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         hipStream_t st;
         int next = 1;
         void mark() {
-            if (prof && next < 4) (void)hipEventRecord(pe->ev[next++], st);
+            if (prof && next <= kPhases) (void)hipEventRecord(pe->ev[next++], st);
         }
         ~Finish() {
             if (!prof) return;
-            while (next < 4) (void)hipEventRecord(pe->ev[next++], st);
+            while (next <= kPhases) (void)hipEventRecord(pe->ev[next++], st);
             g_prof.pending.push_back(*pe);
         }
     } fin{prof, &pe, st};
@@ -664,25 +685,56 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     L.leaves = tab->leaves, L.asrc = tab->asrc, L.bsrc = tab->bsrc;
     L.sc = exps;
     hipError_t e;
-    // Split precisions read both operands with k contiguous: A as m x k, B as its transpose
-    // n x k; operands stored the other way round are transposed into the workspace first.
-    const float *Bt = nullptr;
-    int64_t ldbt = 0;
     if (is_split(plan->prec)) {
-        if (transA) {
-            e = launch_transpose_f32((const float *)A, lda, k, m, (float *)(ws + w.at), round4(k), st);
-            if (e != hipSuccess) return hip_fail(e, "transpose kernel");
-            L.A = ws + w.at, L.lda = round4(k), L.transA = 0;
-        }
-        if (transB) {
-            Bt = (const float *)B, ldbt = ldb;
+        // Split precisions: limb planes of every S_r and T_r^T (k contiguous, zero-padded to
+        // the GEMM tiles), then the limb GEMM, then (L >= 1) the W-combination.
+        const SplitDims d = split_dims(plan->prec, s);
+        PlaneForm fa{};
+        fa.X = (const float *)A;
+        fa.ld_o = transA ? 1 : lda, fa.ld_k = transA ? lda : 1;  // op(A)(i, kk)
+        fa.R = m, fa.K = k, fa.rb = s.mb, fa.kb = s.kb, fa.rowsp = d.mbp, fa.kp = d.kp;
+        fa.leaves = tab->leaves, fa.src = tab->asrc, fa.b_side = 0;
+        fa.e_o = exps.ea, fa.e_k = exps.ep, fa.s_o = -1, fa.s_k = 1;  // 2^(ep_kk - ea_i)
+        fa.planes = (unsigned short *)(ws + w.sp), fa.plane_stride = d.mbp * d.kp;
+        fa.leaf_stride = d.nl * d.mbp * d.kp;
+        PlaneForm fb{};
+        fb.X = (const float *)B;
+        fb.ld_o = transB ? ldb : 1, fb.ld_k = transB ? 1 : ldb;  // op(B)(kk, j) as T^T(j, kk)
+        fb.R = n, fb.K = k, fb.rb = s.nb, fb.kb = s.kb, fb.rowsp = d.nbp, fb.kp = d.kp;
+        fb.leaves = tab->leaves, fb.src = tab->bsrc, fb.b_side = 1;
+        fb.e_o = exps.eb, fb.e_k = exps.ep, fb.s_o = -1, fb.s_k = -1;  // 2^(-ep_kk - eb_j)
+        fb.planes = (unsigned short *)(ws + w.tp), fb.plane_stride = d.nbp * d.kp;
+        fb.leaf_stride = d.nl * d.nbp * d.kp;
+        if ((e = launch_form_planes(plan->prec, fa, tab->nleaves, st)) != hipSuccess ||
+            (e = launch_form_planes(plan->prec, fb, tab->nleaves, st)) != hipSuccess)
+            return hip_fail(e, "limb plane formation");
+        fin.mark();
+        LimbGemm g{};
+        g.S = fa.planes, g.T = fb.planes, g.kp = d.kp;
+        g.s_plane = fa.plane_stride, g.s_leaf = fa.leaf_stride, g.t_plane = fb.plane_stride, g.t_leaf = fb.leaf_stride;
+        g.mb = s.mb, g.nb = s.nb, g.m = m, g.n = n, g.sc = exps;
+        g.tiles_m = (int)(d.mbp / d.bm), g.tiles_n = (int)(d.nbp / 128);
+        if (s.L == 0) {
+            g.out = (float *)C, g.ldo = ldc, g.leaf_stride = 0, g.direct = 1;
         } else {
-            e = launch_transpose_f32((const float *)B, ldb, k, n, (float *)(ws + w.bt), round4(k), st);
-            if (e != hipSuccess) return hip_fail(e, "transpose kernel");
-            Bt = (const float *)(ws + w.bt), ldbt = round4(k);
+            g.out = (float *)(ws + w.leaves), g.ldo = s.nb, g.leaf_stride = s.mb * s.nb, g.direct = 0;
         }
-        L.transB = 0;
+        e = launch_limb_gemm(plan->prec, d.bm, g, tab->nleaves, st);
+        fin.mark();
+        if (e != hipSuccess) return hip_fail(e, "limb GEMM kernel");
+        if (s.L == 0) return FASTMM_OK;
+        CombineLaunch Cb;
+        Cb.elem = el;
+        Cb.M = ws + w.leaves;
+        Cb.leaf_stride = s.mb * s.nb;
+        Cb.C = C, Cb.ldc = ldc, Cb.m = m, Cb.n = n, Cb.mb = s.mb, Cb.nb = s.nb;
+        Cb.NB = tab->NB;
+        Cb.bdest = tab->bdest, Cb.dest = tab->dest;
+        Cb.sc = exps;
+        if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
+        return FASTMM_OK;
     }
+    fin.mark();  // no operand formation pass on the FP64 / FP32 paths
     uint32_t masks[6];
     if (fused_path(plan, s, transA, transB, masks)) {
         // The innermost level runs fused; the L-1 outer levels supply the node operands and,
@@ -719,7 +771,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
         return FASTMM_OK;
     }
-    auto leaf_launch = [&]() { return is_split(plan->prec) ? launch_leaf_split(L, Bt, ldbt, st) : launch_leaf(L, st); };
+    auto leaf_launch = [&]() { return launch_leaf(L, st); };
     if (s.L == 0) {
         L.out = C, L.ldo = ldc, L.leaf_stride = 0, L.direct = 1;
         e = leaf_launch();

@@ -98,6 +98,45 @@ struct NodeLaunch {
 bool node222_supported(const uint32_t masks[6]);
 hipError_t launch_node222(const NodeLaunch &L, hipStream_t s);
 
+// Split precisions, pass 1: limb planes of the leaf operands.  Plane row o, column kk of leaf
+// r holds limb l of the leaf operand element (o, kk): for A, S_r(i, kk); for B, T_r(kk, j)
+// transposed (o = j).  op(X)(o, kk) = X[o * ld_o + kk * ld_k] for o < R, kk < K; the leaf's
+// source blocks (b_side: SrcEntry (br, bc) = (k block, o block)) are rb x kb; every value is
+// multiplied by 2^(s_o e_o[o] + s_k e_k[kk]) when e_o is not null.  Planes are rowsp x kp
+// (multiples of 64; the padding is written as zeros), limb l of leaf r at
+// planes + r * leaf_stride + l * plane_stride.
+struct PlaneForm {
+    const float *X;
+    int64_t ld_o, ld_k;
+    int64_t R, K;
+    int64_t rb, kb;
+    int64_t rowsp, kp;
+    const LeafEntry *leaves;
+    const SrcEntry *src;
+    int b_side;
+    const int32_t *e_o, *e_k;
+    int s_o, s_k;
+    unsigned short *planes;
+    int64_t plane_stride, leaf_stride;
+};
+// Pass 2: M_r = sum of the kept limb products of S_r and T_r, for every leaf and every
+// bm x 128 tile of the padded planes; out is the leaf workspace (leaf r at out + r *
+// leaf_stride, mb x nb, row stride ldo) or, with direct, C (m x n, ldc = ldo) with the
+// outside-scaling factors 2^(ea_i + eb_j) applied.
+struct LimbGemm {
+    const unsigned short *S, *T;
+    int64_t kp, s_plane, s_leaf, t_plane, t_leaf;
+    float *out;
+    int64_t ldo, leaf_stride, mb, nb, m, n;
+    ScaleExps sc;
+    int tiles_m, tiles_n;
+    int direct;
+};
+int limb_count(int prec);                   // limbs per element of a split precision
+int limb_gemm_bm(int prec, int64_t mb);     // tile rows of the limb GEMM (128 or 256)
+hipError_t launch_form_planes(int prec, const PlaneForm &f, int nleaves, hipStream_t s);
+hipError_t launch_limb_gemm(int prec, int bm, const LimbGemm &g, int nleaves, hipStream_t s);
+
 hipError_t launch_leaf(const LeafLaunch &L, hipStream_t s);
 // Pipelined 128x128-tile version for row-major (non-transposed) operands.
 hipError_t launch_leaf_pipelined(const LeafLaunch &L, hipStream_t s);

@@ -1,0 +1,348 @@
+// Split-precision leaf products in two passes: limb planes, then a bf16 / fp16 MFMA GEMM.
+//
+// Pass 1 (form_planes): for every leaf r, every element of S_r = sum_i u_ir A_i (eq. (2), the
+// composite sources of the leaf, scaling exponents applied) is formed in FP32 and split into
+// limbs x = x_1 + x_2 (+ x_3), x_1 = rn(x), x_2 = rn(x - x_1), x_3 = rn(x - x_1 - x_2) (round to
+// nearest even in bf16 or fp16; each residual is exact in FP32).  The limbs are written as
+// 16-bit planes with k contiguous; T_r is written transposed (T_r^T, n-rows by k), so both
+// GEMM operands have k contiguous.  Planes are zero-padded to the GEMM tiles, so the GEMM
+// needs no bounds checks on its loads.
+//
+// Pass 2 (fmm_limb_gemm): M_r = sum over the kept limb products S^(a) T^(b), the products of
+// total order <= 2: x1y1 (one limb), x1y1 + x1y2 + x2y1 (two limbs), plus x1y3 + x2y2 + x3y1
+// (three limbs), smallest terms first, on v_mfma_f32_16x16x32_{bf16,f16} with FP32
+// accumulation.  The output is the leaf-product workspace (the W-combination follows) or, for
+// a single classical leaf, C with the outside-scaling factors applied.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "devtypes.h"
+#include "fastmm.h"
+#include "launch.h"
+
+namespace fastmm {
+namespace {
+
+typedef float g4v __attribute__((ext_vector_type(4)));
+typedef __bf16 gbf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 gh8 __attribute__((ext_vector_type(8)));
+typedef short gs8 __attribute__((ext_vector_type(8)));
+constexpr int kXcds = 8;
+
+template <bool HALF>
+struct LimbT;
+template <>
+struct LimbT<false> {
+    __device__ static unsigned short split(float x, float &back) {
+        const __bf16 h = (__bf16)x;  // round to nearest even
+        back = (float)h;
+        return __builtin_bit_cast(unsigned short, h);
+    }
+    // D(16x16) += A(16x32) B(32x16): lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and
+    // B[8(l/16) .. 8(l/16)+7][l%16]; accumulator element v of lane l is D[4(l/16)+v][l%16].
+    __device__ static g4v mma(gs8 a, gs8 b, g4v c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(gbf8, a), __builtin_bit_cast(gbf8, b), c,
+                                                       0, 0, 0);
+    }
+};
+template <>
+struct LimbT<true> {
+    __device__ static unsigned short split(float x, float &back) {
+        const _Float16 h = (_Float16)x;
+        back = (float)h;
+        return __builtin_bit_cast(unsigned short, h);
+    }
+    __device__ static g4v mma(gs8 a, gs8 b, g4v c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(gh8, a), __builtin_bit_cast(gh8, b), c, 0, 0,
+                                                      0);
+    }
+};
+
+// ------------------------------------------------------------------ pass 1: limb planes
+constexpr int kFT = 64;  // formation tile: 64 plane rows by 64 k
+
+template <bool HALF, int NL, bool SCALED, bool KCONTIG>
+__global__ __launch_bounds__(256) void form_planes(PlaneForm a) {
+    __shared__ float tile[kFT][kFT + 1];
+    const int t = threadIdx.x;
+    const int leaf = blockIdx.z;
+    const int64_t o0 = (int64_t)blockIdx.y * kFT, k0 = (int64_t)blockIdx.x * kFT;
+    const LeafEntry le = a.leaves[leaf];
+    const int begin = __builtin_amdgcn_readfirstlane(a.b_side ? le.b_begin : le.a_begin);
+    const int count = __builtin_amdgcn_readfirstlane(a.b_side ? le.b_count : le.a_count);
+    // element e of this thread: consecutive lanes walk the operand's contiguous direction
+    int lo[16], lk[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        if (KCONTIG) lo[e] = e * 4 + t / 64, lk[e] = t % 64;
+        else lk[e] = e * 4 + t / 64, lo[e] = t % 64;
+    }
+    float v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = 0.f;
+    for (int q = 0; q < count; ++q) {
+        const SrcEntry se = a.src[begin + q];
+        const int64_t bo = a.b_side ? se.bc : se.br, bk = a.b_side ? se.br : se.bc;
+        const float c = se.coef;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t ob = o0 + lo[e], kb = k0 + lk[e];  // inside the leaf block
+            const int64_t o = bo * a.rb + ob, kk = bk * a.kb + kb;  // inside op(X)
+            const bool ok = ob < a.rb && kb < a.kb && o < a.R && kk < a.K;
+            const float y = *(ok ? a.X + o * a.ld_o + kk * a.ld_k : a.X);
+            float x = ok ? y : 0.f;
+            if (SCALED) x = ldexpf(x, a.s_o * a.e_o[ok ? o : 0] + a.s_k * a.e_k[ok ? kk : 0]);
+            v[e] = (q == 0) ? c * x : v[e] + c * x;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) tile[lo[e]][lk[e]] = v[e];
+    __syncthreads();
+    // 64 rows x 8 chunks of 8 k: split and write 16 bytes per limb
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int cidx = t + 256 * u, ro = cidx / 8, rk = (cidx % 8) * 8;
+        unsigned short h[NL][8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float r = tile[ro][rk + j];
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                float back;
+                h[l][j] = LimbT<HALF>::split(r, back);
+                r = r - back;
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            uint4 w;
+            w.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
+            w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
+            w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
+            w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
+            *reinterpret_cast<uint4 *>(a.planes + (int64_t)leaf * a.leaf_stride + l * a.plane_stride +
+                                       (o0 + ro) * a.kp + k0 + rk) = w;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ pass 2: limb GEMM
+__device__ inline int64_t xcd_remap_g(int64_t b, int64_t G) {
+    const int64_t x = b % kXcds, j = b / kXcds;
+    const int64_t per = G / kXcds, rem = G % kXcds;
+    return ((x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + j;
+}
+
+// Limb products (a, b) kept for NL limbs, smallest first.
+template <int NL>
+struct Products;
+template <>
+struct Products<1> {
+    static constexpr int n = 1;
+    static constexpr int a[1] = {0}, b[1] = {0};
+};
+template <>
+struct Products<2> {
+    static constexpr int n = 3;
+    static constexpr int a[3] = {0, 1, 0}, b[3] = {1, 0, 0};
+};
+template <>
+struct Products<3> {
+    static constexpr int n = 6;
+    static constexpr int a[6] = {0, 1, 2, 0, 1, 0}, b[6] = {2, 1, 0, 1, 0, 0};
+};
+
+// Work-group of BM / 32 waves (BM / 64 by 2), each a 64 x 64 tile of the BM x 128 output tile;
+// K stage 32; LDS double-buffered, rows of 32 halves padded to 80 bytes (16-byte fragment reads
+// of consecutive rows fall on distinct banks).
+template <bool HALF, int NL, int BM, bool SCALED, bool DIRECT>
+__global__ __launch_bounds__(BM * 2, 1) void fmm_limb_gemm(LimbGemm a) {
+    constexpr int BN = 128, BK = 32, NT = BM * 2, RS = 40;
+    constexpr int CA = NL * BM * 4 / NT, CB = NL * BN * 4 / NT;  // 16-byte chunks per thread and stage
+    static_assert(CA * NT == NL * BM * 4 && CB * NT == NL * BN * 4, "chunk split");
+    typedef Products<NL> P;
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][NL][BM * RS];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NL][BN * RS];
+
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t tiles = (int64_t)a.tiles_m * a.tiles_n;
+    const int bid = __builtin_amdgcn_readfirstlane((int)xcd_remap_g(blockIdx.x, gridDim.x));
+    const int leaf = __builtin_amdgcn_readfirstlane((int)(bid / tiles));
+    const int rem = __builtin_amdgcn_readfirstlane((int)(bid - (int64_t)leaf * tiles));
+    const int grp = rem / (8 * a.tiles_n);
+    const int gsz = min(8, a.tiles_m - grp * 8);
+    const int gidx = rem - grp * 8 * a.tiles_n;
+    const int64_t tm = __builtin_amdgcn_readfirstlane(grp * 8 + gidx % gsz);
+    const int64_t tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
+
+    const unsigned short *Sp = a.S + (int64_t)leaf * a.s_leaf + tm * BM * a.kp;
+    const unsigned short *Tp = a.T + (int64_t)leaf * a.t_leaf + tn * BN * a.kp;
+    // chunk u of this thread: limb, row, 16-byte column (consecutive lanes along k, then rows);
+    // the same split for every stage
+    auto chunk = [&](int u, int rows, int &l, int &r, int &kc) {
+        const int c = t + NT * u;
+        l = c / (rows * 4), r = (c % (rows * 4)) / 4, kc = c % 4;
+    };
+    // The staging registers are vector values (not arrays), so that they stay in VGPRs.
+    typedef uint32_t stA_t __attribute__((ext_vector_type(4 * CA)));
+    typedef uint32_t stB_t __attribute__((ext_vector_type(4 * CB)));
+#define LIMB_LOAD(k0)                                                                                   \
+    _Pragma("unroll") for (int u = 0; u < CA; ++u) {                                                    \
+        int l, r, kc;                                                                                   \
+        chunk(u, BM, l, r, kc);                                                                         \
+        const uint4 w = *reinterpret_cast<const uint4 *>(Sp + l * a.s_plane + (int64_t)r * a.kp + (k0) + kc * 8); \
+        ra[4 * u] = w.x, ra[4 * u + 1] = w.y, ra[4 * u + 2] = w.z, ra[4 * u + 3] = w.w;                 \
+    }                                                                                                   \
+    _Pragma("unroll") for (int u = 0; u < CB; ++u) {                                                    \
+        int l, r, kc;                                                                                   \
+        chunk(u, BN, l, r, kc);                                                                         \
+        const uint4 w = *reinterpret_cast<const uint4 *>(Tp + l * a.t_plane + (int64_t)r * a.kp + (k0) + kc * 8); \
+        rb[4 * u] = w.x, rb[4 * u + 1] = w.y, rb[4 * u + 2] = w.z, rb[4 * u + 3] = w.w;                 \
+    }
+#define LIMB_STORE(st)                                                                              \
+    _Pragma("unroll") for (int u = 0; u < CA; ++u) {                                                \
+        int l, r, kc;                                                                               \
+        chunk(u, BM, l, r, kc);                                                                     \
+        *reinterpret_cast<uint4 *>(&As[st][l][r * RS + kc * 8]) =                                   \
+            uint4{ra[4 * u], ra[4 * u + 1], ra[4 * u + 2], ra[4 * u + 3]};                          \
+    }                                                                                               \
+    _Pragma("unroll") for (int u = 0; u < CB; ++u) {                                                \
+        int l, r, kc;                                                                               \
+        chunk(u, BN, l, r, kc);                                                                     \
+        *reinterpret_cast<uint4 *>(&Bs[st][l][r * RS + kc * 8]) =                                   \
+            uint4{rb[4 * u], rb[4 * u + 1], rb[4 * u + 2], rb[4 * u + 3]};                          \
+    }
+    stA_t ra;
+    stB_t rb;
+
+    g4v acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = g4v{0.f, 0.f, 0.f, 0.f};
+
+    const int g8 = 8 * (lane >> 4), l16 = lane & 15;
+    const int64_t nk = a.kp / BK;
+    LIMB_LOAD(0)
+    LIMB_STORE(0)
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        const bool more = kt + 1 < nk;
+        if (more) {
+            LIMB_LOAD((kt + 1) * BK)
+        }
+        gs8 fa[4][NL], fb[4][NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                fa[i][l] = *reinterpret_cast<const gs8 *>(&As[cur][l][(wm * 64 + i * 16 + l16) * RS + g8]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                fb[j][l] = *reinterpret_cast<const gs8 *>(&Bs[cur][l][(wn * 64 + j * 16 + l16) * RS + g8]);
+        }
+#pragma unroll
+        for (int p = 0; p < P::n; ++p)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = LimbT<HALF>::mma(fa[i][P::a[p]], fb[j][P::b[p]], acc[i][j]);
+        if (more) {  // the other buffer was last read before the previous barrier
+            LIMB_STORE(cur ^ 1)
+        }
+        __syncthreads();
+    }
+#undef LIMB_LOAD
+#undef LIMB_STORE
+
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = tm * BM + wm * 64 + i * 16 + 4 * (lane >> 4) + v;  // inside the leaf block
+                const int64_t col = tn * BN + wn * 64 + j * 16 + l16;
+                float val = acc[i][j][v];
+                if (DIRECT) {
+                    if (row < a.m && col < a.n) {
+                        if (SCALED) val = ldexpf(val, a.sc.ea[row] + a.sc.eb[col]);
+                        a.out[row * a.ldo + col] = val;
+                    }
+                } else if (row < a.mb && col < a.nb) {
+                    a.out[(int64_t)leaf * a.leaf_stride + row * a.ldo + col] = val;
+                }
+            }
+}
+
+template <bool HALF, int NL>
+hipError_t form_go(const PlaneForm &f, int nleaves, hipStream_t s) {
+    if (f.rowsp <= 0 || f.kp <= 0 || nleaves <= 0) return hipSuccess;
+    if (f.rowsp / kFT > 65535 || nleaves > 65535 || f.kp / kFT > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(f.kp / kFT), (unsigned)(f.rowsp / kFT), (unsigned)nleaves);
+    const bool scaled = f.e_o != nullptr, kc = f.ld_k == 1;
+    if (scaled && kc) hipLaunchKernelGGL((form_planes<HALF, NL, true, true>), grid, dim3(256), 0, s, f);
+    else if (scaled) hipLaunchKernelGGL((form_planes<HALF, NL, true, false>), grid, dim3(256), 0, s, f);
+    else if (kc) hipLaunchKernelGGL((form_planes<HALF, NL, false, true>), grid, dim3(256), 0, s, f);
+    else hipLaunchKernelGGL((form_planes<HALF, NL, false, false>), grid, dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+template <bool HALF, int NL, int BM>
+hipError_t gemm_go(const LimbGemm &g, int nleaves, hipStream_t s) {
+    const int64_t blocks = (int64_t)g.tiles_m * g.tiles_n * nleaves;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const bool scaled = g.sc.ea != nullptr;
+    const dim3 grid((unsigned)blocks), block(BM * 2);
+    if (g.direct) {
+        if (scaled) hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, true, true>), grid, block, 0, s, g);
+        else hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, false, true>), grid, block, 0, s, g);
+    } else {
+        hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, false, false>), grid, block, 0, s, g);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int limb_count(int prec) {
+    switch (prec) {
+        case FASTMM_BF16:
+        case FASTMM_F16: return 1;
+        case FASTMM_BF16X3:
+        case FASTMM_F16X3: return 2;
+        case FASTMM_BF16X6: return 3;
+    }
+    return 0;
+}
+
+int limb_gemm_bm(int prec, int64_t mb) { return (limb_count(prec) == 3 || mb < 256) ? 128 : 256; }
+
+hipError_t launch_form_planes(int prec, const PlaneForm &f, int nleaves, hipStream_t s) {
+    switch (prec) {
+        case FASTMM_BF16: return form_go<false, 1>(f, nleaves, s);
+        case FASTMM_F16: return form_go<true, 1>(f, nleaves, s);
+        case FASTMM_BF16X3: return form_go<false, 2>(f, nleaves, s);
+        case FASTMM_F16X3: return form_go<true, 2>(f, nleaves, s);
+        case FASTMM_BF16X6: return form_go<false, 3>(f, nleaves, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_limb_gemm(int prec, int bm, const LimbGemm &g, int nleaves, hipStream_t s) {
+    switch (prec) {
+        case FASTMM_BF16: return bm == 256 ? gemm_go<false, 1, 256>(g, nleaves, s) : gemm_go<false, 1, 128>(g, nleaves, s);
+        case FASTMM_F16: return bm == 256 ? gemm_go<true, 1, 256>(g, nleaves, s) : gemm_go<true, 1, 128>(g, nleaves, s);
+        case FASTMM_BF16X3:
+            return bm == 256 ? gemm_go<false, 2, 256>(g, nleaves, s) : gemm_go<false, 2, 128>(g, nleaves, s);
+        case FASTMM_F16X3: return bm == 256 ? gemm_go<true, 2, 256>(g, nleaves, s) : gemm_go<true, 2, 128>(g, nleaves, s);
+        case FASTMM_BF16X6: return gemm_go<false, 3, 128>(g, nleaves, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fastmm

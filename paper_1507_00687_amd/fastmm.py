@@ -85,7 +85,7 @@ def lib() -> ctypes.CDLL:
         L.fastmm_backward_workspace_size.argtypes = [vp, i64, i64, i64, ctypes.POINTER(sz)]
         L.fastmm_gemm_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
         L.fastmm_profile_enable.argtypes = [i32]
-        L.fastmm_profile_read.argtypes = [pd, pd, pd, pi32]
+        L.fastmm_profile_read.argtypes = [pd, pd, pd, pd, pi32]
         L.fastmm_strerror.argtypes = [i32]
         L.fastmm_strerror.restype = ctypes.c_char_p
         L.fastmm_last_error.restype = ctypes.c_char_p
@@ -345,10 +345,11 @@ def fastmm_profile_enable(enable: bool = True) -> None:
 
 def fastmm_profile_read() -> dict:
     """Summed milliseconds per phase of the profiled calls since the last read."""
-    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    a, f, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     n = ctypes.c_int()
-    _check(lib().fastmm_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(n)))
-    return {"scaling_ms": a.value, "leaf_ms": b.value, "combine_ms": c.value, "calls": n.value}
+    _check(lib().fastmm_profile_read(ctypes.byref(a), ctypes.byref(f), ctypes.byref(b), ctypes.byref(c),
+                                     ctypes.byref(n)))
+    return {"scaling_ms": a.value, "form_ms": f.value, "leaf_ms": b.value, "combine_ms": c.value, "calls": n.value}
 
 
 def matmul(A, B, plan: Optional[Plan] = None, **plan_kwargs):
