@@ -1,13 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark: effective TFLOP/s (2mkn/t) of recursive fast matrix multiplication on one
-MI355X, beside the classical GEMM built from the same kernel template, with the max-norm
-relative error of both against the long-double CPU reference.
+MI355X, beside the classical GEMM built the same way (same precision form, one leaf), with the
+max-norm relative error of both against the long-double CPU reference.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--algo winograd] [--depth 2]
-                    [--n 8192] [--precision f64] [--scaling none] [--dist uniform01]
+                    [--n 8192] [--precision f16x3] [--beside f32] [--scaling none]
+                    [--dist uniform01] [--fuse auto]
 
-Prints one JSON line.  A step is one fastmm_gemm call (scaling reductions, fused leaf
-products, W-combination) on inputs already resident in HBM.  The leaf-product kernel's
+Default workload: Strassen, depth 1, n = 8192, N(0,1), leaves as FP16 MFMA products with FP32
+accumulation and two-limb split precision (F16X3), the same plan on plain FP32 MFMA reported
+beside it.  Prints one JSON line.  A step is one fastmm_gemm call (scaling reductions, operand
+formation, products, W-combination) on inputs already resident in HBM.  The products kernel's
 average duration comes from HIP events the library records on its launch stream.
 """
 from __future__ import annotations
@@ -41,7 +44,10 @@ def parse():
     ap.add_argument("--depth", type=int, default=1)
     ap.add_argument("--cutoff", type=int, default=256)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--precision", default="f32")
+    ap.add_argument("--precision", default="f16x3",
+                    help="leaf arithmetic: f64, f32, or a split form (bf16, f16, bf16x3, f16x3, bf16x6)")
+    ap.add_argument("--beside", default="f32",
+                    help="also time the same plan in this precision (reported beside the headline; '' = none)")
     ap.add_argument("--scaling", default="none")
     ap.add_argument("--scaling-steps", type=int, default=2)
     ap.add_argument("--dist", default="normal")
@@ -169,6 +175,18 @@ def main():
         ms_cls = time_steps(run_cls, args.steps, args.warmup)
         classical = {"ms_per_step": ms_cls, "value": 2.0 * m * k * n / (ms_cls * 1e-3) / 1e12}
 
+    beside = None
+    if args.beside and args.beside != args.precision:
+        bdt = torch.float64 if args.beside == "f64" else torch.float32
+        bA, bB = (tA, tB) if bdt == tA.dtype else (tA.to(bdt), tB.to(bdt))
+        bplan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
+                       precision=args.beside, fuse=args.fuse)
+        bws = torch.empty(max(bplan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
+        Cb = torch.empty((m, n), dtype=bdt, device="cuda")
+        ms_b = time_steps(lambda: F.fastmm_gemm(bplan, bA, bB, C=Cb, workspace=bws), args.steps, args.warmup)
+        beside = {"precision": args.beside, "path": bplan.path(m, k, n), "ms_per_step": ms_b,
+                  "value": 2.0 * m * k * n / (ms_b * 1e-3) / 1e12}
+
     # timed region: K steps between device synchronisations (one GPU: no barrier needed)
     ms = time_steps(run_fast, args.steps, args.warmup)
     value = 2.0 * m * k * n / (ms * 1e-3) / 1e12
@@ -214,6 +232,9 @@ def main():
     if classical is not None:
         Cc_rows = Cc[torch.from_numpy(rows).cuda()].cpu().numpy()
         err["classical"] = float(np.max(np.abs(Cc_rows.astype(np.longdouble) - ref))) / den
+    if beside is not None:
+        Cb_rows = Cb[torch.from_numpy(rows).cuda()].cpu().numpy()
+        beside["error"] = float(np.max(np.abs(Cb_rows.astype(np.longdouble) - ref))) / den
 
     line = {
         "metric": METRIC,
@@ -232,6 +253,7 @@ def main():
                    "cutoff": args.cutoff, "m": m, "k": k, "n": n, "padded": [Mp, Kp, Np],
                    "precision": args.precision, "scaling": args.scaling, "dist": args.dist, "path": path},
         "classical": classical,
+        "beside": beside,
         "torch_matmul": torch_ref,
         "speedup_vs_classical": (classical["ms_per_step"] / ms) if classical else None,
         "error": err,

@@ -150,12 +150,7 @@ int64_t leaf_desc_build(const LeafLaunch &L, void *dst);
 hipError_t launch_leaf_batched(Elem e, const void *descs, const int64_t *first, const int *direct, int count,
                                int64_t total, int grid, hipStream_t s);
 int leaf_blocks_per_cu(Elem e);
-// Split-precision (bf16 / fp16 limb) version: FP32 A (m x k, row-major, L.A / L.lda) and the
-// transpose of B (n x k, row-major); L.prec selects the limb format and count.
-hipError_t launch_leaf_split(const LeafLaunch &L, const float *Bt, int64_t ldbt, hipStream_t s);
-// out (C x R) = in^T for a row-major R x C FP32 matrix.
-hipError_t launch_transpose_f32(const float *in, int64_t ldi, int64_t R, int64_t C, float *out, int64_t ldo,
-                                hipStream_t s);
+// out (C x R) = in^T for a row-major R x C matrix (FP32 or FP64).
 hipError_t launch_transpose(Elem e, const void *in, int64_t ldi, int64_t R, int64_t C, void *out, int64_t ldo,
                             hipStream_t s);
 hipError_t launch_combine(const CombineLaunch &L, hipStream_t s);
