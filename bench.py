@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--precision", default="f16x3",
                     help="leaf arithmetic: f64, f32, or a split form (bf16, f16, bf16x3, f16x3, bf16x6)")
     ap.add_argument("--beside", default="f32",
-                    help="also time the same plan in this precision (reported beside the headline; '' = none)")
+                    help="also time the same plan in this precision (reported beside the headline; none = skip)")
     ap.add_argument("--scaling", default="none")
     ap.add_argument("--scaling-steps", type=int, default=2)
     ap.add_argument("--dist", default="normal")
@@ -176,7 +176,7 @@ def main():
         classical = {"ms_per_step": ms_cls, "value": 2.0 * m * k * n / (ms_cls * 1e-3) / 1e12}
 
     beside = None
-    if args.beside and args.beside != args.precision:
+    if args.beside and args.beside != "none" and args.beside != args.precision:
         bdt = torch.float64 if args.beside == "f64" else torch.float32
         bA, bB = (tA, tB) if bdt == tA.dtype else (tA.to(bdt), tB.to(bdt))
         bplan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,

@@ -299,8 +299,8 @@ int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 SplitDims split_dims(int prec, const Shape &s) {
     SplitDims d;
     d.nl = limb_count(prec);
-    d.bm = limb_gemm_bm(prec, s.mb);
-    d.mbp = round_up(s.mb, d.bm), d.nbp = round_up(s.nb, 128), d.kp = round_up(s.kb, 64);
+    d.bm = limb_gemm_tile(prec, s.mb, s.nb);
+    d.mbp = round_up(s.mb, d.bm), d.nbp = round_up(s.nb, d.bm), d.kp = round_up(s.kb, 64);
     return d;
 }
 
@@ -692,7 +692,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         PlaneForm fa{};
         fa.X = (const float *)A;
         fa.ld_o = transA ? 1 : lda, fa.ld_k = transA ? lda : 1;  // op(A)(i, kk)
-        fa.R = m, fa.K = k, fa.rb = s.mb, fa.kb = s.kb, fa.rowsp = d.mbp, fa.kp = d.kp;
+        fa.R = m, fa.K = k, fa.rb = s.mb, fa.kb = s.kb, fa.rowsp = d.mbp, fa.kp = d.kp, fa.bt = d.bm;
         fa.leaves = tab->leaves, fa.src = tab->asrc, fa.b_side = 0;
         fa.e_o = exps.ea, fa.e_k = exps.ep, fa.s_o = -1, fa.s_k = 1;  // 2^(ep_kk - ea_i)
         fa.planes = (unsigned short *)(ws + w.sp), fa.plane_stride = d.mbp * d.kp;
@@ -700,7 +700,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         PlaneForm fb{};
         fb.X = (const float *)B;
         fb.ld_o = transB ? ldb : 1, fb.ld_k = transB ? 1 : ldb;  // op(B)(kk, j) as T^T(j, kk)
-        fb.R = n, fb.K = k, fb.rb = s.nb, fb.kb = s.kb, fb.rowsp = d.nbp, fb.kp = d.kp;
+        fb.R = n, fb.K = k, fb.rb = s.nb, fb.kb = s.kb, fb.rowsp = d.nbp, fb.kp = d.kp, fb.bt = d.bm;
         fb.leaves = tab->leaves, fb.src = tab->bsrc, fb.b_side = 1;
         fb.e_o = exps.eb, fb.e_k = exps.ep, fb.s_o = -1, fb.s_k = -1;  // 2^(-ep_kk - eb_j)
         fb.planes = (unsigned short *)(ws + w.tp), fb.plane_stride = d.nbp * d.kp;
@@ -713,7 +713,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         g.S = fa.planes, g.T = fb.planes, g.kp = d.kp;
         g.s_plane = fa.plane_stride, g.s_leaf = fa.leaf_stride, g.t_plane = fb.plane_stride, g.t_leaf = fb.leaf_stride;
         g.mb = s.mb, g.nb = s.nb, g.m = m, g.n = n, g.sc = exps;
-        g.tiles_m = (int)(d.mbp / d.bm), g.tiles_n = (int)(d.nbp / 128);
+        g.tiles_m = (int)(d.mbp / d.bm), g.tiles_n = (int)(d.nbp / d.bm);
         if (s.L == 0) {
             g.out = (float *)C, g.ldo = ldc, g.leaf_stride = 0, g.direct = 1;
         } else {

@@ -103,14 +103,15 @@ hipError_t launch_node222(const NodeLaunch &L, hipStream_t s);
 // transposed (o = j).  op(X)(o, kk) = X[o * ld_o + kk * ld_k] for o < R, kk < K; the leaf's
 // source blocks (b_side: SrcEntry (br, bc) = (k block, o block)) are rb x kb; every value is
 // multiplied by 2^(s_o e_o[o] + s_k e_k[kk]) when e_o is not null.  Planes are rowsp x kp
-// (multiples of 64; the padding is written as zeros), limb l of leaf r at
-// planes + r * leaf_stride + l * plane_stride.
+// (multiples of 64 and of bt; the padding is written as zeros), limb l of leaf r at
+// planes + r * leaf_stride + l * plane_stride, blocked in bt x 32 pieces (see bt).
 struct PlaneForm {
     const float *X;
     int64_t ld_o, ld_k;
     int64_t R, K;
     int64_t rb, kb;
     int64_t rowsp, kp;
+    int64_t bt;  // plane blocking: element (o, kk) at ((o/bt)(kp/32) + kk/32)(32 bt) + (o%bt) 32 + kk%32
     const LeafEntry *leaves;
     const SrcEntry *src;
     int b_side;
@@ -120,7 +121,7 @@ struct PlaneForm {
     int64_t plane_stride, leaf_stride;
 };
 // Pass 2: M_r = sum of the kept limb products of S_r and T_r, for every leaf and every
-// bm x 128 tile of the padded planes; out is the leaf workspace (leaf r at out + r *
+// bm x bm tile of the padded planes (bm = limb_gemm_tile); out is the leaf workspace (leaf r at out + r *
 // leaf_stride, mb x nb, row stride ldo) or, with direct, C (m x n, ldc = ldo) with the
 // outside-scaling factors 2^(ea_i + eb_j) applied.
 struct LimbGemm {
@@ -133,7 +134,7 @@ struct LimbGemm {
     int direct;
 };
 int limb_count(int prec);                   // limbs per element of a split precision
-int limb_gemm_bm(int prec, int64_t mb);     // tile rows of the limb GEMM (128 or 256)
+int limb_gemm_tile(int prec, int64_t mb, int64_t nb);  // square tile of the limb GEMM (128 or 256)
 hipError_t launch_form_planes(int prec, const PlaneForm &f, int nleaves, hipStream_t s);
 hipError_t launch_limb_gemm(int prec, int bm, const LimbGemm &g, int nleaves, hipStream_t s);
 

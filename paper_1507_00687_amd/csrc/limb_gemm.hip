@@ -6,7 +6,8 @@
 // nearest even in bf16 or fp16; each residual is exact in FP32).  The limbs are written as
 // 16-bit planes with k contiguous; T_r is written transposed (T_r^T, n-rows by k), so both
 // GEMM operands have k contiguous.  Planes are zero-padded to the GEMM tiles, so the GEMM
-// needs no bounds checks on its loads.
+// needs no bounds checks on its loads, and blocked in (tile rows) x 32 k pieces, so the GEMM
+// reads each stage's tile as one contiguous run.
 //
 // Pass 2 (fmm_limb_gemm): M_r = sum over the kept limb products S^(a) T^(b), the products of
 // total order <= 2: x1y1 (one limb), x1y1 + x1y2 + x2y1 (two limbs), plus x1y3 + x2y2 + x3y1
@@ -121,8 +122,10 @@ __global__ __launch_bounds__(256) void form_planes(PlaneForm a) {
             w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
             w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
             w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
+            const int64_t o = o0 + ro, kk = k0 + rk;  // blocked layout: (bt rows) x (32 k) tiles
             *reinterpret_cast<uint4 *>(a.planes + (int64_t)leaf * a.leaf_stride + l * a.plane_stride +
-                                       (o0 + ro) * a.kp + k0 + rk) = w;
+                                       ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 +
+                                       kk % 32) = w;
         }
     }
 }
@@ -153,12 +156,15 @@ struct Products<3> {
     static constexpr int a[6] = {0, 1, 2, 0, 1, 0}, b[6] = {2, 1, 0, 1, 0, 0};
 };
 
-// Work-group of BM / 32 waves (BM / 64 by 2), each a 64 x 64 tile of the BM x 128 output tile;
-// K stage 32; LDS double-buffered, rows of 32 halves padded to 80 bytes (16-byte fragment reads
-// of consecutive rows fall on distinct banks).
-template <bool HALF, int NL, int BM, bool SCALED, bool DIRECT>
-__global__ __launch_bounds__(BM * 2, 1) void fmm_limb_gemm(LimbGemm a) {
-    constexpr int BN = 128, BK = 32, NT = BM * 2, RS = 40;
+// Work-group of 2 x 2 waves, each a (BM/2) x (BN/2) tile of the BM x BN output tile (64 x 64 or,
+// for large blocks, 128 x 128: the larger wave tile halves the LDS bytes read per MFMA); K stage
+// 32; LDS double-buffered, rows of 32 halves (64 bytes, four 16-byte chunks) with chunk c of row r
+// stored at chunk c ^ ((r / 2) mod 4), so that the 16-byte fragment reads (16 rows, one chunk)
+// and the staging writes (consecutive chunks and rows) both fall on distinct banks.
+template <bool HALF, int NL, int BM, int BN, bool SCALED, bool DIRECT>
+__global__ __launch_bounds__(256, 1) void fmm_limb_gemm(LimbGemm a) {
+    constexpr int BK = 32, NT = 256, RS = 32;
+    constexpr int TI = BM / 32, TJ = BN / 32;  // 16 x 16 MFMA blocks per wave
     constexpr int CA = NL * BM * 4 / NT, CB = NL * BN * 4 / NT;  // 16-byte chunks per thread and stage
     static_assert(CA * NT == NL * BM * 4 && CB * NT == NL * BN * 4, "chunk split");
     typedef Products<NL> P;
@@ -177,8 +183,11 @@ __global__ __launch_bounds__(BM * 2, 1) void fmm_limb_gemm(LimbGemm a) {
     const int64_t tm = __builtin_amdgcn_readfirstlane(grp * 8 + gidx % gsz);
     const int64_t tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
 
+    // planes are blocked in BM x 32 tiles (BM == BN): the tile of stage kt is contiguous
     const unsigned short *Sp = a.S + (int64_t)leaf * a.s_leaf + tm * BM * a.kp;
     const unsigned short *Tp = a.T + (int64_t)leaf * a.t_leaf + tn * BN * a.kp;
+    static_assert(BM == BN, "square tiles");
+    auto swz = [](int r, int c) { return c ^ ((r >> 1) & 3); };
     // chunk u of this thread: limb, row, 16-byte column (consecutive lanes along k, then rows);
     // the same split for every stage
     auto chunk = [&](int u, int rows, int &l, int &r, int &kc) {
@@ -192,38 +201,38 @@ __global__ __launch_bounds__(BM * 2, 1) void fmm_limb_gemm(LimbGemm a) {
     _Pragma("unroll") for (int u = 0; u < CA; ++u) {                                                    \
         int l, r, kc;                                                                                   \
         chunk(u, BM, l, r, kc);                                                                         \
-        const uint4 w = *reinterpret_cast<const uint4 *>(Sp + l * a.s_plane + (int64_t)r * a.kp + (k0) + kc * 8); \
+        const uint4 w = *reinterpret_cast<const uint4 *>(Sp + l * a.s_plane + (k0) * BM + r * 32 + kc * 8); \
         ra[4 * u] = w.x, ra[4 * u + 1] = w.y, ra[4 * u + 2] = w.z, ra[4 * u + 3] = w.w;                 \
     }                                                                                                   \
     _Pragma("unroll") for (int u = 0; u < CB; ++u) {                                                    \
         int l, r, kc;                                                                                   \
         chunk(u, BN, l, r, kc);                                                                         \
-        const uint4 w = *reinterpret_cast<const uint4 *>(Tp + l * a.t_plane + (int64_t)r * a.kp + (k0) + kc * 8); \
+        const uint4 w = *reinterpret_cast<const uint4 *>(Tp + l * a.t_plane + (k0) * BN + r * 32 + kc * 8); \
         rb[4 * u] = w.x, rb[4 * u + 1] = w.y, rb[4 * u + 2] = w.z, rb[4 * u + 3] = w.w;                 \
     }
 #define LIMB_STORE(st)                                                                              \
     _Pragma("unroll") for (int u = 0; u < CA; ++u) {                                                \
         int l, r, kc;                                                                               \
         chunk(u, BM, l, r, kc);                                                                     \
-        *reinterpret_cast<uint4 *>(&As[st][l][r * RS + kc * 8]) =                                   \
+        *reinterpret_cast<uint4 *>(&As[st][l][r * RS + 8 * swz(r, kc)]) =                           \
             uint4{ra[4 * u], ra[4 * u + 1], ra[4 * u + 2], ra[4 * u + 3]};                          \
     }                                                                                               \
     _Pragma("unroll") for (int u = 0; u < CB; ++u) {                                                \
         int l, r, kc;                                                                               \
         chunk(u, BN, l, r, kc);                                                                     \
-        *reinterpret_cast<uint4 *>(&Bs[st][l][r * RS + kc * 8]) =                                   \
+        *reinterpret_cast<uint4 *>(&Bs[st][l][r * RS + 8 * swz(r, kc)]) =                           \
             uint4{rb[4 * u], rb[4 * u + 1], rb[4 * u + 2], rb[4 * u + 3]};                          \
     }
     stA_t ra;
     stB_t rb;
 
-    g4v acc[4][4];
+    g4v acc[TI][TJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = g4v{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TJ; ++j) acc[i][j] = g4v{0.f, 0.f, 0.f, 0.f};
 
-    const int g8 = 8 * (lane >> 4), l16 = lane & 15;
+    const int g = lane >> 4, l16 = lane & 15;
     const int64_t nk = a.kp / BK;
     LIMB_LOAD(0)
     LIMB_STORE(0)
@@ -234,22 +243,26 @@ __global__ __launch_bounds__(BM * 2, 1) void fmm_limb_gemm(LimbGemm a) {
         if (more) {
             LIMB_LOAD((kt + 1) * BK)
         }
-        gs8 fa[4][NL], fb[4][NL];
+        gs8 fa[TI][NL], fb[TJ][NL];
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                fa[i][l] = *reinterpret_cast<const gs8 *>(&As[cur][l][(wm * 64 + i * 16 + l16) * RS + g8]);
+            for (int i = 0; i < TI; ++i) {
+                const int rr = wm * (BM / 2) + i * 16 + l16;
+                fa[i][l] = *reinterpret_cast<const gs8 *>(&As[cur][l][rr * RS + 8 * swz(rr, g)]);
+            }
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                fb[j][l] = *reinterpret_cast<const gs8 *>(&Bs[cur][l][(wn * 64 + j * 16 + l16) * RS + g8]);
+            for (int j = 0; j < TJ; ++j) {
+                const int rr = wn * (BN / 2) + j * 16 + l16;
+                fb[j][l] = *reinterpret_cast<const gs8 *>(&Bs[cur][l][rr * RS + 8 * swz(rr, g)]);
+            }
         }
 #pragma unroll
         for (int p = 0; p < P::n; ++p)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = LimbT<HALF>::mma(fa[i][P::a[p]], fb[j][P::b[p]], acc[i][j]);
+                for (int j = 0; j < TJ; ++j) acc[i][j] = LimbT<HALF>::mma(fa[i][P::a[p]], fb[j][P::b[p]], acc[i][j]);
         if (more) {  // the other buffer was last read before the previous barrier
             LIMB_STORE(cur ^ 1)
         }
@@ -259,13 +272,13 @@ __global__ __launch_bounds__(BM * 2, 1) void fmm_limb_gemm(LimbGemm a) {
 #undef LIMB_STORE
 
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < TJ; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t row = tm * BM + wm * 64 + i * 16 + 4 * (lane >> 4) + v;  // inside the leaf block
-                const int64_t col = tn * BN + wn * 64 + j * 16 + l16;
+                const int64_t row = tm * BM + wm * (BM / 2) + i * 16 + 4 * (lane >> 4) + v;  // inside the leaf block
+                const int64_t col = tn * BN + wn * (BN / 2) + j * 16 + l16;
                 float val = acc[i][j][v];
                 if (DIRECT) {
                     if (row < a.m && col < a.n) {
@@ -291,20 +304,28 @@ hipError_t form_go(const PlaneForm &f, int nleaves, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <bool HALF, int NL, int BM>
+template <bool HALF, int NL, int BM, int BN>
 hipError_t gemm_go(const LimbGemm &g, int nleaves, hipStream_t s) {
     const int64_t blocks = (int64_t)g.tiles_m * g.tiles_n * nleaves;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const bool scaled = g.sc.ea != nullptr;
-    const dim3 grid((unsigned)blocks), block(BM * 2);
+    const dim3 grid((unsigned)blocks), block(256);
     if (g.direct) {
-        if (scaled) hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, true, true>), grid, block, 0, s, g);
-        else hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, false, true>), grid, block, 0, s, g);
+        if (scaled) hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, BN, true, true>), grid, block, 0, s, g);
+        else hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, BN, false, true>), grid, block, 0, s, g);
     } else {
-        hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, false, false>), grid, block, 0, s, g);
+        hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, BN, false, false>), grid, block, 0, s, g);
     }
     return hipGetLastError();
+}
+
+template <bool HALF, int NL>
+hipError_t gemm_tile(int bm, const LimbGemm &g, int nleaves, hipStream_t s) {
+    if constexpr (NL < 3) {
+        if (bm == 256) return gemm_go<HALF, NL, 256, 256>(g, nleaves, s);
+    }
+    return gemm_go<HALF, NL, 128, 128>(g, nleaves, s);
 }
 
 }  // namespace
@@ -320,7 +341,9 @@ int limb_count(int prec) {
     return 0;
 }
 
-int limb_gemm_bm(int prec, int64_t mb) { return (limb_count(prec) == 3 || mb < 256) ? 128 : 256; }
+int limb_gemm_tile(int prec, int64_t mb, int64_t nb) {
+    return (limb_count(prec) < 3 && mb >= 256 && nb >= 256) ? 256 : 128;
+}
 
 hipError_t launch_form_planes(int prec, const PlaneForm &f, int nleaves, hipStream_t s) {
     switch (prec) {
@@ -335,12 +358,11 @@ hipError_t launch_form_planes(int prec, const PlaneForm &f, int nleaves, hipStre
 
 hipError_t launch_limb_gemm(int prec, int bm, const LimbGemm &g, int nleaves, hipStream_t s) {
     switch (prec) {
-        case FASTMM_BF16: return bm == 256 ? gemm_go<false, 1, 256>(g, nleaves, s) : gemm_go<false, 1, 128>(g, nleaves, s);
-        case FASTMM_F16: return bm == 256 ? gemm_go<true, 1, 256>(g, nleaves, s) : gemm_go<true, 1, 128>(g, nleaves, s);
-        case FASTMM_BF16X3:
-            return bm == 256 ? gemm_go<false, 2, 256>(g, nleaves, s) : gemm_go<false, 2, 128>(g, nleaves, s);
-        case FASTMM_F16X3: return bm == 256 ? gemm_go<true, 2, 256>(g, nleaves, s) : gemm_go<true, 2, 128>(g, nleaves, s);
-        case FASTMM_BF16X6: return gemm_go<false, 3, 128>(g, nleaves, s);
+        case FASTMM_BF16: return gemm_tile<false, 1>(bm, g, nleaves, s);
+        case FASTMM_F16: return gemm_tile<true, 1>(bm, g, nleaves, s);
+        case FASTMM_BF16X3: return gemm_tile<false, 2>(bm, g, nleaves, s);
+        case FASTMM_F16X3: return gemm_tile<true, 2>(bm, g, nleaves, s);
+        case FASTMM_BF16X6: return gemm_tile<false, 3>(bm, g, nleaves, s);
     }
     return hipErrorInvalidValue;
 }
