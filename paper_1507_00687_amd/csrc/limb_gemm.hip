@@ -161,10 +161,10 @@ struct Products<3> {
 // 32; LDS double-buffered, rows of 32 halves (64 bytes, four 16-byte chunks) with chunk c of row r
 // stored at chunk c ^ ((r / 2) mod 4), so that the 16-byte fragment reads (16 rows, one chunk)
 // and the staging writes (consecutive chunks and rows) both fall on distinct banks.
-template <bool HALF, int NL, int BM, int BN, bool SCALED, bool DIRECT>
-__global__ __launch_bounds__(256, 1) void fmm_limb_gemm(LimbGemm a) {
-    constexpr int BK = 32, NT = 256, RS = 32;
-    constexpr int TI = BM / 32, TJ = BN / 32;  // 16 x 16 MFMA blocks per wave
+template <bool HALF, int NL, int BM, int BN, int WM, int WN, bool SCALED, bool DIRECT>
+__global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm(LimbGemm a) {
+    constexpr int BK = 32, NT = 64 * WM * WN, RS = 32;
+    constexpr int TI = BM / (16 * WM), TJ = BN / (16 * WN);  // 16 x 16 MFMA blocks per wave
     constexpr int CA = NL * BM * 4 / NT, CB = NL * BN * 4 / NT;  // 16-byte chunks per thread and stage
     static_assert(CA * NT == NL * BM * 4 && CB * NT == NL * BN * 4, "chunk split");
     typedef Products<NL> P;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256, 1) void fmm_limb_gemm(LimbGemm a) {
     __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NL][BN * RS];
 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WN, wn = wave % WN;
     const int64_t tiles = (int64_t)a.tiles_m * a.tiles_n;
     const int bid = __builtin_amdgcn_readfirstlane((int)xcd_remap_g(blockIdx.x, gridDim.x));
     const int leaf = __builtin_amdgcn_readfirstlane((int)(bid / tiles));
@@ -248,12 +248,12 @@ __global__ __launch_bounds__(256, 1) void fmm_limb_gemm(LimbGemm a) {
         for (int l = 0; l < NL; ++l) {
 #pragma unroll
             for (int i = 0; i < TI; ++i) {
-                const int rr = wm * (BM / 2) + i * 16 + l16;
+                const int rr = wm * (BM / WM) + i * 16 + l16;
                 fa[i][l] = *reinterpret_cast<const gs8 *>(&As[cur][l][rr * RS + 8 * swz(rr, g)]);
             }
 #pragma unroll
             for (int j = 0; j < TJ; ++j) {
-                const int rr = wn * (BN / 2) + j * 16 + l16;
+                const int rr = wn * (BN / WN) + j * 16 + l16;
                 fb[j][l] = *reinterpret_cast<const gs8 *>(&Bs[cur][l][rr * RS + 8 * swz(rr, g)]);
             }
         }
@@ -277,8 +277,8 @@ __global__ __launch_bounds__(256, 1) void fmm_limb_gemm(LimbGemm a) {
         for (int j = 0; j < TJ; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t row = tm * BM + wm * (BM / 2) + i * 16 + 4 * (lane >> 4) + v;  // inside the leaf block
-                const int64_t col = tn * BN + wn * (BN / 2) + j * 16 + l16;
+                const int64_t row = tm * BM + wm * (BM / WM) + i * 16 + 4 * (lane >> 4) + v;  // inside the leaf block
+                const int64_t col = tn * BN + wn * (BN / WN) + j * 16 + l16;
                 float val = acc[i][j][v];
                 if (DIRECT) {
                     if (row < a.m && col < a.n) {
@@ -304,18 +304,18 @@ hipError_t form_go(const PlaneForm &f, int nleaves, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <bool HALF, int NL, int BM, int BN>
+template <bool HALF, int NL, int BM, int BN, int WM, int WN>
 hipError_t gemm_go(const LimbGemm &g, int nleaves, hipStream_t s) {
     const int64_t blocks = (int64_t)g.tiles_m * g.tiles_n * nleaves;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const bool scaled = g.sc.ea != nullptr;
-    const dim3 grid((unsigned)blocks), block(256);
+    const dim3 grid((unsigned)blocks), block(64 * WM * WN);
     if (g.direct) {
-        if (scaled) hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, BN, true, true>), grid, block, 0, s, g);
-        else hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, BN, false, true>), grid, block, 0, s, g);
+        if (scaled) hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, BN, WM, WN, true, true>), grid, block, 0, s, g);
+        else hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, BN, WM, WN, false, true>), grid, block, 0, s, g);
     } else {
-        hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, BN, false, false>), grid, block, 0, s, g);
+        hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, BN, WM, WN, false, false>), grid, block, 0, s, g);
     }
     return hipGetLastError();
 }
@@ -323,9 +323,9 @@ hipError_t gemm_go(const LimbGemm &g, int nleaves, hipStream_t s) {
 template <bool HALF, int NL>
 hipError_t gemm_tile(int bm, const LimbGemm &g, int nleaves, hipStream_t s) {
     if constexpr (NL < 3) {
-        if (bm == 256) return gemm_go<HALF, NL, 256, 256>(g, nleaves, s);
+        if (bm == 256) return gemm_go<HALF, NL, 256, 256, 2, 4>(g, nleaves, s);
     }
-    return gemm_go<HALF, NL, 128, 128>(g, nleaves, s);
+    return gemm_go<HALF, NL, 128, 128, 2, 2>(g, nleaves, s);
 }
 
 }  // namespace
