@@ -71,6 +71,7 @@ struct Tables {
     SrcEntry *asrc = nullptr;
     SrcEntry *bsrc = nullptr;
     BlockDests *bdest = nullptr;
+    float *ucoef = nullptr, *vcoef = nullptr;  // the rule's U (M0K0 x R) and V (K0N0 x R), row-major
     DestEntry *dest = nullptr;
     int device = -1;
     ~Tables() {
@@ -83,6 +84,8 @@ struct Tables {
             (void)hipFree(bsrc);
             (void)hipFree(bdest);
             (void)hipFree(dest);
+            (void)hipFree(ucoef);
+            (void)hipFree(vcoef);
             (void)hipSetDevice(cur);
         }
     }
@@ -304,11 +307,57 @@ SplitDims split_dims(int prec, const Shape &s) {
     return d;
 }
 
+// Split precisions form the leaf operands from the composite source lists (form_planes: every
+// leaf reads its own sources, (nnz(U)/R)^L of them on average) or level by level (form_node:
+// every level reads each node operand once and writes all R children).  The composite pass
+// streams better; the level-by-level one wins once the average fan-in is large (measured on
+// MI355X at n = 8192: <4,2,4> depth 2, fan-in ~12, 5.7 against 8.1 ms; Strassen depth 2,
+// fan-in 2.9, 1.75 against 0.95 ms).  Level by level needs every product live (then the
+// composite leaves are exactly the R^L children, in the same order).
+bool level_formation(const fastmm_plan_s *p, const Shape &s) {
+    const Algo &a = plan_algo(p);
+    if (s.L < 2) return false;
+    int64_t all = 1;
+    for (int l = 0; l < s.L; ++l) all *= a.R;
+    if (leaf_count(a, s.L) != all) return false;
+    int64_t nu = 0, nv = 0;
+    for (int64_t x : a.U) nu += x != 0;
+    for (int64_t x : a.V) nv += x != 0;
+    const double fan = 0.5 * (std::pow((double)nu / a.R, s.L) + std::pow((double)nv / a.R, s.L));
+    return fan > 8.0;
+}
+
+// Geometry of the inner levels 1 .. L-1 of one operand side (FP32 children in the workspace):
+// child block size, row stride, bytes per child, byte offset of the level; the last entry's
+// offset is the total.
+struct InnerLevel {
+    int64_t cb_o, cb_k, y_ld, y_stride, count;
+    size_t off;
+};
+std::vector<InnerLevel> inner_levels(const fastmm_plan_s *p, const Shape &s, bool side_b) {
+    const Algo &a = plan_algo(p);
+    const int nO = side_b ? a.N0 : a.M0, nK = a.K0;
+    const int64_t O = side_b ? s.Np : s.Mp, K = s.Kp;
+    std::vector<InnerLevel> v;
+    int64_t po = 1, pk = 1, count = 1;
+    size_t off = 0;
+    for (int l = 1; l < s.L; ++l) {
+        po *= nO, pk *= nK, count *= a.R;
+        InnerLevel e;
+        e.cb_o = O / po, e.cb_k = K / pk, e.y_ld = (e.cb_k + 7) / 8 * 8, e.y_stride = e.cb_o * e.y_ld;
+        e.count = count, e.off = off;
+        off = align256(off + 4 * (size_t)count * e.y_stride);
+        v.push_back(e);
+    }
+    v.push_back(InnerLevel{0, 0, 0, 0, 0, off});
+    return v;
+}
+
 // Workspace layout: [ea m][ep k][eb n][flags 2] int32 | [maxA max(m,k)][maxB max(k,n)] elems |
 // split precisions: [S limb planes][T^T limb planes] 16-bit | [leaf products nleaves * mb * nb]
 // elems.
 struct WsLayout {
-    size_t ea, ep, eb, flags, maxA, maxB, sp, tp, leaves, total;
+    size_t ea, ep, eb, flags, maxA, maxB, sp, tp, ia, ib, leaves, total;
 };
 
 WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n) {
@@ -328,6 +377,10 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
         const size_t nleaves = (size_t)leaf_count(plan_algo(p), s.L);
         w.sp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.mbp * d.kp);
         w.tp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.nbp * d.kp);
+        if (level_formation(p, s)) {
+            w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
+            w.ib = off, off = align256(off + inner_levels(p, s, true).back().off);
+        }
     }
     w.leaves = off;
     if (s.L > 0) off = align256(off + es * (size_t)leaf_count(plan_algo(p), s.L) * s.mb * s.nb);
@@ -386,6 +439,16 @@ fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
         (e = upload(&t->bsrc, ht.bsrc)) != hipSuccess || (e = upload(&t->bdest, ht.bdest)) != hipSuccess ||
         (e = upload(&t->dest, ht.dest)) != hipSuccess)
         return hip_fail(e, "uploading task tables");
+    {
+        const Algo &a = plan_algo(p);
+        std::vector<float> u((size_t)a.M0 * a.K0 * a.R), v((size_t)a.K0 * a.N0 * a.R);
+        for (int i = 0; i < a.M0 * a.K0; ++i)
+            for (int r = 0; r < a.R; ++r) u[(size_t)i * a.R + r] = (float)a.u(i, r);
+        for (int j = 0; j < a.K0 * a.N0; ++j)
+            for (int r = 0; r < a.R; ++r) v[(size_t)j * a.R + r] = (float)a.v(j, r);
+        if ((e = upload(&t->ucoef, u)) != hipSuccess || (e = upload(&t->vcoef, v)) != hipSuccess)
+            return hip_fail(e, "uploading coefficients");
+    }
     *out = t.get();
     p->tables[key] = std::move(t);
     return FASTMM_OK;
@@ -689,12 +752,16 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         // Split precisions: limb planes of every S_r and T_r^T (k contiguous, zero-padded to
         // the GEMM tiles), then the limb GEMM, then (L >= 1) the W-combination.
         const SplitDims d = split_dims(plan->prec, s);
+        // With scaling the operands have row / column maxima near 1; fp16 limbs are then moved
+        // up by 2^8 (exact), away from fp16's subnormal range, and the products down by 2^-16.
+        const bool f16 = plan->prec == FASTMM_F16 || plan->prec == FASTMM_F16X3;
+        const int pre = (f16 && exps.ea) ? 8 : 0;
         PlaneForm fa{};
         fa.X = (const float *)A;
         fa.ld_o = transA ? 1 : lda, fa.ld_k = transA ? lda : 1;  // op(A)(i, kk)
         fa.R = m, fa.K = k, fa.rb = s.mb, fa.kb = s.kb, fa.rowsp = d.mbp, fa.kp = d.kp, fa.bt = d.bm;
         fa.leaves = tab->leaves, fa.src = tab->asrc, fa.b_side = 0;
-        fa.e_o = exps.ea, fa.e_k = exps.ep, fa.s_o = -1, fa.s_k = 1;  // 2^(ep_kk - ea_i)
+        fa.e_o = exps.ea, fa.e_k = exps.ep, fa.s_o = -1, fa.s_k = 1, fa.pre_exp = pre;  // 2^(ep_kk - ea_i)
         fa.planes = (unsigned short *)(ws + w.sp), fa.plane_stride = d.mbp * d.kp;
         fa.leaf_stride = d.nl * d.mbp * d.kp;
         PlaneForm fb{};
@@ -702,17 +769,56 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         fb.ld_o = transB ? ldb : 1, fb.ld_k = transB ? 1 : ldb;  // op(B)(kk, j) as T^T(j, kk)
         fb.R = n, fb.K = k, fb.rb = s.nb, fb.kb = s.kb, fb.rowsp = d.nbp, fb.kp = d.kp, fb.bt = d.bm;
         fb.leaves = tab->leaves, fb.src = tab->bsrc, fb.b_side = 1;
-        fb.e_o = exps.eb, fb.e_k = exps.ep, fb.s_o = -1, fb.s_k = -1;  // 2^(-ep_kk - eb_j)
+        fb.e_o = exps.eb, fb.e_k = exps.ep, fb.s_o = -1, fb.s_k = -1, fb.pre_exp = pre;  // 2^(-ep_kk - eb_j)
         fb.planes = (unsigned short *)(ws + w.tp), fb.plane_stride = d.nbp * d.kp;
         fb.leaf_stride = d.nl * d.nbp * d.kp;
-        if ((e = launch_form_planes(plan->prec, fa, tab->nleaves, st)) != hipSuccess ||
-            (e = launch_form_planes(plan->prec, fb, tab->nleaves, st)) != hipSuccess)
+        if (level_formation(plan, s)) {
+            // level by level: every level reads its node operands once and writes all R children
+            const Algo &al = plan_algo(plan);
+            auto form_side = [&](bool side_b) -> hipError_t {
+                const PlaneForm &pf = side_b ? fb : fa;
+                const std::vector<InnerLevel> lv = inner_levels(plan, s, side_b);
+                char *ibase = ws + (side_b ? w.ib : w.ia);
+                int64_t nodes = 1;
+                for (int l = 1; l <= s.L; ++l) {
+                    NodeForm nf{};
+                    if (l == 1) {
+                        nf.X = pf.X, nf.ld_o = pf.ld_o, nf.ld_k = pf.ld_k, nf.R = pf.R, nf.K = pf.K, nf.first = 1;
+                        nf.e_o = pf.e_o, nf.e_k = pf.e_k, nf.s_o = pf.s_o, nf.s_k = pf.s_k, nf.pre_exp = pf.pre_exp;
+                    } else {
+                        const InnerLevel &in = lv[l - 2];
+                        nf.X = (const float *)(ibase + in.off), nf.ld_o = in.y_ld, nf.ld_k = 1;
+                        nf.node_stride = in.y_stride, nf.first = 0;
+                    }
+                    nf.nO = side_b ? al.N0 : al.M0, nf.nK = al.K0, nf.side_b = side_b ? 1 : 0, nf.R_ = al.R;
+                    nf.coef = side_b ? tab->vcoef : tab->ucoef;
+                    if (l == s.L) {
+                        nf.cb_o = pf.rb, nf.cb_k = pf.kb, nf.last = 1;
+                        nf.planes = pf.planes, nf.rowsp = pf.rowsp, nf.kp = pf.kp, nf.bt = pf.bt;
+                        nf.plane_stride = pf.plane_stride, nf.leaf_stride = pf.leaf_stride;
+                    } else {
+                        const InnerLevel &out = lv[l - 1];
+                        nf.cb_o = out.cb_o, nf.cb_k = out.cb_k, nf.last = 0;
+                        nf.Y = (float *)(ibase + out.off), nf.y_ld = out.y_ld, nf.y_stride = out.y_stride;
+                    }
+                    if (nodes > 65535) return hipErrorInvalidValue;
+                    hipError_t er = launch_form_node(plan->prec, nf, (int)nodes, st);
+                    if (er != hipSuccess) return er;
+                    nodes *= al.R;
+                }
+                return hipSuccess;
+            };
+            if ((e = form_side(false)) != hipSuccess || (e = form_side(true)) != hipSuccess)
+                return hip_fail(e, "limb plane formation");
+        } else if ((e = launch_form_planes(plan->prec, fa, tab->nleaves, st)) != hipSuccess ||
+                   (e = launch_form_planes(plan->prec, fb, tab->nleaves, st)) != hipSuccess) {
             return hip_fail(e, "limb plane formation");
+        }
         fin.mark();
         LimbGemm g{};
         g.S = fa.planes, g.T = fb.planes, g.kp = d.kp;
         g.s_plane = fa.plane_stride, g.s_leaf = fa.leaf_stride, g.t_plane = fb.plane_stride, g.t_leaf = fb.leaf_stride;
-        g.mb = s.mb, g.nb = s.nb, g.m = m, g.n = n, g.sc = exps;
+        g.mb = s.mb, g.nb = s.nb, g.m = m, g.n = n, g.sc = exps, g.post_exp = -2 * pre;
         g.tiles_m = (int)(d.mbp / d.bm), g.tiles_n = (int)(d.nbp / d.bm);
         if (s.L == 0) {
             g.out = (float *)C, g.ldo = ldc, g.leaf_stride = 0, g.direct = 1;

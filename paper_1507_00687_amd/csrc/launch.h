@@ -117,6 +117,7 @@ struct PlaneForm {
     int b_side;
     const int32_t *e_o, *e_k;
     int s_o, s_k;
+    int pre_exp;  // with scaling (e_o not null): every value also times 2^pre_exp
     unsigned short *planes;
     int64_t plane_stride, leaf_stride;
 };
@@ -130,9 +131,38 @@ struct LimbGemm {
     float *out;
     int64_t ldo, leaf_stride, mb, nb, m, n;
     ScaleExps sc;
+    int post_exp;  // every product times 2^post_exp (undoes the formation's pre_exp)
     int tiles_m, tiles_n;
     int direct;
 };
+// Split precisions, pass 1 level by level: one recursion level of the operand formation.  The
+// node operand of node q is op(X) itself on the first level (element (o, kk) at
+// X[o * ld_o + kk * ld_k], zero outside R x K, scaled by 2^(s_o e_o[o] + s_k e_k[kk] + pre_exp)
+// when e_o is not null) or, below it, the FP32 block X + q * node_stride (element (o, kk) at
+// o * ld_o + kk).  It has nO x nK sub-blocks of cb_o x cb_k; sub-block s sits at o-block
+// (side_b ? s / nK : s % nO) and k-block (side_b ? s % nK : s / nO) (eq. (1): A and B blocks
+// column-major).  Child c = sum_s coef[s * R_ + c] X_s of node q gets index q * R_ + c and is
+// written either as limb planes (last: same layout as PlaneForm, rowsp x kp, blocked by bt) or as
+// an FP32 block Y + index * y_stride with row stride y_ld (a multiple of 8, >= cb_k; columns
+// cb_k .. y_ld-1 written as zeros).
+struct NodeForm {
+    const float *X;
+    int64_t ld_o, ld_k, R, K;
+    int64_t node_stride;
+    int first;
+    int nO, nK, side_b, R_;
+    const float *coef;
+    int64_t cb_o, cb_k;
+    const int32_t *e_o, *e_k;
+    int s_o, s_k, pre_exp;
+    int last;
+    float *Y;
+    int64_t y_stride, y_ld;
+    unsigned short *planes;
+    int64_t rowsp, kp, bt, plane_stride, leaf_stride;
+    int nl, half;  // set by launch_form_node from the precision
+};
+hipError_t launch_form_node(int prec, const NodeForm &f, int nodes, hipStream_t s);
 int limb_count(int prec);                   // limbs per element of a split precision
 int limb_gemm_tile(int prec, int64_t mb, int64_t nb);  // square tile of the limb GEMM (128 or 256)
 hipError_t launch_form_planes(int prec, const PlaneForm &f, int nleaves, hipStream_t s);

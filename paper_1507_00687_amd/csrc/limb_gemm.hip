@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void form_planes(PlaneForm a) {
             const bool ok = ob < a.rb && kb < a.kb && o < a.R && kk < a.K;
             const float y = *(ok ? a.X + o * a.ld_o + kk * a.ld_k : a.X);
             float x = ok ? y : 0.f;
-            if (SCALED) x = ldexpf(x, a.s_o * a.e_o[ok ? o : 0] + a.s_k * a.e_k[ok ? kk : 0]);
+            if (SCALED) x = ldexpf(x, a.s_o * a.e_o[ok ? o : 0] + a.s_k * a.e_k[ok ? kk : 0] + a.pre_exp);
             v[e] = (q == 0) ? c * x : v[e] + c * x;
         }
     }
@@ -126,6 +126,93 @@ __global__ __launch_bounds__(256) void form_planes(PlaneForm a) {
             *reinterpret_cast<uint4 *>(a.planes + (int64_t)leaf * a.leaf_stride + l * a.plane_stride +
                                        ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 +
                                        kk % 32) = w;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ pass 1, level by level
+// One recursion level of the operand formation for a node operand X (eq. (1)): the node's nS
+// sub-blocks X_s are read once and all R children C_c = sum_s coef[s][c] X_s are written, as
+// FP32 blocks (inner levels) or as limb planes (last level).  Each work-group handles a TO x 64
+// tile position (o, kk) of the child blocks: it stages the nS sub-block tiles in LDS, then forms
+// every child tile from them.  Children of node q are numbered q R + c, the order of the
+// composite leaves (first level most significant).
+template <int TO>
+__global__ __launch_bounds__(256) void form_node(NodeForm a) {
+    extern __shared__ float ntile[];  // [nS][TO][65], then the nS x R_ coefficients
+    const int t = threadIdx.x;
+    const int q = blockIdx.z;
+    const int64_t o0 = (int64_t)blockIdx.y * TO, k0 = (int64_t)blockIdx.x * 64;
+    const int nS = a.nO * a.nK;
+    const bool kc = a.ld_k == 1;
+    const float *X = a.X + (a.first ? 0 : (int64_t)q * a.node_stride);
+    float *coef = ntile + nS * TO * 65;
+    for (int i = t; i < nS * a.R_; i += 256) coef[i] = a.coef[i];
+    for (int sb = 0; sb < nS; ++sb) {
+        const int ob = a.side_b ? sb / a.nK : sb % a.nO, kbk = a.side_b ? sb % a.nK : sb / a.nO;
+        for (int e = t; e < TO * 64; e += 256) {
+            // consecutive lanes along the operand's contiguous direction
+            const int lo = kc ? e / 64 : e % TO, lk = kc ? e % 64 : e / TO;
+            const int64_t oc = o0 + lo, kcn = k0 + lk;  // inside the child block
+            const int64_t o = ob * a.cb_o + oc, kk = kbk * a.cb_k + kcn;  // inside the node operand
+            bool ok = oc < a.cb_o && kcn < a.cb_k;
+            if (a.first) ok = ok && o < a.R && kk < a.K;
+            const float y = *(ok ? X + o * a.ld_o + kk * a.ld_k : X);
+            float x = ok ? y : 0.f;
+            if (a.first && a.e_o) x = ldexpf(x, a.s_o * a.e_o[ok ? o : 0] + a.s_k * a.e_k[ok ? kk : 0] + a.pre_exp);
+            ntile[(sb * TO + lo) * 65 + lk] = x;
+        }
+    }
+    __syncthreads();
+    for (int c = 0; c < a.R_; ++c) {
+        for (int task = t; task < TO * 8; task += 256) {
+            // consecutive lanes on consecutive rows: the row stride of 65 words puts them on
+            // distinct banks for every k offset
+            const int ro = task % TO, rk = (task / TO) * 8;
+            float v[8];
+            bool first = true;
+            for (int sb = 0; sb < nS; ++sb) {
+                const float u = coef[sb * a.R_ + c];
+                if (u == 0.f) continue;
+                const float *src = &ntile[(sb * TO + ro) * 65 + rk];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = first ? u * src[j] : v[j] + u * src[j];
+                first = false;
+            }
+            if (first) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = 0.f;
+            }
+            const int64_t child = (int64_t)q * a.R_ + c, o = o0 + ro, kk = k0 + rk;
+            if (a.last) {
+                unsigned short h[3][8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    float r = v[j];
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) {
+                        float back;
+                        h[l][j] = a.half ? LimbT<true>::split(r, back) : LimbT<false>::split(r, back);
+                        r = r - back;
+                    }
+                }
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    if (l >= a.nl) break;
+                    uint4 w;
+                    w.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
+                    w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
+                    w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
+                    w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
+                    *reinterpret_cast<uint4 *>(a.planes + child * a.leaf_stride + l * a.plane_stride +
+                                               ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 +
+                                               kk % 32) = w;
+                }
+            } else if (o < a.cb_o && kk < a.y_ld) {
+                float *dst = a.Y + child * a.y_stride + o * a.y_ld + kk;
+                *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                *reinterpret_cast<float4 *>(dst + 4) = make_float4(v[4], v[5], v[6], v[7]);
+            }
         }
     }
 }
@@ -281,11 +368,12 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm(LimbGemm a) {
                 const int64_t col = tn * BN + wn * (BN / WN) + j * 16 + l16;
                 float val = acc[i][j][v];
                 if (DIRECT) {
-                    if (row < a.m && col < a.n) {
-                        if (SCALED) val = ldexpf(val, a.sc.ea[row] + a.sc.eb[col]);
+                    if (row < a.m && col < a.n) {  // one power-of-two factor: exact unless it underflows
+                        if (SCALED) val = ldexpf(val, a.post_exp + a.sc.ea[row] + a.sc.eb[col]);
                         a.out[row * a.ldo + col] = val;
                     }
                 } else if (row < a.mb && col < a.nb) {
+                    if (a.post_exp) val = ldexpf(val, a.post_exp);
                     a.out[(int64_t)leaf * a.leaf_stride + row * a.ldo + col] = val;
                 }
             }
@@ -343,6 +431,25 @@ int limb_count(int prec) {
 
 int limb_gemm_tile(int prec, int64_t mb, int64_t nb) {
     return (limb_count(prec) < 3 && mb >= 256 && nb >= 256) ? 256 : 128;
+}
+
+hipError_t launch_form_node(int prec, const NodeForm &f, int nodes, hipStream_t s) {
+    NodeForm a = f;
+    a.nl = limb_count(prec);
+    a.half = (prec == FASTMM_F16 || prec == FASTMM_F16X3) ? 1 : 0;
+    const int nS = a.nO * a.nK;
+    if (nS < 1 || nS > 16 || nodes <= 0) return nodes <= 0 ? hipSuccess : hipErrorInvalidValue;
+    const int TO = nS <= 4 ? 32 : (nS <= 8 ? 16 : 8);
+    const int64_t ext_o = a.last ? a.rowsp : a.cb_o, ext_k = a.last ? a.kp : a.y_ld;
+    const int64_t gx = (ext_k + 63) / 64, gy = (ext_o + TO - 1) / TO;
+    if (gx <= 0 || gy <= 0) return hipSuccess;
+    if (gx > 0x7fffffffLL || gy > 65535 || nodes > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)nodes);
+    const size_t lds = ((size_t)nS * TO * 65 + (size_t)nS * a.R_) * sizeof(float);
+    if (TO == 32) hipLaunchKernelGGL(form_node<32>, grid, dim3(256), lds, s, a);
+    else if (TO == 16) hipLaunchKernelGGL(form_node<16>, grid, dim3(256), lds, s, a);
+    else hipLaunchKernelGGL(form_node<8>, grid, dim3(256), lds, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_form_planes(int prec, const PlaneForm &f, int nleaves, hipStream_t s) {

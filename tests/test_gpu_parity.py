@@ -223,12 +223,25 @@ U_EFF = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11, "bf16x3": 2.0 ** -16, "f16x3": 2.
     ("f424", 1, (160, 96, 200)),
     ("winograd", 1, (130, 257, 99)),
     ("classical", 0, (300, 129, 257)),
+    ("f323", 2, (200, 150, 220)),     # two formation levels, ragged
+    ("strassen", 3, (300, 260, 280)),  # three formation levels
 ])
 def test_split_precision_integer_inputs_bit_exact(precision, name, depth, shape):
     # Every S/T entry is a multiple of 1/2 below 2^7 in magnitude, so the first limb holds it
     # exactly in bf16 and fp16 and the FP32 accumulation of the integer products is exact.
     print(f"\n[split-int] {name} L={depth} {shape} {precision}", flush=True)
     A, B = make_pair("int8", 2, *shape, dtype=np.float32)
+    got = run_gpu(_plan(name, depth, 1, precision), A, B)
+    assert np.array_equal(got.astype(np.float64), _exact(A, B))
+
+
+@pytest.mark.parametrize("precision", ["f16x3", "bf16x6"])
+@pytest.mark.parametrize("name,depth,shape", [("f424", 2, (200, 40, 180)), ("f244", 2, (70, 180, 150))])
+def test_split_precision_level_formation_integer_exact(precision, name, depth, shape):
+    # High fan-in plans form their limb planes level by level (an inner FP32 level, then the
+    # planes); with two or three limbs every S/T entry (a multiple of 1/4 below 2^11) is exact.
+    print(f"\n[split-levels] {name} L={depth} {shape} {precision}", flush=True)
+    A, B = make_pair("int8", 6, *shape, dtype=np.float32)
     got = run_gpu(_plan(name, depth, 1, precision), A, B)
     assert np.array_equal(got.astype(np.float64), _exact(A, B))
 
