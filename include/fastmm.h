@@ -213,12 +213,14 @@ fastmm_status fastmm_batched_workspace_size(const fastmm_plan_t *plans, const fa
                                             int count, size_t *bytes);
 
 /* Multiply `count` independent problems, problem i with plans[i] (its own rule, depth,
- * cutoff and scaling; all plans must share one precision, FASTMM_F64 or FASTMM_F32).  Each
- * problem's scaling steps run first; then ONE persistent launch computes the leaf tiles of all
- * problems (work items ordered by problem, largest inner dimension first, assigned to
- * work-groups round-robin: deterministic), then the W-combinations.  Outputs must not overlap
- * any input.  The per-call descriptor table is copied from host memory into the workspace
- * (a staged copy). */
+ * cutoff and scaling; all plans must share one precision).  Each problem's scaling steps run
+ * first (and, for the split precisions, its limb-plane formation); then ONE launch computes the
+ * leaf tiles of all problems (work items ordered by problem, largest inner dimension first:
+ * FP64/FP32 on persistent work-groups assigned round-robin, split precisions one work-group per
+ * item with one limb-GEMM tile for the whole batch; deterministic either way), then the
+ * W-combinations.  FP64/FP32 problems always take the leaf path (fastmm_plan_path).  Outputs
+ * must not overlap any input.  The per-call descriptor table is copied from host memory into
+ * the workspace (a staged copy). */
 fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_problem *probs, int count,
                                   void *workspace, size_t ws_bytes, void *stream);
 

@@ -299,10 +299,11 @@ struct SplitDims {
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-SplitDims split_dims(int prec, const Shape &s) {
+// bm_force (a batch's common tile) overrides the tile chosen for the shape.
+SplitDims split_dims(int prec, const Shape &s, int bm_force = 0) {
     SplitDims d;
     d.nl = limb_count(prec);
-    d.bm = limb_gemm_tile(prec, s.mb, s.nb);
+    d.bm = bm_force ? bm_force : limb_gemm_tile(prec, s.mb, s.nb);
     d.mbp = round_up(s.mb, d.bm), d.nbp = round_up(s.nb, d.bm), d.kp = round_up(s.kb, 64);
     return d;
 }
@@ -360,7 +361,7 @@ struct WsLayout {
     size_t ea, ep, eb, flags, maxA, maxB, sp, tp, ia, ib, leaves, total;
 };
 
-WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n) {
+WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n, int bm_force = 0) {
     WsLayout w{};
     const size_t es = elem_size(p->prec);
     size_t off = 0;
@@ -373,7 +374,7 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
         w.maxB = off, off = align256(off + es * (size_t)std::max(k, n));
     }
     if (is_split(p->prec)) {
-        const SplitDims d = split_dims(p->prec, s);
+        const SplitDims d = split_dims(p->prec, s, bm_force);
         const size_t nleaves = (size_t)leaf_count(plan_algo(p), s.L);
         w.sp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.mbp * d.kp);
         w.tp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.nbp * d.kp);
@@ -677,6 +678,88 @@ fastmm_status fastmm_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, in
     return FASTMM_OK;
 }
 
+namespace fastmm {
+namespace {
+// Split precisions, pass 1: the limb planes of every leaf's S_r and T_r^T (scaling applied),
+// composite or level by level; fills the plane part of the limb-GEMM launch g.
+hipError_t split_form(fastmm_plan_s *plan, const Shape &s, const SplitDims &d, const void *A, int64_t lda,
+                      int transA, const void *B, int64_t ldb, int transB, int64_t m, int64_t k, int64_t n,
+                      const ScaleExps &exps, char *ws, const WsLayout &w, const Tables *tab, hipStream_t st,
+                      LimbGemm &g) {
+    hipError_t e;
+    // With scaling the operands have row / column maxima near 1; fp16 limbs are then moved
+    // up by 2^8 (exact), away from fp16's subnormal range, and the products down by 2^-16.
+    const bool f16 = plan->prec == FASTMM_F16 || plan->prec == FASTMM_F16X3;
+    const int pre = (f16 && exps.ea) ? 8 : 0;
+    PlaneForm fa{};
+    fa.X = (const float *)A;
+    fa.ld_o = transA ? 1 : lda, fa.ld_k = transA ? lda : 1;  // op(A)(i, kk)
+    fa.R = m, fa.K = k, fa.rb = s.mb, fa.kb = s.kb, fa.rowsp = d.mbp, fa.kp = d.kp, fa.bt = d.bm;
+    fa.leaves = tab->leaves, fa.src = tab->asrc, fa.b_side = 0;
+    fa.e_o = exps.ea, fa.e_k = exps.ep, fa.s_o = -1, fa.s_k = 1, fa.pre_exp = pre;  // 2^(ep_kk - ea_i)
+    fa.planes = (unsigned short *)(ws + w.sp), fa.plane_stride = d.mbp * d.kp;
+    fa.leaf_stride = d.nl * d.mbp * d.kp;
+    PlaneForm fb{};
+    fb.X = (const float *)B;
+    fb.ld_o = transB ? ldb : 1, fb.ld_k = transB ? 1 : ldb;  // op(B)(kk, j) as T^T(j, kk)
+    fb.R = n, fb.K = k, fb.rb = s.nb, fb.kb = s.kb, fb.rowsp = d.nbp, fb.kp = d.kp, fb.bt = d.bm;
+    fb.leaves = tab->leaves, fb.src = tab->bsrc, fb.b_side = 1;
+    fb.e_o = exps.eb, fb.e_k = exps.ep, fb.s_o = -1, fb.s_k = -1, fb.pre_exp = pre;  // 2^(-ep_kk - eb_j)
+    fb.planes = (unsigned short *)(ws + w.tp), fb.plane_stride = d.nbp * d.kp;
+    fb.leaf_stride = d.nl * d.nbp * d.kp;
+    if (level_formation(plan, s)) {
+        // level by level: every level reads its node operands once and writes all R children
+        const Algo &al = plan_algo(plan);
+        auto form_side = [&](bool side_b) -> hipError_t {
+            const PlaneForm &pf = side_b ? fb : fa;
+            const std::vector<InnerLevel> lv = inner_levels(plan, s, side_b);
+            char *ibase = ws + (side_b ? w.ib : w.ia);
+            int64_t nodes = 1;
+            for (int l = 1; l <= s.L; ++l) {
+                NodeForm nf{};
+                if (l == 1) {
+                    nf.X = pf.X, nf.ld_o = pf.ld_o, nf.ld_k = pf.ld_k, nf.R = pf.R, nf.K = pf.K, nf.first = 1;
+                    nf.e_o = pf.e_o, nf.e_k = pf.e_k, nf.s_o = pf.s_o, nf.s_k = pf.s_k, nf.pre_exp = pf.pre_exp;
+                } else {
+                    const InnerLevel &in = lv[l - 2];
+                    nf.X = (const float *)(ibase + in.off), nf.ld_o = in.y_ld, nf.ld_k = 1;
+                    nf.node_stride = in.y_stride, nf.first = 0;
+                }
+                nf.nO = side_b ? al.N0 : al.M0, nf.nK = al.K0, nf.side_b = side_b ? 1 : 0, nf.R_ = al.R;
+                nf.coef = side_b ? tab->vcoef : tab->ucoef;
+                if (l == s.L) {
+                    nf.cb_o = pf.rb, nf.cb_k = pf.kb, nf.last = 1;
+                    nf.planes = pf.planes, nf.rowsp = pf.rowsp, nf.kp = pf.kp, nf.bt = pf.bt;
+                    nf.plane_stride = pf.plane_stride, nf.leaf_stride = pf.leaf_stride;
+                } else {
+                    const InnerLevel &out = lv[l - 1];
+                    nf.cb_o = out.cb_o, nf.cb_k = out.cb_k, nf.last = 0;
+                    nf.Y = (float *)(ibase + out.off), nf.y_ld = out.y_ld, nf.y_stride = out.y_stride;
+                }
+                if (nodes > 65535) return hipErrorInvalidValue;
+                hipError_t er = launch_form_node(plan->prec, nf, (int)nodes, st);
+                if (er != hipSuccess) return er;
+                nodes *= al.R;
+            }
+            return hipSuccess;
+        };
+        if ((e = form_side(false)) != hipSuccess || (e = form_side(true)) != hipSuccess)
+            return e;
+    } else if ((e = launch_form_planes(plan->prec, fa, tab->nleaves, st)) != hipSuccess ||
+               (e = launch_form_planes(plan->prec, fb, tab->nleaves, st)) != hipSuccess) {
+        return e;
+    }
+    g = LimbGemm{};
+    g.S = fa.planes, g.T = fb.planes, g.kp = d.kp;
+    g.s_plane = fa.plane_stride, g.s_leaf = fa.leaf_stride, g.t_plane = fb.plane_stride, g.t_leaf = fb.leaf_stride;
+    g.mb = s.mb, g.nb = s.nb, g.m = m, g.n = n, g.sc = exps, g.post_exp = -2 * pre;
+    g.tiles_m = (int)(d.mbp / d.bm), g.tiles_n = (int)(d.nbp / d.bm);
+    return hipSuccess;
+}
+
+}  // namespace
+}  // namespace fastmm
+
 fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int transA, const void *B, int64_t ldb,
                              int transB, void *C, int64_t ldc, int64_t m, int64_t k, int64_t n, void *workspace,
                              size_t ws_bytes, void *stream) {
@@ -752,74 +835,10 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         // Split precisions: limb planes of every S_r and T_r^T (k contiguous, zero-padded to
         // the GEMM tiles), then the limb GEMM, then (L >= 1) the W-combination.
         const SplitDims d = split_dims(plan->prec, s);
-        // With scaling the operands have row / column maxima near 1; fp16 limbs are then moved
-        // up by 2^8 (exact), away from fp16's subnormal range, and the products down by 2^-16.
-        const bool f16 = plan->prec == FASTMM_F16 || plan->prec == FASTMM_F16X3;
-        const int pre = (f16 && exps.ea) ? 8 : 0;
-        PlaneForm fa{};
-        fa.X = (const float *)A;
-        fa.ld_o = transA ? 1 : lda, fa.ld_k = transA ? lda : 1;  // op(A)(i, kk)
-        fa.R = m, fa.K = k, fa.rb = s.mb, fa.kb = s.kb, fa.rowsp = d.mbp, fa.kp = d.kp, fa.bt = d.bm;
-        fa.leaves = tab->leaves, fa.src = tab->asrc, fa.b_side = 0;
-        fa.e_o = exps.ea, fa.e_k = exps.ep, fa.s_o = -1, fa.s_k = 1, fa.pre_exp = pre;  // 2^(ep_kk - ea_i)
-        fa.planes = (unsigned short *)(ws + w.sp), fa.plane_stride = d.mbp * d.kp;
-        fa.leaf_stride = d.nl * d.mbp * d.kp;
-        PlaneForm fb{};
-        fb.X = (const float *)B;
-        fb.ld_o = transB ? ldb : 1, fb.ld_k = transB ? 1 : ldb;  // op(B)(kk, j) as T^T(j, kk)
-        fb.R = n, fb.K = k, fb.rb = s.nb, fb.kb = s.kb, fb.rowsp = d.nbp, fb.kp = d.kp, fb.bt = d.bm;
-        fb.leaves = tab->leaves, fb.src = tab->bsrc, fb.b_side = 1;
-        fb.e_o = exps.eb, fb.e_k = exps.ep, fb.s_o = -1, fb.s_k = -1, fb.pre_exp = pre;  // 2^(-ep_kk - eb_j)
-        fb.planes = (unsigned short *)(ws + w.tp), fb.plane_stride = d.nbp * d.kp;
-        fb.leaf_stride = d.nl * d.nbp * d.kp;
-        if (level_formation(plan, s)) {
-            // level by level: every level reads its node operands once and writes all R children
-            const Algo &al = plan_algo(plan);
-            auto form_side = [&](bool side_b) -> hipError_t {
-                const PlaneForm &pf = side_b ? fb : fa;
-                const std::vector<InnerLevel> lv = inner_levels(plan, s, side_b);
-                char *ibase = ws + (side_b ? w.ib : w.ia);
-                int64_t nodes = 1;
-                for (int l = 1; l <= s.L; ++l) {
-                    NodeForm nf{};
-                    if (l == 1) {
-                        nf.X = pf.X, nf.ld_o = pf.ld_o, nf.ld_k = pf.ld_k, nf.R = pf.R, nf.K = pf.K, nf.first = 1;
-                        nf.e_o = pf.e_o, nf.e_k = pf.e_k, nf.s_o = pf.s_o, nf.s_k = pf.s_k, nf.pre_exp = pf.pre_exp;
-                    } else {
-                        const InnerLevel &in = lv[l - 2];
-                        nf.X = (const float *)(ibase + in.off), nf.ld_o = in.y_ld, nf.ld_k = 1;
-                        nf.node_stride = in.y_stride, nf.first = 0;
-                    }
-                    nf.nO = side_b ? al.N0 : al.M0, nf.nK = al.K0, nf.side_b = side_b ? 1 : 0, nf.R_ = al.R;
-                    nf.coef = side_b ? tab->vcoef : tab->ucoef;
-                    if (l == s.L) {
-                        nf.cb_o = pf.rb, nf.cb_k = pf.kb, nf.last = 1;
-                        nf.planes = pf.planes, nf.rowsp = pf.rowsp, nf.kp = pf.kp, nf.bt = pf.bt;
-                        nf.plane_stride = pf.plane_stride, nf.leaf_stride = pf.leaf_stride;
-                    } else {
-                        const InnerLevel &out = lv[l - 1];
-                        nf.cb_o = out.cb_o, nf.cb_k = out.cb_k, nf.last = 0;
-                        nf.Y = (float *)(ibase + out.off), nf.y_ld = out.y_ld, nf.y_stride = out.y_stride;
-                    }
-                    if (nodes > 65535) return hipErrorInvalidValue;
-                    hipError_t er = launch_form_node(plan->prec, nf, (int)nodes, st);
-                    if (er != hipSuccess) return er;
-                    nodes *= al.R;
-                }
-                return hipSuccess;
-            };
-            if ((e = form_side(false)) != hipSuccess || (e = form_side(true)) != hipSuccess)
-                return hip_fail(e, "limb plane formation");
-        } else if ((e = launch_form_planes(plan->prec, fa, tab->nleaves, st)) != hipSuccess ||
-                   (e = launch_form_planes(plan->prec, fb, tab->nleaves, st)) != hipSuccess) {
+        LimbGemm g;
+        if ((e = split_form(plan, s, d, A, lda, transA, B, ldb, transB, m, k, n, exps, ws, w, tab, st, g)) != hipSuccess)
             return hip_fail(e, "limb plane formation");
-        }
         fin.mark();
-        LimbGemm g{};
-        g.S = fa.planes, g.T = fb.planes, g.kp = d.kp;
-        g.s_plane = fa.plane_stride, g.s_leaf = fa.leaf_stride, g.t_plane = fb.plane_stride, g.t_leaf = fb.leaf_stride;
-        g.mb = s.mb, g.nb = s.nb, g.m = m, g.n = n, g.sc = exps, g.post_exp = -2 * pre;
-        g.tiles_m = (int)(d.mbp / d.bm), g.tiles_n = (int)(d.nbp / d.bm);
         if (s.L == 0) {
             g.out = (float *)C, g.ldo = ldc, g.leaf_stride = 0, g.direct = 1;
         } else {
@@ -930,6 +949,7 @@ namespace {
 struct BatchLayout {
     std::vector<size_t> ws_off, ws_size;
     size_t descs = 0, first = 0, direct = 0, total = 0;
+    int bm = 0;  // split precisions: the limb-GEMM tile shared by the batch
 };
 
 fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem *probs, int count, BatchLayout &bl) {
@@ -941,18 +961,27 @@ fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem *pro
         if (!plans[i]) return fail(FASTMM_EINVAL, "null plan in batch");
         if (prec < 0) prec = plans[i]->prec;
         if (plans[i]->prec != prec) return fail(FASTMM_EUNSUPPORTED, "batched plans must share one precision");
-        if (prec != FASTMM_F64 && prec != FASTMM_F32)
-            return fail(FASTMM_EUNSUPPORTED, "batched launch supports FP64 and FP32 leaves");
         const fastmm_problem &q = probs[i];
         if (q.m < 0 || q.k < 0 || q.n < 0) return fail(FASTMM_EINVAL, "negative size in batch");
+    }
+    if (count > 0 && is_split(prec)) {  // one limb-GEMM tile for the whole batch
+        bl.bm = 256;
+        for (int i = 0; i < count; ++i) {
+            const Shape s = shape_of(plans[i], probs[i].m, probs[i].k, probs[i].n);
+            bl.bm = std::min(bl.bm, limb_gemm_tile(prec, s.mb, s.nb));
+        }
+    }
+    for (int i = 0; i < count; ++i) {
+        const fastmm_problem &q = probs[i];
         const Shape s = shape_of(plans[i], q.m, q.k, q.n);
-        const size_t w = ws_layout(plans[i], s, q.m, q.k, q.n).total;
+        const size_t w = ws_layout(plans[i], s, q.m, q.k, q.n, bl.bm).total;
         bl.ws_off.push_back(off);
         bl.ws_size.push_back(w);
         off = align256(off + w);
     }
     const Elem el = prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
-    bl.descs = off, off = align256(off + leaf_desc_bytes(el) * (size_t)std::max(count, 1));
+    const size_t db = is_split(prec) ? sizeof(LimbGemm) : leaf_desc_bytes(el);
+    bl.descs = off, off = align256(off + db * (size_t)std::max(count, 1));
     bl.first = off, off = align256(off + 8 * (size_t)(count + 1));
     bl.direct = off, off = align256(off + 4 * (size_t)std::max(count, 1));
     bl.total = off;
@@ -992,6 +1021,7 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
     if (((uintptr_t)workspace & 255) != 0) return fail(FASTMM_EINVAL, "workspace must be 256-byte aligned");
     const Elem el = plans[0]->prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
     const size_t es = elem_size(plans[0]->prec);
+    const bool split = is_split(plans[0]->prec);
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
     // validate every problem before launching anything
@@ -1031,12 +1061,41 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
             continue;
         }
         const Shape sh = shape_of(p, q.m, q.k, q.n);
-        const WsLayout w = ws_layout(p, sh, q.m, q.k, q.n);
+        const WsLayout w = ws_layout(p, sh, q.m, q.k, q.n, bl.bm);
         char *pws = ws + bl.ws_off[i];
         Tables *tab = nullptr;
         if ((st = get_tables(p, sh.L, &tab)) != FASTMM_OK) return st;
         ScaleExps exps;
         if ((st = run_scaling(p, q.A, q.k, 0, q.B, q.n, 0, q.m, q.k, q.n, pws, w, s, &exps)) != FASTMM_OK) return st;
+        if (split) {
+            // limb planes now; the products of every problem in the one launch below
+            Item it;
+            it.idx = i;
+            it.kb = sh.kb;
+            it.combine = sh.L > 0;
+            const SplitDims d = split_dims(p->prec, sh, bl.bm);
+            LimbGemm g;
+            if ((e = split_form(p, sh, d, q.A, q.k, 0, q.B, q.n, 0, q.m, q.k, q.n, exps, pws, w, tab, s, g)) !=
+                hipSuccess)
+                return hip_fail(e, "limb plane formation");
+            if (sh.L == 0) {
+                g.out = (float *)q.C, g.ldo = q.n, g.leaf_stride = 0, g.direct = 1;
+            } else {
+                g.out = (float *)(pws + w.leaves), g.ldo = sh.nb, g.leaf_stride = sh.mb * sh.nb, g.direct = 0;
+                CombineLaunch &c = it.cb;
+                c.elem = el;
+                c.M = pws + w.leaves;
+                c.leaf_stride = sh.mb * sh.nb;
+                c.C = q.C, c.ldc = q.n, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
+                c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
+            }
+            it.direct = g.direct;
+            it.desc.resize(sizeof(LimbGemm));
+            std::memcpy(it.desc.data(), &g, sizeof(LimbGemm));
+            it.tiles = (int64_t)tab->nleaves * g.tiles_m * g.tiles_n;
+            items.push_back(std::move(it));
+            continue;
+        }
         LeafLaunch L;
         L.elem = el;
         L.prec = p->prec;
@@ -1079,7 +1138,7 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
     } stg;
     if (stg.pending && (e = hipEventSynchronize(stg.done)) != hipSuccess) return hip_fail(e, "staging wait");
     stg.pending = false;
-    const size_t db = leaf_desc_bytes(el);
+    const size_t db = split ? sizeof(LimbGemm) : leaf_desc_bytes(el);
     stg.descs.assign(db * std::max<size_t>(items.size(), 1), 0);
     stg.first.assign(items.size() + 1, 0);
     stg.direct.assign(std::max<size_t>(items.size(), 1), 0);
@@ -1098,11 +1157,18 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
             return hip_fail(e, "uploading batch descriptors");
         if ((e = hipEventRecord(stg.done, s)) != hipSuccess) return hip_fail(e, "staging event");
         stg.pending = true;
-        const int64_t slots = (int64_t)device_cus() * leaf_blocks_per_cu(el);
-        const int grid = (int)std::min<int64_t>(total, slots);
-        if ((e = launch_leaf_batched(el, ws + bl.descs, (const int64_t *)(ws + bl.first), (const int *)(ws + bl.direct),
-                                     (int)items.size(), total, grid, s)) != hipSuccess)
-            return hip_fail(e, "batched leaf kernel");
+        if (split) {
+            if ((e = launch_limb_gemm_batched(plans[0]->prec, bl.bm, ws + bl.descs, (const int64_t *)(ws + bl.first),
+                                              (int)items.size(), total, s)) != hipSuccess)
+                return hip_fail(e, "batched limb GEMM kernel");
+        } else {
+            const int64_t slots = (int64_t)device_cus() * leaf_blocks_per_cu(el);
+            const int grid = (int)std::min<int64_t>(total, slots);
+            if ((e = launch_leaf_batched(el, ws + bl.descs, (const int64_t *)(ws + bl.first),
+                                         (const int *)(ws + bl.direct), (int)items.size(), total, grid, s)) !=
+                hipSuccess)
+                return hip_fail(e, "batched leaf kernel");
+        }
     }
     for (const Item &it : items)
         if (it.combine && (e = launch_combine(it.cb, s)) != hipSuccess) return hip_fail(e, "combine kernel");

@@ -167,6 +167,11 @@ int limb_count(int prec);                   // limbs per element of a split prec
 int limb_gemm_tile(int prec, int64_t mb, int64_t nb);  // square tile of the limb GEMM (128 or 256)
 hipError_t launch_form_planes(int prec, const PlaneForm &f, int nleaves, hipStream_t s);
 hipError_t launch_limb_gemm(int prec, int bm, const LimbGemm &g, int nleaves, hipStream_t s);
+// Several problems in one launch: descs holds count LimbGemm descriptors (device memory, all
+// with planes blocked for the tile bm), first[count + 1] the prefix sums of their items
+// (leaves x tiles); `total` = first[count] work-groups.
+hipError_t launch_limb_gemm_batched(int prec, int bm, const void *descs, const int64_t *first, int count,
+                                    int64_t total, hipStream_t s);
 
 hipError_t launch_leaf(const LeafLaunch &L, hipStream_t s);
 // Pipelined 128x128-tile version for row-major (non-transposed) operands.

@@ -248,27 +248,26 @@ struct Products<3> {
 // 32; LDS double-buffered, rows of 32 halves (64 bytes, four 16-byte chunks) with chunk c of row r
 // stored at chunk c ^ ((r / 2) mod 4), so that the 16-byte fragment reads (16 rows, one chunk)
 // and the staging writes (consecutive chunks and rows) both fall on distinct banks.
+template <int NL, int BM, int BN>
+struct LimbSmem {
+    __attribute__((aligned(16))) unsigned short As[2][NL][BM * 32];
+    __attribute__((aligned(16))) unsigned short Bs[2][NL][BN * 32];
+};
+
+// Output tile (tm, tn) of leaf `leaf` of the problem a.
 template <bool HALF, int NL, int BM, int BN, int WM, int WN, bool SCALED, bool DIRECT>
-__global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm(LimbGemm a) {
+__device__ __forceinline__ void limb_tile(const LimbGemm &a, int leaf, int64_t tm, int64_t tn,
+                                          LimbSmem<NL, BM, BN> &sm) {
     constexpr int BK = 32, NT = 64 * WM * WN, RS = 32;
     constexpr int TI = BM / (16 * WM), TJ = BN / (16 * WN);  // 16 x 16 MFMA blocks per wave
     constexpr int CA = NL * BM * 4 / NT, CB = NL * BN * 4 / NT;  // 16-byte chunks per thread and stage
     static_assert(CA * NT == NL * BM * 4 && CB * NT == NL * BN * 4, "chunk split");
     typedef Products<NL> P;
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][NL][BM * RS];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NL][BN * RS];
+    auto &As = sm.As;
+    auto &Bs = sm.Bs;
 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave / WN, wn = wave % WN;
-    const int64_t tiles = (int64_t)a.tiles_m * a.tiles_n;
-    const int bid = __builtin_amdgcn_readfirstlane((int)xcd_remap_g(blockIdx.x, gridDim.x));
-    const int leaf = __builtin_amdgcn_readfirstlane((int)(bid / tiles));
-    const int rem = __builtin_amdgcn_readfirstlane((int)(bid - (int64_t)leaf * tiles));
-    const int grp = rem / (8 * a.tiles_n);
-    const int gsz = min(8, a.tiles_m - grp * 8);
-    const int gidx = rem - grp * 8 * a.tiles_n;
-    const int64_t tm = __builtin_amdgcn_readfirstlane(grp * 8 + gidx % gsz);
-    const int64_t tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
 
     // planes are blocked in BM x 32 tiles (BM == BN): the tile of stage kt is contiguous
     const unsigned short *Sp = a.S + (int64_t)leaf * a.s_leaf + tm * BM * a.kp;
@@ -379,6 +378,50 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm(LimbGemm a) {
             }
 }
 
+// Item `item` (leaf-major, tiles in groups of 8 tile rows) of one problem -> (leaf, tm, tn).
+__device__ __forceinline__ void limb_item(const LimbGemm &a, int64_t item, int &leaf, int64_t &tm, int64_t &tn) {
+    const int64_t tiles = (int64_t)a.tiles_m * a.tiles_n;
+    leaf = __builtin_amdgcn_readfirstlane((int)(item / tiles));
+    const int rem = __builtin_amdgcn_readfirstlane((int)(item - (int64_t)leaf * tiles));
+    const int grp = rem / (8 * a.tiles_n);
+    const int gsz = min(8, a.tiles_m - grp * 8);
+    const int gidx = rem - grp * 8 * a.tiles_n;
+    tm = __builtin_amdgcn_readfirstlane(grp * 8 + gidx % gsz);
+    tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
+}
+
+template <bool HALF, int NL, int BM, int BN, int WM, int WN, bool SCALED, bool DIRECT>
+__global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm(LimbGemm a) {
+    __shared__ LimbSmem<NL, BM, BN> sm;
+    int leaf;
+    int64_t tm, tn;
+    limb_item(a, xcd_remap_g(blockIdx.x, gridDim.x), leaf, tm, tn);
+    limb_tile<HALF, NL, BM, BN, WM, WN, SCALED, DIRECT>(a, leaf, tm, tn, sm);
+}
+
+// Several problems in one launch: work-group w runs item w - first[q] of problem q, where
+// first[q] <= w < first[q + 1] (problems ordered by the host, largest inner dimension first).
+template <bool HALF, int NL, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm_batched(const LimbGemm *descs, const int64_t *first,
+                                                                       int count) {
+    __shared__ LimbSmem<NL, BM, BN> sm;
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {  // last q with first[q] <= w
+        const int mid = (lo + hi + 1) / 2;
+        if (first[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    const int q = __builtin_amdgcn_readfirstlane(lo);
+    const LimbGemm a = descs[q];
+    int leaf;
+    int64_t tm, tn;
+    limb_item(a, w - first[q], leaf, tm, tn);
+    if (!a.direct) limb_tile<HALF, NL, BM, BN, WM, WN, false, false>(a, leaf, tm, tn, sm);
+    else if (a.sc.ea) limb_tile<HALF, NL, BM, BN, WM, WN, true, true>(a, leaf, tm, tn, sm);
+    else limb_tile<HALF, NL, BM, BN, WM, WN, false, true>(a, leaf, tm, tn, sm);
+}
+
 template <bool HALF, int NL>
 hipError_t form_go(const PlaneForm &f, int nleaves, hipStream_t s) {
     if (f.rowsp <= 0 || f.kp <= 0 || nleaves <= 0) return hipSuccess;
@@ -406,6 +449,24 @@ hipError_t gemm_go(const LimbGemm &g, int nleaves, hipStream_t s) {
         hipLaunchKernelGGL((fmm_limb_gemm<HALF, NL, BM, BN, WM, WN, false, false>), grid, block, 0, s, g);
     }
     return hipGetLastError();
+}
+
+template <bool HALF, int NL, int BM, int BN, int WM, int WN>
+hipError_t gemm_batched_go(const void *descs, const int64_t *first, int count, int64_t total, hipStream_t s) {
+    if (total <= 0 || count <= 0) return hipSuccess;
+    if (total > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((fmm_limb_gemm_batched<HALF, NL, BM, BN, WM, WN>), dim3((unsigned)total), dim3(64 * WM * WN), 0,
+                       s, (const LimbGemm *)descs, first, count);
+    return hipGetLastError();
+}
+
+template <bool HALF, int NL>
+hipError_t gemm_batched_tile(int bm, const void *descs, const int64_t *first, int count, int64_t total,
+                             hipStream_t s) {
+    if constexpr (NL < 3) {
+        if (bm == 256) return gemm_batched_go<HALF, NL, 256, 256, 2, 4>(descs, first, count, total, s);
+    }
+    return gemm_batched_go<HALF, NL, 128, 128, 2, 2>(descs, first, count, total, s);
 }
 
 template <bool HALF, int NL>
@@ -470,6 +531,18 @@ hipError_t launch_limb_gemm(int prec, int bm, const LimbGemm &g, int nleaves, hi
         case FASTMM_BF16X3: return gemm_tile<false, 2>(bm, g, nleaves, s);
         case FASTMM_F16X3: return gemm_tile<true, 2>(bm, g, nleaves, s);
         case FASTMM_BF16X6: return gemm_tile<false, 3>(bm, g, nleaves, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_limb_gemm_batched(int prec, int bm, const void *descs, const int64_t *first, int count,
+                                    int64_t total, hipStream_t s) {
+    switch (prec) {
+        case FASTMM_BF16: return gemm_batched_tile<false, 1>(bm, descs, first, count, total, s);
+        case FASTMM_F16: return gemm_batched_tile<true, 1>(bm, descs, first, count, total, s);
+        case FASTMM_BF16X3: return gemm_batched_tile<false, 2>(bm, descs, first, count, total, s);
+        case FASTMM_F16X3: return gemm_batched_tile<true, 2>(bm, descs, first, count, total, s);
+        case FASTMM_BF16X6: return gemm_batched_tile<false, 3>(bm, descs, first, count, total, s);
     }
     return hipErrorInvalidValue;
 }

@@ -64,6 +64,19 @@ def test_batched_float_bitwise_equal_to_single_launches(precision, scaling):
         assert O.normwise_error(cb, ref, a, b) <= (1e-13 if precision == "f64" else 5e-5)
 
 
+@pytest.mark.parametrize("precision", ["bf16x3", "f16x3"])
+def test_batched_split_precision_exact_and_equal_to_single_launches(precision):
+    # one limb-GEMM launch for the whole batch (tiles shared by all problems); the limb
+    # products of every output element run in the same order as in single launches
+    A, B, Cb, Cs = _run_batch(precision, "int8")
+    for a, b, cb, cs in zip(A, B, Cb, Cs):
+        exact = (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64)
+        assert np.array_equal(cb.astype(np.float64), exact)
+    A, B, Cb, Cs = _run_batch(precision, "normal")
+    for a, b, cb, cs in zip(A, B, Cb, Cs):
+        assert np.array_equal(cb, cs)
+
+
 def test_batched_repeat_is_deterministic():
     _, _, C1, _ = _run_batch("f32", "normal")
     _, _, C2, _ = _run_batch("f32", "normal")
