@@ -699,6 +699,7 @@ hipError_t split_form(fastmm_plan_s *plan, const Shape &s, const SplitDims &d, c
     fa.e_o = exps.ea, fa.e_k = exps.ep, fa.s_o = -1, fa.s_k = 1, fa.pre_exp = pre;  // 2^(ep_kk - ea_i)
     fa.planes = (unsigned short *)(ws + w.sp), fa.plane_stride = d.mbp * d.kp;
     fa.leaf_stride = d.nl * d.mbp * d.kp;
+    fa.nbo = s.mb > 0 ? (int)(s.Mp / s.mb) : 0, fa.nbk = s.kb > 0 ? (int)(s.Kp / s.kb) : 0;
     PlaneForm fb{};
     fb.X = (const float *)B;
     fb.ld_o = transB ? ldb : 1, fb.ld_k = transB ? 1 : ldb;  // op(B)(kk, j) as T^T(j, kk)
@@ -707,6 +708,7 @@ hipError_t split_form(fastmm_plan_s *plan, const Shape &s, const SplitDims &d, c
     fb.e_o = exps.eb, fb.e_k = exps.ep, fb.s_o = -1, fb.s_k = -1, fb.pre_exp = pre;  // 2^(-ep_kk - eb_j)
     fb.planes = (unsigned short *)(ws + w.tp), fb.plane_stride = d.nbp * d.kp;
     fb.leaf_stride = d.nl * d.nbp * d.kp;
+    fb.nbo = s.nb > 0 ? (int)(s.Np / s.nb) : 0, fb.nbk = s.kb > 0 ? (int)(s.Kp / s.kb) : 0;
     if (level_formation(plan, s)) {
         // level by level: every level reads its node operands once and writes all R children
         const Algo &al = plan_algo(plan);

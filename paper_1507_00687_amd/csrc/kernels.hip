@@ -205,9 +205,11 @@ struct CombineArgs {
 };
 
 // C(i, j) = 2^(ea_i + eb_j) * sum_q coef_q * M_{leaf_q}(i mod mb, j mod nb), summed in list
-// order.  Each thread owns VEC consecutive columns of a row (VEC > 1 only when the block width,
-// n, ldc and the pointers allow 16-byte accesses, so the VEC columns share one column block);
-// every element is written once.
+// order.  A thread owns VEC consecutive columns (x, y .. y+VEC-1) of the leaf-block grid and
+// writes that position of every output block in turn, so the products it reads for one block
+// are re-read for the next from cache, not HBM: each product element leaves HBM once.  VEC > 1
+// only when the block width, n, ldc and the pointers allow 16-byte accesses (so the VEC
+// columns never straddle C's edge); every element of C is written once.
 template <typename T, int VEC>
 struct VecOf;
 template <>
@@ -221,48 +223,55 @@ struct VecOf<double, 2> {
 
 template <typename T, bool SCALED, int VEC>
 __global__ __launch_bounds__(kThreads) void combine_kernel(CombineArgs<T> p) {
-    const int64_t col = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * VEC;
-    if (col >= p.n) return;
-    const int64_t S = col / p.nb, y = col - S * p.nb;
-    for (int64_t row = blockIdx.y; row < p.m; row += gridDim.y) {
-        const int64_t P = row / p.mb, x = row - P * p.mb;
-        const BlockDests bd = p.bdest[P * p.NB + S];
-        T acc[VEC];
-        for (int q = 0; q < bd.count; ++q) {
-            const DestEntry de = p.dest[bd.begin + q];
-            const T *src = p.M + (int64_t)de.leaf * p.leaf_stride + x * p.nb + y;
-            T v[VEC];
-            if constexpr (VEC == 1) {
-                v[0] = *src;
-            } else {
-                const typename VecOf<T, VEC>::t w = *reinterpret_cast<const typename VecOf<T, VEC>::t *>(src);
-                const T *ws = reinterpret_cast<const T *>(&w);
+    const int64_t y = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * VEC;
+    if (y >= p.nb) return;
+    const int64_t nP = (p.m + p.mb - 1) / p.mb, nS = (p.n + p.nb - 1) / p.nb;
+    for (int64_t x = blockIdx.y; x < p.mb; x += gridDim.y) {
+        for (int64_t P = 0; P < nP; ++P) {
+            const int64_t row = P * p.mb + x;
+            if (row >= p.m) break;
+            for (int64_t S = 0; S < nS; ++S) {
+                const int64_t col = S * p.nb + y;
+                if (col >= p.n) break;
+                const BlockDests bd = p.bdest[P * p.NB + S];
+                T acc[VEC];
+                for (int q = 0; q < bd.count; ++q) {
+                    const DestEntry de = p.dest[bd.begin + q];
+                    const T *src = p.M + (int64_t)de.leaf * p.leaf_stride + x * p.nb + y;
+                    T v[VEC];
+                    if constexpr (VEC == 1) {
+                        v[0] = *src;
+                    } else {
+                        const typename VecOf<T, VEC>::t w = *reinterpret_cast<const typename VecOf<T, VEC>::t *>(src);
+                        const T *ws = reinterpret_cast<const T *>(&w);
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) v[e] = ws[e];
+                        for (int e = 0; e < VEC; ++e) v[e] = ws[e];
+                    }
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const T term = (T)de.coef * v[e];
+                        acc[e] = (q == 0) ? term : acc[e] + term;
+                    }
+                }
+                if (bd.count == 0) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[e] = T(0);
+                }
+                if (SCALED) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[e] = ldexp_t(acc[e], p.sc.ea[row] + p.sc.eb[col + e]);
+                }
+                T *dst = p.C + row * p.ldc + col;
+                if constexpr (VEC == 1) {
+                    *dst = acc[0];
+                } else {
+                    typename VecOf<T, VEC>::t w;
+                    T *ws = reinterpret_cast<T *>(&w);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) ws[e] = acc[e];
+                    *reinterpret_cast<typename VecOf<T, VEC>::t *>(dst) = w;
+                }
             }
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const T term = (T)de.coef * v[e];
-                acc[e] = (q == 0) ? term : acc[e] + term;
-            }
-        }
-        if (bd.count == 0) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[e] = T(0);
-        }
-        if (SCALED) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[e] = ldexp_t(acc[e], p.sc.ea[row] + p.sc.eb[col + e]);
-        }
-        T *dst = p.C + row * p.ldc + col;
-        if constexpr (VEC == 1) {
-            *dst = acc[0];
-        } else {
-            typename VecOf<T, VEC>::t w;
-            T *ws = reinterpret_cast<T *>(&w);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) ws[e] = acc[e];
-            *reinterpret_cast<typename VecOf<T, VEC>::t *>(dst) = w;
         }
     }
 }
@@ -462,9 +471,10 @@ hipError_t combine_go(const CombineLaunch &L, hipStream_t s) {
     constexpr int VEC = 16 / (int)sizeof(T);
     const bool vec = L.nb % VEC == 0 && L.n % VEC == 0 && L.ldc % VEC == 0 && (uintptr_t)L.C % 16 == 0 &&
                      (uintptr_t)L.M % 16 == 0 && L.leaf_stride % VEC == 0;
+    if (L.mb <= 0 || L.nb <= 0) return hipErrorInvalidValue;
     const int per = vec ? VEC : 1;
-    const int64_t cols = (L.n + per - 1) / per;
-    dim3 grid((unsigned)((cols + kThreads - 1) / kThreads), (unsigned)(L.m < 65535 ? L.m : 65535));
+    const int64_t cols = (L.nb + per - 1) / per;  // threads span one leaf block; each visits every block
+    dim3 grid((unsigned)((cols + kThreads - 1) / kThreads), (unsigned)(L.mb < 65535 ? L.mb : 65535));
     const bool sc = L.sc.ea != nullptr;
     if (vec) {
         if (sc) hipLaunchKernelGGL((combine_kernel<T, true, VEC>), grid, dim3(kThreads), 0, s, a);

@@ -120,6 +120,7 @@ struct PlaneForm {
     int pre_exp;  // with scaling (e_o not null): every value also times 2^pre_exp
     unsigned short *planes;
     int64_t plane_stride, leaf_stride;
+    int nbo, nbk;  // leaf-block grid of op(X): nbo blocks along o, nbk along k (0: unknown)
 };
 // Pass 2: M_r = sum of the kept limb products of S_r and T_r, for every leaf and every
 // bm x bm tile of the padded planes (bm = limb_gemm_tile); out is the leaf workspace (leaf r at out + r *

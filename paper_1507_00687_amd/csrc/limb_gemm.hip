@@ -130,6 +130,123 @@ __global__ __launch_bounds__(256) void form_planes(PlaneForm a) {
     }
 }
 
+// ------------------------------------------------------------------ pass 1, all leaves at once
+// The same limb planes, with every source element read from HBM once: a work-group takes one
+// 64 x 64 tile position inside the leaf blocks, loads that tile of every block of op(X) (the
+// nbo x nbk leaf-block grid) into registers, then forms each leaf's S_r from them in turn.
+// A leaf's coefficients sit in a dense leaves x blocks table in LDS (zero where a block is not
+// one of its sources); blocks are summed in the order of the rule's single block index at
+// depth 1 (column-major for A, row-major over (n-block, k-block) for B), which is the order of
+// the source lists there.  EPT elements per thread and block; at most 64 / EPT blocks.
+constexpr int kAllMaxCoef = 4096;  // leaves x blocks entries of the coefficient table
+
+template <bool HALF, int NL, bool SCALED, bool KCONTIG, int EPT>
+__global__ __launch_bounds__(4096 / EPT) void form_all(PlaneForm a, int nleaves) {
+    constexpr int NT = 4096 / EPT, NB = 64 / EPT, RP = NT / 64;
+    __shared__ float tile[kFT][kFT + 1];
+    __shared__ float coef[kAllMaxCoef];
+    const int t = threadIdx.x;
+    const int nbo = a.nbo, nbk = a.nbk, nblk = nbo * nbk;
+    for (int i = t; i < nleaves * nblk; i += NT) coef[i] = 0.f;
+    __syncthreads();
+    for (int leaf = t; leaf < nleaves; leaf += NT) {
+        const LeafEntry le = a.leaves[leaf];
+        const int begin = a.b_side ? le.b_begin : le.a_begin, count = a.b_side ? le.b_count : le.a_count;
+        for (int q = 0; q < count; ++q) {
+            const SrcEntry se = a.src[begin + q];
+            const int bo = a.b_side ? se.bc : se.br, bk = a.b_side ? se.br : se.bc;
+            coef[leaf * nblk + (a.b_side ? bo * nbk + bk : bk * nbo + bo)] += se.coef;
+        }
+    }
+    const int64_t o0 = (int64_t)blockIdx.y * kFT, k0 = (int64_t)blockIdx.x * kFT;
+    // scaling exponents of the work-group's rows and columns in every block (staged in LDS)
+    __shared__ int32_t eo_s[SCALED ? NB * kFT : 1], ek_s[SCALED ? NB * kFT : 1];
+    if (SCALED) {
+        for (int i = t; i < nbo * kFT; i += NT) {
+            const int64_t ob = o0 + i % kFT, o = (i / kFT) * a.rb + ob;
+            eo_s[i] = (ob < a.rb && o < a.R) ? a.s_o * a.e_o[o] + a.pre_exp : 0;
+        }
+        for (int i = t; i < nbk * kFT; i += NT) {
+            const int64_t kb = k0 + i % kFT, kk = (i / kFT) * a.kb + kb;
+            ek_s[i] = (kb < a.kb && kk < a.K) ? a.s_k * a.e_k[kk] : 0;
+        }
+    }
+    __syncthreads();  // coefficient table and exponents complete
+    int lo[EPT], lk[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        if (KCONTIG) lo[e] = e * RP + t / 64, lk[e] = t % 64;
+        else lk[e] = e * RP + t / 64, lo[e] = t % 64;
+    }
+    float x[NB][EPT];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int bo = a.b_side ? b / nbk : b % nbo, bk = a.b_side ? b % nbk : b / nbo;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t ob = o0 + lo[e], kb = k0 + lk[e];  // inside the leaf block
+            const int64_t o = bo * a.rb + ob, kk = bk * a.kb + kb;  // inside op(X)
+            const bool ok = b < nblk && ob < a.rb && kb < a.kb && o < a.R && kk < a.K;
+            const float y = *(ok ? a.X + o * a.ld_o + kk * a.ld_k : a.X);
+            float v = ok ? y : 0.f;
+            x[b][e] = v;
+        }
+    }
+    for (int leaf = 0; leaf < nleaves; ++leaf) {
+        float v[EPT];
+        bool first = true;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float c = b < nblk ? coef[leaf * nblk + b] : 0.f;
+            if (c != 0.f) {
+                const int bo = a.b_side ? b / nbk : b % nbo, bk = a.b_side ? b % nbk : b / nbo;
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    // scaling applied here (exact), so the loads above hold only the raw values
+                    const float xs = SCALED ? ldexpf(x[b][e], eo_s[bo * kFT + lo[e]] + ek_s[bk * kFT + lk[e]]) : x[b][e];
+                    v[e] = first ? c * xs : v[e] + c * xs;
+                }
+                first = false;
+            }
+        }
+        if (first) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) v[e] = 0.f;
+        }
+        if (leaf > 0) __syncthreads();  // the previous leaf's chunks have been read
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) tile[lo[e]][lk[e]] = v[e];
+        __syncthreads();
+        // 64 rows x 8 chunks of 8 k: split and write 16 bytes per limb
+        for (int cidx = t; cidx < kFT * 8; cidx += NT) {
+            const int ro = cidx / 8, rk = (cidx % 8) * 8;
+            unsigned short h[NL][8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                float r = tile[ro][rk + j];
+#pragma unroll
+                for (int l = 0; l < NL; ++l) {
+                    float back;
+                    h[l][j] = LimbT<HALF>::split(r, back);
+                    r = r - back;
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                uint4 w;
+                w.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
+                w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
+                w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
+                w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
+                const int64_t o = o0 + ro, kk = k0 + rk;
+                *reinterpret_cast<uint4 *>(a.planes + (int64_t)leaf * a.leaf_stride + l * a.plane_stride +
+                                           ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 +
+                                           kk % 32) = w;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ pass 1, level by level
 // One recursion level of the operand formation for a node operand X (eq. (1)): the node's nS
 // sub-blocks X_s are read once and all R children C_c = sum_s coef[s][c] X_s are written, as
@@ -255,7 +372,8 @@ struct LimbSmem {
 };
 
 // Output tile (tm, tn) of leaf `leaf` of the problem a.
-template <bool HALF, int NL, int BM, int BN, int WM, int WN, bool SCALED, bool DIRECT>
+// DYN: the output mode (DIRECT, SCALED) is read from the descriptor at run time (batched launch).
+template <bool HALF, int NL, int BM, int BN, int WM, int WN, bool SCALED, bool DIRECT, bool DYN = false>
 __device__ __forceinline__ void limb_tile(const LimbGemm &a, int leaf, int64_t tm, int64_t tn,
                                           LimbSmem<NL, BM, BN> &sm) {
     constexpr int BK = 32, NT = 64 * WM * WN, RS = 32;
@@ -357,6 +475,8 @@ __device__ __forceinline__ void limb_tile(const LimbGemm &a, int leaf, int64_t t
 #undef LIMB_LOAD
 #undef LIMB_STORE
 
+    const bool direct = DYN ? a.direct != 0 : DIRECT;
+    const bool scaled = DYN ? a.sc.ea != nullptr : SCALED;
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -366,9 +486,9 @@ __device__ __forceinline__ void limb_tile(const LimbGemm &a, int leaf, int64_t t
                 const int64_t row = tm * BM + wm * (BM / WM) + i * 16 + 4 * (lane >> 4) + v;  // inside the leaf block
                 const int64_t col = tn * BN + wn * (BN / WN) + j * 16 + l16;
                 float val = acc[i][j][v];
-                if (DIRECT) {
+                if (direct) {
                     if (row < a.m && col < a.n) {  // one power-of-two factor: exact unless it underflows
-                        if (SCALED) val = ldexpf(val, a.post_exp + a.sc.ea[row] + a.sc.eb[col]);
+                        if (scaled) val = ldexpf(val, a.post_exp + a.sc.ea[row] + a.sc.eb[col]);
                         a.out[row * a.ldo + col] = val;
                     }
                 } else if (row < a.mb && col < a.nb) {
@@ -417,15 +537,31 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm_batched(const L
     int leaf;
     int64_t tm, tn;
     limb_item(a, w - first[q], leaf, tm, tn);
-    if (!a.direct) limb_tile<HALF, NL, BM, BN, WM, WN, false, false>(a, leaf, tm, tn, sm);
-    else if (a.sc.ea) limb_tile<HALF, NL, BM, BN, WM, WN, true, true>(a, leaf, tm, tn, sm);
-    else limb_tile<HALF, NL, BM, BN, WM, WN, false, true>(a, leaf, tm, tn, sm);
+    limb_tile<HALF, NL, BM, BN, WM, WN, true, true, true>(a, leaf, tm, tn, sm);
+}
+
+template <bool HALF, int NL, int EPT>
+hipError_t form_all_go(const PlaneForm &f, int nleaves, hipStream_t s) {
+    const dim3 grid((unsigned)(f.kp / kFT), (unsigned)(f.rowsp / kFT)), block(4096 / EPT);
+    const bool scaled = f.e_o != nullptr, kc = f.ld_k == 1;
+    if (scaled && kc) hipLaunchKernelGGL((form_all<HALF, NL, true, true, EPT>), grid, block, 0, s, f, nleaves);
+    else if (scaled) hipLaunchKernelGGL((form_all<HALF, NL, true, false, EPT>), grid, block, 0, s, f, nleaves);
+    else if (kc) hipLaunchKernelGGL((form_all<HALF, NL, false, true, EPT>), grid, block, 0, s, f, nleaves);
+    else hipLaunchKernelGGL((form_all<HALF, NL, false, false, EPT>), grid, block, 0, s, f, nleaves);
+    return hipGetLastError();
 }
 
 template <bool HALF, int NL>
 hipError_t form_go(const PlaneForm &f, int nleaves, hipStream_t s) {
     if (f.rowsp <= 0 || f.kp <= 0 || nleaves <= 0) return hipSuccess;
     if (f.rowsp / kFT > 65535 || nleaves > 65535 || f.kp / kFT > 0x7fffffffLL) return hipErrorInvalidValue;
+    // every source block read once when the block grid and the coefficient table are small
+    const int64_t nblk = (int64_t)f.nbo * f.nbk;
+    if (f.nbo > 0 && f.nbk > 0 && nblk <= 16 && nblk * nleaves <= kAllMaxCoef) {
+        if (nblk <= 4) return form_all_go<HALF, NL, 16>(f, nleaves, s);
+        if (nblk <= 8) return form_all_go<HALF, NL, 8>(f, nleaves, s);
+        return form_all_go<HALF, NL, 4>(f, nleaves, s);
+    }
     const dim3 grid((unsigned)(f.kp / kFT), (unsigned)(f.rowsp / kFT), (unsigned)nleaves);
     const bool scaled = f.e_o != nullptr, kc = f.ld_k == 1;
     if (scaled && kc) hipLaunchKernelGGL((form_planes<HALF, NL, true, true>), grid, dim3(256), 0, s, f);
