@@ -235,22 +235,34 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(CombineArgs<T> p) {
                 if (col >= p.n) break;
                 const BlockDests bd = p.bdest[P * p.NB + S];
                 T acc[VEC];
-                for (int q = 0; q < bd.count; ++q) {
-                    const DestEntry de = p.dest[bd.begin + q];
-                    const T *src = p.M + (int64_t)de.leaf * p.leaf_stride + x * p.nb + y;
-                    T v[VEC];
-                    if constexpr (VEC == 1) {
-                        v[0] = *src;
-                    } else {
-                        const typename VecOf<T, VEC>::t w = *reinterpret_cast<const typename VecOf<T, VEC>::t *>(src);
-                        const T *ws = reinterpret_cast<const T *>(&w);
+                // contributions in groups of up to 4: the group's loads are issued together,
+                // then added in list order
+                for (int q0 = 0; q0 < bd.count; q0 += 4) {
+                    const int nq = bd.count - q0 < 4 ? bd.count - q0 : 4;
+                    DestEntry de[4];
+                    T v[4][VEC];
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) v[e] = ws[e];
+                    for (int u = 0; u < 4; ++u) {
+                        if (u >= nq) break;
+                        de[u] = p.dest[bd.begin + q0 + u];
+                        const T *src = p.M + (int64_t)de[u].leaf * p.leaf_stride + x * p.nb + y;
+                        if constexpr (VEC == 1) {
+                            v[u][0] = *src;
+                        } else {
+                            const typename VecOf<T, VEC>::t w = *reinterpret_cast<const typename VecOf<T, VEC>::t *>(src);
+                            const T *ws = reinterpret_cast<const T *>(&w);
+#pragma unroll
+                            for (int e = 0; e < VEC; ++e) v[u][e] = ws[e];
+                        }
                     }
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        const T term = (T)de.coef * v[e];
-                        acc[e] = (q == 0) ? term : acc[e] + term;
+                    for (int u = 0; u < 4; ++u) {
+                        if (u >= nq) break;
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            const T term = (T)de[u].coef * v[u][e];
+                            acc[e] = (q0 + u == 0) ? term : acc[e] + term;
+                        }
                     }
                 }
                 if (bd.count == 0) {
