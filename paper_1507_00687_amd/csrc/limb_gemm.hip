@@ -137,14 +137,16 @@ __global__ __launch_bounds__(256) void form_planes(PlaneForm a) {
 // A leaf's coefficients sit in a dense leaves x blocks table in LDS (zero where a block is not
 // one of its sources); blocks are summed in the order of the rule's single block index at
 // depth 1 (column-major for A, row-major over (n-block, k-block) for B), which is the order of
-// the source lists there.  EPT elements per thread and block; at most 64 / EPT blocks.
+// the source lists there.  EPT elements per thread and block; at most 64 / EPT blocks.  The
+// table takes nleaves x blocks floats of dynamic LDS (sized per launch, so that small tables
+// leave the occupancy of a streaming kernel).
 constexpr int kAllMaxCoef = 4096;  // leaves x blocks entries of the coefficient table
 
 template <bool HALF, int NL, bool SCALED, bool KCONTIG, int EPT>
 __global__ __launch_bounds__(4096 / EPT) void form_all(PlaneForm a, int nleaves) {
     constexpr int NT = 4096 / EPT, NB = 64 / EPT, RP = NT / 64;
     __shared__ float tile[kFT][kFT + 1];
-    __shared__ float coef[kAllMaxCoef];
+    extern __shared__ float coef[];  // nleaves x nblk
     const int t = threadIdx.x;
     const int nbo = a.nbo, nbk = a.nbk, nblk = nbo * nbk;
     for (int i = t; i < nleaves * nblk; i += NT) coef[i] = 0.f;
@@ -544,10 +546,11 @@ template <bool HALF, int NL, int EPT>
 hipError_t form_all_go(const PlaneForm &f, int nleaves, hipStream_t s) {
     const dim3 grid((unsigned)(f.kp / kFT), (unsigned)(f.rowsp / kFT)), block(4096 / EPT);
     const bool scaled = f.e_o != nullptr, kc = f.ld_k == 1;
-    if (scaled && kc) hipLaunchKernelGGL((form_all<HALF, NL, true, true, EPT>), grid, block, 0, s, f, nleaves);
-    else if (scaled) hipLaunchKernelGGL((form_all<HALF, NL, true, false, EPT>), grid, block, 0, s, f, nleaves);
-    else if (kc) hipLaunchKernelGGL((form_all<HALF, NL, false, true, EPT>), grid, block, 0, s, f, nleaves);
-    else hipLaunchKernelGGL((form_all<HALF, NL, false, false, EPT>), grid, block, 0, s, f, nleaves);
+    const size_t lds = (size_t)nleaves * f.nbo * f.nbk * sizeof(float);
+    if (scaled && kc) hipLaunchKernelGGL((form_all<HALF, NL, true, true, EPT>), grid, block, lds, s, f, nleaves);
+    else if (scaled) hipLaunchKernelGGL((form_all<HALF, NL, true, false, EPT>), grid, block, lds, s, f, nleaves);
+    else if (kc) hipLaunchKernelGGL((form_all<HALF, NL, false, true, EPT>), grid, block, lds, s, f, nleaves);
+    else hipLaunchKernelGGL((form_all<HALF, NL, false, false, EPT>), grid, block, lds, s, f, nleaves);
     return hipGetLastError();
 }
 
@@ -556,8 +559,10 @@ hipError_t form_go(const PlaneForm &f, int nleaves, hipStream_t s) {
     if (f.rowsp <= 0 || f.kp <= 0 || nleaves <= 0) return hipSuccess;
     if (f.rowsp / kFT > 65535 || nleaves > 65535 || f.kp / kFT > 0x7fffffffLL) return hipErrorInvalidValue;
     // every source block read once when the block grid and the coefficient table are small
+    // (a single block, the classical product, needs no sharing: the per-leaf kernel below
+    // holds fewer registers and streams faster)
     const int64_t nblk = (int64_t)f.nbo * f.nbk;
-    if (f.nbo > 0 && f.nbk > 0 && nblk <= 16 && nblk * nleaves <= kAllMaxCoef) {
+    if (f.nbo > 0 && f.nbk > 0 && nblk > 1 && nblk <= 16 && nblk * nleaves <= kAllMaxCoef) {
         if (nblk <= 4) return form_all_go<HALF, NL, 16>(f, nleaves, s);
         if (nblk <= 8) return form_all_go<HALF, NL, 8>(f, nleaves, s);
         return form_all_go<HALF, NL, 4>(f, nleaves, s);

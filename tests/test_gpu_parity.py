@@ -282,6 +282,35 @@ def test_split_precision_with_outside_scaling_badly_scaled(precision):
     assert rel <= theorem_bound("strassen", 128, 128, 128, 2, 1, U_EFF[precision])
 
 
+@pytest.mark.parametrize("precision", ["f16x3", "bf16x3"])
+@pytest.mark.parametrize("name,depth,shape", [
+    ("strassen", 1, (150, 200, 130)),  # 2 x 2 block grids
+    ("f424", 1, (160, 96, 200)),       # 4 x 2 / 4 x 2 block grids
+    ("strassen", 2, (260, 200, 240)),  # 4 x 4 block grids
+])
+def test_split_precision_outside_scaling_integer_exact(precision, name, depth, shape):
+    # Outside scaling multiplies row i of A by 2^-ea_i and column j of B by 2^-eb_j: every
+    # product term of C'(i, j) carries the same factor, so on small integers the scaled limbs,
+    # the FP32 accumulation and the unscaling are all exact.
+    print(f"\n[split-scaled-int] {name} L={depth} {shape} {precision}", flush=True)
+    A, B = make_pair("int8", 9, *shape, dtype=np.float32)
+    got = run_gpu(_plan(name, depth, 1, precision, scaling="outside"), A, B)
+    assert np.array_equal(got.astype(np.float64), _exact(A, B))
+
+
+@pytest.mark.parametrize("name,depth", [("strassen", 1), ("f424", 1), ("winograd", 2)])
+def test_transposed_split_depths(name, depth):
+    # Transposed operands reach the plane formation with the other contiguous direction.
+    m, k, n = 136, 200, 120
+    A, B = make_pair("int8", 7, m, k, n, dtype=np.float32)
+    for ta, tb in [(True, False), (False, True), (True, True)]:
+        print(f"\n[split-trans] {name} L={depth} transA={ta} transB={tb}", flush=True)
+        As = np.ascontiguousarray(A.T) if ta else A
+        Bs = np.ascontiguousarray(B.T) if tb else B
+        got = run_gpu(_plan(name, depth, 1, "f16x3"), As, Bs, ta, tb)
+        assert np.array_equal(got.astype(np.float64), _exact(A, B))
+
+
 @pytest.mark.parametrize("precision", ["bf16x3", "f32", "f64"])
 def test_transposed_split_and_mfma(precision):
     m, k, n = 96, 130, 72
