@@ -60,6 +60,12 @@ def parse():
                     help="fusion mode of the plan (off: leaf products + W-combination)")
     ap.add_argument("--torch-ref", action="store_true",
                     help="also time torch.matmul (vendor BLAS) on the same operands, as context")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="time a batch of this many rectangular problems (dims drawn from 512..8192) with "
+                         "autotuned plans in one batched launch, instead of the single-product workload")
+    ap.add_argument("--tune-cache", default="", help="JSON cache of the autotuner's choices (batch mode)")
+    ap.add_argument("--max-instability", type=float, default=16.0,
+                    help="autotuner admission cap on (E/K0^2)^L (batch mode)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
@@ -138,12 +144,119 @@ def cpu_baseline_leg(args, A, B, rows):
     return out
 
 
+def leaf_flops(F, plan_algo, plan, m, k, n, precision):
+    """Product flops one launch executes for a plan on (m, k, n): leaves x limb products x 2 mb kb nb."""
+    L, Mp, Kp, Np = plan.shape(m, k, n)
+    if plan_algo == "classical" or L == 0:
+        return 2.0 * Mp * Kp * Np * PRODUCTS[precision]
+    info = F.fastmm_algo_info(plan_algo)
+    mb, kb, nb = Mp // info["M0"] ** L, Kp // info["K0"] ** L, Np // info["N0"] ** L
+    return 2.0 * mb * kb * nb * info["R"] ** L * PRODUCTS[precision]
+
+
+def batch_main(args):
+    """A batch of rectangular problems (dims drawn from {512, ..., 8192}, tall-skinny included,
+    N(0,1) entries from a seeded generator on the GPU), plans chosen per shape by the autotuner,
+    run as one fastmm_gemm_batched call per step; the same batch with classical plans beside."""
+    import numpy as np
+    import torch
+
+    import paper_1507_00687_amd as F
+    from paper_1507_00687_amd import tune as T
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(args.seed)
+    dims = np.array([512, 1024, 2048, 4096, 8192])
+    shapes = [tuple(int(x) for x in rng.choice(dims, 3)) for _ in range(args.batch)]
+    dt = torch.float64 if args.precision == "f64" else torch.float32
+    gen = torch.Generator(device="cuda").manual_seed(args.seed)
+    As = [torch.randn((m, k), dtype=dt, device="cuda", generator=gen) for m, k, n in shapes]
+    Bs = [torch.randn((k, n), dtype=dt, device="cuda", generator=gen) for m, k, n in shapes]
+    Cs = [torch.empty((m, n), dtype=dt, device="cuda") for m, k, n in shapes]
+    t0 = time.perf_counter()
+    choices = T.tune(shapes, precision=args.precision, cache=args.tune_cache or None, max_depth=2,
+                     cutoffs=(256,), max_instability=args.max_instability, reps=2)
+    tune_s = time.perf_counter() - t0
+    plans = [choices[sh].plan(args.precision) for sh in shapes]
+    cplans = [F.Plan("classical", 0, 1, precision=args.precision) for _ in shapes]
+    ws = torch.empty(max(F.fastmm_batched_workspace_size(plans, As, Bs), 1), dtype=torch.uint8, device="cuda")
+    cws = torch.empty(max(F.fastmm_batched_workspace_size(cplans, As, Bs), 1), dtype=torch.uint8, device="cuda")
+    Cc = [torch.empty_like(c) for c in Cs]
+    flops = sum(2.0 * m * k * n for m, k, n in shapes)
+    run = lambda: F.fastmm_gemm_batched(plans, As, Bs, Cs, workspace=ws)
+    ms_cls = time_steps(lambda: F.fastmm_gemm_batched(cplans, As, Bs, Cc, workspace=cws), args.steps, args.warmup)
+    ms = time_steps(run, args.steps, args.warmup)
+
+    F.fastmm_profile_enable(True)
+    F.fastmm_profile_read()
+    for _ in range(args.steps):
+        run()
+    prof = F.fastmm_profile_read()
+    F.fastmm_profile_enable(False)
+    calls = max(prof["calls"], 1)
+    leaf_ms = prof["leaf_ms"] / calls
+    executed = sum(leaf_flops(F, choices[sh].algo, p, *sh, args.precision) for sh, p in zip(shapes, plans))
+    achieved = executed / (leaf_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+
+    # errors of a few problems on sampled rows against the long-double reference (oracle leg)
+    from oracle import fastmm_oracle as O
+
+    err_fast = err_cls = 0.0
+    for i in np.unique(np.linspace(0, len(shapes) - 1, 4).astype(int)):
+        m, k, n = shapes[i]
+        rows = np.unique(np.linspace(0, m - 1, 4).astype(np.int64))
+        A64 = As[i].double().cpu().numpy()
+        B64 = Bs[i].double().cpu().numpy()
+        ref = O.reference_rows(A64, B64, rows)
+        err_fast = max(err_fast, O.normwise_error(Cs[i].cpu().numpy(), ref, A64, B64, rows))
+        err_cls = max(err_cls, O.normwise_error(Cc[i].cpu().numpy(), ref, A64, B64, rows))
+    mix = {}
+    for sh in shapes:
+        c = choices[sh]
+        key = f"{c.algo} L={c.depth}" if c.depth else "classical"
+        mix[key] = mix.get(key, 0) + 1
+    kname = "fmm_limb_gemm_batched" if args.precision in ("bf16", "f16", "bf16x3", "f16x3", "bf16x6") else \
+        "fmm_leaf_batched"
+    line = {
+        "metric": METRIC,
+        "value": flops / (ms * 1e-3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"batch of {len(shapes)} problems, dims from 512..8192 (seed {args.seed}), "
+                               f"autotuned plans, {args.precision}, N(0,1)",
+                   "problems": len(shapes), "flops_2mkn": flops, "plan_mix": mix,
+                   "tuning_s": tune_s, "max_instability": args.max_instability},
+        "classical": {"ms_per_step": ms_cls, "value": flops / (ms_cls * 1e-3) / 1e12},
+        "speedup_vs_classical": ms_cls / ms,
+        "error": {"fast": err_fast, "classical": err_cls, "problems_sampled": 4, "rows_per_problem": 4,
+                  "reference": "long double classical (oracle)"},
+        "phases_ms": {"scaling": prof["scaling_ms"] / calls, "form": prof["form_ms"] / calls, "leaf": leaf_ms,
+                      "combine": prof["combine_ms"] / calls},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None, "kernel": kname, "flops_per_launch": executed},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built",
               file=sys.stderr)
         sys.exit(2)
+    if args.batch > 0:
+        batch_main(args)
+        return
     import numpy as np
     import torch
 

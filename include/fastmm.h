@@ -253,10 +253,11 @@ fastmm_status fastmm_scaling_exponents(fastmm_plan_t plan, const void *A, const 
 
 /* ---- diagnostics ------------------------------------------------------------------- */
 
-/* Phase timing for measurement: while enabled (nonzero), every fastmm_gemm / gemm_ex call
- * on the calling thread records HIP events on its stream around its four phases (scaling
- * reductions; operand formation, i.e. the limb planes of the split precisions, zero
- * otherwise; the products kernel; the W-combination).  fastmm_profile_read synchronises on the
+/* Phase timing for measurement: while enabled (nonzero), every fastmm_gemm / gemm_ex /
+ * gemm_batched call on the calling thread records HIP events on its stream around its four
+ * phases (scaling reductions; operand formation, i.e. the limb planes of the split precisions,
+ * zero otherwise; the products kernel, for a batch its one launch with the descriptor upload;
+ * the W-combination; a batch counts as one call).  fastmm_profile_read synchronises on the
  * last recorded events and returns the summed milliseconds of each phase and the number of
  * calls since the last read (then resets).  Any output pointer may be NULL. */
 fastmm_status fastmm_profile_enable(int enable);

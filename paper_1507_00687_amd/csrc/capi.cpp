@@ -682,6 +682,29 @@ namespace fastmm {
 namespace {
 // Split precisions, pass 1: the limb planes of every leaf's S_r and T_r^T (scaling applied),
 // composite or level by level; fills the plane part of the limb-GEMM launch g.
+// Profiler marks of one call: event 0 when it starts, one event as each phase (scaling,
+// operand formation, products, W-combination) ends; phases not reached are recorded empty
+// when the call returns, on every exit path.
+struct PhaseMarks {
+    bool prof;
+    PhaseEvents pe{};
+    hipStream_t st;
+    int next = 1;
+    explicit PhaseMarks(hipStream_t s) : prof(g_prof.on), st(s) {
+        if (!prof) return;
+        for (int i = 0; i <= kPhases; ++i) pe.ev[i] = g_prof.get();
+        (void)hipEventRecord(pe.ev[0], st);
+    }
+    void mark() {
+        if (prof && next <= kPhases) (void)hipEventRecord(pe.ev[next++], st);
+    }
+    ~PhaseMarks() {
+        if (!prof) return;
+        while (next <= kPhases) (void)hipEventRecord(pe.ev[next++], st);
+        g_prof.pending.push_back(pe);
+    }
+};
+
 hipError_t split_form(fastmm_plan_s *plan, const Shape &s, const SplitDims &d, const void *A, int64_t lda,
                       int transA, const void *B, int64_t ldb, int transB, int64_t m, int64_t k, int64_t n,
                       const ScaleExps &exps, char *ws, const WsLayout &w, const Tables *tab, hipStream_t st,
@@ -796,26 +819,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     fastmm_status stt = get_tables(plan, s.L, &tab);
     if (stt != FASTMM_OK) return stt;
     char *ws = (char *)workspace;
-    PhaseEvents pe{};
-    const bool prof = g_prof.on;
-    if (prof) {
-        for (int i = 0; i <= kPhases; ++i) pe.ev[i] = g_prof.get();
-        (void)hipEventRecord(pe.ev[0], st);
-    }
-    struct Finish {  // records the remaining phase marks on every exit path
-        bool prof;
-        PhaseEvents *pe;
-        hipStream_t st;
-        int next = 1;
-        void mark() {
-            if (prof && next <= kPhases) (void)hipEventRecord(pe->ev[next++], st);
-        }
-        ~Finish() {
-            if (!prof) return;
-            while (next <= kPhases) (void)hipEventRecord(pe->ev[next++], st);
-            g_prof.pending.push_back(*pe);
-        }
-    } fin{prof, &pe, st};
+    PhaseMarks fin(st);
     ScaleExps exps;
     stt = run_scaling(plan, A, lda, transA, B, ldb, transB, m, k, n, ws, w, st, &exps);
     fin.mark();
@@ -948,9 +952,10 @@ fastmm_status rotated_plan(fastmm_plan_s *p, int times, fastmm_plan_s **out) {
 
 namespace fastmm {
 namespace {
+constexpr int kModes = 4;  // FP32 / FP64 batch items: scaled operands or not x output to C or not
 struct BatchLayout {
     std::vector<size_t> ws_off, ws_size;
-    size_t descs = 0, first = 0, direct = 0, total = 0;
+    size_t descs = 0, first = 0, total = 0;
     int bm = 0;  // split precisions: the limb-GEMM tile shared by the batch
 };
 
@@ -984,8 +989,7 @@ fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem *pro
     const Elem el = prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
     const size_t db = is_split(prec) ? sizeof(LimbGemm) : leaf_desc_bytes(el);
     bl.descs = off, off = align256(off + db * (size_t)std::max(count, 1));
-    bl.first = off, off = align256(off + 8 * (size_t)(count + 1));
-    bl.direct = off, off = align256(off + 4 * (size_t)std::max(count, 1));
+    bl.first = off, off = align256(off + 8 * (size_t)(count + kModes));  // one prefix array per mode
     bl.total = off;
     return FASTMM_OK;
 }
@@ -1047,13 +1051,27 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
         int idx;
         int64_t kb;
         std::vector<char> desc;
-        int direct;
+        int mode;  // FP32 / FP64: 2 * scaled + direct (one launch per mode); split: 0
         int64_t tiles;
         CombineLaunch cb;
         bool combine;
     };
     std::vector<Item> items;
     hipError_t e;
+    PhaseMarks fin(s);
+    // every problem's scaling steps, then every problem's operand formation (split precisions)
+    std::vector<ScaleExps> exps_all(count);
+    for (int i = 0; i < count; ++i) {
+        const fastmm_problem &q = probs[i];
+        fastmm_plan_s *p = plans[i];
+        if (q.m == 0 || q.n == 0 || q.k == 0) continue;
+        const Shape sh = shape_of(p, q.m, q.k, q.n);
+        const WsLayout w = ws_layout(p, sh, q.m, q.k, q.n, bl.bm);
+        if ((st = run_scaling(p, q.A, q.k, 0, q.B, q.n, 0, q.m, q.k, q.n, ws + bl.ws_off[i], w, s, &exps_all[i])) !=
+            FASTMM_OK)
+            return st;
+    }
+    fin.mark();
     for (int i = 0; i < count; ++i) {
         const fastmm_problem &q = probs[i];
         fastmm_plan_s *p = plans[i];
@@ -1067,8 +1085,7 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
         char *pws = ws + bl.ws_off[i];
         Tables *tab = nullptr;
         if ((st = get_tables(p, sh.L, &tab)) != FASTMM_OK) return st;
-        ScaleExps exps;
-        if ((st = run_scaling(p, q.A, q.k, 0, q.B, q.n, 0, q.m, q.k, q.n, pws, w, s, &exps)) != FASTMM_OK) return st;
+        const ScaleExps exps = exps_all[i];
         if (split) {
             // limb planes now; the products of every problem in the one launch below
             Item it;
@@ -1091,7 +1108,7 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
                 c.C = q.C, c.ldc = q.n, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
                 c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
             }
-            it.direct = g.direct;
+            it.mode = 0;
             it.desc.resize(sizeof(LimbGemm));
             std::memcpy(it.desc.data(), &g, sizeof(LimbGemm));
             it.tiles = (int64_t)tab->nleaves * g.tiles_m * g.tiles_n;
@@ -1121,20 +1138,22 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
             c.C = q.C, c.ldc = q.n, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
             c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
         }
-        it.direct = L.direct;
+        it.mode = 2 * (exps.ea != nullptr ? 1 : 0) + (L.direct ? 1 : 0);
         it.desc.resize(leaf_desc_bytes(el));
         it.tiles = leaf_desc_build(L, it.desc.data());
         items.push_back(std::move(it));
     }
+    fin.mark();
     // largest inner dimension first: the longest work items start earliest
-    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.kb > b.kb; });
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+        return a.mode != b.mode ? a.mode < b.mode : a.kb > b.kb;
+    });
     // Host staging of the descriptor table: kept per thread until the copies of the previous
     // batched call on this thread have completed (an event marks them), so the stream never
     // has to be synchronised.
     thread_local struct Staging {
         std::vector<char> descs;
         std::vector<int64_t> first;
-        std::vector<int> direct;
         hipEvent_t done = nullptr;
         bool pending = false;
     } stg;
@@ -1142,36 +1161,47 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
     stg.pending = false;
     const size_t db = split ? sizeof(LimbGemm) : leaf_desc_bytes(el);
     stg.descs.assign(db * std::max<size_t>(items.size(), 1), 0);
-    stg.first.assign(items.size() + 1, 0);
-    stg.direct.assign(std::max<size_t>(items.size(), 1), 0);
+    stg.first.clear();
+    // one group of consecutive items per mode, each with its own prefix array of item offsets
+    struct Group {
+        size_t begin, end, first_off;
+        int64_t total;
+        int mode;
+    };
+    std::vector<Group> groups;
     for (size_t i = 0; i < items.size(); ++i) {
         std::memcpy(stg.descs.data() + i * db, items[i].desc.data(), db);
-        stg.first[i + 1] = stg.first[i] + items[i].tiles;
-        stg.direct[i] = items[i].direct;
+        if (groups.empty() || groups.back().mode != items[i].mode) {
+            groups.push_back(Group{i, i, stg.first.size(), 0, items[i].mode});
+            stg.first.push_back(0);
+        }
+        Group &g = groups.back();
+        g.end = i + 1;
+        g.total += items[i].tiles;
+        stg.first.push_back(g.total);
     }
-    const int64_t total = stg.first.back();
-    if (total > 0) {
+    if (!groups.empty()) {
         if (!stg.done && (e = hipEventCreateWithFlags(&stg.done, hipEventDisableTiming)) != hipSuccess)
             return hip_fail(e, "staging event");
         if ((e = hipMemcpyAsync(ws + bl.descs, stg.descs.data(), db * items.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(ws + bl.first, stg.first.data(), 8 * stg.first.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(ws + bl.direct, stg.direct.data(), 4 * items.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
+            (e = hipMemcpyAsync(ws + bl.first, stg.first.data(), 8 * stg.first.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
             return hip_fail(e, "uploading batch descriptors");
         if ((e = hipEventRecord(stg.done, s)) != hipSuccess) return hip_fail(e, "staging event");
         stg.pending = true;
+    }
+    for (const Group &g : groups) {
+        if (g.total <= 0) continue;
+        const char *gd = ws + bl.descs + g.begin * db;
+        const int64_t *gf = (const int64_t *)(ws + bl.first) + g.first_off;
+        const int gc = (int)(g.end - g.begin);
         if (split) {
-            if ((e = launch_limb_gemm_batched(plans[0]->prec, bl.bm, ws + bl.descs, (const int64_t *)(ws + bl.first),
-                                              (int)items.size(), total, s)) != hipSuccess)
+            if ((e = launch_limb_gemm_batched(plans[0]->prec, bl.bm, gd, gf, gc, g.total, s)) != hipSuccess)
                 return hip_fail(e, "batched limb GEMM kernel");
-        } else {
-            const int64_t slots = (int64_t)device_cus() * leaf_blocks_per_cu(el);
-            const int grid = (int)std::min<int64_t>(total, slots);
-            if ((e = launch_leaf_batched(el, ws + bl.descs, (const int64_t *)(ws + bl.first),
-                                         (const int *)(ws + bl.direct), (int)items.size(), total, grid, s)) !=
-                hipSuccess)
-                return hip_fail(e, "batched leaf kernel");
+        } else if ((e = launch_leaf_batched(el, g.mode >> 1, g.mode & 1, gd, gf, gc, g.total, s)) != hipSuccess) {
+            return hip_fail(e, "batched leaf kernel");
         }
     }
+    fin.mark();
     for (const Item &it : items)
         if (it.combine && (e = launch_combine(it.cb, s)) != hipSuccess) return hip_fail(e, "combine kernel");
     return FASTMM_OK;

@@ -177,16 +177,16 @@ hipError_t launch_limb_gemm_batched(int prec, int bm, const void *descs, const i
 hipError_t launch_leaf(const LeafLaunch &L, hipStream_t s);
 // Pipelined 128x128-tile version for row-major (non-transposed) operands.
 hipError_t launch_leaf_pipelined(const LeafLaunch &L, hipStream_t s);
-// Batched persistent version (row-major operands, FP64/FP32): leaf_desc_build writes the
-// device descriptor of one problem's launch to `dst` (leaf_desc_bytes(e) bytes, host memory)
-// and returns its number of work items; launch_leaf_batched runs `total` items of `count`
-// problems (descriptors, item prefix offsets first[count+1] and direct flags in device memory)
-// on `grid` persistent work-groups.
+// Batched version (row-major operands, FP64/FP32): leaf_desc_build writes the device
+// descriptor of one problem's launch to `dst` (leaf_desc_bytes(e) bytes, host memory) and
+// returns its number of work items; launch_leaf_batched runs `total` items of `count` problems
+// that share one mode (scaled operands or not, output to C or to the leaf workspace), with the
+// descriptors and the item prefix offsets first[count + 1] in device memory, one work-group
+// per item.
 size_t leaf_desc_bytes(Elem e);
 int64_t leaf_desc_build(const LeafLaunch &L, void *dst);
-hipError_t launch_leaf_batched(Elem e, const void *descs, const int64_t *first, const int *direct, int count,
-                               int64_t total, int grid, hipStream_t s);
-int leaf_blocks_per_cu(Elem e);
+hipError_t launch_leaf_batched(Elem e, int scaled, int direct, const void *descs, const int64_t *first, int count,
+                               int64_t total, hipStream_t s);
 // out (C x R) = in^T for a row-major R x C matrix (FP32 or FP64).
 hipError_t launch_transpose(Elem e, const void *in, int64_t ldi, int64_t R, int64_t C, void *out, int64_t ldo,
                             hipStream_t s);

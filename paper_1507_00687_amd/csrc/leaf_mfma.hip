@@ -452,35 +452,32 @@ __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T>
     leaf_tile<T, SCALED, DIRECT>(p, leaf, tm, tn, sm);
 }
 
-// Persistent batched launch over several problems (each with its own plan tables): work item
-// w (in [0, total)) belongs to the problem q with first[q] <= w < first[q+1], ordered by the
-// host (largest K first); work-group g processes items g, g + G, g + 2G, ... in order, so the
-// assignment is static and the results deterministic.
-template <typename T>
-__global__ __launch_bounds__(kNT, 1) void fmm_leaf_batched(const PArgs<T> *probs, const int64_t *first,
-                                                                     const int *direct, int count, int64_t total) {
+// Batched launch over several problems of one output mode (each with its own plan tables):
+// work-group w runs work item w, which belongs to the problem q with first[q] <= w < first[q+1]
+// (problems ordered by the host, largest K first, so the longest items are dispatched first).
+// The host launches one such kernel per (scaling, output) mode present in the batch, so each
+// is the single-problem tile code with its register count and occupancy.
+template <typename T, bool SCALED, bool DIRECT>
+__global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_batched(const PArgs<T> *__restrict__ probs,
+                                                                     const int64_t *__restrict__ first, int count,
+                                                                     int64_t total) {
     __shared__ typename Tile<T>::Smem sm;
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        int q = 0;
-        while (q + 1 < count && first[q + 1] <= w) ++q;
-        q = __builtin_amdgcn_readfirstlane(q);
-        const PArgs<T> &p = probs[q];
-        const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
-        const int64_t local = w - first[q];
-        const int leaf = __builtin_amdgcn_readfirstlane((int)(local / tiles));
-        const int rem = __builtin_amdgcn_readfirstlane((int)(local - (int64_t)leaf * tiles));
-        int64_t tm, tn;
-        tile_coords(rem, p.tiles_m, p.tiles_n, tm, tn);
-        const bool scaled = p.sc.ea != nullptr, dir = direct[q] != 0;
-        if (scaled) {
-            if (dir) leaf_tile<T, true, true>(p, leaf, tm, tn, sm);
-            else leaf_tile<T, true, false>(p, leaf, tm, tn, sm);
-        } else {
-            if (dir) leaf_tile<T, false, true>(p, leaf, tm, tn, sm);
-            else leaf_tile<T, false, false>(p, leaf, tm, tn, sm);
-        }
-        __syncthreads();  // the next item reuses the LDS buffers
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {  // last q with first[q] <= w
+        const int mid = (lo + hi + 1) / 2;
+        if (first[mid] <= w) lo = mid;
+        else hi = mid - 1;
     }
+    const int q = __builtin_amdgcn_readfirstlane(lo);
+    const PArgs<T> p = probs[q];
+    const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
+    const int64_t local = w - first[q];
+    const int leaf = __builtin_amdgcn_readfirstlane((int)(local / tiles));
+    const int rem = __builtin_amdgcn_readfirstlane((int)(local - (int64_t)leaf * tiles));
+    int64_t tm, tn;
+    tile_coords(rem, p.tiles_m, p.tiles_n, tm, tn);
+    leaf_tile<T, SCALED, DIRECT>(p, leaf, tm, tn, sm);
 }
 
 
@@ -540,19 +537,28 @@ int64_t leaf_desc_build(const LeafLaunch &L, void *dst) {
     return (int64_t)a.tiles_m * a.tiles_n * L.nleaves;
 }
 
-hipError_t launch_leaf_batched(Elem e, const void *descs, const int64_t *first, const int *direct, int count,
-                               int64_t total, int grid, hipStream_t s) {
-    if (total <= 0) return hipSuccess;
-    if (e == Elem::F64)
-        hipLaunchKernelGGL(fmm_leaf_batched<double>, dim3(grid), dim3(kNT), 0, s, (const PArgs<double> *)descs, first,
-                           direct, count, total);
-    else
-        hipLaunchKernelGGL(fmm_leaf_batched<float>, dim3(grid), dim3(kNT), 0, s, (const PArgs<float> *)descs, first,
-                           direct, count, total);
+template <typename T>
+hipError_t batched_go(int scaled, int direct, const void *descs, const int64_t *first, int count, int64_t total,
+                      hipStream_t s) {
+    const PArgs<T> *d = (const PArgs<T> *)descs;
+    const dim3 grid((unsigned)total), block(kNT);
+    if (scaled) {
+        if (direct) hipLaunchKernelGGL((fmm_leaf_batched<T, true, true>), grid, block, 0, s, d, first, count, total);
+        else hipLaunchKernelGGL((fmm_leaf_batched<T, true, false>), grid, block, 0, s, d, first, count, total);
+    } else {
+        if (direct) hipLaunchKernelGGL((fmm_leaf_batched<T, false, true>), grid, block, 0, s, d, first, count, total);
+        else hipLaunchKernelGGL((fmm_leaf_batched<T, false, false>), grid, block, 0, s, d, first, count, total);
+    }
     return hipGetLastError();
 }
 
-int leaf_blocks_per_cu(Elem) { return 1; }  // the batched kernel holds all four tile variants
+hipError_t launch_leaf_batched(Elem e, int scaled, int direct, const void *descs, const int64_t *first, int count,
+                               int64_t total, hipStream_t s) {
+    if (total <= 0 || count <= 0) return hipSuccess;
+    if (total > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (e == Elem::F64) return batched_go<double>(scaled, direct, descs, first, count, total, s);
+    return batched_go<float>(scaled, direct, descs, first, count, total, s);
+}
 
 hipError_t launch_leaf_pipelined(const LeafLaunch &L, hipStream_t s) {
     if (L.elem == Elem::F64) return go<double>(L, s);

@@ -524,8 +524,8 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm(LimbGemm a) {
 // Several problems in one launch: work-group w runs item w - first[q] of problem q, where
 // first[q] <= w < first[q + 1] (problems ordered by the host, largest inner dimension first).
 template <bool HALF, int NL, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm_batched(const LimbGemm *descs, const int64_t *first,
-                                                                       int count) {
+__global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm_batched(const LimbGemm *__restrict__ descs,
+                                                                       const int64_t *__restrict__ first, int count) {
     __shared__ LimbSmem<NL, BM, BN> sm;
     const int64_t w = blockIdx.x;
     int lo = 0, hi = count - 1;

@@ -255,6 +255,30 @@ def fastmm_gemm_ex(plan: Plan, A, transA: bool, B, transB: bool, C=None, workspa
     return C
 
 
+def _batch_problems(plans, As, Bs, Cs):
+    count = len(As)
+    probs = (_Problem * max(count, 1))()
+    for i, (a, b, c) in enumerate(zip(As, Bs, Cs)):
+        if a.shape[1] != b.shape[0]:
+            raise ValueError(f"problem {i}: inner dimensions differ")
+        if a.dtype != plans[i].dtype or b.dtype != plans[i].dtype:
+            raise TypeError(f"problem {i}: operands must be {plans[i].dtype}")
+        probs[i] = _Problem(a.data_ptr(), b.data_ptr(), c.data_ptr() if c is not None else 0, a.shape[0], a.shape[1],
+                            b.shape[1])
+    handles = (ctypes.c_void_p * max(count, 1))(*[p.handle.value for p in plans])
+    return probs, handles
+
+
+def fastmm_batched_workspace_size(plans, As, Bs) -> int:
+    """Workspace bytes fastmm_gemm_batched needs for these problems."""
+    if not (len(As) == len(Bs) == len(plans)):
+        raise ValueError("plans, As and Bs must have the same length")
+    probs, handles = _batch_problems(plans, As, Bs, [None] * len(As))
+    need = ctypes.c_size_t()
+    _check(lib().fastmm_batched_workspace_size(handles, probs, len(As), ctypes.byref(need)))
+    return need.value
+
+
 def fastmm_gemm_batched(plans, As, Bs, Cs=None, workspace=None, stream=None):
     """C_i = A_i @ B_i for all i with plans[i]; one persistent leaf launch for the batch."""
     import torch
@@ -266,14 +290,7 @@ def fastmm_gemm_batched(plans, As, Bs, Cs=None, workspace=None, stream=None):
     Bs = [b.contiguous() for b in Bs]
     if Cs is None:
         Cs = [torch.empty((a.shape[0], b.shape[1]), dtype=a.dtype, device=a.device) for a, b in zip(As, Bs)]
-    probs = (_Problem * max(count, 1))()
-    for i, (a, b, c) in enumerate(zip(As, Bs, Cs)):
-        if a.shape[1] != b.shape[0]:
-            raise ValueError(f"problem {i}: inner dimensions differ")
-        if a.dtype != plans[i].dtype or b.dtype != plans[i].dtype:
-            raise TypeError(f"problem {i}: operands must be {plans[i].dtype}")
-        probs[i] = _Problem(a.data_ptr(), b.data_ptr(), c.data_ptr(), a.shape[0], a.shape[1], b.shape[1])
-    handles = (ctypes.c_void_p * max(count, 1))(*[p.handle.value for p in plans])
+    probs, handles = _batch_problems(plans, As, Bs, Cs)
     need = ctypes.c_size_t()
     _check(lib().fastmm_batched_workspace_size(handles, probs, count, ctypes.byref(need)))
     if workspace is None:

@@ -6,6 +6,11 @@ Theorem 4.1 over the classical K0^L -- stays within `max_instability` (the relat
 instability (E/K0^2)^L of section 5.3 is the same quantity up to the inner dimension); the
 fastest admitted candidate wins.  Results are cached in a JSON file keyed by shape and
 precision, so tuning can resume.  The timing itself runs the product through libfastmm.so.
+
+By default a candidate is timed the way a batch runs it: as one fastmm_gemm_batched call over
+enough copies of the shape to give the GPU several hundred output tiles, the time divided by
+the copies.  (Timed alone, a small classical product leaves most compute units idle and the
+extra leaves of a fast rule look like a gain that a full batch does not see.)
 """
 from __future__ import annotations
 
@@ -68,13 +73,42 @@ def _time_plan(plan, A, B, C, ws, reps: int) -> float:
     return times[len(times) // 2]
 
 
-def _key(m, k, n, precision):
-    return f"{m}x{k}x{n}:{precision}"
+def _time_plan_batched(plan, A, B, Cs, reps: int) -> float:
+    """Milliseconds per problem of one batched call over len(Cs) copies of (A, B)."""
+    import torch
+
+    from .fastmm import fastmm_batched_workspace_size, fastmm_gemm_batched
+
+    c = len(Cs)
+    plans, As, Bs = [plan] * c, [A] * c, [B] * c
+    ws = torch.empty(max(fastmm_batched_workspace_size(plans, As, Bs), 1), dtype=torch.uint8, device="cuda")
+    fastmm_gemm_batched(plans, As, Bs, Cs, workspace=ws)  # warm-up (uploads the task table)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        start.record()
+        fastmm_gemm_batched(plans, As, Bs, Cs, workspace=ws)
+        stop.record()
+        stop.synchronize()
+        times.append(start.elapsed_time(stop))
+    times.sort()
+    return times[len(times) // 2] / c
+
+
+def batch_copies(m: int, n: int, target_tiles: int = 512, max_copies: int = 32) -> int:
+    """Copies of an m x n output that give about target_tiles output tiles of 256 x 256."""
+    tiles = -(-m // 256) * -(-n // 256)
+    return max(1, min(max_copies, -(-target_tiles // tiles)))
+
+
+def _key(m, k, n, precision, in_batch=True):
+    return f"{m}x{k}x{n}:{precision}" + (":batch" if in_batch else "")
 
 
 def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 3, cutoffs=(256,),
-               max_instability: float = float("inf"), reps: int = 3, A=None, B=None) -> Choice:
-    """Measure every admitted candidate on (m, k, n) and return the fastest."""
+               max_instability: float = float("inf"), reps: int = 3, A=None, B=None, in_batch: bool = True) -> Choice:
+    """Measure every admitted candidate on (m, k, n) and return the fastest (timed inside a
+    batch of copies when in_batch, else alone)."""
     import torch
 
     from .fastmm import Plan
@@ -86,6 +120,7 @@ def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 
     if B is None:
         B = torch.randn((k, n), dtype=dt, device="cuda", generator=gen)
     C = torch.empty((m, n), dtype=dt, device="cuda")
+    Cs = [torch.empty((m, n), dtype=dt, device="cuda") for _ in range(batch_copies(m, n))] if in_batch else None
     best: Optional[Choice] = None
     seen = set()
     for algo, depth, cutoff in candidates(max_depth, cutoffs):
@@ -97,8 +132,11 @@ def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 
         inst = relative_instability(algo, levels)
         if inst > max_instability:
             continue
-        ws = torch.empty(max(plan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
-        ms = _time_plan(plan, A, B, C, ws, reps)
+        if in_batch:
+            ms = _time_plan_batched(plan, A, B, Cs, reps)
+        else:
+            ws = torch.empty(max(plan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
+            ms = _time_plan(plan, A, B, C, ws, reps)
         if best is None or ms < best.ms:
             best = Choice(algo, depth if levels else 0, cutoff, ms, inst)
     assert best is not None
@@ -114,7 +152,7 @@ def tune(shapes: Iterable[Tuple[int, int, int]], precision: str = "f32", cache: 
             store = json.load(f)
     out = {}
     for (m, k, n) in dict.fromkeys(tuple(s) for s in shapes):
-        key = _key(m, k, n, precision)
+        key = _key(m, k, n, precision, kw.get("in_batch", True))
         if key in store:
             out[(m, k, n)] = Choice(**store[key])
             continue
