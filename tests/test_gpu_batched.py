@@ -77,6 +77,33 @@ def test_batched_split_precision_exact_and_equal_to_single_launches(precision):
         assert np.array_equal(cb, cs)
 
 
+@pytest.mark.parametrize("precision", ["f32", "f64", "f16x3"])
+def test_batched_mixed_scaling_and_output_modes(precision):
+    # plans with and without outside scaling, classical (written straight to C) and fast
+    # (leaf workspace, then the W-combination) in one batch: every mode's group of work items
+    import torch
+
+    import paper_1507_00687_amd as F
+
+    dt = np_dtype(precision) if precision != "f16x3" else np.float32
+    specs = [("classical", 0, "none", (130, 70, 90)), ("strassen", 1, "outside", (256, 128, 160)),
+             ("classical", 0, "outside", (96, 200, 64)), ("winograd", 2, "none", (150, 260, 170)),
+             ("f424", 1, "outside", (160, 96, 200)), ("strassen", 2, "none", (70, 300, 90))]
+    plans, As, Bs, hostA, hostB = [], [], [], [], []
+    for i, (name, depth, scaling, (m, k, n)) in enumerate(specs):
+        A, B = make_pair("int8", 200 + i, m, k, n, dtype=dt)
+        hostA.append(A)
+        hostB.append(B)
+        plans.append(F.Plan(name, depth, 1, precision=precision, scaling=scaling))
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+    Cs = F.fastmm_gemm_batched(plans, As, Bs)
+    torch.cuda.synchronize()
+    for a, b, c in zip(hostA, hostB, Cs):
+        exact = (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64)
+        assert np.array_equal(c.cpu().numpy().astype(np.float64), exact)
+
+
 def test_batched_repeat_is_deterministic():
     _, _, C1, _ = _run_batch("f32", "normal")
     _, _, C2, _ = _run_batch("f32", "normal")
