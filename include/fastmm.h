@@ -160,6 +160,21 @@ typedef enum {
  * arithmetic; at depth 1 they round identically (bitwise equal results). */
 fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode);
 
+/* Non-uniform recursion (section 3.4; Examples 4.2 and 4.3): gives every internal node of the
+ * plan's recursion tree its own rule.  node_algos[i] is the rule id of node i in breadth-first
+ * order: node [l, r_1 .. r_{l-1}] (level l, reached through the 0-based products r_1 ..
+ * r_{l-1}) is entry (R^(l-1) - 1) / (R - 1) + (r_1 .. r_{l-1} read as a base-R number), so
+ * count = 1 + R + ... + R^(depth-1).  Every rule must have the plan rule's <M0,K0,N0;R> (for
+ * instance the permutation variants [U, (P x I) V, (I x P) W] of Example 4.2, registered with
+ * fastmm_algo_register) and every product live.  count = 0 restores the plan's rule at every
+ * node.  When the cutoff leaves fewer levels, the tree's first levels apply.  Such plans take
+ * the leaf path (and the limb planes of the split precisions); fastmm_gemm_backward rejects
+ * them (FASTMM_EUNSUPPORTED).  Must not be called while calls using the plan are in flight
+ * (the plan's cached task tables are rebuilt).  Errors: FASTMM_EINVAL (null list, unknown
+ * id), FASTMM_ESHAPE (wrong count, a rule of another shape), FASTMM_EUNSUPPORTED (a rule with
+ * a product that never reaches C). */
+fastmm_status fastmm_plan_set_tree(fastmm_plan_t plan, const int *node_algos, int64_t count);
+
 /* The path (fastmm_path) fastmm_gemm_ex takes for this shape and these transposition flags. */
 fastmm_status fastmm_plan_path(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, int transA,
                                int transB, int *path);

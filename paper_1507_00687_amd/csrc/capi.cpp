@@ -114,13 +114,33 @@ const size_t kMaxTableEntries = size_t(1) << 24;
 // r = (r_1..r_L) has A sources prod_l U[i_l, r_l] A_(i_1..i_L), B sources likewise, and
 // contributes prod_l W[k_l, r_l] M_r to output block (k_1..k_L).  Level 1 is the most
 // significant digit of every composite block coordinate.
-bool build_tables(const Algo &a, int L, HostTables &ht, std::string &err) {
+// Composite tables of eq. (2) unrolled over L levels.  `nodes` (optional) gives the rule of
+// every internal node of the recursion tree in breadth-first order (section 3.4's non-uniform
+// recursion: node [l, r_1 .. r_{l-1}] is entry (R^(l-1) - 1) / (R - 1) + (r_1 .. r_{l-1} in
+// base R)); all share a's <M0,K0,N0;R>.  Without it, a is used at every node.
+bool build_tables(const Algo &a, int L, HostTables &ht, std::string &err,
+                  const std::vector<const Algo *> *nodes = nullptr) {
     const int M0 = a.M0, K0 = a.K0, N0 = a.N0, R = a.R;
     ht.MB = ht.KB = ht.NB = 1;
     for (int l = 0; l < L; ++l) ht.MB *= M0, ht.KB *= K0, ht.NB *= N0;
-    const auto Unz = col_nonzeros(a.U, M0 * K0, R);
-    const auto Vnz = col_nonzeros(a.V, K0 * N0, R);
-    const auto Wnz = col_nonzeros(a.W, M0 * N0, R);
+    struct NZ {
+        std::vector<std::vector<std::pair<int, int64_t>>> U, V, W;
+        int den_U, den_V, den_W;
+    };
+    std::map<const Algo *, NZ> nzs;
+    auto nz_of = [&](const Algo *x) -> const NZ & {
+        auto it = nzs.find(x);
+        if (it == nzs.end())
+            it = nzs.emplace(x, NZ{col_nonzeros(x->U, M0 * K0, R), col_nonzeros(x->V, K0 * N0, R),
+                                   col_nonzeros(x->W, M0 * N0, R), x->den_U, x->den_V, x->den_W}).first;
+        return it->second;
+    };
+    std::vector<int64_t> level_off(L + 1, 0);  // breadth-first index of the first node of each level
+    for (int l = 1, cnt = 1; l <= L; ++l, cnt *= R) level_off[l] = level_off[l - 1] + cnt;
+    if (nodes && (int64_t)nodes->size() < level_off[L]) {
+        err = "recursion tree has fewer nodes than the levels used";
+        return false;
+    }
     std::vector<std::vector<DestEntry>> per_block((size_t)ht.MB * ht.NB);
     int64_t nleaves_all = 1;
     for (int l = 0; l < L; ++l) nleaves_all *= R;
@@ -129,26 +149,36 @@ bool build_tables(const Algo &a, int L, HostTables &ht, std::string &err) {
         return false;
     }
     std::vector<int> r(L, 0);
+    std::vector<const NZ *> lv(L, nullptr);  // the rule of each level on this leaf's path
     for (int64_t leaf_all = 0; leaf_all < nleaves_all; ++leaf_all) {
         {  // odometer: r[0] most significant
             int64_t x = leaf_all;
             for (int l = L - 1; l >= 0; --l) r[l] = (int)(x % R), x /= R;
         }
+        int64_t prefix = 0;
+        for (int l = 0; l < L; ++l) {
+            lv[l] = &nz_of(nodes ? (*nodes)[(size_t)(level_off[l] + prefix)] : &a);
+            prefix = prefix * R + r[l];
+        }
         bool zero = false;
         for (int l = 0; l < L; ++l)
-            if (Unz[r[l]].empty() || Vnz[r[l]].empty() || Wnz[r[l]].empty()) zero = true;
+            if (lv[l]->U[r[l]].empty() || lv[l]->V[r[l]].empty() || lv[l]->W[r[l]].empty()) zero = true;
         if (zero) continue;  // this product never reaches C
         const int leaf = (int)ht.leaves.size();
         LeafEntry le{(int32_t)ht.asrc.size(), 0, (int32_t)ht.bsrc.size(), 0};
         // cartesian products over levels of the per-level nonzero lists
-        auto expand = [&](const std::vector<std::vector<std::pair<int, int64_t>>> &nz, int den, int rowsz,
-                          int colsz_base, bool is_c, std::vector<SrcEntry> *out_src) {
+        // which: 0 = U (A sources), 1 = V (B sources), 2 = W (C destinations)
+        auto expand = [&](int which, int rowsz, int colsz_base, bool is_c, std::vector<SrcEntry> *out_src) {
+            auto list = [&](int l) -> const std::vector<std::pair<int, int64_t>> & {
+                return which == 0 ? lv[l]->U[r[l]] : which == 1 ? lv[l]->V[r[l]] : lv[l]->W[r[l]];
+            };
             std::vector<int> idx(L, 0);
             while (true) {
                 int64_t br = 0, bc = 0;
                 double coef = 1.0;
                 for (int l = 0; l < L; ++l) {
-                    const auto &e = nz[r[l]][idx[l]];
+                    const auto &e = list(l)[idx[l]];
+                    const int den = which == 0 ? lv[l]->den_U : which == 1 ? lv[l]->den_V : lv[l]->den_W;
                     int p, q;
                     if (is_c) {  // row-major single index over M0 x N0
                         p = e.first / N0, q = e.first % N0;
@@ -165,13 +195,13 @@ bool build_tables(const Algo &a, int L, HostTables &ht, std::string &err) {
                     out_src->push_back({(int32_t)br, (int32_t)bc, (float)coef, 0});
                 }
                 int l = L - 1;
-                while (l >= 0 && ++idx[l] == (int)nz[r[l]].size()) idx[l] = 0, --l;
+                while (l >= 0 && ++idx[l] == (int)list(l).size()) idx[l] = 0, --l;
                 if (l < 0) break;
             }
         };
-        expand(Unz, a.den_U, M0, K0, false, &ht.asrc);
-        expand(Vnz, a.den_V, K0, N0, false, &ht.bsrc);
-        expand(Wnz, a.den_W, M0, N0, true, nullptr);
+        expand(0, M0, K0, false, &ht.asrc);
+        expand(1, K0, N0, false, &ht.bsrc);
+        expand(2, M0, N0, true, nullptr);
         le.a_count = (int32_t)(ht.asrc.size() - le.a_begin);
         le.b_count = (int32_t)(ht.bsrc.size() - le.b_begin);
         ht.leaves.push_back(le);
@@ -213,6 +243,9 @@ struct fastmm_plan_s {
     fastmm_scaling sc{0, 0, 0.0};
     int prec = FASTMM_F64;
     int fuse = FASTMM_FUSE_AUTO;  // fastmm_fusion
+    // Non-uniform recursion: the rule id of every internal node, breadth first (empty: `algo`
+    // at every node).
+    std::vector<int> tree;
     std::mutex mu;
     std::map<std::pair<int, int>, std::unique_ptr<fastmm::Tables>> tables;  // (L, device)
     // Sub-plans with the rotated rules, made on first use by the backward pass.
@@ -223,6 +256,19 @@ namespace fastmm {
 namespace {
 
 const Algo &plan_algo(const fastmm_plan_s *p) { return *algo_get(p->algo); }
+
+// The per-node rules of a non-uniform plan (empty for a uniform one).
+std::vector<const Algo *> plan_nodes(const fastmm_plan_s *p) {
+    std::vector<const Algo *> v;
+    for (int id : p->tree) v.push_back(algo_get(id));
+    return v;
+}
+
+bool build_plan_tables(const fastmm_plan_s *p, int L, HostTables &ht, std::string &err) {
+    if (p->tree.empty()) return build_tables(plan_algo(p), L, ht, err);
+    const std::vector<const Algo *> nodes = plan_nodes(p);
+    return build_tables(plan_algo(p), L, ht, err, &nodes);
+}
 
 Shape shape_of(const fastmm_plan_s *p, int64_t m, int64_t k, int64_t n) {
     const Algo &a = plan_algo(p);
@@ -317,7 +363,7 @@ SplitDims split_dims(int prec, const Shape &s, int bm_force = 0) {
 // composite leaves are exactly the R^L children, in the same order).
 bool level_formation(const fastmm_plan_s *p, const Shape &s) {
     const Algo &a = plan_algo(p);
-    if (s.L < 2) return false;
+    if (s.L < 2 || !p->tree.empty()) return false;  // per-level coefficients: uniform plans only
     int64_t all = 1;
     for (int l = 0; l < s.L; ++l) all *= a.R;
     if (leaf_count(a, s.L) != all) return false;
@@ -396,6 +442,7 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
 // round trip through memory wins.
 bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, uint32_t masks[6]) {
     if (p->fuse == FASTMM_FUSE_OFF || s.L < 1 || transA || transB) return false;
+    if (!p->tree.empty()) return false;  // the fused kernel compiles one rule for the innermost level
     if (p->prec != FASTMM_F64 && p->prec != FASTMM_F32) return false;
     if (p->fuse == FASTMM_FUSE_AUTO && p->prec == FASTMM_F64 && s.L < 2) return false;
     return rule_masks_222(plan_algo(p), masks) && node222_supported(masks);
@@ -430,7 +477,7 @@ fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
     }
     HostTables ht;
     std::string err;
-    if (!build_tables(plan_algo(p), L, ht, err)) return fail(FASTMM_EUNSUPPORTED, err);
+    if (!build_plan_tables(p, L, ht, err)) return fail(FASTMM_EUNSUPPORTED, err);
     std::unique_ptr<Tables> t(new Tables());
     t->L = L;
     t->nleaves = (int)ht.leaves.size();
@@ -657,6 +704,34 @@ fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode) {
     plan->fuse = mode;
     for (auto &r : plan->rot)
         if (r) r->fuse = plan->fuse;
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_plan_set_tree(fastmm_plan_t plan, const int *node_algos, int64_t count) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    const Algo &a = plan_algo(plan);
+    std::vector<int> tree;
+    if (count > 0) {
+        if (!node_algos) return fail(FASTMM_EINVAL, "null node rule list");
+        int64_t need = 0, lev = 1;
+        for (int l = 0; l < plan->depth; ++l, lev *= a.R) {
+            need += lev;
+            if (need > 4096) return fail(FASTMM_EINVAL, "recursion tree too large");
+        }
+        if (count != need)
+            return fail(FASTMM_ESHAPE, "the tree needs one rule per internal node: " + std::to_string(need));
+        for (int64_t i = 0; i < count; ++i) {
+            const Algo *x = algo_get(node_algos[i]);
+            if (!x) return fail(FASTMM_EINVAL, "unknown rule id in the tree");
+            if (x->M0 != a.M0 || x->K0 != a.K0 || x->N0 != a.N0 || x->R != a.R)
+                return fail(FASTMM_ESHAPE, "every node rule must have the plan rule's <M0,K0,N0;R>");
+            if (leaf_count(*x, 1) != x->R) return fail(FASTMM_EUNSUPPORTED, "node rules must have every product live");
+        }
+        tree.assign(node_algos, node_algos + count);
+    }
+    std::lock_guard<std::mutex> g(plan->mu);
+    plan->tree = std::move(tree);
+    plan->tables.clear();  // rebuilt for the new tree on next use
     return FASTMM_OK;
 }
 
@@ -1209,6 +1284,7 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
 
 fastmm_status fastmm_backward_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, size_t *bytes) {
     if (check_plan(plan)) return FASTMM_EINVAL;
+    if (!plan->tree.empty()) return fail(FASTMM_EUNSUPPORTED, "backward of a non-uniform plan is not built");
     if (!bytes || m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "bad arguments");
     fastmm_plan_s *ra = nullptr, *rb = nullptr;
     fastmm_status st;
@@ -1225,6 +1301,7 @@ fastmm_status fastmm_gemm_backward(fastmm_plan_t plan, const void *A, const void
                                    void *dB, int64_t m, int64_t k, int64_t n, void *workspace, size_t ws_bytes,
                                    void *stream) {
     if (check_plan(plan)) return FASTMM_EINVAL;
+    if (!plan->tree.empty()) return fail(FASTMM_EUNSUPPORTED, "backward of a non-uniform plan is not built");
     if (m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "negative size");
     if ((dA && (!G || !B)) || (dB && (!G || !A))) return fail(FASTMM_EINVAL, "null input");
     if (m == 0 || k == 0) return FASTMM_OK;
@@ -1274,7 +1351,7 @@ fastmm_status fastmm_task_table(fastmm_plan_t plan, int levels, int64_t counts[5
     if (levels < 0 || levels > 8 || !counts) return fail(FASTMM_EINVAL, "bad arguments");
     HostTables ht;
     std::string err;
-    if (!build_tables(plan_algo(plan), levels, ht, err)) return fail(FASTMM_EUNSUPPORTED, err);
+    if (!build_plan_tables(plan, levels, ht, err)) return fail(FASTMM_EUNSUPPORTED, err);
     counts[0] = (int64_t)ht.leaves.size();
     counts[1] = (int64_t)ht.asrc.size();
     counts[2] = (int64_t)ht.bsrc.size();

@@ -74,6 +74,7 @@ def lib() -> ctypes.CDLL:
         L.fastmm_plan_shape.argtypes = [vp, i64, i64, i64, pi32, pi64, pi64, pi64]
         L.fastmm_workspace_size.argtypes = [vp, i64, i64, i64, ctypes.POINTER(sz)]
         L.fastmm_plan_set_fusion.argtypes = [vp, i32]
+        L.fastmm_plan_set_tree.argtypes = [vp, pi32, i64]
         L.fastmm_plan_path.argtypes = [vp, i64, i64, i64, i32, i32, pi32]
         L.fastmm_gemm.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
         L.fastmm_gemm_ex.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64, i64, i64, i64, vp, sz, vp]
@@ -93,7 +94,7 @@ def lib() -> ctypes.CDLL:
                      "fastmm_plan_destroy", "fastmm_plan_shape", "fastmm_workspace_size", "fastmm_gemm",
                      "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read", "fastmm_task_table",
                      "fastmm_backward_workspace_size", "fastmm_gemm_backward", "fastmm_batched_workspace_size",
-                     "fastmm_gemm_batched", "fastmm_plan_set_fusion", "fastmm_plan_path"):
+                     "fastmm_gemm_batched", "fastmm_plan_set_fusion", "fastmm_plan_path", "fastmm_plan_set_tree"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -161,6 +162,16 @@ class Plan:
         mode = FUSION[fuse] if isinstance(fuse, str) else (FUSION["auto"] if fuse else FUSION["off"])
         if mode != FUSION["auto"]:
             _check(lib().fastmm_plan_set_fusion(self._h, mode))
+
+    def set_tree(self, node_algos) -> "Plan":
+        """Non-uniform recursion: one rule (name or id) per internal node, breadth first
+        (node [l, r_1 .. r_{l-1}] at (R^(l-1) - 1)/(R - 1) + (r_1 .. r_{l-1} in base R)); an
+        empty list restores the plan's rule everywhere."""
+        ids = [_id(ALGOS, a) for a in node_algos]
+        arr = (ctypes.c_int32 * max(len(ids), 1))(*ids)
+        _check(lib().fastmm_plan_set_tree(self._h, arr, len(ids)))
+        self.tree = list(node_algos)
+        return self
 
     def path(self, m: int, k: int, n: int, transA: bool = False, transB: bool = False) -> str:
         """'fused' or 'leaf': the execution path of an m x k by k x n product."""

@@ -10,6 +10,7 @@ import pytest
 
 from oracle import coeffs as C
 from oracle import fastmm_oracle as O
+from synth import make_pair
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "fastmm.h")
@@ -163,3 +164,109 @@ def test_fused_path_matches_rules_by_coefficients(F):
     U, V, W = (_int_rows(M)[:, perm] for M in (a.U, a.V, a.W))
     uid = F.fastmm_algo_register(2, 2, 2, 7, U, V, W, 0)
     assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "leaf"
+
+
+# ----------------------------------------------------------------- non-uniform recursion trees
+from tests.trees import dalberto_tree, f323_tree  # noqa: E402
+
+
+def _eval_tables(tab, A, B, M0, K0, N0, L):
+    """C from a composite task table (eq. (2) unrolled): every leaf's product of its source
+    sums, then every output block the sum of its contributions (exact on small integers)."""
+    m, k = A.shape
+    n = B.shape[1]
+    mb, kb, nb = m // M0 ** L, k // K0 ** L, n // N0 ** L
+    blk = lambda X, r, c, h, w: X[r * h:(r + 1) * h, c * w:(c + 1) * w]
+    Ms = []
+    for a0, ac, b0, bc in tab["leaves"]:
+        S = sum(tab["acoef"][i] * blk(A, *tab["asrc"][i], mb, kb) for i in range(a0, a0 + ac))
+        T = sum(tab["bcoef"][i] * blk(B, *tab["bsrc"][i], kb, nb) for i in range(b0, b0 + bc))
+        Ms.append(S @ T)
+    Cm = np.zeros((m, n))
+    NB = N0 ** L
+    for b, (d0, dc) in enumerate(tab["bdest"]):
+        P_, S_ = divmod(b, NB)
+        acc = sum(tab["dest_coef"][i] * Ms[tab["dest_leaf"][i]] for i in range(d0, d0 + dc))
+        Cm[P_ * mb:(P_ + 1) * mb, S_ * nb:(S_ + 1) * nb] = acc
+    return Cm
+
+
+@pytest.mark.parametrize("tree,base,dims", [("dalberto", "strassen", (2, 2, 2)), ("f323", "f323", (3, 2, 3))])
+def test_tree_task_table_equals_oracle_tree(F, tree, base, dims):
+    ids, rule = (dalberto_tree if tree == "dalberto" else f323_tree)(F)
+    p = F.Plan(base, 2, 1).set_tree(ids)
+    M0, K0, N0 = dims
+    A, B = make_pair("int8", 31, M0 * M0 * 3, K0 * K0 * 2, N0 * N0 * 3)
+    tab = F.fastmm_task_table(p, 2)
+    got = _eval_tables(tab, A, B, M0, K0, N0, 2)
+    want = O.fast_tree(A, B, rule, [dims, dims])
+    assert np.array_equal(got, want)
+    # and the tree really differs from the uniform rule's table
+    uni = F.fastmm_task_table(F.Plan(base, 2, 1), 2)
+    assert not (np.array_equal(uni["bsrc"], tab["bsrc"]) and np.array_equal(uni["dest_leaf"], tab["dest_leaf"])
+                and np.array_equal(uni["bcoef"], tab["bcoef"]) and np.array_equal(uni["dest_coef"], tab["dest_coef"]))
+
+
+def _tree_composites(rule, R, dims):
+    """Per leaf (r1, r2), in odometer order: the sets of composite A sources, B sources and
+    (output block, coefficient) destinations of a two-level tree, from eq. (2) with the rule of
+    each node (A, B blocks column-major, C row-major)."""
+    M0, K0, N0 = dims
+    out = []
+    for r1 in range(R):
+        top, child = rule(()), rule((r1,))
+        for r2 in range(R):
+            def srcs(X1, X2, rows):
+                got = set()
+                for i1, row1 in enumerate(X1):
+                    for i2, row2 in enumerate(X2):
+                        c = row1[r1] * row2[r2]
+                        if c != 0:
+                            p1, q1, p2, q2 = i1 % rows, i1 // rows, i2 % rows, i2 // rows
+                            cols = len(X1) // rows
+                            got.add((p1 * rows + p2, q1 * cols + q2, float(c)))
+                return got
+            dests = set()
+            for k1, row1 in enumerate(top.W):
+                for k2, row2 in enumerate(child.W):
+                    c = row1[r1] * row2[r2]
+                    if c != 0:
+                        P_ = (k1 // N0) * M0 + k2 // N0
+                        S_ = (k1 % N0) * N0 + k2 % N0
+                        dests.add((P_, S_, float(c)))
+            out.append((srcs(top.U, child.U, M0), srcs(top.V, child.V, K0), dests))
+    return out
+
+
+@pytest.mark.parametrize("tree,base,dims", [("dalberto", "strassen", (2, 2, 2)), ("f323", "f323", (3, 2, 3))])
+def test_tree_task_table_structure(F, tree, base, dims):
+    # The right rule at the right node: every leaf's composite sources and destinations.
+    ids, rule = (dalberto_tree if tree == "dalberto" else f323_tree)(F)
+    R = C.get(base).R
+    tab = F.fastmm_task_table(F.Plan(base, 2, 1).set_tree(ids), 2)
+    want = _tree_composites(rule, R, dims)
+    assert len(tab["leaves"]) == len(want)
+    NB = dims[2] ** 2
+    dest_of = {}
+    for b, (d0, dc) in enumerate(tab["bdest"]):
+        for i in range(d0, d0 + dc):
+            dest_of.setdefault(int(tab["dest_leaf"][i]), set()).add((b // NB, b % NB, float(tab["dest_coef"][i])))
+    for leaf, ((a0, ac, b0, bc), (wa, wb, wd)) in enumerate(zip(tab["leaves"], want)):
+        ga = {(int(tab["asrc"][i][0]), int(tab["asrc"][i][1]), float(tab["acoef"][i])) for i in range(a0, a0 + ac)}
+        gb = {(int(tab["bsrc"][i][0]), int(tab["bsrc"][i][1]), float(tab["bcoef"][i])) for i in range(b0, b0 + bc)}
+        assert ga == wa and gb == wb and dest_of.get(leaf, set()) == wd, leaf
+
+
+def test_tree_argument_errors(F):
+    ids, _ = dalberto_tree(F)
+    p = F.Plan("strassen", 2, 1)
+    with pytest.raises(F.FastmmError):
+        p.set_tree(ids[:-1])  # one node short
+    with pytest.raises(F.FastmmError):
+        p.set_tree([F.ALGOS["f323"]] * 8)  # another shape
+    with pytest.raises(F.FastmmError):
+        p.set_tree([10 ** 6] * 8)  # unknown id
+    p.set_tree(ids)
+    assert p.path(128, 128, 128) == "leaf"  # tree plans take the leaf path
+    p.set_tree([])
+    assert F.Plan("strassen", 2, 1, precision="f32").path(128, 128, 128) == "fused"

@@ -1,0 +1,73 @@
+"""GPU tests of non-uniform recursion (section 3.4): the trees of Examples 4.2 and 4.3 on the
+leaf path (FP64, FP32) and the split-precision path, single and batched, against the oracle's
+per-node recursion."""
+import numpy as np
+import pytest
+
+from oracle import fastmm_oracle as O
+from synth import make_pair
+from tests.gpu_util import np_dtype, run_gpu
+from tests.trees import dalberto_tree, f323_tree
+
+pytestmark = pytest.mark.gpu
+
+TREES = {"dalberto": (dalberto_tree, "strassen", (2, 2, 2)), "f323": (f323_tree, "f323", (3, 2, 3))}
+
+
+def _tree_plan(F, tree, precision, cutoff=1):
+    build, base, dims = TREES[tree]
+    ids, rule = build(F)
+    return F.Plan(base, 2, cutoff, precision=precision).set_tree(ids), rule, dims
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16x3"])
+@pytest.mark.parametrize("tree,shape", [("dalberto", (256, 256, 256)), ("dalberto", (130, 70, 190)),
+                                        ("f323", (200, 150, 220))])
+def test_tree_integer_exact(precision, tree, shape):
+    import paper_1507_00687_amd as F
+
+    print(f"\n[tree-int] {tree} {shape} {precision}", flush=True)
+    plan, _, _ = _tree_plan(F, tree, precision)
+    A, B = make_pair("int8", 41, *shape, dtype=np.float64 if precision == "f64" else np.float32)
+    got = run_gpu(plan, A, B)
+    assert np.array_equal(got.astype(np.float64), (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("tree", ["dalberto", "f323"])
+def test_tree_float_against_oracle_tree(precision, tree):
+    import paper_1507_00687_amd as F
+
+    shape = (288, 200, 288)
+    print(f"\n[tree-float] {tree} {shape} {precision}", flush=True)
+    plan, rule, dims = _tree_plan(F, tree, precision)
+    A, B = make_pair("normal", 42, *shape, dtype=np_dtype(precision))
+    got = run_gpu(plan, A, B)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ref = O.reference_rows(A64, B64)
+    err = O.normwise_error(got, ref, A64, B64)
+    err_oracle = O.normwise_error(O.fast_tree(A, B, rule, [dims, dims]), ref, A64, B64)
+    u = 2.0 ** -53 if precision == "f64" else 2.0 ** -24
+    print(f"  error {err:.3e}, oracle's own {err_oracle:.3e}", flush=True)
+    assert err <= 4 * err_oracle + 8 * u
+    assert err <= (1e-13 if precision == "f64" else 5e-5)
+
+
+def test_tree_in_a_batch_and_backward_rejected():
+    import torch
+
+    import paper_1507_00687_amd as F
+
+    tplan, _, _ = _tree_plan(F, "dalberto", "f32")
+    uplan = F.Plan("strassen", 2, 1, precision="f32")
+    shapes = [(256, 128, 192), (100, 300, 60), (64, 64, 64)]
+    plans = [tplan, uplan, tplan]
+    host = [make_pair("int8", 50 + i, *s, dtype=np.float32) for i, s in enumerate(shapes)]
+    As = [torch.from_numpy(a).cuda() for a, _ in host]
+    Bs = [torch.from_numpy(b).cuda() for _, b in host]
+    Cs = F.fastmm_gemm_batched(plans, As, Bs)
+    torch.cuda.synchronize()
+    for (a, b), c in zip(host, Cs):
+        assert np.array_equal(c.cpu().numpy().astype(np.float64), (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
+    with pytest.raises(F.FastmmError):
+        F.fastmm_gemm_backward(tplan, As[0], Bs[0], torch.ones((256, 192), device="cuda"))
