@@ -63,6 +63,13 @@ def parse():
     ap.add_argument("--batch", type=int, default=0,
                     help="time a batch of this many rectangular problems (dims drawn from 512..8192) with "
                          "autotuned plans in one batched launch, instead of the single-product workload")
+    ap.add_argument("--scaling-study", action="store_true",
+                    help="the section 6.5 scaling study on the GPU (FP64 Strassen, L = 1..6, the seven "
+                         "scaling schedules, the three distributions, componentwise error) instead of the "
+                         "throughput workload")
+    ap.add_argument("--study-n", type=int, default=2000)
+    ap.add_argument("--study-pairs", type=int, default=5)
+    ap.add_argument("--study-rows", type=int, default=32, help="sampled rows per product for the error")
     ap.add_argument("--tune-cache", default="", help="JSON cache of the autotuner's choices (batch mode)")
     ap.add_argument("--max-instability", type=float, default=16.0,
                     help="autotuner admission cap on (E/K0^2)^L (batch mode)")
@@ -248,6 +255,65 @@ def batch_main(args):
     print(json.dumps(line), flush=True)
 
 
+def scaling_study(args):
+    """Componentwise error max_ij |c^_ij - c_ij| / |c_ij| (over sampled rows, maximum over the
+    pairs) of Strassen's algorithm in FP64 on the GPU, L = 1..6, for the seven scaling schedules
+    and the three input distributions of section 6.5; the long-double oracle gives c."""
+    import numpy as np
+    import torch
+
+    import paper_1507_00687_amd as F
+    from oracle import fastmm_oracle as O
+    from synth.gen import fig3_pair
+
+    torch.cuda.set_device(0)
+    n = args.study_n
+    schedules = [("none", 2), ("outside", 2), ("inside", 2), ("out_in", 2), ("in_out", 2), ("repeated", 4),
+                 ("repeated", 20)]
+    rows = np.unique(np.linspace(0, n - 1, args.study_rows).astype(np.int64))
+    table = {}
+    t0 = time.perf_counter()
+    gpu_ms = 0.0
+    for dist in (1, 2, 3):
+        pairs = [fig3_pair(1000 + p, n, dist) for p in range(args.study_pairs)]
+        refs = [O.reference_rows(A, B, rows) for A, B in pairs]
+        dev = [(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()) for A, B in pairs]
+        for depth in range(1, 7):
+            for mode, steps in schedules:
+                key = f"{mode}{steps}" if mode == "repeated" else mode
+                plan = F.Plan("strassen", depth, 1, scaling=mode, steps=steps, precision="f64")
+                err = 0.0
+                for (tA, tB), ref in zip(dev, refs):
+                    ta = time.perf_counter()
+                    Cg = F.fastmm_gemm(plan, tA, tB)
+                    torch.cuda.synchronize()
+                    gpu_ms += (time.perf_counter() - ta) * 1e3
+                    got = Cg[torch.from_numpy(rows).cuda()].cpu().numpy()
+                    err = max(err, O.componentwise_error(got, ref))
+                table.setdefault(f"dist{dist}", {}).setdefault(key, []).append(err)
+        print(f"distribution {dist} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    line = {
+        "metric": "componentwise relative error of Strassen (FP64, GPU) under the section 6.5 scaling "
+                  "schedules, max over pairs and sampled rows; index = L - 1",
+        "value": None,
+        "unit": "relative error",
+        "n_gpus": 1,
+        "steps": None,
+        "warmup": None,
+        "ms_per_step": gpu_ms / (3 * 6 * len(schedules) * args.study_pairs),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"scaling study: N={n}, {args.study_pairs} pairs per distribution, "
+                               f"{len(rows)} sampled rows, Strassen L=1..6 (cutoff 1)",
+                   "schedules": [f"{m}{s}" if m == "repeated" else m for m, s in schedules]},
+        "errors": table,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -256,6 +322,9 @@ def main():
         sys.exit(2)
     if args.batch > 0:
         batch_main(args)
+        return
+    if args.scaling_study:
+        scaling_study(args)
         return
     import numpy as np
     import torch
