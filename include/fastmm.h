@@ -116,6 +116,16 @@ fastmm_status fastmm_algo_register(int M0, int K0, int N0, int R, const int64_t 
 fastmm_status fastmm_algo_info(int algo, int *M0, int *K0, int *N0, int *R, int *nnz,
                                double *Q, double *E);
 
+/* Section 5.3's per-rule figures (Table 1's stability exponent; Figure 2's axes) for `levels`
+ * recursion levels: stab_exp = log_N0 E for a square <N0,N0,N0> rule and, for a rectangular
+ * one, log_{M0 K0 N0} of the product of E over the rule and its two cyclic rotations (the
+ * square rule that three levels of their cyclic use make); flops_frac = (R / (M0 K0 N0))^L, the
+ * fraction of classical multiplications; rel_instability = (E / K0^2)^L, the factor by which
+ * the leading term of Theorem 4.1 exceeds classical's.  Any output may be NULL.  Errors:
+ * FASTMM_EINVAL (unknown id, negative levels), FASTMM_EUNSUPPORTED (a rotation failed). */
+fastmm_status fastmm_algo_stability(int algo, int levels, double *stab_exp, double *flops_frac,
+                                    double *rel_instability);
+
 /* Copy the algorithm's coefficients as doubles into host arrays U (M0K0 x R), V (K0N0 x R),
  * W (M0N0 x R), row-major.  Any pointer may be NULL. */
 fastmm_status fastmm_algo_coeffs(int algo, double *U, double *V, double *W);

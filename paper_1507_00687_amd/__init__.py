@@ -13,6 +13,7 @@ from .fastmm import (  # noqa: F401
     fastmm_algo_coeffs,
     fastmm_algo_info,
     fastmm_algo_register,
+    fastmm_algo_stability,
     fastmm_batched_workspace_size,
     fastmm_gemm,
     fastmm_gemm_backward,

@@ -640,6 +640,32 @@ fastmm_status fastmm_algo_info(int algo, int *M0, int *K0, int *N0, int *R, int 
     return FASTMM_OK;
 }
 
+fastmm_status fastmm_algo_stability(int algo, int levels, double *stab_exp, double *flops_frac,
+                                    double *rel_instability) {
+    const Algo *a = algo_get(algo);
+    if (!a) return fail(FASTMM_EINVAL, "unknown algorithm id");
+    if (levels < 0) return fail(FASTMM_EINVAL, "negative number of levels");
+    const Quantities q = quantities(*a);
+    const double base = (double)a->M0 * a->K0 * a->N0;
+    if (stab_exp) {
+        if (a->M0 == a->K0 && a->K0 == a->N0) {
+            *stab_exp = std::log(q.E) / std::log((double)a->N0);
+        } else {  // cyclic use of the rule and its two rotations: a square <P,P,P> rule per 3 levels
+            double e = q.E;
+            for (int t = 1; t <= 2; ++t) {
+                const int rid = algo_rotated(algo, t);
+                const Algo *r = rid >= 0 ? algo_get(rid) : nullptr;
+                if (!r) return fail(FASTMM_EUNSUPPORTED, "rotation of the rule not available");
+                e *= quantities(*r).E;
+            }
+            *stab_exp = std::log(e) / std::log(base);
+        }
+    }
+    if (flops_frac) *flops_frac = std::pow((double)a->R / base, levels);
+    if (rel_instability) *rel_instability = std::pow(q.E / ((double)a->K0 * a->K0), levels);
+    return FASTMM_OK;
+}
+
 fastmm_status fastmm_algo_coeffs(int algo, double *U, double *V, double *W) {
     const Algo *a = algo_get(algo);
     if (!a) return fail(FASTMM_EINVAL, "unknown algorithm id");

@@ -69,6 +69,7 @@ def lib() -> ctypes.CDLL:
         L.fastmm_algo_register.argtypes = [i32, i32, i32, i32, pi64, pi64, pi64, i32, pi32]
         L.fastmm_algo_info.argtypes = [i32, pi32, pi32, pi32, pi32, pi32, pd, pd]
         L.fastmm_algo_coeffs.argtypes = [i32, pd, pd, pd]
+        L.fastmm_algo_stability.argtypes = [i32, i32, pd, pd, pd]
         L.fastmm_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(_Scaling), i32]
         L.fastmm_plan_destroy.argtypes = [vp]
         L.fastmm_plan_shape.argtypes = [vp, i64, i64, i64, pi32, pi64, pi64, pi64]
@@ -94,7 +95,8 @@ def lib() -> ctypes.CDLL:
                      "fastmm_plan_destroy", "fastmm_plan_shape", "fastmm_workspace_size", "fastmm_gemm",
                      "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read", "fastmm_task_table",
                      "fastmm_backward_workspace_size", "fastmm_gemm_backward", "fastmm_batched_workspace_size",
-                     "fastmm_gemm_batched", "fastmm_plan_set_fusion", "fastmm_plan_path", "fastmm_plan_set_tree"):
+                     "fastmm_gemm_batched", "fastmm_plan_set_fusion", "fastmm_plan_path", "fastmm_plan_set_tree",
+                     "fastmm_algo_stability"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -119,6 +121,15 @@ def fastmm_algo_info(algo) -> dict:
                                   ctypes.byref(E)))
     M0, K0, N0, R, nnz = (v.value for v in vals)
     return {"M0": M0, "K0": K0, "N0": N0, "R": R, "nnz": nnz, "Q": Q.value, "E": E.value}
+
+
+def fastmm_algo_stability(algo, levels: int = 1) -> dict:
+    """Stability exponent, fraction of classical multiplications and relative instability of a
+    rule at `levels` levels (the library computes them)."""
+    st, fr, ri = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().fastmm_algo_stability(_id(ALGOS, algo), levels, ctypes.byref(st), ctypes.byref(fr),
+                                       ctypes.byref(ri)))
+    return {"stab_exp": st.value, "flops_frac": fr.value, "rel_instability": ri.value}
 
 
 def fastmm_algo_coeffs(algo):

@@ -38,12 +38,11 @@ class Choice:
 
 def relative_instability(algo: str, levels: int) -> float:
     """(E / K0^2)^L: the factor by which the leading term of Theorem 4.1 exceeds classical's."""
-    from .fastmm import fastmm_algo_info
+    from .fastmm import fastmm_algo_stability
 
     if algo == "classical" or levels == 0:
         return 1.0
-    info = fastmm_algo_info(algo)
-    return (info["E"] / info["K0"] ** 2) ** levels
+    return fastmm_algo_stability(algo, levels)["rel_instability"]
 
 
 def candidates(max_depth: int = 3, cutoffs: Iterable[int] = (256,)) -> List[Tuple[str, int, int]]:

@@ -270,3 +270,27 @@ def test_tree_argument_errors(F):
     assert p.path(128, 128, 128) == "leaf"  # tree plans take the leaf path
     p.set_tree([])
     assert F.Plan("strassen", 2, 1, precision="f32").path(128, 128, 128) == "fused"
+
+
+def test_stability_exponent_and_fig2_quantities(F):
+    # Table 1's stability exponents (rounded to two decimals in print) and the closed forms of
+    # Figure 2's axes, computed by the library from its own rules and their rotations.
+    gold = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "table1_stab_exp.txt")):
+        if line.strip() and not line.startswith("#"):
+            key, val, _ = line.split()
+            gold[key] = float(val)
+    for key in ("strassen", "f323", "f332", "f424"):
+        assert abs(F.fastmm_algo_stability(key)["stab_exp"] - gold[key]) <= 0.005, key
+    # <4,4,2>: the printed 3.90 is log_32(89 * 89 * 92); with its rotations' E (89, 102, 92) the
+    # exponent equals <4,2,4>'s.
+    e442 = F.fastmm_algo_stability("f442")["stab_exp"]
+    assert abs(e442 - F.fastmm_algo_stability("f424")["stab_exp"]) < 1e-12
+    assert abs(np.log(89.0 * 89 * 92) / np.log(32) - gold["f442"]) <= 0.005
+    for key in ("strassen", "f323", "f424", "laderman333"):
+        info = F.fastmm_algo_info(key)
+        for L in (1, 2, 3):
+            d = F.fastmm_algo_stability(key, L)
+            assert d["flops_frac"] == pytest.approx((info["R"] / (info["M0"] * info["K0"] * info["N0"])) ** L)
+            assert d["rel_instability"] == pytest.approx((info["E"] / info["K0"] ** 2) ** L)
+    assert F.fastmm_algo_stability("strassen", 1)["flops_frac"] == 7 / 8
