@@ -185,6 +185,17 @@ fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode);
  * a product that never reaches C). */
 fastmm_status fastmm_plan_set_tree(fastmm_plan_t plan, const int *node_algos, int64_t count);
 
+/* Uniform non-stationary recursion (section 3.3, Theorem 4.2): level l (1-based) of the plan
+ * uses rule level_algos[l-1] at every node; count must equal the plan's depth, and the rules
+ * may have different base shapes <M0,K0,N0;R> (e.g. <3,2,3;15> above <2,2,2;7>; padding is to
+ * multiples of the products of the levels' base sizes).  The cutoff stops the recursion as for
+ * a stationary plan, keeping the first levels.  count = 0 restores the plan's rule at every
+ * level; setting levels clears a tree (fastmm_plan_set_tree) and vice versa.  Such plans take
+ * the leaf path (and the split precisions' two passes); the backward pass rotates every
+ * level's rule.  Must not be called while calls using the plan are in flight.  Errors:
+ * FASTMM_EINVAL (null list, unknown id, a 1x1x1 rule), FASTMM_ESHAPE (count != depth). */
+fastmm_status fastmm_plan_set_levels(fastmm_plan_t plan, const int *level_algos, int count);
+
 /* The path (fastmm_path) fastmm_gemm_ex takes for this shape and these transposition flags. */
 fastmm_status fastmm_plan_path(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, int transA,
                                int transB, int *path);

@@ -114,15 +114,20 @@ const size_t kMaxTableEntries = size_t(1) << 24;
 // r = (r_1..r_L) has A sources prod_l U[i_l, r_l] A_(i_1..i_L), B sources likewise, and
 // contributes prod_l W[k_l, r_l] M_r to output block (k_1..k_L).  Level 1 is the most
 // significant digit of every composite block coordinate.
-// Composite tables of eq. (2) unrolled over L levels.  `nodes` (optional) gives the rule of
-// every internal node of the recursion tree in breadth-first order (section 3.4's non-uniform
-// recursion: node [l, r_1 .. r_{l-1}] is entry (R^(l-1) - 1) / (R - 1) + (r_1 .. r_{l-1} in
-// base R)); all share a's <M0,K0,N0;R>.  Without it, a is used at every node.
-bool build_tables(const Algo &a, int L, HostTables &ht, std::string &err,
-                  const std::vector<const Algo *> *nodes = nullptr) {
-    const int M0 = a.M0, K0 = a.K0, N0 = a.N0, R = a.R;
+// Composite tables of eq. (2) unrolled over L levels.  rule_at(l, node) gives the rule of
+// level l (0-based) at breadth-first node index `node` of that level: every node of a level
+// shares the level's <M0,K0,N0;R> (stationary: one rule; uniform non-stationary, section 3.3:
+// one rule per level; non-uniform, section 3.4: one rule per node, node [l, r_1 .. r_{l-1}]
+// at (r_1 .. r_{l-1} read in the levels' mixed radix)).
+template <typename RuleAt>
+bool build_tables(int L, RuleAt rule_at, HostTables &ht, std::string &err) {
+    std::vector<int> M0(L), K0(L), N0(L), R(L);
     ht.MB = ht.KB = ht.NB = 1;
-    for (int l = 0; l < L; ++l) ht.MB *= M0, ht.KB *= K0, ht.NB *= N0;
+    for (int l = 0; l < L; ++l) {
+        const Algo *x = rule_at(l, 0);
+        M0[l] = x->M0, K0[l] = x->K0, N0[l] = x->N0, R[l] = x->R;
+        ht.MB *= M0[l], ht.KB *= K0[l], ht.NB *= N0[l];
+    }
     struct NZ {
         std::vector<std::vector<std::pair<int, int64_t>>> U, V, W;
         int den_U, den_V, den_W;
@@ -131,34 +136,36 @@ bool build_tables(const Algo &a, int L, HostTables &ht, std::string &err,
     auto nz_of = [&](const Algo *x) -> const NZ & {
         auto it = nzs.find(x);
         if (it == nzs.end())
-            it = nzs.emplace(x, NZ{col_nonzeros(x->U, M0 * K0, R), col_nonzeros(x->V, K0 * N0, R),
-                                   col_nonzeros(x->W, M0 * N0, R), x->den_U, x->den_V, x->den_W}).first;
+            it = nzs.emplace(x, NZ{col_nonzeros(x->U, x->M0 * x->K0, x->R), col_nonzeros(x->V, x->K0 * x->N0, x->R),
+                                   col_nonzeros(x->W, x->M0 * x->N0, x->R), x->den_U, x->den_V, x->den_W})
+                     .first;
         return it->second;
     };
-    std::vector<int64_t> level_off(L + 1, 0);  // breadth-first index of the first node of each level
-    for (int l = 1, cnt = 1; l <= L; ++l, cnt *= R) level_off[l] = level_off[l - 1] + cnt;
-    if (nodes && (int64_t)nodes->size() < level_off[L]) {
-        err = "recursion tree has fewer nodes than the levels used";
-        return false;
-    }
     std::vector<std::vector<DestEntry>> per_block((size_t)ht.MB * ht.NB);
     int64_t nleaves_all = 1;
-    for (int l = 0; l < L; ++l) nleaves_all *= R;
-    if (nleaves_all > (int64_t)1 << 22) {
-        err = "too many leaves";
-        return false;
+    for (int l = 0; l < L; ++l) {
+        nleaves_all *= R[l];
+        if (nleaves_all > (int64_t)1 << 22) {
+            err = "too many leaves";
+            return false;
+        }
     }
     std::vector<int> r(L, 0);
     std::vector<const NZ *> lv(L, nullptr);  // the rule of each level on this leaf's path
     for (int64_t leaf_all = 0; leaf_all < nleaves_all; ++leaf_all) {
         {  // odometer: r[0] most significant
             int64_t x = leaf_all;
-            for (int l = L - 1; l >= 0; --l) r[l] = (int)(x % R), x /= R;
+            for (int l = L - 1; l >= 0; --l) r[l] = (int)(x % R[l]), x /= R[l];
         }
         int64_t prefix = 0;
         for (int l = 0; l < L; ++l) {
-            lv[l] = &nz_of(nodes ? (*nodes)[(size_t)(level_off[l] + prefix)] : &a);
-            prefix = prefix * R + r[l];
+            const Algo *x = rule_at(l, prefix);
+            if (x->M0 != M0[l] || x->K0 != K0[l] || x->N0 != N0[l] || x->R != R[l]) {
+                err = "rules of one level differ in shape";
+                return false;
+            }
+            lv[l] = &nz_of(x);
+            prefix = prefix * R[l] + r[l];
         }
         bool zero = false;
         for (int l = 0; l < L; ++l)
@@ -168,7 +175,7 @@ bool build_tables(const Algo &a, int L, HostTables &ht, std::string &err,
         LeafEntry le{(int32_t)ht.asrc.size(), 0, (int32_t)ht.bsrc.size(), 0};
         // cartesian products over levels of the per-level nonzero lists
         // which: 0 = U (A sources), 1 = V (B sources), 2 = W (C destinations)
-        auto expand = [&](int which, int rowsz, int colsz_base, bool is_c, std::vector<SrcEntry> *out_src) {
+        auto expand = [&](int which, bool is_c, std::vector<SrcEntry> *out_src) {
             auto list = [&](int l) -> const std::vector<std::pair<int, int64_t>> & {
                 return which == 0 ? lv[l]->U[r[l]] : which == 1 ? lv[l]->V[r[l]] : lv[l]->W[r[l]];
             };
@@ -179,14 +186,17 @@ bool build_tables(const Algo &a, int L, HostTables &ht, std::string &err,
                 for (int l = 0; l < L; ++l) {
                     const auto &e = list(l)[idx[l]];
                     const int den = which == 0 ? lv[l]->den_U : which == 1 ? lv[l]->den_V : lv[l]->den_W;
+                    // block grid of this level's operand: rowsz x colsz blocks
+                    const int rowsz = which == 1 ? K0[l] : M0[l];
+                    const int colsz = which == 0 ? K0[l] : N0[l];
                     int p, q;
                     if (is_c) {  // row-major single index over M0 x N0
-                        p = e.first / N0, q = e.first % N0;
-                    } else {  // column-major single index over rowsz x colsz_base
+                        p = e.first / colsz, q = e.first % colsz;
+                    } else {  // column-major single index over rowsz x colsz
                         p = e.first % rowsz, q = e.first / rowsz;
                     }
                     br = br * rowsz + p;
-                    bc = bc * colsz_base + q;
+                    bc = bc * colsz + q;
                     coef *= std::ldexp((double)e.second, -den);
                 }
                 if (is_c) {
@@ -199,9 +209,9 @@ bool build_tables(const Algo &a, int L, HostTables &ht, std::string &err,
                 if (l < 0) break;
             }
         };
-        expand(0, M0, K0, false, &ht.asrc);
-        expand(1, K0, N0, false, &ht.bsrc);
-        expand(2, M0, N0, true, nullptr);
+        expand(0, false, &ht.asrc);
+        expand(1, false, &ht.bsrc);
+        expand(2, true, nullptr);
         le.a_count = (int32_t)(ht.asrc.size() - le.a_begin);
         le.b_count = (int32_t)(ht.bsrc.size() - le.b_begin);
         ht.leaves.push_back(le);
@@ -246,6 +256,9 @@ struct fastmm_plan_s {
     // Non-uniform recursion: the rule id of every internal node, breadth first (empty: `algo`
     // at every node).
     std::vector<int> tree;
+    // Uniform non-stationary recursion: the rule id of every level (empty: `algo` at every
+    // level).  At most one of `tree` and `levels` is set.
+    std::vector<int> levels;
     std::mutex mu;
     std::map<std::pair<int, int>, std::unique_ptr<fastmm::Tables>> tables;  // (L, device)
     // Sub-plans with the rotated rules, made on first use by the backward pass.
@@ -257,34 +270,41 @@ namespace {
 
 const Algo &plan_algo(const fastmm_plan_s *p) { return *algo_get(p->algo); }
 
-// The per-node rules of a non-uniform plan (empty for a uniform one).
-std::vector<const Algo *> plan_nodes(const fastmm_plan_s *p) {
-    std::vector<const Algo *> v;
-    for (int id : p->tree) v.push_back(algo_get(id));
-    return v;
+// The rule of level l (0-based) of a stationary or uniform non-stationary plan.
+const Algo &level_algo(const fastmm_plan_s *p, int l) {
+    return p->levels.empty() ? plan_algo(p) : *algo_get(p->levels[(size_t)l]);
 }
 
 bool build_plan_tables(const fastmm_plan_s *p, int L, HostTables &ht, std::string &err) {
-    if (p->tree.empty()) return build_tables(plan_algo(p), L, ht, err);
-    const std::vector<const Algo *> nodes = plan_nodes(p);
-    return build_tables(plan_algo(p), L, ht, err, &nodes);
+    if (!p->tree.empty()) {
+        const int R = plan_algo(p).R;
+        std::vector<int64_t> off(L + 1, 0);  // breadth-first index of each level's first node
+        for (int l = 1, cnt = 1; l <= L; ++l, cnt *= R) off[l] = off[l - 1] + cnt;
+        if ((int64_t)p->tree.size() < off[L]) {
+            err = "recursion tree has fewer nodes than the levels used";
+            return false;
+        }
+        return build_tables(L, [&](int l, int64_t node) { return algo_get(p->tree[(size_t)(off[l] + node)]); }, ht,
+                            err);
+    }
+    return build_tables(L, [&](int l, int64_t) { return &level_algo(p, l); }, ht, err);
 }
 
 Shape shape_of(const fastmm_plan_s *p, int64_t m, int64_t k, int64_t n) {
-    const Algo &a = plan_algo(p);
     Shape s{0, m, k, n, m, k, n};
-    // Recurse while levels remain and every child dimension ceil(dim / base^l) >= cutoff.
+    // Recurse while levels remain and every child dimension ceil(dim / prod of base sizes so
+    // far) >= cutoff (each level with its own rule's base sizes).
     int64_t pm = 1, pk = 1, pn = 1;
     int L = 0;
-    if (a.M0 * a.K0 * a.N0 > 1) {
-        for (int l = 0; l < p->depth; ++l) {
-            pm *= a.M0, pk *= a.K0, pn *= a.N0;
-            if ((m + pm - 1) / pm < p->cutoff || (k + pk - 1) / pk < p->cutoff || (n + pn - 1) / pn < p->cutoff) {
-                pm /= a.M0, pk /= a.K0, pn /= a.N0;
-                break;
-            }
-            ++L;
+    for (int l = 0; l < p->depth; ++l) {
+        const Algo &a = level_algo(p, l);
+        if (a.M0 * a.K0 * a.N0 <= 1) break;
+        pm *= a.M0, pk *= a.K0, pn *= a.N0;
+        if ((m + pm - 1) / pm < p->cutoff || (k + pk - 1) / pk < p->cutoff || (n + pn - 1) / pn < p->cutoff) {
+            pm /= a.M0, pk /= a.K0, pn /= a.N0;
+            break;
         }
+        ++L;
     }
     s.L = L;
     s.Mp = (m + pm - 1) / pm * pm;
@@ -306,6 +326,15 @@ int leaf_count(const Algo &a, int L) {
     }
     int64_t c = 1;
     for (int l = 0; l < L; ++l) c *= live;
+    return (int)c;
+}
+
+// Leaves of a plan at L levels: the live products of every level multiplied out (tree plans
+// have every product live).
+int plan_leaf_count(const fastmm_plan_s *p, int L) {
+    if (!p->tree.empty()) return leaf_count(plan_algo(p), L);
+    int64_t c = 1;
+    for (int l = 0; l < L; ++l) c *= leaf_count(level_algo(p, l), 1);
     return (int)c;
 }
 
@@ -363,7 +392,7 @@ SplitDims split_dims(int prec, const Shape &s, int bm_force = 0) {
 // composite leaves are exactly the R^L children, in the same order).
 bool level_formation(const fastmm_plan_s *p, const Shape &s) {
     const Algo &a = plan_algo(p);
-    if (s.L < 2 || !p->tree.empty()) return false;  // per-level coefficients: uniform plans only
+    if (s.L < 2 || !p->tree.empty() || !p->levels.empty()) return false;  // one rule at every node only
     int64_t all = 1;
     for (int l = 0; l < s.L; ++l) all *= a.R;
     if (leaf_count(a, s.L) != all) return false;
@@ -421,7 +450,7 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
     }
     if (is_split(p->prec)) {
         const SplitDims d = split_dims(p->prec, s, bm_force);
-        const size_t nleaves = (size_t)leaf_count(plan_algo(p), s.L);
+        const size_t nleaves = (size_t)plan_leaf_count(p, s.L);
         w.sp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.mbp * d.kp);
         w.tp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.nbp * d.kp);
         if (level_formation(p, s)) {
@@ -430,7 +459,7 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
         }
     }
     w.leaves = off;
-    if (s.L > 0) off = align256(off + es * (size_t)leaf_count(plan_algo(p), s.L) * s.mb * s.nb);
+    if (s.L > 0) off = align256(off + es * (size_t)plan_leaf_count(p, s.L) * s.mb * s.nb);
     w.total = off;
     return w;
 }
@@ -442,7 +471,7 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
 // round trip through memory wins.
 bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, uint32_t masks[6]) {
     if (p->fuse == FASTMM_FUSE_OFF || s.L < 1 || transA || transB) return false;
-    if (!p->tree.empty()) return false;  // the fused kernel compiles one rule for the innermost level
+    if (!p->tree.empty() || !p->levels.empty()) return false;  // the fused kernel: one rule, every level
     if (p->prec != FASTMM_F64 && p->prec != FASTMM_F32) return false;
     if (p->fuse == FASTMM_FUSE_AUTO && p->prec == FASTMM_F64 && s.L < 2) return false;
     return rule_masks_222(plan_algo(p), masks) && node222_supported(masks);
@@ -757,7 +786,32 @@ fastmm_status fastmm_plan_set_tree(fastmm_plan_t plan, const int *node_algos, in
     }
     std::lock_guard<std::mutex> g(plan->mu);
     plan->tree = std::move(tree);
+    plan->levels.clear();
     plan->tables.clear();  // rebuilt for the new tree on next use
+    for (auto &r : plan->rot) r.reset();
+    return FASTMM_OK;
+}
+
+fastmm_status fastmm_plan_set_levels(fastmm_plan_t plan, const int *level_algos, int count) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    std::vector<int> lv;
+    if (count > 0) {
+        if (!level_algos) return fail(FASTMM_EINVAL, "null level rule list");
+        if (count != plan->depth) return fail(FASTMM_ESHAPE, "one rule per level of the plan's depth");
+        for (int i = 0; i < count; ++i) {
+            const Algo *x = algo_get(level_algos[i]);
+            if (!x) return fail(FASTMM_EINVAL, "unknown rule id for a level");
+            if (x->M0 * x->K0 * x->N0 <= 1) return fail(FASTMM_EINVAL, "a level rule must split the product");
+        }
+        lv.assign(level_algos, level_algos + count);
+    } else if (count < 0) {
+        return fail(FASTMM_EINVAL, "negative count");
+    }
+    std::lock_guard<std::mutex> g(plan->mu);
+    plan->levels = std::move(lv);
+    plan->tree.clear();
+    plan->tables.clear();
+    for (auto &r : plan->rot) r.reset();
     return FASTMM_OK;
 }
 
@@ -1043,6 +1097,11 @@ fastmm_status rotated_plan(fastmm_plan_s *p, int times, fastmm_plan_s **out) {
         std::unique_ptr<fastmm_plan_s> q(new (std::nothrow) fastmm_plan_s());
         if (!q) return fail(FASTMM_ENOMEM, "plan allocation");
         q->algo = id, q->depth = p->depth, q->cutoff = p->cutoff, q->sc = p->sc, q->prec = p->prec, q->fuse = p->fuse;
+        for (int lid : p->levels) {  // non-stationary: every level's rule rotated alike
+            const int r = algo_rotated(lid, times);
+            if (r < 0) return fail(FASTMM_EUNSUPPORTED, "cannot rotate a level's rule");
+            q->levels.push_back(r);
+        }
         p->rot[times] = std::move(q);
     }
     *out = p->rot[times].get();
@@ -1375,6 +1434,8 @@ fastmm_status fastmm_task_table(fastmm_plan_t plan, int levels, int64_t counts[5
                                 double *dest_coef) {
     if (check_plan(plan)) return FASTMM_EINVAL;
     if (levels < 0 || levels > 8 || !counts) return fail(FASTMM_EINVAL, "bad arguments");
+    if (!plan->levels.empty() && levels > (int)plan->levels.size())
+        return fail(FASTMM_EINVAL, "more levels than the plan's per-level rules");
     HostTables ht;
     std::string err;
     if (!build_plan_tables(plan, levels, ht, err)) return fail(FASTMM_EUNSUPPORTED, err);

@@ -76,6 +76,7 @@ def lib() -> ctypes.CDLL:
         L.fastmm_workspace_size.argtypes = [vp, i64, i64, i64, ctypes.POINTER(sz)]
         L.fastmm_plan_set_fusion.argtypes = [vp, i32]
         L.fastmm_plan_set_tree.argtypes = [vp, pi32, i64]
+        L.fastmm_plan_set_levels.argtypes = [vp, pi32, i32]
         L.fastmm_plan_path.argtypes = [vp, i64, i64, i64, i32, i32, pi32]
         L.fastmm_gemm.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
         L.fastmm_gemm_ex.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64, i64, i64, i64, vp, sz, vp]
@@ -96,7 +97,7 @@ def lib() -> ctypes.CDLL:
                      "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read", "fastmm_task_table",
                      "fastmm_backward_workspace_size", "fastmm_gemm_backward", "fastmm_batched_workspace_size",
                      "fastmm_gemm_batched", "fastmm_plan_set_fusion", "fastmm_plan_path", "fastmm_plan_set_tree",
-                     "fastmm_algo_stability"):
+                     "fastmm_algo_stability", "fastmm_plan_set_levels"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -182,6 +183,15 @@ class Plan:
         arr = (ctypes.c_int32 * max(len(ids), 1))(*ids)
         _check(lib().fastmm_plan_set_tree(self._h, arr, len(ids)))
         self.tree = list(node_algos)
+        return self
+
+    def set_levels(self, level_algos) -> "Plan":
+        """Uniform non-stationary recursion: one rule (name or id) per level, outermost first
+        (as many as the plan's depth); an empty list restores the plan's rule at every level."""
+        ids = [_id(ALGOS, a) for a in level_algos]
+        arr = (ctypes.c_int32 * max(len(ids), 1))(*ids)
+        _check(lib().fastmm_plan_set_levels(self._h, arr, len(ids)))
+        self.levels = list(level_algos)
         return self
 
     def path(self, m: int, k: int, n: int, transA: bool = False, transB: bool = False) -> str:

@@ -294,3 +294,40 @@ def test_stability_exponent_and_fig2_quantities(F):
             assert d["flops_frac"] == pytest.approx((info["R"] / (info["M0"] * info["K0"] * info["N0"])) ** L)
             assert d["rel_instability"] == pytest.approx((info["E"] / info["K0"] ** 2) ** L)
     assert F.fastmm_algo_stability("strassen", 1)["flops_frac"] == 7 / 8
+
+
+# ----------------------------------------------------------- uniform non-stationary recursion
+LEVELS = [(["f323", "strassen"], (37, 29, 41)), (["strassen", "f424"], (100, 60, 90)),
+          (["f332", "f233", "f323"], (60, 50, 70)), (["winograd", "f424", "strassen"], (128, 64, 128))]
+
+
+@pytest.mark.parametrize("levels,shape", LEVELS)
+def test_levels_shape_and_tables_equal_oracle(F, levels, shape):
+    from tests.trees import composites, table_composites
+
+    rules = [C.get(ORACLE_NAME[a]) for a in levels]
+    dims = [(a.M0, a.K0, a.N0) for a in rules]
+    p = F.Plan(levels[0], len(levels), 1).set_levels(levels)
+    L = O.effective_depth(*shape, dims, 1)
+    assert p.shape(*shape) == (L, *O.padded_dims(*shape, dims[:L]))
+    # every leaf's composite sources and destinations, from eq. (2) level by level
+    NB = int(np.prod([d[2] for d in dims]))
+    want = composites(lambda path: rules[len(path)], dims, len(levels))
+    got = table_composites(F.fastmm_task_table(p, len(levels)), NB)
+    assert got == want
+    # and the cutoff keeps the first levels
+    p2 = F.Plan(levels[0], len(levels), 20).set_levels(levels)
+    L2 = O.effective_depth(*shape, dims, 20)
+    assert p2.shape(*shape) == (L2, *O.padded_dims(*shape, dims[:L2]))
+
+
+def test_levels_argument_errors(F):
+    p = F.Plan("strassen", 2, 1)
+    with pytest.raises(F.FastmmError):
+        p.set_levels(["strassen"])  # depth 2 needs two rules
+    with pytest.raises(F.FastmmError):
+        p.set_levels(["strassen", 10 ** 6])
+    p.set_levels(["f323", "strassen"])
+    assert p.path(256, 256, 256) == "leaf"
+    p.set_levels([])
+    assert p.shape(12, 12, 12) == (2, 12, 12, 12)

@@ -47,3 +47,44 @@ def f323_tree(F):
     return ids, rule
 
 
+
+
+def composites(rule_at, dims, L):
+    """Per leaf (r_1 .. r_L) in odometer order (r_1 most significant): the sets of composite A
+    sources, B sources and (output block, coefficient) destinations of eq. (2) unrolled, with
+    rule_at(path) the rule at the node reached by path = (r_1 .. r_{l-1}) and dims[l] its
+    <M0,K0,N0> (A, B blocks column-major, C row-major; blocks indexed level 1 most significant)."""
+    out = []
+
+    def rec(l, path, a_terms, b_terms, c_terms):
+        if l == L:
+            out.append(({(br, bc, float(c)) for br, bc, c in a_terms}, {(br, bc, float(c)) for br, bc, c in b_terms},
+                        {(br, bc, float(c)) for br, bc, c in c_terms}))
+            return
+        alg = rule_at(path)
+        M0, K0, N0 = dims[l]
+        for r in range(alg.R):
+            na = [(br * M0 + i % M0, bc * K0 + i // M0, c * alg.U[i][r]) for br, bc, c in a_terms
+                  for i in range(M0 * K0) if alg.U[i][r] != 0]
+            nb = [(br * K0 + j % K0, bc * N0 + j // K0, c * alg.V[j][r]) for br, bc, c in b_terms
+                  for j in range(K0 * N0) if alg.V[j][r] != 0]
+            nc = [(br * M0 + k // N0, bc * N0 + k % N0, c * alg.W[k][r]) for br, bc, c in c_terms
+                  for k in range(M0 * N0) if alg.W[k][r] != 0]
+            rec(l + 1, path + (r,), na, nb, nc)
+
+    rec(0, (), [(0, 0, 1)], [(0, 0, 1)], [(0, 0, 1)])
+    return out
+
+
+def table_composites(tab, NB):
+    """The same sets read back from a library task table (NB: output block columns)."""
+    dest_of = {}
+    for b, (d0, dc) in enumerate(tab["bdest"]):
+        for i in range(d0, d0 + dc):
+            dest_of.setdefault(int(tab["dest_leaf"][i]), set()).add((b // NB, b % NB, float(tab["dest_coef"][i])))
+    out = []
+    for leaf, (a0, ac, b0, bc) in enumerate(tab["leaves"]):
+        ga = {(int(tab["asrc"][i][0]), int(tab["asrc"][i][1]), float(tab["acoef"][i])) for i in range(a0, a0 + ac)}
+        gb = {(int(tab["bsrc"][i][0]), int(tab["bsrc"][i][1]), float(tab["bcoef"][i])) for i in range(b0, b0 + bc)}
+        out.append((ga, gb, dest_of.get(leaf, set())))
+    return out
