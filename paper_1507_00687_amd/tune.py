@@ -28,12 +28,16 @@ class Choice:
     depth: int
     cutoff: int
     ms: float
-    instability: float  # (E / K0^2)^L of the levels actually used (1 for classical)
+    instability: float  # product over the levels used of E / K0^2 (1 for classical)
+    levels: Optional[List[str]] = None  # a rule per level (uniform non-stationary), else None
 
     def plan(self, precision: str, **kw):
         from .fastmm import Plan
 
-        return Plan(self.algo, self.depth, self.cutoff, precision=precision, **kw)
+        p = Plan(self.algo, self.depth, self.cutoff, precision=precision, **kw)
+        if self.levels:
+            p.set_levels(self.levels)
+        return p
 
 
 def relative_instability(algo: str, levels: int) -> float:
@@ -45,12 +49,21 @@ def relative_instability(algo: str, levels: int) -> float:
     return fastmm_algo_stability(algo, levels)["rel_instability"]
 
 
-def candidates(max_depth: int = 3, cutoffs: Iterable[int] = (256,)) -> List[Tuple[str, int, int]]:
-    out = [("classical", 0, 1)]
+def candidates(max_depth: int = 3, cutoffs: Iterable[int] = (256,), non_stationary: bool = False):
+    """(rule, depth, cutoff, levels) tuples: classical, every rule stationary at depths
+    1..max_depth and, with non_stationary, every ordered pair of distinct rules as two levels
+    (section 3.3; shapes far from square are where mixed base cases pay)."""
+    out = [("classical", 0, 1, None)]
     for a in RULES:
         for d in range(1, max_depth + 1):
             for c in cutoffs:
-                out.append((a, d, c))
+                out.append((a, d, c, None))
+    if non_stationary and max_depth >= 2:
+        for a in RULES:
+            for b in RULES:
+                if a != b:
+                    for c in cutoffs:
+                        out.append((a, 2, c, [a, b]))
     return out
 
 
@@ -105,7 +118,8 @@ def _key(m, k, n, precision, in_batch=True):
 
 
 def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 3, cutoffs=(256,),
-               max_instability: float = float("inf"), reps: int = 3, A=None, B=None, in_batch: bool = True) -> Choice:
+               max_instability: float = float("inf"), reps: int = 3, A=None, B=None, in_batch: bool = True,
+               non_stationary: bool = False) -> Choice:
     """Measure every admitted candidate on (m, k, n) and return the fastest (timed inside a
     batch of copies when in_batch, else alone)."""
     import torch
@@ -122,13 +136,18 @@ def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 
     Cs = [torch.empty((m, n), dtype=dt, device="cuda") for _ in range(batch_copies(m, n))] if in_batch else None
     best: Optional[Choice] = None
     seen = set()
-    for algo, depth, cutoff in candidates(max_depth, cutoffs):
+    for algo, depth, cutoff, lv in candidates(max_depth, cutoffs, non_stationary):
         plan = Plan(algo, depth, cutoff, precision=precision)
+        if lv:
+            plan.set_levels(lv)
         levels = plan.shape(m, k, n)[0]
-        if (algo, levels) in seen or (levels == 0 and algo != "classical"):
+        key = (tuple(lv[:levels]) if lv else (algo,) * levels)
+        if key in seen or (levels == 0 and algo != "classical"):
             continue  # same computation as a candidate already measured
-        seen.add((algo, levels))
-        inst = relative_instability(algo, levels)
+        seen.add(key)
+        inst = 1.0
+        for r in key:
+            inst *= relative_instability(r, 1)
         if inst > max_instability:
             continue
         if in_batch:
@@ -137,7 +156,7 @@ def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 
             ws = torch.empty(max(plan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
             ms = _time_plan(plan, A, B, C, ws, reps)
         if best is None or ms < best.ms:
-            best = Choice(algo, depth if levels else 0, cutoff, ms, inst)
+            best = Choice(algo, depth if levels else 0, cutoff, ms, inst, list(lv[:levels]) if (lv and levels) else None)
     assert best is not None
     return best
 

@@ -145,3 +145,21 @@ def test_autotune_picks_a_valid_plan_and_caches(tmp_path):
     # a stability cap of 1 admits only the classical kernel
     capped = tune.tune([(256, 256, 256)], precision="f32", max_instability=1.0, max_depth=1, reps=1)
     assert capped[(256, 256, 256)].algo == "classical"
+
+
+def test_autotune_with_per_level_rules():
+    # Non-stationary candidates (a rule per level) join the search; the winner runs correctly.
+    import torch
+
+    import paper_1507_00687_amd as F
+    from paper_1507_00687_amd import tune
+
+    shape = (512, 256, 1024)
+    res = tune.tune([shape], precision="f32", max_depth=2, reps=1, non_stationary=True)
+    ch = res[shape]
+    plan = ch.plan("f32")
+    A, B = make_pair("int8", 90, *shape, dtype=np.float32)
+    C = F.fastmm_gemm(plan, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()).cpu().numpy()
+    assert np.array_equal(C.astype(np.float64), (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64))
+    assert ch.levels is None or len(ch.levels) == ch.depth
+    print(f"\n  chose {ch}", flush=True)
