@@ -2,6 +2,8 @@
 // GEMM (S/T formation folded into the tile loads, MFMA leaf product) and the W-combination.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdint>
 
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(CombineArgs<T> p) {
     if (y >= p.nb) return;
     const int64_t nP = (p.m + p.mb - 1) / p.mb, nS = (p.n + p.nb - 1) / p.nb;
     for (int64_t x = blockIdx.y; x < p.mb; x += gridDim.y) {
-        for (int64_t P = 0; P < nP; ++P) {
+        for (int64_t P = blockIdx.z; P < nP; P += gridDim.z) {  // block rows spread over z when positions are few
             const int64_t row = P * p.mb + x;
             if (row >= p.m) break;
             for (int64_t S = 0; S < nS; ++S) {
@@ -486,7 +488,12 @@ hipError_t combine_go(const CombineLaunch &L, hipStream_t s) {
     if (L.mb <= 0 || L.nb <= 0) return hipErrorInvalidValue;
     const int per = vec ? VEC : 1;
     const int64_t cols = (L.nb + per - 1) / per;  // threads span one leaf block; each visits every block
-    dim3 grid((unsigned)((cols + kThreads - 1) / kThreads), (unsigned)(L.mb < 65535 ? L.mb : 65535));
+    // with few positions (small leaf blocks, many output blocks) the output block rows are
+    // spread over gridDim.z, for about 4M threads in flight
+    const int64_t nP = (L.m + L.mb - 1) / L.mb, threads = cols * L.mb;
+    const int64_t z = std::max<int64_t>(1, std::min<int64_t>(nP, ((int64_t)1 << 22) / std::max<int64_t>(threads, 1)));
+    dim3 grid((unsigned)((cols + kThreads - 1) / kThreads), (unsigned)(L.mb < 65535 ? L.mb : 65535),
+              (unsigned)std::min<int64_t>(z, 65535));
     const bool sc = L.sc.ea != nullptr;
     if (vec) {
         if (sc) hipLaunchKernelGGL((combine_kernel<T, true, VEC>), grid, dim3(kThreads), 0, s, a);
