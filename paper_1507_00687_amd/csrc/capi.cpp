@@ -290,6 +290,8 @@ bool build_plan_tables(const fastmm_plan_s *p, int L, HostTables &ht, std::strin
     return build_tables(L, [&](int l, int64_t) { return &level_algo(p, l); }, ht, err);
 }
 
+constexpr int64_t kBlockAlign = 8;
+
 Shape shape_of(const fastmm_plan_s *p, int64_t m, int64_t k, int64_t n) {
     Shape s{0, m, k, n, m, k, n};
     // Recurse while levels remain and every child dimension ceil(dim / prod of base sizes so
@@ -307,10 +309,15 @@ Shape shape_of(const fastmm_plan_s *p, int64_t m, int64_t k, int64_t n) {
         ++L;
     }
     s.L = L;
-    s.Mp = (m + pm - 1) / pm * pm;
-    s.Kp = (k + pk - 1) / pk * pk;
-    s.Np = (n + pn - 1) / pn * pn;
-    s.mb = s.Mp / pm, s.kb = s.Kp / pk, s.nb = s.Np / pn;
+    // Leaf blocks are rounded up to a multiple of kBlockAlign elements when there is a level, so
+    // every block starts 16-byte aligned (vector loads in every precision); the extra zero
+    // padding is at most kBlockAlign - 1 rows / columns per block.
+    auto block = [&](int64_t dim, int64_t prod) {
+        const int64_t b = (dim + prod - 1) / prod;
+        return L > 0 ? (b + kBlockAlign - 1) / kBlockAlign * kBlockAlign : b;
+    };
+    s.mb = block(m, pm), s.kb = block(k, pk), s.nb = block(n, pn);
+    s.Mp = s.mb * pm, s.Kp = s.kb * pk, s.Np = s.nb * pn;
     return s;
 }
 

@@ -68,9 +68,24 @@ def test_library_tables_equal_oracle_tables(F, name):
 def test_plan_shape_matches_oracle_rules(F, name, depth, cutoff, shape):
     p = F.Plan(name, depth, cutoff)
     a = C.get(ORACLE_NAME[name])
-    L = O.effective_depth(*shape, [(a.M0, a.K0, a.N0)] * depth, cutoff)
-    pads = O.padded_dims(*shape, [(a.M0, a.K0, a.N0)] * L)
-    assert p.shape(*shape) == (L, *pads)
+    dims = [(a.M0, a.K0, a.N0)] * depth
+    L = O.effective_depth(*shape, dims, cutoff)
+    assert p.shape(*shape) == (L, *aligned_pads(shape, dims[:L]))
+
+
+def aligned_pads(shape, dims):
+    """The planner's padding: the oracle's (minimal) leaf block, rounded up to a multiple of 8
+    elements when there is a level, times the product of the base sizes."""
+    minimal = O.padded_dims(*shape, dims)
+    if not dims:
+        return minimal
+    out = []
+    for i, d in enumerate(shape):
+        prod = int(np.prod([x[i] for x in dims]))
+        b = -(-d // prod)
+        out.append(-(-b // 8) * 8 * prod)
+    assert all(o >= mn for o, mn in zip(out, minimal))
+    return tuple(out)
 
 
 def test_register_rejects_non_brent(F):
@@ -309,7 +324,7 @@ def test_levels_shape_and_tables_equal_oracle(F, levels, shape):
     dims = [(a.M0, a.K0, a.N0) for a in rules]
     p = F.Plan(levels[0], len(levels), 1).set_levels(levels)
     L = O.effective_depth(*shape, dims, 1)
-    assert p.shape(*shape) == (L, *O.padded_dims(*shape, dims[:L]))
+    assert p.shape(*shape) == (L, *aligned_pads(shape, dims[:L]))
     # every leaf's composite sources and destinations, from eq. (2) level by level
     NB = int(np.prod([d[2] for d in dims]))
     want = composites(lambda path: rules[len(path)], dims, len(levels))
@@ -318,7 +333,7 @@ def test_levels_shape_and_tables_equal_oracle(F, levels, shape):
     # and the cutoff keeps the first levels
     p2 = F.Plan(levels[0], len(levels), 20).set_levels(levels)
     L2 = O.effective_depth(*shape, dims, 20)
-    assert p2.shape(*shape) == (L2, *O.padded_dims(*shape, dims[:L2]))
+    assert p2.shape(*shape) == (L2, *aligned_pads(shape, dims[:L2]))
 
 
 def test_levels_argument_errors(F):
@@ -330,4 +345,4 @@ def test_levels_argument_errors(F):
     p.set_levels(["f323", "strassen"])
     assert p.path(256, 256, 256) == "leaf"
     p.set_levels([])
-    assert p.shape(12, 12, 12) == (2, 12, 12, 12)
+    assert p.shape(32, 32, 32) == (2, 32, 32, 32)
