@@ -8,6 +8,8 @@ the two share no code.
 Parity pins (tests/test_oracle_*.py) tie it to the paper: Brent equations in exact
 arithmetic, Table 1 quantities, the stability vectors of Examples 4.2 and 4.3, exact
 agreement with integer matrix products, the worked scaling examples 6.1-6.5, the closed
-form of Lemma D.5 and the invariants of Lemma D.1.  Parity unpinned: the per-level (node)
-scaling reading and the distributions of the scaling study (their figure data is absent).
+form of Lemma D.5 and the invariants of Lemma D.1.  Scaling at every level (a reading; the
+paper prints no values for it) is pinned by exact integer products, its reduction to one
+scaling at depth 1 and the per-node properties of the scaled operands.  Parity unpinned: the
+distributions of the scaling study (their figure data is absent).
 """

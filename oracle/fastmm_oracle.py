@@ -15,7 +15,9 @@ What it computes, each piece following the paper:
   * fast_tree(...)          -- uniform and non-uniform non-stationary recursion
                                (sections 3.3, 3.4): one rule per level or per tree node.
   * outside/inside/repeated scaling -- Algorithms 1, 2, 3 (section 6), with the stopping
-                               test of Theorem 6.5 and an exact power-of-two variant.
+                               test of Theorem 6.5 and an exact power-of-two variant;
+                               applied once (scaled_fast) or at every inner node of the
+                               recursion (scaled_fast_every_level, a reading).
   * bounds                  -- Theorems 4.1 and 4.2 and the non-uniform quantities of
                                section 4.5; normwise and componentwise error measures.
 
@@ -347,6 +349,47 @@ def scaled_fast(A, B, alg: Bilinear, depth: int, cutoff: int = 1, mode: str = "n
     sc = scale(A, B, schedule_for(mode, steps), tau, pow2)
     Cp = fast(sc.A, sc.B, alg, depth, cutoff, leaf)
     return (sc.r.astype(Cp.dtype)[:, None] * Cp) * sc.s.astype(Cp.dtype)[None, :]
+
+
+def scaled_fast_every_level(A, B, rules: Sequence[Bilinear], cutoff: int = 1, mode: str = "none",
+                            steps: int = 2, tau: Optional[float] = None, pow2: bool = True,
+                            leaf: Optional[Callable] = None, trace: Optional[list] = None) -> np.ndarray:
+    """Diagonal scaling applied at every level (a reading: the paper scales once, before the
+    multiplication).  `rules` holds one rule per level (the same rule repeated for a
+    stationary algorithm); the cutoff may stop the recursion earlier.  Every node of the
+    recursion with at least one level below it runs the scaling steps (Algorithms 1-3) on its
+    own operands, splits the scaled operands by one level of eq. (2) -- its children are
+    handled the same way -- and multiplies its W-combined product by D_A on the left and D_B
+    on the right.  Leaves are not scaled: power-of-two factors commute exactly with the
+    classical product.  `trace`, when given, receives (level, ScalingResult) for every
+    scaled node, in the order the recursion visits them."""
+    leaf = leaf or classical
+    m, k = A.shape
+    n = B.shape[1]
+    dims = [(a.M0, a.K0, a.N0) for a in rules]
+    L = effective_depth(m, k, n, dims, cutoff)
+    schedule = schedule_for(mode, steps)
+
+    def node(X, Y, level):
+        if level == L:
+            return leaf(X, Y)
+        sc = scale(X, Y, schedule, tau, pow2)
+        if trace is not None:
+            trace.append((level, sc))
+        alg = rules[level]
+        Cp = _rec(sc.A, sc.B, lambda path: alg, 1, (), lambda S, T: node(S, T, level + 1))
+        return (sc.r.astype(Cp.dtype)[:, None] * Cp) * sc.s.astype(Cp.dtype)[None, :]
+
+    if L == 0:  # the root is the only node: one scaling around the classical product
+        sc = scale(A, B, schedule, tau, pow2)
+        Cp = leaf(sc.A, sc.B)
+        return (sc.r.astype(Cp.dtype)[:, None] * Cp) * sc.s.astype(Cp.dtype)[None, :]
+    Mp, Kp, Np = padded_dims(m, k, n, dims[:L])
+    Ap = np.zeros((Mp, Kp), dtype=A.dtype)
+    Ap[:m, :k] = A
+    Bp = np.zeros((Kp, Np), dtype=B.dtype)
+    Bp[:k, :n] = B
+    return np.ascontiguousarray(node(Ap, Bp, 0)[:m, :n])
 
 
 # --------------------------------------------------------------------------------- bounds

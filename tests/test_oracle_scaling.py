@@ -205,3 +205,87 @@ def test_scaling_improves_componentwise_error_on_example_6_1_pattern():
     e_none = O.componentwise_error(O.fast(A, B, C.strassen(), 3), ref)
     e_out = O.componentwise_error(O.scaled_fast(A, B, C.strassen(), 3, mode="outside"), ref)
     assert e_out < 1e-13 < e_none
+
+
+# ---- scaling at every level (a reading: the paper scales once; here every inner node of the
+# recursion runs the same steps on its own operands and unscales its product)
+
+def _dyadic_pair(seed, m, k, n, span=6):
+    """Small integers times powers of two (2^-6 .. 2^6) per row of A and per column of B: the
+    scaled operands, every product and every partial sum the method forms stay exact dyadic
+    numbers within FP64's 53 bits, so C is exact.  (With 2^+-12, inside factors that differ
+    between the added blocks widen the sums beyond 53 bits and they round.)"""
+    from synth import make_pair
+
+    A, B = make_pair("int8", seed, m, k, n)
+    rng = np.random.default_rng(seed)
+    A = A * np.ldexp(1.0, rng.integers(-span, span + 1, m))[:, None]
+    B = B * np.ldexp(1.0, rng.integers(-span, span + 1, n))[None, :]
+    return A, B
+
+
+def _exact(A, B):
+    from fractions import Fraction
+
+    # exact product through integer mantissas: A = a 2^-e, B = b 2^-f with a, b integers
+    ea, eb = 40, 40
+    a = np.rint(np.ldexp(A, ea)).astype(object)
+    b = np.rint(np.ldexp(B, eb)).astype(object)
+    assert np.array_equal(np.ldexp(a.astype(np.float64), -ea), A)
+    c = a.dot(b)
+    return np.vectorize(lambda x: float(Fraction(int(x), 2 ** (ea + eb))))(c)
+
+
+@pytest.mark.parametrize("mode,steps", [("outside", 2), ("inside", 2), ("out_in", 2), ("repeated", 4)])
+@pytest.mark.parametrize("rules,shape", [((C.strassen(),) * 2, (24, 20, 28)), ((C.strassen(),) * 3, (32, 16, 40)),
+                                         ((C.f323(), C.strassen()), (30, 14, 27))])
+def test_every_level_scaling_is_exact_on_dyadic_inputs(mode, steps, rules, shape):
+    A, B = _dyadic_pair(5, *shape)
+    got = O.scaled_fast_every_level(A, B, list(rules), 1, mode, steps)
+    assert np.array_equal(got, _exact(A, B))
+
+
+@pytest.mark.parametrize("mode,steps", [("outside", 2), ("out_in", 2), ("in_out", 2), ("repeated", 20)])
+def test_every_level_scaling_at_depth_one_is_scaling_once(mode, steps):
+    A, B = badly_scaled(7, 22, 18, 26)
+    once = O.scaled_fast(A, B, C.strassen(), 1, 1, mode, steps)
+    every = O.scaled_fast_every_level(A, B, [C.strassen()], 1, mode, steps)
+    assert np.array_equal(once, every)
+
+
+@pytest.mark.parametrize("sched_mode", ["outside", "out_in", "repeated"])
+def test_every_inner_node_is_scaled(sched_mode):
+    # depth 3 Strassen: 1 + 7 + 49 inner nodes, visited depth first; after the node's last O
+    # step its operands have row (A) and column (B) maxima in (1/2, 1] (zero lines excepted);
+    # after a last I step every column of the node's A' has the maximum of the matching row
+    # of B' to within a factor 2 (power-of-two factors, Lemma D.5)
+    A, B = badly_scaled(9, 40, 48, 56)
+    trace = []
+    O.scaled_fast_every_level(A, B, [C.strassen()] * 3, 1, sched_mode, 3, trace=trace)
+    assert [lv for lv, _ in trace].count(0) == 1
+    assert [lv for lv, _ in trace].count(1) == 7
+    assert [lv for lv, _ in trace].count(2) == 49
+    assert [lv for lv, _ in trace][:3] == [0, 1, 2]
+    for lv, sc in trace:
+        assert sc.A.shape == (40 // 2 ** lv, 48 // 2 ** lv) and sc.B.shape == (48 // 2 ** lv, 56 // 2 ** lv)
+        if sc.steps[-1] == "O":
+            for mx in (np.max(np.abs(sc.A), axis=1), np.max(np.abs(sc.B), axis=0)):
+                nz = mx[mx > 0]
+                assert np.all((nz > 0.5) & (nz <= 1.0))
+        else:
+            ca, rb = np.max(np.abs(sc.A), axis=0), np.max(np.abs(sc.B), axis=1)
+            ok = (ca > 0) & (rb > 0)
+            ratio = ca[ok] / rb[ok]
+            assert np.all((ratio >= 0.5) & (ratio <= 2.0))
+
+
+def test_every_level_scaling_with_cutoff_and_no_levels():
+    A, B = badly_scaled(11, 20, 12, 18)
+    # cutoff 8 stops Strassen after one level on k = 12 (12/2 = 6 < 8 at the first level)
+    assert O.effective_depth(20, 12, 18, [(2, 2, 2)] * 3, 8) == 0
+    got = O.scaled_fast_every_level(A, B, [C.strassen()] * 3, 8, "out_in")
+    sc = O.scale(A, B, "OI")
+    want = (sc.r[:, None] * O.classical(sc.A, sc.B)) * sc.s[None, :]
+    assert np.array_equal(got, want)
+    ref = O.reference_rows(A, B)
+    assert O.componentwise_error(got, ref) < 1e-13
