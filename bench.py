@@ -50,6 +50,8 @@ def parse():
                     help="also time the same plan in this precision (reported beside the headline; none = skip)")
     ap.add_argument("--scaling", default="none")
     ap.add_argument("--scaling-steps", type=int, default=2)
+    ap.add_argument("--per-level", action="store_true",
+                    help="run the scaling steps at every inner node of the recursion, not only once")
     ap.add_argument("--dist", default="normal")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--err-rows", type=int, default=16)
@@ -258,7 +260,8 @@ def batch_main(args):
 def scaling_study(args):
     """Componentwise error max_ij |c^_ij - c_ij| / |c_ij| (over sampled rows, maximum over the
     pairs) of Strassen's algorithm in FP64 on the GPU, L = 1..6, for the seven scaling schedules
-    and the three input distributions of section 6.5; the long-double oracle gives c."""
+    and the three input distributions of section 6.5 (with --per-level, also each schedule run at
+    every inner node of the recursion); the long-double oracle gives c."""
     import numpy as np
     import torch
 
@@ -268,8 +271,10 @@ def scaling_study(args):
 
     torch.cuda.set_device(0)
     n = args.study_n
-    schedules = [("none", 2), ("outside", 2), ("inside", 2), ("out_in", 2), ("in_out", 2), ("repeated", 4),
-                 ("repeated", 20)]
+    schedules = [(m, s, False) for m, s in [("none", 2), ("outside", 2), ("inside", 2), ("out_in", 2),
+                                              ("in_out", 2), ("repeated", 4), ("repeated", 20)]]
+    if args.per_level:  # the same schedules run at every inner node as well
+        schedules += [(m, s, True) for m, s, _ in schedules if m != "none"]
     rows = np.unique(np.linspace(0, n - 1, args.study_rows).astype(np.int64))
     table = {}
     t0 = time.perf_counter()
@@ -279,9 +284,9 @@ def scaling_study(args):
         refs = [O.reference_rows(A, B, rows) for A, B in pairs]
         dev = [(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()) for A, B in pairs]
         for depth in range(1, 7):
-            for mode, steps in schedules:
-                key = f"{mode}{steps}" if mode == "repeated" else mode
-                plan = F.Plan("strassen", depth, 1, scaling=mode, steps=steps, precision="f64")
+            for mode, steps, every in schedules:
+                key = (f"{mode}{steps}" if mode == "repeated" else mode) + ("_every_level" if every else "")
+                plan = F.Plan("strassen", depth, 1, scaling=mode, steps=steps, precision="f64", per_level=every)
                 err = 0.0
                 for (tA, tB), ref in zip(dev, refs):
                     ta = time.perf_counter()
@@ -308,7 +313,8 @@ def scaling_study(args):
         "data": "synthetic",
         "config": {"workload": f"scaling study: N={n}, {args.study_pairs} pairs per distribution, "
                                f"{len(rows)} sampled rows, Strassen L=1..6 (cutoff 1)",
-                   "schedules": [f"{m}{s}" if m == "repeated" else m for m, s in schedules]},
+                   "schedules": [(f"{m}{s}" if m == "repeated" else m) + ("_every_level" if e else "")
+                                 for m, s, e in schedules]},
         "errors": table,
     }
     print(json.dumps(line), flush=True)
@@ -340,7 +346,7 @@ def main():
     tA = torch.from_numpy(A).cuda()
     tB = torch.from_numpy(B).cuda()
     plan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
-                  precision=args.precision, fuse=args.fuse)
+                  precision=args.precision, fuse=args.fuse, per_level=args.per_level)
     L, Mp, Kp, Np = plan.shape(m, k, n)
     path = plan.path(m, k, n)
     kname, ksource = product_kernel(args.precision, path)
@@ -362,7 +368,7 @@ def main():
         bdt = torch.float64 if args.beside == "f64" else torch.float32
         bA, bB = (tA, tB) if bdt == tA.dtype else (tA.to(bdt), tB.to(bdt))
         bplan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
-                       precision=args.beside, fuse=args.fuse)
+                       precision=args.beside, fuse=args.fuse, per_level=args.per_level)
         bws = torch.empty(max(bplan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
         Cb = torch.empty((m, n), dtype=bdt, device="cuda")
         ms_b = time_steps(lambda: F.fastmm_gemm(bplan, bA, bB, C=Cb, workspace=bws), args.steps, args.warmup)
@@ -386,10 +392,13 @@ def main():
     nleaves = info["R"] ** L if args.algo != "classical" else 1
     mb, kb, nb = Mp // info["M0"] ** L, Kp // info["K0"] ** L, Np // info["N0"] ** L
     flops_per_launch = 2.0 * mb * kb * nb * nleaves * PRODUCTS[args.precision]
+    # one recorded call per step, or (scaling at every level) one per node product of the
+    # first level, each with its own products launch
+    flops_per_launch *= args.steps / calls
     achieved = flops_per_launch / (leaf_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     workload = (f"{args.algo} L={args.depth} cutoff={args.cutoff} n={n} {args.precision} {args.dist} "
-                f"scaling={args.scaling} path={path}")
+                f"scaling={args.scaling}{' per-level' if args.per_level else ''} path={path}")
 
     torch_ref = None
     if args.torch_ref:

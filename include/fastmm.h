@@ -97,6 +97,17 @@ typedef struct {
     double tau; /* > 0: stop early by the test of Theorem 6.5, applied to every step after
                    the first O step on the unrounded factors; evaluated on the device (the
                    remaining steps become no-ops), no host synchronisation; 0: run all steps */
+    int per_level; /* 0: the steps run once, on A and B (section 6).  1: also on the operands
+                   S_r, T_r of every inner node of the recursion (a reading of scaling "at
+                   every level"; the paper scales once): the node scales its operands,
+                   multiplies them by one level of eq. (2) whose children do the same, and
+                   unscales its product.  Nodes on the last level are not scaled (power-of-two
+                   factors commute exactly with the classical product), so plans of depth
+                   <= 1 behave as with 0.  From depth 2 the first level's node operands and
+                   products are written to the workspace (fastmm_workspace_size accounts for
+                   them and for the nested products).  Stationary and uniform non-stationary
+                   plans; not with fastmm_plan_set_tree or fastmm_gemm_batched
+                   (FASTMM_EUNSUPPORTED). */
 } fastmm_scaling;
 
 typedef struct fastmm_plan_s *fastmm_plan_t;
@@ -149,9 +160,12 @@ fastmm_status fastmm_plan_shape(fastmm_plan_t plan, int64_t m, int64_t k, int64_
 typedef enum {
     FASTMM_PATH_LEAF = 0,  /* one launch over all leaf products M_r = S_r T_r (S and T formed
                               while loading, eq. (2)), then one W-combination launch */
-    FASTMM_PATH_FUSED = 1  /* the innermost level fused: each work-group forms S_r, T_r, the R
+    FASTMM_PATH_FUSED = 1, /* the innermost level fused: each work-group forms S_r, T_r, the R
                               products and the W-sums of eq. (1) for one tile of a node of the
                               recursion; the outer L-1 levels as in the leaf path */
+    FASTMM_PATH_EVERY_LEVEL = 2 /* scaling at every level (fastmm_scaling.per_level, depth >= 2):
+                              the first level's node operands written out, each node product
+                              by a call of the remaining levels, then the W-combination */
 } fastmm_path;
 
 /* Fusion modes (fastmm_plan_set_fusion). */
@@ -293,7 +307,9 @@ fastmm_status fastmm_scaling_exponents(fastmm_plan_t plan, const void *A, const 
  * gemm_batched call on the calling thread records HIP events on its stream around its four
  * phases (scaling reductions; operand formation, i.e. the limb planes of the split precisions,
  * zero otherwise; the products kernel, for a batch its one launch with the descriptor upload;
- * the W-combination; a batch counts as one call).  fastmm_profile_read synchronises on the
+ * the W-combination; a batch counts as one call; with scaling at every level the calls that
+ * multiply the first level's node operands are the ones recorded, one each, and the first
+ * level's own passes are not).  fastmm_profile_read synchronises on the
  * last recorded events and returns the summed milliseconds of each phase and the number of
  * calls since the last read (then resets).  Any output pointer may be NULL. */
 fastmm_status fastmm_profile_enable(int enable);

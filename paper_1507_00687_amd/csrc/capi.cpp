@@ -250,7 +250,7 @@ struct fastmm_plan_s {
     int algo = 0;
     int depth = 0;
     int cutoff = 1;
-    fastmm_scaling sc{0, 0, 0.0};
+    fastmm_scaling sc{0, 0, 0.0, 0};
     int prec = FASTMM_F64;
     int fuse = FASTMM_FUSE_AUTO;  // fastmm_fusion
     // Non-uniform recursion: the rule id of every internal node, breadth first (empty: `algo`
@@ -263,6 +263,9 @@ struct fastmm_plan_s {
     std::map<std::pair<int, int>, std::unique_ptr<fastmm::Tables>> tables;  // (L, device)
     // Sub-plans with the rotated rules, made on first use by the backward pass.
     std::unique_ptr<fastmm_plan_s> rot[3];
+    // Scaling at every level: the plans of the first level's node products, by the depth of
+    // the call that uses them (made on first use).
+    std::map<int, std::unique_ptr<fastmm_plan_s>> node_plans;
 };
 
 namespace fastmm {
@@ -443,8 +446,8 @@ struct WsLayout {
     size_t ea, ep, eb, flags, maxA, maxB, sp, tp, ia, ib, leaves, total;
 };
 
-WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n, int bm_force = 0) {
-    WsLayout w{};
+// The scaling part of a workspace (exponents, flags, maxima); returns its end.
+size_t scaling_layout(const fastmm_plan_s *p, int64_t m, int64_t k, int64_t n, WsLayout &w) {
     const size_t es = elem_size(p->prec);
     size_t off = 0;
     if (p->sc.mode != FASTMM_SCALE_NONE) {
@@ -455,6 +458,13 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
         w.maxA = off, off = align256(off + es * (size_t)std::max(m, k));
         w.maxB = off, off = align256(off + es * (size_t)std::max(k, n));
     }
+    return off;
+}
+
+WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n, int bm_force = 0) {
+    WsLayout w{};
+    const size_t es = elem_size(p->prec);
+    size_t off = scaling_layout(p, m, k, n, w);
     if (is_split(p->prec)) {
         const SplitDims d = split_dims(p->prec, s, bm_force);
         const size_t nleaves = (size_t)plan_leaf_count(p, s.L);
@@ -722,7 +732,7 @@ fastmm_status fastmm_plan_create(fastmm_plan_t *out, int algo, int depth, int cu
     if (depth < 0 || depth > 8) return fail(FASTMM_EINVAL, "depth must be in [0, 8]");
     if (cutoff < 1) return fail(FASTMM_EINVAL, "cutoff must be >= 1");
     if (precision < FASTMM_F64 || precision > FASTMM_BF16X6) return fail(FASTMM_EINVAL, "unknown precision");
-    fastmm_scaling sc{FASTMM_SCALE_NONE, 0, 0.0};
+    fastmm_scaling sc{FASTMM_SCALE_NONE, 0, 0.0, 0};
     if (scaling) {
         sc = *scaling;
         if (sc.mode < FASTMM_SCALE_NONE || sc.mode > FASTMM_SCALE_REPEATED)
@@ -730,6 +740,7 @@ fastmm_status fastmm_plan_create(fastmm_plan_t *out, int algo, int depth, int cu
         if (sc.mode == FASTMM_SCALE_REPEATED && (sc.steps < 1 || sc.steps > 256))
             return fail(FASTMM_EINVAL, "repeated scaling needs 1 <= steps <= 256");
         if (!(sc.tau >= 0.0) || std::isinf(sc.tau)) return fail(FASTMM_EINVAL, "tau must be finite and >= 0");
+        if (sc.per_level != 0 && sc.per_level != 1) return fail(FASTMM_EINVAL, "per_level must be 0 or 1");
     }
     fastmm_plan_s *p = new (std::nothrow) fastmm_plan_s();
     if (!p) return fail(FASTMM_ENOMEM, "plan allocation");
@@ -766,6 +777,7 @@ fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode) {
     plan->fuse = mode;
     for (auto &r : plan->rot)
         if (r) r->fuse = plan->fuse;
+    plan->node_plans.clear();  // remade with the new mode on next use
     return FASTMM_OK;
 }
 
@@ -774,6 +786,8 @@ fastmm_status fastmm_plan_set_tree(fastmm_plan_t plan, const int *node_algos, in
     const Algo &a = plan_algo(plan);
     std::vector<int> tree;
     if (count > 0) {
+        if (plan->sc.per_level && plan->sc.mode != FASTMM_SCALE_NONE)
+            return fail(FASTMM_EUNSUPPORTED, "scaling at every level needs one rule per level, not a tree");
         if (!node_algos) return fail(FASTMM_EINVAL, "null node rule list");
         int64_t need = 0, lev = 1;
         for (int l = 0; l < plan->depth; ++l, lev *= a.R) {
@@ -796,6 +810,7 @@ fastmm_status fastmm_plan_set_tree(fastmm_plan_t plan, const int *node_algos, in
     plan->levels.clear();
     plan->tables.clear();  // rebuilt for the new tree on next use
     for (auto &r : plan->rot) r.reset();
+    plan->node_plans.clear();
     return FASTMM_OK;
 }
 
@@ -819,8 +834,16 @@ fastmm_status fastmm_plan_set_levels(fastmm_plan_t plan, const int *level_algos,
     plan->tree.clear();
     plan->tables.clear();
     for (auto &r : plan->rot) r.reset();
+    plan->node_plans.clear();
     return FASTMM_OK;
 }
+
+namespace fastmm {
+namespace {
+bool every_level(const fastmm_plan_s *p, const Shape &s);
+fastmm_status every_level_total(fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n, size_t *bytes);
+}  // namespace
+}  // namespace fastmm
 
 fastmm_status fastmm_plan_path(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, int transA, int transB,
                                int *path) {
@@ -828,7 +851,9 @@ fastmm_status fastmm_plan_path(fastmm_plan_t plan, int64_t m, int64_t k, int64_t
     if (!path || m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "bad arguments");
     const Shape s = shape_of(plan, m, k, n);
     uint32_t masks[6];
-    *path = fused_path(plan, s, transA, transB, masks) ? FASTMM_PATH_FUSED : FASTMM_PATH_LEAF;
+    *path = every_level(plan, s)                         ? FASTMM_PATH_EVERY_LEVEL
+            : fused_path(plan, s, transA, transB, masks) ? FASTMM_PATH_FUSED
+                                                         : FASTMM_PATH_LEAF;
     return FASTMM_OK;
 }
 
@@ -836,6 +861,7 @@ fastmm_status fastmm_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, in
     if (check_plan(plan)) return FASTMM_EINVAL;
     if (!bytes || m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "bad arguments");
     const Shape s = shape_of(plan, m, k, n);
+    if (every_level(plan, s)) return every_level_total(plan, s, m, k, n, bytes);
     *bytes = ws_layout(plan, s, m, k, n).total;
     return FASTMM_OK;
 }
@@ -852,7 +878,7 @@ struct PhaseMarks {
     PhaseEvents pe{};
     hipStream_t st;
     int next = 1;
-    explicit PhaseMarks(hipStream_t s) : prof(g_prof.on), st(s) {
+    explicit PhaseMarks(hipStream_t s, bool record = true) : prof(g_prof.on && record), st(s) {
         if (!prof) return;
         for (int i = 0; i <= kPhases; ++i) pe.ev[i] = g_prof.get();
         (void)hipEventRecord(pe.ev[0], st);
@@ -944,6 +970,119 @@ hipError_t split_form(fastmm_plan_s *plan, const Shape &s, const SplitDims &d, c
     return hipSuccess;
 }
 
+// ---- scaling at every level
+// From depth 2, a plan with per-level scaling runs the first level itself: the scaling steps
+// on op(A), op(B); the node operands S_r, T_r of eq. (2) written out with those factors
+// applied; each node product by the plan of the remaining levels (which scales S_r, T_r in
+// turn); the W-combination with the factors D_A, D_B of the first step.
+bool every_level(const fastmm_plan_s *p, const Shape &s) {
+    return p->sc.per_level && p->sc.mode != FASTMM_SCALE_NONE && s.L >= 2;
+}
+
+// The plan of the node products of a depth-L call: levels 2 .. L of p, same cutoff, scaling,
+// precision and fusion.
+fastmm_status node_plan(fastmm_plan_s *p, int L, fastmm_plan_s **out) {
+    std::lock_guard<std::mutex> g(p->mu);
+    std::unique_ptr<fastmm_plan_s> &q = p->node_plans[L];
+    if (!q) {
+        q.reset(new (std::nothrow) fastmm_plan_s());
+        if (!q) return fail(FASTMM_ENOMEM, "plan allocation");
+        q->algo = p->algo, q->depth = L - 1, q->cutoff = p->cutoff, q->sc = p->sc, q->prec = p->prec;
+        q->fuse = p->fuse;
+        if (!p->levels.empty()) q->levels.assign(p->levels.begin() + 1, p->levels.begin() + L);
+    }
+    *out = q.get();
+    return FASTMM_OK;
+}
+
+// Workspace: [scaling part] | [S_r nodes][T_r nodes][node products] elems | [workspace of the
+// node products' calls, shared by them in turn].
+struct EveryLevelWs {
+    WsLayout sc;
+    size_t sn, tn, mn, sub, sub_bytes, total;
+    int64_t mb1, kb1, nb1;
+    int nodes;
+    fastmm_plan_s *child;
+};
+
+fastmm_status every_level_layout(fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n,
+                                 EveryLevelWs &w) {
+    w = EveryLevelWs{};
+    const Algo &a = level_algo(p, 0);
+    w.mb1 = s.Mp / a.M0, w.kb1 = s.Kp / a.K0, w.nb1 = s.Np / a.N0;
+    w.nodes = leaf_count(a, 1);
+    const size_t es = elem_size(p->prec);
+    size_t off = scaling_layout(p, m, k, n, w.sc);
+    w.sn = off, off = align256(off + es * (size_t)w.nodes * w.mb1 * w.kb1);
+    w.tn = off, off = align256(off + es * (size_t)w.nodes * w.kb1 * w.nb1);
+    w.mn = off, off = align256(off + es * (size_t)w.nodes * w.mb1 * w.nb1);
+    fastmm_status st = node_plan(p, s.L, &w.child);
+    if (st != FASTMM_OK) return st;
+    if ((st = fastmm_workspace_size(w.child, w.mb1, w.kb1, w.nb1, &w.sub_bytes)) != FASTMM_OK) return st;
+    w.sub = off, off = align256(off + w.sub_bytes);
+    w.total = off;
+    return FASTMM_OK;
+}
+
+fastmm_status every_level_total(fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n, size_t *bytes) {
+    EveryLevelWs w;
+    fastmm_status st = every_level_layout(p, s, m, k, n, w);
+    if (st == FASTMM_OK) *bytes = w.total;
+    return st;
+}
+
+fastmm_status gemm_every_level(fastmm_plan_s *p, const Shape &s, const void *A, int64_t lda, int transA,
+                               const void *B, int64_t ldb, int transB, void *C, int64_t ldc, int64_t m, int64_t k,
+                               int64_t n, void *workspace, size_t ws_bytes, hipStream_t st) {
+    EveryLevelWs w;
+    fastmm_status stt = every_level_layout(p, s, m, k, n, w);
+    if (stt != FASTMM_OK) return stt;
+    if (workspace == nullptr || ws_bytes < w.total)
+        return fail(FASTMM_EWORKSPACE, "workspace of " + std::to_string(w.total) + " bytes required");
+    if (((uintptr_t)workspace & 255) != 0) return fail(FASTMM_EINVAL, "workspace must be 256-byte aligned");
+    Tables *tab = nullptr;
+    if ((stt = get_tables(p, 1, &tab)) != FASTMM_OK) return stt;
+    if (tab->nleaves != w.nodes) return fail(FASTMM_EUNSUPPORTED, "node count mismatch");
+    char *ws = (char *)workspace;
+    const size_t es = elem_size(p->prec);
+    const Elem el = p->prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
+    // The profiler records the node products' calls (each with its own phases, so that the
+    // product kernels' durations stay per launch), not this level.
+    ScaleExps exps;
+    stt = run_scaling(p, A, lda, transA, B, ldb, transB, m, k, n, ws, w.sc, st, &exps);
+    if (stt != FASTMM_OK) return stt;
+    NodeDense fa{};
+    fa.elem = el, fa.X = A, fa.ld_r = transA ? 1 : lda, fa.ld_c = transA ? lda : 1, fa.R = m, fa.K = k;
+    fa.rb = w.mb1, fa.cb = w.kb1, fa.nodes = tab->leaves, fa.src = tab->asrc, fa.b_side = 0;
+    fa.e_r = exps.ea, fa.e_c = exps.ep, fa.s_r = -1, fa.s_c = 1;  // 2^(ep_kk - ea_i)
+    fa.Y = ws + w.sn, fa.y_stride = w.mb1 * w.kb1, fa.y_ld = w.kb1;
+    NodeDense fb{};
+    fb.elem = el, fb.X = B, fb.ld_r = transB ? 1 : ldb, fb.ld_c = transB ? ldb : 1, fb.R = k, fb.K = n;
+    fb.rb = w.kb1, fb.cb = w.nb1, fb.nodes = tab->leaves, fb.src = tab->bsrc, fb.b_side = 1;
+    fb.e_r = exps.ep, fb.e_c = exps.eb, fb.s_r = -1, fb.s_c = -1;  // 2^(-ep_kk - eb_j)
+    fb.Y = ws + w.tn, fb.y_stride = w.kb1 * w.nb1, fb.y_ld = w.nb1;
+    hipError_t e;
+    if ((e = launch_node_dense(fa, w.nodes, st)) != hipSuccess || (e = launch_node_dense(fb, w.nodes, st)) != hipSuccess)
+        return hip_fail(e, "node operand formation");
+    for (int q = 0; q < w.nodes; ++q) {
+        stt = fastmm_gemm_ex(w.child, ws + w.sn + es * (size_t)q * w.mb1 * w.kb1, w.kb1, 0,
+                             ws + w.tn + es * (size_t)q * w.kb1 * w.nb1, w.nb1, 0,
+                             ws + w.mn + es * (size_t)q * w.mb1 * w.nb1, w.nb1, w.mb1, w.kb1, w.nb1,
+                             ws + w.sub, w.sub_bytes, st);
+        if (stt != FASTMM_OK) return stt;
+    }
+    CombineLaunch Cb;
+    Cb.elem = el;
+    Cb.M = ws + w.mn;
+    Cb.leaf_stride = w.mb1 * w.nb1;
+    Cb.C = C, Cb.ldc = ldc, Cb.m = m, Cb.n = n, Cb.mb = w.mb1, Cb.nb = w.nb1;
+    Cb.NB = tab->NB;
+    Cb.bdest = tab->bdest, Cb.dest = tab->dest;
+    Cb.sc = exps;
+    if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
+    return FASTMM_OK;
+}
+
 }  // namespace
 }  // namespace fastmm
 
@@ -971,12 +1110,14 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     if (ranges_overlap(C, cbytes, A, abytes) || ranges_overlap(C, cbytes, B, bbytes))
         return fail(FASTMM_EALIAS, "C overlaps A or B");
     const Shape s = shape_of(plan, m, k, n);
+    if (((uintptr_t)A % es) || ((uintptr_t)B % es) || ((uintptr_t)C % es))
+        return fail(FASTMM_EINVAL, "misaligned operand");
+    if (every_level(plan, s))
+        return gemm_every_level(plan, s, A, lda, transA, B, ldb, transB, C, ldc, m, k, n, workspace, ws_bytes, st);
     const WsLayout w = ws_layout(plan, s, m, k, n);
     if (w.total > 0 && (workspace == nullptr || ws_bytes < w.total))
         return fail(FASTMM_EWORKSPACE, "workspace of " + std::to_string(w.total) + " bytes required");
     if (w.total > 0 && ((uintptr_t)workspace & 255) != 0) return fail(FASTMM_EINVAL, "workspace must be 256-byte aligned");
-    if (((uintptr_t)A % es) || ((uintptr_t)B % es) || ((uintptr_t)C % es))
-        return fail(FASTMM_EINVAL, "misaligned operand");
     Tables *tab = nullptr;
     fastmm_status stt = get_tables(plan, s.L, &tab);
     if (stt != FASTMM_OK) return stt;
@@ -1148,6 +1289,8 @@ fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem *pro
     for (int i = 0; i < count; ++i) {
         const fastmm_problem &q = probs[i];
         const Shape s = shape_of(plans[i], q.m, q.k, q.n);
+        if (every_level(plans[i], s))
+            return fail(FASTMM_EUNSUPPORTED, "scaling at every level runs through fastmm_gemm_ex, not in a batch");
         const size_t w = ws_layout(plans[i], s, q.m, q.k, q.n, bl.bm).total;
         bl.ws_off.push_back(off);
         bl.ws_size.push_back(w);

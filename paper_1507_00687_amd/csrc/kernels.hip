@@ -290,6 +290,63 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(CombineArgs<T> p) {
     }
 }
 
+template <typename T>
+struct NodeDenseArgs {
+    const T *X;
+    int64_t ld_r, ld_c, R, K, rb, cb;
+    const LeafEntry *nodes;
+    const SrcEntry *src;
+    int b_side;
+    const int32_t *e_r, *e_c;
+    int s_r, s_c;
+    T *Y;
+    int64_t y_stride, y_ld;
+};
+
+// Node operands of the first recursion level written out (eq. (2)): node q is the sum over
+// its source list of coef * block (br, bc) of op(X), each element scaled first.  One thread
+// per column of the node block, rows strided over blockIdx.y, node q = blockIdx.z.
+template <typename T, bool SCALED>
+__global__ __launch_bounds__(kThreads) void node_dense_kernel(NodeDenseArgs<T> p) {
+    const int q = blockIdx.z;
+    const LeafEntry le = p.nodes[q];
+    const int begin = p.b_side ? le.b_begin : le.a_begin;
+    const int count = p.b_side ? le.b_count : le.a_count;
+    const int64_t col = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (col >= p.cb) return;
+    T *Y = p.Y + (int64_t)q * p.y_stride;
+    for (int64_t row = blockIdx.y; row < p.rb; row += gridDim.y) {
+        T acc = T(0);
+        for (int j = 0; j < count; ++j) {
+            const SrcEntry se = p.src[begin + j];
+            const int64_t gr = (int64_t)se.br * p.rb + row, gc = (int64_t)se.bc * p.cb + col;
+            T v = T(0);
+            if (gr < p.R && gc < p.K) {
+                v = p.X[gr * p.ld_r + gc * p.ld_c];
+                if (SCALED) v = ldexp_t(v, p.s_r * p.e_r[gr] + p.s_c * p.e_c[gc]);
+            }
+            const T term = (T)se.coef * v;
+            acc = j == 0 ? term : acc + term;
+        }
+        Y[row * p.y_ld + col] = acc;
+    }
+}
+
+template <typename T>
+hipError_t node_dense_go(const NodeDense &f, int nodes, hipStream_t s) {
+    NodeDenseArgs<T> a;
+    a.X = (const T *)f.X;
+    a.ld_r = f.ld_r, a.ld_c = f.ld_c, a.R = f.R, a.K = f.K, a.rb = f.rb, a.cb = f.cb;
+    a.nodes = f.nodes, a.src = f.src, a.b_side = f.b_side;
+    a.e_r = f.e_r, a.e_c = f.e_c, a.s_r = f.s_r, a.s_c = f.s_c;
+    a.Y = (T *)f.Y, a.y_stride = f.y_stride, a.y_ld = f.y_ld;
+    const int64_t gx = (f.cb + kThreads - 1) / kThreads;
+    dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(f.rb, 1024), (unsigned)nodes);
+    if (f.e_r) hipLaunchKernelGGL((node_dense_kernel<T, true>), grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((node_dense_kernel<T, false>), grid, dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 __global__ void fill_i32_kernel(int32_t *p, int64_t count, int32_t value) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -594,6 +651,13 @@ hipError_t launch_leaf(const LeafLaunch &L, hipStream_t s) {
 hipError_t launch_combine(const CombineLaunch &L, hipStream_t s) {
     if (L.elem == Elem::F64) return combine_go<double>(L, s);
     return combine_go<float>(L, s);
+}
+
+hipError_t launch_node_dense(const NodeDense &f, int nodes, hipStream_t s) {
+    if (nodes <= 0 || f.rb <= 0 || f.cb <= 0) return hipSuccess;
+    if (nodes > 65535 || (f.cb + kThreads - 1) / kThreads > 0x7fffffff) return hipErrorInvalidValue;
+    if (f.elem == Elem::F64) return node_dense_go<double>(f, nodes, s);
+    return node_dense_go<float>(f, nodes, s);
 }
 
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s) {

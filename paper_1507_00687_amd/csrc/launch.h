@@ -51,6 +51,24 @@ struct CombineLaunch {
     ScaleExps sc;
 };
 
+// Node operands of the first recursion level, written out: node q (q < nodes) of op(X)
+// (R x K, element (row, col) at X[row * ld_r + col * ld_c], zero outside) is the sum over its
+// source list (A side: asrc of the depth-1 tables, B side: bsrc) of coef * block (br, bc), the
+// blocks rb x cb; every element is multiplied by 2^(s_r e_r[row] + s_c e_c[col]) when e_r is
+// not null.  Node q goes to Y + q * y_stride (rb x cb, row stride y_ld).
+struct NodeDense {
+    Elem elem;
+    const void *X;
+    int64_t ld_r, ld_c, R, K, rb, cb;
+    const LeafEntry *nodes;
+    const SrcEntry *src;
+    int b_side;
+    const int32_t *e_r, *e_c;
+    int s_r, s_c;
+    void *Y;
+    int64_t y_stride, y_ld;
+};
+
 // Scaling-step reductions (Algorithms 1-3).  `kind` 'O' or 'I'.  Operands are op(A) (m x k)
 // and op(B) (k x n).  `maxA`, `maxB` hold (m | k) and (k | n) maxima scratch of the element
 // type; `exps` are updated in place; `flags` are two int32 (stop, fail) for the optional
@@ -191,6 +209,7 @@ hipError_t launch_leaf_batched(Elem e, int scaled, int direct, const void *descs
 hipError_t launch_transpose(Elem e, const void *in, int64_t ldi, int64_t R, int64_t C, void *out, int64_t ldo,
                             hipStream_t s);
 hipError_t launch_combine(const CombineLaunch &L, hipStream_t s);
+hipError_t launch_node_dense(const NodeDense &f, int nodes, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
 hipError_t launch_zero_elems(Elem e, void *C, int64_t ldc, int64_t m, int64_t n, hipStream_t s);
 hipError_t launch_scale_step(const ScaleStep &S, hipStream_t s);

@@ -45,7 +45,8 @@ class _Problem(ctypes.Structure):
 
 
 class _Scaling(ctypes.Structure):
-    _fields_ = [("mode", ctypes.c_int), ("steps", ctypes.c_int), ("tau", ctypes.c_double)]
+    _fields_ = [("mode", ctypes.c_int), ("steps", ctypes.c_int), ("tau", ctypes.c_double),
+                ("per_level", ctypes.c_int)]
 
 
 _lib = None
@@ -160,15 +161,19 @@ def fastmm_algo_register(M0, K0, N0, R, num_U, num_V, num_W, log2_den=0) -> int:
 
 # --------------------------------------------------------------------------------- plans
 class Plan:
-    """A fastmm plan: algorithm, recursion depth, cutoff, scaling procedure, precision."""
+    """A fastmm plan: algorithm, recursion depth, cutoff, scaling procedure, precision.
+
+    per_level=True runs the scaling steps also on the operands of every inner node of the
+    recursion (scaling at every level), not only on A and B."""
 
     def __init__(self, algo="strassen", depth: int = 1, cutoff: int = 1, scaling: str = "none",
-                 steps: int = 2, tau: float = 0.0, precision: str = "f64", fuse="auto"):
+                 steps: int = 2, tau: float = 0.0, precision: str = "f64", fuse="auto",
+                 per_level: bool = False):
         self.algo, self.depth, self.cutoff = algo, depth, cutoff
         self.scaling, self.steps, self.tau, self.precision = scaling, steps, tau, precision
-        self.fuse = fuse
+        self.fuse, self.per_level = fuse, per_level
         self._h = ctypes.c_void_p()
-        sc = _Scaling(_id(SCALE_MODES, scaling), steps, tau)
+        sc = _Scaling(_id(SCALE_MODES, scaling), steps, tau, int(bool(per_level)))
         _check(lib().fastmm_plan_create(ctypes.byref(self._h), _id(ALGOS, algo), depth, cutoff, ctypes.byref(sc),
                                         _id(PRECISIONS, precision)))
         mode = FUSION[fuse] if isinstance(fuse, str) else (FUSION["auto"] if fuse else FUSION["off"])
@@ -195,10 +200,10 @@ class Plan:
         return self
 
     def path(self, m: int, k: int, n: int, transA: bool = False, transB: bool = False) -> str:
-        """'fused' or 'leaf': the execution path of an m x k by k x n product."""
+        """'leaf', 'fused' or 'every_level': the execution path of an m x k by k x n product."""
         v = ctypes.c_int()
         _check(lib().fastmm_plan_path(self._h, m, k, n, int(transA), int(transB), ctypes.byref(v)))
-        return "fused" if v.value == 1 else "leaf"
+        return {0: "leaf", 1: "fused", 2: "every_level"}[v.value]
 
     @property
     def handle(self):

@@ -346,3 +346,42 @@ def test_levels_argument_errors(F):
     assert p.path(256, 256, 256) == "leaf"
     p.set_levels([])
     assert p.shape(32, 32, 32) == (2, 32, 32, 32)
+
+
+def test_every_level_scaling_plan_rules(F):
+    import torch
+
+    from tests.trees import dalberto_tree
+
+    m = k = n = 256
+    once = F.Plan("strassen", 2, 1, scaling="out_in", precision="f32")
+    every = F.Plan("strassen", 2, 1, scaling="out_in", precision="f32", per_level=True)
+    # from depth 2: the first level's node operands and products (7 each of 128 x 128) plus
+    # the nested products' own workspace
+    nested = F.Plan("strassen", 1, 1, scaling="out_in", precision="f32").workspace_size(128, 128, 128)
+    assert every.workspace_size(m, k, n) >= 7 * 3 * 128 * 128 * 4 + nested
+    assert every.workspace_size(m, k, n) > once.workspace_size(m, k, n)
+    assert every.path(m, k, n) == "every_level" and once.path(m, k, n) == "fused"
+    # depth <= 1 (or no scaling, or the cutoff stopping at one level): as scaling once
+    for depth, mode, cutoff in ((1, "out_in", 1), (2, "none", 1), (2, "outside", 100)):
+        a = F.Plan("strassen", depth, cutoff, scaling=mode, per_level=True)
+        b = F.Plan("strassen", depth, cutoff, scaling=mode)
+        assert a.workspace_size(m, k, n) == b.workspace_size(m, k, n)
+        assert a.path(m, k, n) == b.path(m, k, n) != "every_level"
+    # uniform non-stationary plans nest the remaining levels' rules
+    lv = F.Plan("f323", 2, 1, scaling="outside", precision="f64", per_level=True).set_levels(["f323", "strassen"])
+    assert lv.workspace_size(300, 200, 300) > 0
+    # not with trees, not in a batch (from depth 2)
+    ids, _ = dalberto_tree(F)
+    with pytest.raises(F.FastmmError):
+        F.Plan("strassen", 2, 1, scaling="outside", per_level=True).set_tree(ids)
+    F.Plan("strassen", 2, 1, scaling="none", per_level=True).set_tree(ids)  # no scaling: no conflict
+    A, B = torch.zeros((m, k)), torch.zeros((k, n))
+    with pytest.raises(F.FastmmError):
+        F.fastmm_batched_workspace_size([every], [A], [B])
+    shallow = F.Plan("strassen", 1, 1, scaling="out_in", precision="f32", per_level=True)
+    assert F.fastmm_batched_workspace_size([shallow], [A], [B]) > 0
+    # per_level must be 0 or 1 in the C struct
+    h = ctypes.c_void_p()
+    sc = F.fastmm._Scaling(1, 2, 0.0, 2)
+    assert F.lib().fastmm_plan_create(ctypes.byref(h), 1, 2, 1, ctypes.byref(sc), 1) != 0

@@ -8,6 +8,7 @@ import pytest
 from oracle import coeffs as C
 from oracle import fastmm_oracle as O
 from synth import badly_scaled
+from tests.dyadic import dyadic_pair, exact_product
 
 Z = 2.0 ** -20
 SZ = 2.0 ** -10  # sqrt(Z)
@@ -210,39 +211,13 @@ def test_scaling_improves_componentwise_error_on_example_6_1_pattern():
 # ---- scaling at every level (a reading: the paper scales once; here every inner node of the
 # recursion runs the same steps on its own operands and unscales its product)
 
-def _dyadic_pair(seed, m, k, n, span=6):
-    """Small integers times powers of two (2^-6 .. 2^6) per row of A and per column of B: the
-    scaled operands, every product and every partial sum the method forms stay exact dyadic
-    numbers within FP64's 53 bits, so C is exact.  (With 2^+-12, inside factors that differ
-    between the added blocks widen the sums beyond 53 bits and they round.)"""
-    from synth import make_pair
-
-    A, B = make_pair("int8", seed, m, k, n)
-    rng = np.random.default_rng(seed)
-    A = A * np.ldexp(1.0, rng.integers(-span, span + 1, m))[:, None]
-    B = B * np.ldexp(1.0, rng.integers(-span, span + 1, n))[None, :]
-    return A, B
-
-
-def _exact(A, B):
-    from fractions import Fraction
-
-    # exact product through integer mantissas: A = a 2^-e, B = b 2^-f with a, b integers
-    ea, eb = 40, 40
-    a = np.rint(np.ldexp(A, ea)).astype(object)
-    b = np.rint(np.ldexp(B, eb)).astype(object)
-    assert np.array_equal(np.ldexp(a.astype(np.float64), -ea), A)
-    c = a.dot(b)
-    return np.vectorize(lambda x: float(Fraction(int(x), 2 ** (ea + eb))))(c)
-
-
 @pytest.mark.parametrize("mode,steps", [("outside", 2), ("inside", 2), ("out_in", 2), ("repeated", 4)])
 @pytest.mark.parametrize("rules,shape", [((C.strassen(),) * 2, (24, 20, 28)), ((C.strassen(),) * 3, (32, 16, 40)),
                                          ((C.f323(), C.strassen()), (30, 14, 27))])
 def test_every_level_scaling_is_exact_on_dyadic_inputs(mode, steps, rules, shape):
-    A, B = _dyadic_pair(5, *shape)
+    A, B = dyadic_pair(5, *shape)
     got = O.scaled_fast_every_level(A, B, list(rules), 1, mode, steps)
-    assert np.array_equal(got, _exact(A, B))
+    assert np.array_equal(got, exact_product(A, B))
 
 
 @pytest.mark.parametrize("mode,steps", [("outside", 2), ("out_in", 2), ("in_out", 2), ("repeated", 20)])
