@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "devtypes.h"
 #include "launch.h"
@@ -380,41 +381,134 @@ __device__ inline T nanmax(T a, T b) {
     return (b > a || b != b) ? b : a;
 }
 
-// out[r] = max_c |X(r,c)| * 2^(sr*er[r] + sc*ec[c]) over a stored row-major R x C matrix
-// whose rows are contiguous.  One wave per row.
+// 16-byte loads of VEC elements (VEC = 1: plain loads) and of the matching VEC exponents.
+template <typename T, int VEC>
+struct Vec {
+    typedef T v_t __attribute__((ext_vector_type(VEC)));
+    typedef int e_t __attribute__((ext_vector_type(VEC)));
+    __device__ static v_t load(const T *p) { return *reinterpret_cast<const v_t *>(p); }
+    __device__ static e_t exps(const int32_t *p) { return *reinterpret_cast<const e_t *>(p); }
+};
 template <typename T>
+struct Vec<T, 1> {
+    typedef T v_t;
+    typedef int e_t;
+    __device__ static v_t load(const T *p) { return *p; }
+    __device__ static e_t exps(const int32_t *p) { return *p; }
+};
+template <typename V>
+__device__ inline auto lane_of(const V &v, int j) {
+    if constexpr (std::is_arithmetic<V>::value) return v;
+    else return v[j];
+}
+
+// out[r] = max_c |X(r,c)| * 2^(sr*er[r] + sc*ec[c]) over a stored row-major R x C matrix
+// whose rows are contiguous.  One wave per row; each lane takes VEC consecutive elements per
+// load (rows 16-byte aligned when VEC > 1), four loads in flight, the tail element-wise.
+template <typename T, int VEC>
 __global__ __launch_bounds__(kThreads) void rowmax_kernel(const T *X, int64_t ld, int64_t R, int64_t C,
                                                            const int32_t *er, int sr, const int32_t *ec, int sc,
                                                            T *out) {
+    typedef Vec<T, VEC> V;
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
     if (r >= R) return;
     const int rexp = sr * er[r];
-    T mx = T(0);
-    for (int64_t c = lane; c < C; c += 64) {
-        const T v = ldexp_t(fabs(X[r * ld + c]), rexp + sc * ec[c]);
-        mx = nanmax(mx, v);
-    }
+    const T *row = X + r * ld;
+    T mx[4] = {T(0), T(0), T(0), T(0)};
+    const int64_t Cv = C / VEC * VEC, step = 64 * VEC;
+    int64_t c = (int64_t)lane * VEC;
+    for (; c + 3 * step < Cv; c += 4 * step) {
+        typename V::v_t x[4];
+        typename V::e_t e[4];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mx = nanmax(mx, (T)__shfl_xor(mx, off, 64));
-    if (lane == 0) out[r] = mx;
+        for (int u = 0; u < 4; ++u) x[u] = V::load(row + c + u * step), e[u] = V::exps(ec + c + u * step);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const T xv = lane_of(x[u], j);
+                const int ev = lane_of(e[u], j);
+                mx[u] = nanmax(mx[u], ldexp_t(fabs(xv), rexp + sc * ev));
+            }
+    }
+    for (; c < Cv; c += step) {
+        const typename V::v_t x = V::load(row + c);
+        const typename V::e_t e = V::exps(ec + c);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const T xv = lane_of(x, j);
+            const int ev = lane_of(e, j);
+            mx[0] = nanmax(mx[0], ldexp_t(fabs(xv), rexp + sc * ev));
+        }
+    }
+    for (int64_t t = Cv + lane; t < C; t += 64) mx[1] = nanmax(mx[1], ldexp_t(fabs(row[t]), rexp + sc * ec[t]));
+    T m = nanmax(nanmax(mx[0], mx[1]), nanmax(mx[2], mx[3]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = nanmax(m, (T)__shfl_xor(m, off, 64));
+    if (lane == 0) out[r] = m;
 }
 
-// out[c] = max_r |X(r,c)| * 2^(sr*er[r] + sc*ec[c]); each block covers 256 columns and a
-// chunk of rows, partial maxima merged with an unsigned atomic max on the IEEE bit pattern
-// (order-independent, so the result is deterministic).  `out` must start at +0.
-template <typename T>
+// out[c] = max_r |X(r,c)| * 2^(sr*er[r] + sc*ec[c]).  A work-group covers 64 VEC columns
+// (16-byte loads when VEC > 1: rows 16-byte aligned) and a chunk of rows; each of its four
+// waves takes every fourth row of the chunk, so a wave reads whole 64 VEC-column row
+// segments.  The waves' maxima meet in LDS and one atomic max per column (on the IEEE bit
+// pattern: order-independent, so the result is deterministic) merges the work-groups.  `out`
+// must start at +0.
+template <typename T, int VEC>
 __global__ __launch_bounds__(kThreads) void colmax_kernel(const T *X, int64_t ld, int64_t R, int64_t C,
                                                            const int32_t *er, int sr, const int32_t *ec, int sc,
                                                            int64_t rows_per_block, T *out) {
-    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (c >= C) return;
+    typedef Vec<T, VEC> V;
+    constexpr int kGroups = kThreads / 64;
+    __shared__ T part[kGroups][64 * VEC];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int64_t c0 = ((int64_t)blockIdx.x * 64 + lane) * VEC;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
     const int64_t r1 = r0 + rows_per_block < R ? r0 + rows_per_block : R;
-    const int cexp = sc * ec[c];
-    T mx = T(0);
-    for (int64_t r = r0; r < r1; ++r) mx = nanmax(mx, ldexp_t(fabs(X[r * ld + c]), cexp + sr * er[r]));
-    atomicMax(reinterpret_cast<typename Bits<T>::u *>(out + c), Bits<T>::of(mx));
+    T mx[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) mx[j] = T(0);
+    if (c0 + VEC <= C) {
+        const typename V::e_t ce = V::exps(ec + c0);
+        int64_t r = r0 + grp;
+        for (; r + 3 * kGroups < r1; r += 4 * kGroups) {
+            typename V::v_t x[4];
+            int e[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                x[u] = V::load(X + (r + u * kGroups) * ld + c0), e[u] = sr * er[r + u * kGroups];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int j = 0; j < VEC; ++j)
+                    mx[j] = nanmax(mx[j], ldexp_t(fabs(lane_of(x[u], j)), e[u] + sc * lane_of(ce, j)));
+        }
+        for (; r < r1; r += kGroups) {
+            const typename V::v_t x = V::load(X + r * ld + c0);
+            const int e = sr * er[r];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) mx[j] = nanmax(mx[j], ldexp_t(fabs(lane_of(x, j)), e + sc * lane_of(ce, j)));
+        }
+    } else {
+        for (int j = 0; j < VEC && c0 + j < C; ++j) {
+            const int cexp = sc * ec[c0 + j];
+            for (int64_t r = r0 + grp; r < r1; r += kGroups)
+                mx[j] = nanmax(mx[j], ldexp_t(fabs(X[r * ld + c0 + j]), cexp + sr * er[r]));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) part[grp][lane * VEC + j] = mx[j];
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            T m = part[0][lane * VEC + j];
+#pragma unroll
+            for (int g = 1; g < kGroups; ++g) m = nanmax(m, part[g][lane * VEC + j]);
+            if (c0 + j < C) atomicMax(reinterpret_cast<typename Bits<T>::u *>(out + c0 + j), Bits<T>::of(m));
+        }
+    }
 }
 
 template <typename T>
@@ -569,22 +663,52 @@ inline unsigned grid1d(int64_t count, int per) {
     return (unsigned)g;
 }
 
+// Elements per 16-byte load for a stored row-major matrix: 16 / sizeof(T) when every row
+// starts 16-byte aligned, else 1.
+template <typename T>
+constexpr int kVec = 16 / (int)sizeof(T);
+template <typename T>
+bool rows_aligned(const T *X, int64_t ld) {
+    return ((uintptr_t)X % 16) == 0 && ld % kVec<T> == 0;
+}
+
+template <typename T>
+void launch_rowmax(const T *X, int64_t ld, int64_t R, int64_t C, const int32_t *er, int sr, const int32_t *ec,
+                   int sc, T *out, hipStream_t s) {
+    const dim3 grid((unsigned)((R + 3) / 4));
+    if (rows_aligned(X, ld))
+        hipLaunchKernelGGL((rowmax_kernel<T, kVec<T>>), grid, dim3(kThreads), 0, s, X, ld, R, C, er, sr, ec, sc, out);
+    else
+        hipLaunchKernelGGL((rowmax_kernel<T, 1>), grid, dim3(kThreads), 0, s, X, ld, R, C, er, sr, ec, sc, out);
+}
+
+// Column maxima of a stored R x C matrix: about 2048 work-groups of at least 32 rows.
+template <typename T>
+void launch_colmax(const T *X, int64_t ld, int64_t R, int64_t C, const int32_t *er, int sr, const int32_t *ec,
+                   int sc, T *out, hipStream_t s) {
+    hipLaunchKernelGGL(zero_elems_kernel<T>, dim3(grid1d(C, kThreads)), dim3(kThreads), 0, s, out, C);
+    if (R <= 0) return;  // empty columns: maxima 0
+    const int vec = rows_aligned(X, ld) ? kVec<T> : 1;
+    const int64_t gx = (C + 64 * vec - 1) / (64 * vec);
+    int64_t rpb = std::max<int64_t>(32, (R * gx + 2047) / 2048);
+    const int64_t gy = std::min<int64_t>((R + rpb - 1) / rpb, 65535);
+    rpb = (R + gy - 1) / gy;
+    const dim3 grid((unsigned)gx, (unsigned)gy);
+    if (vec > 1)
+        hipLaunchKernelGGL((colmax_kernel<T, kVec<T>>), grid, dim3(kThreads), 0, s, X, ld, R, C, er, sr, ec, sc, rpb,
+                           out);
+    else
+        hipLaunchKernelGGL((colmax_kernel<T, 1>), grid, dim3(kThreads), 0, s, X, ld, R, C, er, sr, ec, sc, rpb, out);
+}
+
 // Logical reductions over op(X) where op(X) is R x C; the stored matrix is row-major with
 // contiguous rows (trans == 0) or op(X) = stored^T (trans != 0).
 template <typename T>
 hipError_t reduce_rows(const T *X, int64_t ld, int trans, int64_t R, int64_t C, const int32_t *er, int sr,
                        const int32_t *ec, int sc, T *out, hipStream_t s) {
     if (R <= 0) return hipSuccess;
-    if (!trans) {
-        hipLaunchKernelGGL(rowmax_kernel<T>, dim3((unsigned)((R + 3) / 4)), dim3(kThreads), 0, s, X, ld, R, C, er,
-                           sr, ec, sc, out);
-    } else {
-        // rows of op(X) are columns of the stored C x R matrix
-        hipLaunchKernelGGL(zero_elems_kernel<T>, dim3(grid1d(R, kThreads)), dim3(kThreads), 0, s, out, R);
-        const int64_t rpb = 64;
-        dim3 grid((unsigned)((R + kThreads - 1) / kThreads), (unsigned)((C + rpb - 1) / rpb));
-        hipLaunchKernelGGL(colmax_kernel<T>, grid, dim3(kThreads), 0, s, X, ld, C, R, ec, sc, er, sr, rpb, out);
-    }
+    if (!trans) launch_rowmax<T>(X, ld, R, C, er, sr, ec, sc, out, s);
+    else launch_colmax<T>(X, ld, C, R, ec, sc, er, sr, out, s);  // rows of op(X): columns of the stored C x R
     return hipGetLastError();
 }
 
@@ -592,15 +716,8 @@ template <typename T>
 hipError_t reduce_cols(const T *X, int64_t ld, int trans, int64_t R, int64_t C, const int32_t *er, int sr,
                        const int32_t *ec, int sc, T *out, hipStream_t s) {
     if (C <= 0) return hipSuccess;
-    if (!trans) {
-        hipLaunchKernelGGL(zero_elems_kernel<T>, dim3(grid1d(C, kThreads)), dim3(kThreads), 0, s, out, C);
-        const int64_t rpb = 64;
-        dim3 grid((unsigned)((C + kThreads - 1) / kThreads), (unsigned)((R + rpb - 1) / rpb));
-        hipLaunchKernelGGL(colmax_kernel<T>, grid, dim3(kThreads), 0, s, X, ld, R, C, er, sr, ec, sc, rpb, out);
-    } else {
-        hipLaunchKernelGGL(rowmax_kernel<T>, dim3((unsigned)((C + 3) / 4)), dim3(kThreads), 0, s, X, ld, C, R, ec,
-                           sc, er, sr, out);
-    }
+    if (!trans) launch_colmax<T>(X, ld, R, C, er, sr, ec, sc, out, s);
+    else launch_rowmax<T>(X, ld, C, R, ec, sc, er, sr, out, s);
     return hipGetLastError();
 }
 
