@@ -510,6 +510,28 @@ std::string schedule_of(const fastmm_scaling &sc) {
     return "";
 }
 
+// The W-combination reads each product once, in registers, for one or two levels of
+// <2,K0,2> rules with at most 8 products each, every product live (leaf of (r1, r2):
+// r1 R2 + r2), summing level by level; otherwise it follows the composite destination lists.
+void set_kron(const fastmm_plan_s *p, int levels, int nleaves, CombineLaunch &Cb) {
+    Cb.kron = 0;
+    if (levels < 1 || levels > 2 || !p->tree.empty()) return;
+    const Algo &a1 = level_algo(p, 0);
+    if (a1.M0 != 2 || a1.N0 != 2 || a1.R > 8) return;
+    for (int k = 0; k < 4; ++k)
+        for (int r = 0; r < a1.R; ++r) Cb.w1[k][r] = (float)a1.w(k, r);
+    Cb.R1 = a1.R;
+    if (levels == 1) {
+        if (nleaves == a1.R) Cb.kron = 1;
+        return;
+    }
+    const Algo &a2 = level_algo(p, 1);
+    if (a2.M0 != 2 || a2.N0 != 2 || a2.R > 8 || nleaves != a1.R * a2.R) return;
+    for (int k = 0; k < 4; ++k)
+        for (int r = 0; r < a2.R; ++r) Cb.w2[k][r] = (float)a2.w(k, r);
+    Cb.R2 = a2.R, Cb.kron = 2;
+}
+
 fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1079,6 +1101,7 @@ fastmm_status gemm_every_level(fastmm_plan_s *p, const Shape &s, const void *A, 
     Cb.NB = tab->NB;
     Cb.bdest = tab->bdest, Cb.dest = tab->dest;
     Cb.sc = exps;
+    set_kron(p, 1, tab->nleaves, Cb);
     if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
     return FASTMM_OK;
 }
@@ -1165,6 +1188,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         Cb.NB = tab->NB;
         Cb.bdest = tab->bdest, Cb.dest = tab->dest;
         Cb.sc = exps;
+        set_kron(plan, s.L, tab->nleaves, Cb);
         if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
         return FASTMM_OK;
     }
@@ -1202,6 +1226,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         Cb.NB = outer->NB;
         Cb.bdest = outer->bdest, Cb.dest = outer->dest;
         Cb.sc = exps;
+        set_kron(plan, s.L - 1, outer->nleaves, Cb);
         if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
         return FASTMM_OK;
     }
@@ -1225,6 +1250,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     Cb.NB = tab->NB;
     Cb.bdest = tab->bdest, Cb.dest = tab->dest;
     Cb.sc = exps;
+    set_kron(plan, s.L, tab->nleaves, Cb);
     if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
     return FASTMM_OK;
 }
@@ -1417,6 +1443,7 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
                 c.leaf_stride = sh.mb * sh.nb;
                 c.C = q.C, c.ldc = q.n, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
                 c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
+                set_kron(p, sh.L, tab->nleaves, c);
             }
             it.mode = 0;
             it.desc.resize(sizeof(LimbGemm));
@@ -1447,6 +1474,7 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
             c.leaf_stride = sh.mb * sh.nb;
             c.C = q.C, c.ldc = q.n, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
             c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
+            set_kron(p, sh.L, tab->nleaves, c);
         }
         it.mode = 2 * (exps.ea != nullptr ? 1 : 0) + (L.direct ? 1 : 0);
         it.desc.resize(leaf_desc_bytes(el));

@@ -224,6 +224,21 @@ struct VecOf<double, 2> {
     typedef double2 t;
 };
 
+// VEC consecutive int32 exponents in one load (the exponent vectors are 16-byte aligned and
+// VEC divides the column index wherever VEC > 1).
+template <int VEC>
+__device__ inline void load_exps(const int32_t *e, int (&out)[VEC]) {
+    if constexpr (VEC == 4) {
+        const int4 t = *reinterpret_cast<const int4 *>(e);
+        out[0] = t.x, out[1] = t.y, out[2] = t.z, out[3] = t.w;
+    } else if constexpr (VEC == 2) {
+        const int2 t = *reinterpret_cast<const int2 *>(e);
+        out[0] = t.x, out[1] = t.y;
+    } else {
+        out[0] = e[0];
+    }
+}
+
 template <typename T, bool SCALED, int VEC>
 __global__ __launch_bounds__(kThreads) void combine_kernel(CombineArgs<T> p) {
     const int64_t y = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * VEC;
@@ -273,8 +288,11 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(CombineArgs<T> p) {
                     for (int e = 0; e < VEC; ++e) acc[e] = T(0);
                 }
                 if (SCALED) {
+                    int eb[VEC];
+                    load_exps<VEC>(p.sc.eb + col, eb);
+                    const int ea = p.sc.ea[row];
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) acc[e] = ldexp_t(acc[e], p.sc.ea[row] + p.sc.eb[col + e]);
+                    for (int e = 0; e < VEC; ++e) acc[e] = ldexp_t(acc[e], ea + eb[e]);
                 }
                 T *dst = p.C + row * p.ldc + col;
                 if constexpr (VEC == 1) {
@@ -286,6 +304,174 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(CombineArgs<T> p) {
                     for (int e = 0; e < VEC; ++e) ws[e] = acc[e];
                     *reinterpret_cast<typename VecOf<T, VEC>::t *>(dst) = w;
                 }
+            }
+        }
+    }
+}
+
+template <typename T>
+struct Combine2Args {
+    const T *M;
+    int64_t leaf_stride;
+    T *C;
+    int64_t ldc, m, n, mb, nb;
+    int R1, R2;
+    float w1[4][8], w2[4][8];
+    ScaleExps sc;
+};
+
+// The W-combination of two levels of <2,K0,2> rules, level by level as the recursion of eq.
+// (2) sums it: for each first-level product r1 the thread forms the four second-level sums
+// N(p2) = sum_r2 w2[p2][r2] M_(r1,r2), then adds w1[p1][r1] N(p2) to output block (p1, p2);
+// both sums in increasing product order, zero coefficients skipped.  A thread owns VEC
+// consecutive columns of one row of the leaf-block grid and keeps all 16 output blocks of that
+// position in registers, so each product element is read once.
+template <typename T, bool SCALED, int VEC>
+__global__ __launch_bounds__(kThreads) void combine2_kernel(Combine2Args<T> p) {
+    const int64_t y = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * VEC;
+    if (y >= p.nb) return;
+    for (int64_t x = blockIdx.y; x < p.mb; x += gridDim.y) {
+        T acc[4][4][VEC];
+        bool seen[4] = {false, false, false, false};
+        for (int r1 = 0; r1 < p.R1; ++r1) {
+            T mv[8][VEC];
+#pragma unroll
+            for (int r2 = 0; r2 < 8; ++r2) {
+                if (r2 < p.R2) {
+                    const T *src = p.M + (int64_t)(r1 * p.R2 + r2) * p.leaf_stride + x * p.nb + y;
+                    if constexpr (VEC == 1) {
+                        mv[r2][0] = *src;
+                    } else {
+                        const typename VecOf<T, VEC>::t w = *reinterpret_cast<const typename VecOf<T, VEC>::t *>(src);
+                        const T *ws = reinterpret_cast<const T *>(&w);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) mv[r2][e] = ws[e];
+                    }
+                }
+            }
+            T nsum[4][VEC];
+#pragma unroll
+            for (int p2 = 0; p2 < 4; ++p2) {
+                bool first = true;
+#pragma unroll
+                for (int r2 = 0; r2 < 8; ++r2) {
+                    const float w = r2 < p.R2 ? p.w2[p2][r2] : 0.f;
+                    if (w != 0.f) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            const T term = (T)w * mv[r2][e];
+                            nsum[p2][e] = first ? term : nsum[p2][e] + term;
+                        }
+                        first = false;
+                    }
+                }
+                if (first) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) nsum[p2][e] = T(0);
+                }
+            }
+#pragma unroll
+            for (int p1 = 0; p1 < 4; ++p1) {
+                const float w = p.w1[p1][r1];
+                if (w != 0.f) {
+#pragma unroll
+                    for (int p2 = 0; p2 < 4; ++p2)
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            const T term = (T)w * nsum[p2][e];
+                            acc[p1][p2][e] = seen[p1] ? acc[p1][p2][e] + term : term;
+                        }
+                    seen[p1] = true;
+                }
+            }
+        }
+#pragma unroll
+        for (int p1 = 0; p1 < 4; ++p1)
+#pragma unroll
+            for (int p2 = 0; p2 < 4; ++p2) {
+                const int64_t row = (2 * (p1 >> 1) + (p2 >> 1)) * p.mb + x;
+                const int64_t col = (2 * (p1 & 1) + (p2 & 1)) * p.nb + y;
+                if (row >= p.m || col >= p.n) continue;
+                T out[VEC];
+                int eb[VEC];
+                if (SCALED) load_exps<VEC>(p.sc.eb + col, eb);
+                const int ea = SCALED ? p.sc.ea[row] : 0;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    out[e] = seen[p1] ? acc[p1][p2][e] : T(0);
+                    if (SCALED) out[e] = ldexp_t(out[e], ea + eb[e]);
+                }
+                T *dst = p.C + row * p.ldc + col;
+                if constexpr (VEC == 1) {
+                    *dst = out[0];
+                } else {
+                    typename VecOf<T, VEC>::t w;
+                    T *ws = reinterpret_cast<T *>(&w);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) ws[e] = out[e];
+                    *reinterpret_cast<typename VecOf<T, VEC>::t *>(dst) = w;
+                }
+            }
+    }
+}
+
+// One level of a <2,K0,2> rule: C_p = sum_r w1[p][r] M_r for the four output blocks, products
+// in increasing order (the order of the destination lists), each product element read once.
+template <typename T, bool SCALED, int VEC>
+__global__ __launch_bounds__(kThreads) void combine1_kernel(Combine2Args<T> p) {
+    const int64_t y = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * VEC;
+    if (y >= p.nb) return;
+    for (int64_t x = blockIdx.y; x < p.mb; x += gridDim.y) {
+        T mv[8][VEC];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (r < p.R1) {
+                const T *src = p.M + (int64_t)r * p.leaf_stride + x * p.nb + y;
+                if constexpr (VEC == 1) {
+                    mv[r][0] = *src;
+                } else {
+                    const typename VecOf<T, VEC>::t w = *reinterpret_cast<const typename VecOf<T, VEC>::t *>(src);
+                    const T *ws = reinterpret_cast<const T *>(&w);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) mv[r][e] = ws[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int p1 = 0; p1 < 4; ++p1) {
+            const int64_t row = (p1 >> 1) * p.mb + x, col = (p1 & 1) * p.nb + y;
+            if (row >= p.m || col >= p.n) continue;
+            T acc[VEC];
+            bool first = true;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const float w = r < p.R1 ? p.w1[p1][r] : 0.f;
+                if (w != 0.f) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const T term = (T)w * mv[r][e];
+                        acc[e] = first ? term : acc[e] + term;
+                    }
+                    first = false;
+                }
+            }
+            int eb[VEC];
+            if (SCALED) load_exps<VEC>(p.sc.eb + col, eb);
+            const int ea = SCALED ? p.sc.ea[row] : 0;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if (first) acc[e] = T(0);
+                if (SCALED) acc[e] = ldexp_t(acc[e], ea + eb[e]);
+            }
+            T *dst = p.C + row * p.ldc + col;
+            if constexpr (VEC == 1) {
+                *dst = acc[0];
+            } else {
+                typename VecOf<T, VEC>::t w;
+                T *ws = reinterpret_cast<T *>(&w);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) ws[e] = acc[e];
+                *reinterpret_cast<typename VecOf<T, VEC>::t *>(dst) = w;
             }
         }
     }
@@ -624,7 +810,49 @@ hipError_t leaf_trans(const LeafLaunch &L, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t combine2_go(const CombineLaunch &L, hipStream_t s) {
+    Combine2Args<T> a;
+    a.M = (const T *)L.M;
+    a.leaf_stride = L.leaf_stride;
+    a.C = (T *)L.C;
+    a.ldc = L.ldc, a.m = L.m, a.n = L.n, a.mb = L.mb, a.nb = L.nb;
+    a.R1 = L.R1, a.R2 = L.R2;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 8; ++j) a.w1[i][j] = L.w1[i][j], a.w2[i][j] = L.w2[i][j];
+    a.sc = L.sc;
+    if (L.R1 < 1 || L.R1 > 8 || (L.kron == 2 && (L.R2 < 1 || L.R2 > 8))) return hipErrorInvalidValue;
+    constexpr int VEC = 16 / (int)sizeof(T);
+    const bool vec = L.nb % VEC == 0 && L.n % VEC == 0 && L.ldc % VEC == 0 && (uintptr_t)L.C % 16 == 0 &&
+                     (uintptr_t)L.M % 16 == 0 && L.leaf_stride % VEC == 0;
+    const int per = vec ? VEC : 1;
+    const int64_t cols = (L.nb + per - 1) / per;
+    dim3 grid((unsigned)((cols + kThreads - 1) / kThreads), (unsigned)(L.mb < 65535 ? L.mb : 65535));
+    const bool sc = L.sc.ea != nullptr;
+    if (L.kron == 1) {
+        if (vec) {
+            if (sc) hipLaunchKernelGGL((combine1_kernel<T, true, VEC>), grid, dim3(kThreads), 0, s, a);
+            else hipLaunchKernelGGL((combine1_kernel<T, false, VEC>), grid, dim3(kThreads), 0, s, a);
+        } else {
+            if (sc) hipLaunchKernelGGL((combine1_kernel<T, true, 1>), grid, dim3(kThreads), 0, s, a);
+            else hipLaunchKernelGGL((combine1_kernel<T, false, 1>), grid, dim3(kThreads), 0, s, a);
+        }
+    } else if (vec) {
+        if (sc) hipLaunchKernelGGL((combine2_kernel<T, true, VEC>), grid, dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((combine2_kernel<T, false, VEC>), grid, dim3(kThreads), 0, s, a);
+    } else {
+        if (sc) hipLaunchKernelGGL((combine2_kernel<T, true, 1>), grid, dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((combine2_kernel<T, false, 1>), grid, dim3(kThreads), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t combine_go(const CombineLaunch &L, hipStream_t s) {
+    if (L.kron) {
+        if (L.m <= 0 || L.n <= 0) return hipSuccess;
+        if (L.mb <= 0 || L.nb <= 0) return hipErrorInvalidValue;
+        return combine2_go<T>(L, s);
+    }
     CombineArgs<T> a;
     a.M = (const T *)L.M;
     a.leaf_stride = L.leaf_stride;

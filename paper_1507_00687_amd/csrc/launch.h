@@ -49,6 +49,13 @@ struct CombineLaunch {
     const BlockDests *bdest;
     const DestEntry *dest;
     ScaleExps sc;
+    // One or two levels of <2,K0,2> rules with at most 8 products each, every product live
+    // (leaf r1 R2 + r2): kron = 1 sums C_p1 = sum_r1 w1[p1][r1] M_r1; kron = 2 sums level by
+    // level, C_(p1,p2) = sum_r1 w1[p1][r1] sum_r2 w2[p2][r2] M_(r1,r2) (p = i N0 + j, output
+    // block row 2 i1 + i2, column 2 j1 + j2); each product read once, the lists above unused.
+    int kron = 0;
+    int R1 = 0, R2 = 0;
+    float w1[4][8] = {}, w2[4][8] = {};
 };
 
 // Node operands of the first recursion level, written out: node q (q < nodes) of op(X)
