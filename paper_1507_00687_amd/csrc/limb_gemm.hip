@@ -194,6 +194,16 @@ __global__ __launch_bounds__(4096 / EPT) void form_all(PlaneForm a, int nleaves)
             x[b][e] = v;
         }
     }
+    if (SCALED) {  // once per element, not once per leaf that uses it (exact: powers of two)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int bo = a.b_side ? b / nbk : b % nbo, bk = a.b_side ? b % nbk : b / nbo;
+            if (b < nblk) {
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) x[b][e] = ldexpf(x[b][e], eo_s[bo * kFT + lo[e]] + ek_s[bk * kFT + lk[e]]);
+            }
+        }
+    }
     for (int leaf = 0; leaf < nleaves; ++leaf) {
         float v[EPT];
         bool first = true;
@@ -201,13 +211,8 @@ __global__ __launch_bounds__(4096 / EPT) void form_all(PlaneForm a, int nleaves)
         for (int b = 0; b < NB; ++b) {
             const float c = b < nblk ? coef[leaf * nblk + b] : 0.f;
             if (c != 0.f) {
-                const int bo = a.b_side ? b / nbk : b % nbo, bk = a.b_side ? b % nbk : b / nbo;
 #pragma unroll
-                for (int e = 0; e < EPT; ++e) {
-                    // scaling applied here (exact), so the loads above hold only the raw values
-                    const float xs = SCALED ? ldexpf(x[b][e], eo_s[bo * kFT + lo[e]] + ek_s[bk * kFT + lk[e]]) : x[b][e];
-                    v[e] = first ? c * xs : v[e] + c * xs;
-                }
+                for (int e = 0; e < EPT; ++e) v[e] = first ? c * x[b][e] : v[e] + c * x[b][e];
                 first = false;
             }
         }
