@@ -484,18 +484,26 @@ __device__ __forceinline__ void limb_tile(const LimbGemm &a, int leaf, int64_t t
 
     const bool direct = DYN ? a.direct != 0 : DIRECT;
     const bool scaled = DYN ? a.sc.ea != nullptr : SCALED;
+    // column exponents of the lane's TJ columns, loaded once (direct scaled output only)
+    int ebj[TJ];
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+        const int64_t col = tn * BN + wn * (BN / WN) + j * 16 + l16;
+        ebj[j] = (direct && scaled && col < a.n) ? a.sc.eb[col] : 0;
+    }
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j)
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = tm * BM + wm * (BM / WM) + i * 16 + 4 * (lane >> 4) + v;  // inside the leaf block
+            const int eai = (direct && scaled && row < a.m) ? a.post_exp + a.sc.ea[row] : 0;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = tm * BM + wm * (BM / WM) + i * 16 + 4 * (lane >> 4) + v;  // inside the leaf block
+            for (int j = 0; j < TJ; ++j) {
                 const int64_t col = tn * BN + wn * (BN / WN) + j * 16 + l16;
                 float val = acc[i][j][v];
                 if (direct) {
                     if (row < a.m && col < a.n) {  // one power-of-two factor: exact unless it underflows
-                        if (scaled) val = ldexpf(val, a.post_exp + a.sc.ea[row] + a.sc.eb[col]);
+                        if (scaled) val = ldexpf(val, eai + ebj[j]);
                         a.out[row * a.ldo + col] = val;
                     }
                 } else if (row < a.mb && col < a.nb) {
@@ -503,6 +511,7 @@ __device__ __forceinline__ void limb_tile(const LimbGemm &a, int leaf, int64_t t
                     a.out[(int64_t)leaf * a.leaf_stride + row * a.ldo + col] = val;
                 }
             }
+        }
 }
 
 // Item `item` (leaf-major, tiles in groups of 8 tile rows) of one problem -> (leaf, tm, tn).
