@@ -288,55 +288,57 @@ __global__ __launch_bounds__(256) void form_node(NodeForm a) {
         }
     }
     __syncthreads();
-    for (int c = 0; c < a.R_; ++c) {
-        for (int task = t; task < TO * 8; task += 256) {
-            // consecutive lanes on consecutive rows: the row stride of 65 words puts them on
-            // distinct banks for every k offset
-            const int ro = task % TO, rk = (task / TO) * 8;
-            float v[8];
-            bool first = true;
-            for (int sb = 0; sb < nS; ++sb) {
-                const float u = coef[sb * a.R_ + c];
-                if (u == 0.f) continue;
-                const float *src = &ntile[(sb * TO + ro) * 65 + rk];
+    // (child, task) pairs flattened, so that every thread has work when TO x 8 < 256
+    for (int w = t; w < a.R_ * TO * 8; w += 256) {
+        const int c = w / (TO * 8), task = w - c * (TO * 8);
+        // eight consecutive lanes cover one row's 64 k, so a wave writes whole rows: 256
+        // contiguous bytes of an FP32 child, or two 512-byte runs of a plane piece (rows of
+        // a piece are adjacent).  The LDS row stride of 65 words keeps the reads at most
+        // two-way bank conflicted.
+        const int ro = task / 8, rk = (task % 8) * 8;
+        float v[8];
+        bool first = true;
+        for (int sb = 0; sb < nS; ++sb) {
+            const float u = coef[sb * a.R_ + c];
+            if (u == 0.f) continue;
+            const float *src = &ntile[(sb * TO + ro) * 65 + rk];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = first ? u * src[j] : v[j] + u * src[j];
-                first = false;
-            }
-            if (first) {
+            for (int j = 0; j < 8; ++j) v[j] = first ? u * src[j] : v[j] + u * src[j];
+            first = false;
+        }
+        if (first) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = 0.f;
-            }
-            const int64_t child = (int64_t)q * a.R_ + c, o = o0 + ro, kk = k0 + rk;
-            if (a.last) {
-                unsigned short h[3][8];
+            for (int j = 0; j < 8; ++j) v[j] = 0.f;
+        }
+        const int64_t child = (int64_t)q * a.R_ + c, o = o0 + ro, kk = k0 + rk;
+        if (a.last) {
+            unsigned short h[3][8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    float r = v[j];
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) {
-                        float back;
-                        h[l][j] = a.half ? LimbT<true>::split(r, back) : LimbT<false>::split(r, back);
-                        r = r - back;
-                    }
-                }
+            for (int j = 0; j < 8; ++j) {
+                float r = v[j];
 #pragma unroll
                 for (int l = 0; l < 3; ++l) {
-                    if (l >= a.nl) break;
-                    uint4 w;
-                    w.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
-                    w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
-                    w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
-                    w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
-                    *reinterpret_cast<uint4 *>(a.planes + child * a.leaf_stride + l * a.plane_stride +
-                                               ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 +
-                                               kk % 32) = w;
+                    float back;
+                    h[l][j] = a.half ? LimbT<true>::split(r, back) : LimbT<false>::split(r, back);
+                    r = r - back;
                 }
-            } else if (o < a.cb_o && kk < a.y_ld) {
-                float *dst = a.Y + child * a.y_stride + o * a.y_ld + kk;
-                *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-                *reinterpret_cast<float4 *>(dst + 4) = make_float4(v[4], v[5], v[6], v[7]);
             }
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                if (l >= a.nl) break;
+                uint4 w;
+                w.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
+                w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
+                w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
+                w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
+                *reinterpret_cast<uint4 *>(a.planes + child * a.leaf_stride + l * a.plane_stride +
+                                           ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 +
+                                           kk % 32) = w;
+            }
+        } else if (o < a.cb_o && kk < a.y_ld) {
+            float *dst = a.Y + child * a.y_stride + o * a.y_ld + kk;
+            *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+            *reinterpret_cast<float4 *>(dst + 4) = make_float4(v[4], v[5], v[6], v[7]);
         }
     }
 }
