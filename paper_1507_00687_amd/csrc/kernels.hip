@@ -477,6 +477,93 @@ __global__ __launch_bounds__(kThreads) void combine1_kernel(Combine2Args<T> p) {
     }
 }
 
+// One level of any rule with at most 16 output blocks (M0 N0 <= 16) and at most 64 products,
+// from the destination lists: C_p = sum_r W[p][r] M_r in list order.  The lists are expanded
+// into a dense W in LDS; a thread streams the products of its position (VEC columns of one row
+// of the leaf-block grid), each read once, four loads in flight, into the output blocks it
+// keeps in registers.
+constexpr int kCombineMaxBlocks = 16, kCombineMaxProducts = 64;
+
+template <typename T, bool SCALED, int VEC>
+__global__ __launch_bounds__(kThreads) void combine_level_kernel(CombineArgs<T> p, int nblocks, int nprod) {
+    __shared__ float wt[kCombineMaxProducts][kCombineMaxBlocks];
+    for (int i = threadIdx.x; i < kCombineMaxProducts * kCombineMaxBlocks; i += kThreads)
+        wt[i / kCombineMaxBlocks][i % kCombineMaxBlocks] = 0.f;
+    __syncthreads();
+    for (int b = threadIdx.x; b < nblocks; b += kThreads) {
+        const BlockDests bd = p.bdest[b];
+        for (int q = 0; q < bd.count; ++q) {
+            const DestEntry de = p.dest[bd.begin + q];
+            wt[de.leaf][b] = de.coef;
+        }
+    }
+    __syncthreads();
+    const int64_t y = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * VEC;
+    if (y >= p.nb) return;
+    for (int64_t x = blockIdx.y; x < p.mb; x += gridDim.y) {
+        T acc[kCombineMaxBlocks][VEC];
+        bool seen[kCombineMaxBlocks];
+#pragma unroll
+        for (int b = 0; b < kCombineMaxBlocks; ++b) seen[b] = false;
+        for (int r0 = 0; r0 < nprod; r0 += 4) {
+            T mv[4][VEC];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (r0 + u < nprod) {
+                    const T *src = p.M + (int64_t)(r0 + u) * p.leaf_stride + x * p.nb + y;
+                    if constexpr (VEC == 1) {
+                        mv[u][0] = *src;
+                    } else {
+                        const typename VecOf<T, VEC>::t w = *reinterpret_cast<const typename VecOf<T, VEC>::t *>(src);
+                        const T *ws = reinterpret_cast<const T *>(&w);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) mv[u][e] = ws[e];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int b = 0; b < kCombineMaxBlocks; ++b) {
+                    const float w = r0 + u < nprod ? wt[r0 + u][b] : 0.f;
+                    if (w != 0.f) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            const T term = (T)w * mv[u][e];
+                            acc[b][e] = seen[b] ? acc[b][e] + term : term;
+                        }
+                        seen[b] = true;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kCombineMaxBlocks; ++b) {
+            const int64_t row = (b / p.NB) * p.mb + x, col = (b % p.NB) * p.nb + y;
+            if (b >= nblocks || row >= p.m || col >= p.n) continue;
+            int eb[VEC];
+            if (SCALED) load_exps<VEC>(p.sc.eb + col, eb);
+            const int ea = SCALED ? p.sc.ea[row] : 0;
+            T out[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                out[e] = seen[b] ? acc[b][e] : T(0);
+                if (SCALED) out[e] = ldexp_t(out[e], ea + eb[e]);
+            }
+            T *dst = p.C + row * p.ldc + col;
+            if constexpr (VEC == 1) {
+                *dst = out[0];
+            } else {
+                typename VecOf<T, VEC>::t w;
+                T *ws = reinterpret_cast<T *>(&w);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) ws[e] = out[e];
+                *reinterpret_cast<typename VecOf<T, VEC>::t *>(dst) = w;
+            }
+        }
+    }
+}
+
 template <typename T>
 struct NodeDenseArgs {
     const T *X;
@@ -847,7 +934,41 @@ hipError_t combine2_go(const CombineLaunch &L, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t combine_level_go(const CombineLaunch &L, hipStream_t s) {
+    CombineArgs<T> a;
+    a.M = (const T *)L.M;
+    a.leaf_stride = L.leaf_stride;
+    a.C = (T *)L.C;
+    a.ldc = L.ldc, a.m = L.m, a.n = L.n, a.mb = L.mb, a.nb = L.nb;
+    a.NB = L.NB;
+    a.bdest = L.bdest, a.dest = L.dest, a.sc = L.sc;
+    const int nblocks = L.R2, nprod = L.R1;  // output blocks, products
+    if (nblocks < 1 || nblocks > kCombineMaxBlocks || nprod < 1 || nprod > kCombineMaxProducts || L.NB < 1)
+        return hipErrorInvalidValue;
+    constexpr int VEC = 16 / (int)sizeof(T);
+    const bool vec = L.nb % VEC == 0 && L.n % VEC == 0 && L.ldc % VEC == 0 && (uintptr_t)L.C % 16 == 0 &&
+                     (uintptr_t)L.M % 16 == 0 && L.leaf_stride % VEC == 0;
+    const int per = vec ? VEC : 1;
+    const int64_t cols = (L.nb + per - 1) / per;
+    dim3 grid((unsigned)((cols + kThreads - 1) / kThreads), (unsigned)(L.mb < 65535 ? L.mb : 65535));
+    const bool sc = L.sc.ea != nullptr;
+    if (vec) {
+        if (sc) hipLaunchKernelGGL((combine_level_kernel<T, true, VEC>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
+        else hipLaunchKernelGGL((combine_level_kernel<T, false, VEC>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
+    } else {
+        if (sc) hipLaunchKernelGGL((combine_level_kernel<T, true, 1>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
+        else hipLaunchKernelGGL((combine_level_kernel<T, false, 1>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t combine_go(const CombineLaunch &L, hipStream_t s) {
+    if (L.kron == 3) {
+        if (L.m <= 0 || L.n <= 0) return hipSuccess;
+        if (L.mb <= 0 || L.nb <= 0) return hipErrorInvalidValue;
+        return combine_level_go<T>(L, s);
+    }
     if (L.kron) {
         if (L.m <= 0 || L.n <= 0) return hipSuccess;
         if (L.mb <= 0 || L.nb <= 0) return hipErrorInvalidValue;

@@ -53,6 +53,9 @@ struct CombineLaunch {
     // (leaf r1 R2 + r2): kron = 1 sums C_p1 = sum_r1 w1[p1][r1] M_r1; kron = 2 sums level by
     // level, C_(p1,p2) = sum_r1 w1[p1][r1] sum_r2 w2[p2][r2] M_(r1,r2) (p = i N0 + j, output
     // block row 2 i1 + i2, column 2 j1 + j2); each product read once, the lists above unused.
+    // kron = 3: one level of any rule with at most 16 output blocks (R2 of them, NB per row)
+    // and at most 64 products (R1), every product live: the lists, expanded in LDS, are
+    // summed from registers with each product read once.
     int kron = 0;
     int R1 = 0, R2 = 0;
     float w1[4][8] = {}, w2[4][8] = {};
