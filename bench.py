@@ -72,6 +72,11 @@ def parse():
     ap.add_argument("--study-n", type=int, default=2000)
     ap.add_argument("--study-pairs", type=int, default=5)
     ap.add_argument("--study-rows", type=int, default=32, help="sampled rows per product for the error")
+    ap.add_argument("--study-dist", default="fig3", choices=["fig3", "badly"],
+                    help="the three distributions of section 6.5, or D1 R D2 with diagonals 10^u, "
+                         "u ~ U(-6, 6) per row / column")
+    ap.add_argument("--study-max-depth", type=int, default=6)
+    ap.add_argument("--study-precision", default="f64", help="f64, f32 or a split form")
     ap.add_argument("--tune-cache", default="", help="JSON cache of the autotuner's choices (batch mode)")
     ap.add_argument("--max-instability", type=float, default=16.0,
                     help="autotuner admission cap on (E/K0^2)^L (batch mode)")
@@ -267,10 +272,16 @@ def scaling_study(args):
 
     import paper_1507_00687_amd as F
     from oracle import fastmm_oracle as O
-    from synth.gen import fig3_pair
+    from synth.gen import badly_scaled, fig3_pair
 
     torch.cuda.set_device(0)
     n = args.study_n
+    depths = list(range(1, args.study_max_depth + 1))
+    prec = args.study_precision
+    dt = np.float64 if prec == "f64" else np.float32
+    # the three distributions of section 6.5, or the row/column-scaled D1 R D2 inputs
+    dists = [("badly", lambda seed: badly_scaled(seed, n, n, n))] if args.study_dist == "badly" else \
+        [(f"dist{d}", (lambda d: lambda seed: fig3_pair(seed, n, d))(d)) for d in (1, 2, 3)]
     schedules = [(m, s, False) for m, s in [("none", 2), ("outside", 2), ("inside", 2), ("out_in", 2),
                                               ("in_out", 2), ("repeated", 4), ("repeated", 20)]]
     if args.per_level:  # the same schedules run at every inner node as well
@@ -279,43 +290,52 @@ def scaling_study(args):
     table = {}
     t0 = time.perf_counter()
     gpu_ms = 0.0
-    for dist in (1, 2, 3):
-        pairs = [fig3_pair(1000 + p, n, dist) for p in range(args.study_pairs)]
+    normwise = {}
+    for name, gen in dists:
+        pairs = [gen(1000 + p) for p in range(args.study_pairs)]
         refs = [O.reference_rows(A, B, rows) for A, B in pairs]
-        dev = [(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()) for A, B in pairs]
-        for depth in range(1, 7):
+        dev = [(torch.from_numpy(A.astype(dt)).cuda(), torch.from_numpy(B.astype(dt)).cuda()) for A, B in pairs]
+        for depth in depths:
             for mode, steps, every in schedules:
                 key = (f"{mode}{steps}" if mode == "repeated" else mode) + ("_every_level" if every else "")
-                plan = F.Plan("strassen", depth, 1, scaling=mode, steps=steps, precision="f64", per_level=every)
-                err = 0.0
-                for (tA, tB), ref in zip(dev, refs):
+                plan = F.Plan("strassen", depth, 1, scaling=mode, steps=steps, precision=prec, per_level=every)
+                err = errn = 0.0
+                for (A, B), (tA, tB), ref in zip(pairs, dev, refs):
                     ta = time.perf_counter()
                     Cg = F.fastmm_gemm(plan, tA, tB)
                     torch.cuda.synchronize()
                     gpu_ms += (time.perf_counter() - ta) * 1e3
-                    got = Cg[torch.from_numpy(rows).cuda()].cpu().numpy()
+                    got = Cg[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+                    if not np.all(np.isfinite(got)):  # overflow (e.g. fp16 limbs of unscaled inputs)
+                        err = errn = float("inf")
+                        continue
                     err = max(err, O.componentwise_error(got, ref))
-                table.setdefault(f"dist{dist}", {}).setdefault(key, []).append(err)
-        print(f"distribution {dist} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+                    errn = max(errn, float(np.max(np.abs(got.astype(np.longdouble) - ref))) /
+                               (float(np.max(np.abs(A))) * float(np.max(np.abs(B)))))
+                table.setdefault(name, {}).setdefault(key, []).append(err)
+                normwise.setdefault(name, {}).setdefault(key, []).append(errn)
+        print(f"{name} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     line = {
-        "metric": "componentwise relative error of Strassen (FP64, GPU) under the section 6.5 scaling "
+        "metric": f"componentwise relative error of Strassen ({prec}, GPU) under the section 6.5 scaling "
                   "schedules, max over pairs and sampled rows; index = L - 1",
         "value": None,
         "unit": "relative error",
         "n_gpus": 1,
         "steps": None,
         "warmup": None,
-        "ms_per_step": gpu_ms / (3 * 6 * len(schedules) * args.study_pairs),
+        "ms_per_step": gpu_ms / (len(dists) * len(depths) * len(schedules) * args.study_pairs),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": prec,
         "data": "synthetic",
         "config": {"workload": f"scaling study: N={n}, {args.study_pairs} pairs per distribution, "
-                               f"{len(rows)} sampled rows, Strassen L=1..6 (cutoff 1)",
+                               f"{len(rows)} sampled rows, Strassen L=1..{depths[-1]} (cutoff 1), "
+                               f"inputs {args.study_dist}",
                    "schedules": [(f"{m}{s}" if m == "repeated" else m) + ("_every_level" if e else "")
                                  for m, s, e in schedules]},
         "errors": table,
+        "normwise_errors": normwise,
     }
     print(json.dumps(line), flush=True)
 
