@@ -46,3 +46,14 @@ def test_combination_float_within_oracle(name, depth):
     err_oracle = O.normwise_error(O.fast(A, B, C.get(name), depth), ref, A, B)
     print(f"  error {err:.3e}, oracle's own {err_oracle:.3e}", flush=True)
     assert err <= 4 * err_oracle + 8 * 2.0 ** -53
+
+
+@pytest.mark.parametrize("precision", ["f64", "f16x3"])
+@pytest.mark.parametrize("name,depth", CASES)
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 2), (9, 4, 17)])
+def test_combination_tiny_shapes(precision, name, depth, shape):
+    print(f"\n[combine-tiny] {name} L={depth} {shape} {precision}", flush=True)
+    A, B = make_pair("int8", 92, *shape, dtype=np.float64 if precision == "f64" else np.float32)
+    got = run_gpu(_plan(name, depth, precision), A, B)
+    exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+    assert np.array_equal(got.astype(np.float64), exact)

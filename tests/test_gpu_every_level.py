@@ -109,3 +109,17 @@ def test_every_level_backward_exact():
     torch.cuda.synchronize()
     assert np.array_equal(dA.cpu().numpy(), exact_product(G, B.T))
     assert np.array_equal(dB.cpu().numpy(), exact_product(A.T, G))
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 3, 7), (2, 9, 1), (17, 1, 33)])
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16x3"])
+def test_every_level_tiny_and_degenerate_shapes(shape, precision):
+    import paper_1507_00687_amd as F
+
+    print(f"\n[every-level-tiny] {shape} {precision}", flush=True)
+    A, B = dyadic_pair(29, *shape, span=3)
+    dt = np.float64 if precision == "f64" else np.float32
+    p = F.Plan("strassen", 2, 1, scaling="out_in", precision=precision, per_level=True)
+    got = run_gpu(p, A.astype(dt), B.astype(dt))
+    assert got.shape == (shape[0], shape[2])
+    assert np.array_equal(got.astype(np.float64), exact_product(A, B))
