@@ -184,6 +184,14 @@ typedef enum {
  * arithmetic; at depth 1 they round identically (bitwise equal results). */
 fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode);
 
+/* Output tile of the split-precision limb GEMM (a tuning choice, not part of the method): 0 =
+ * chosen by the leaf-block shape (256 x 256 for blocks of at least 256 x 256 and at most two
+ * limbs, else 128 x 128), or 128 / 256 forced.  256 needs at most two limbs
+ * (FASTMM_EUNSUPPORTED otherwise); a nonzero tile on a plan that is not split precision is
+ * FASTMM_EUNSUPPORTED; other values FASTMM_EINVAL.  In a batched call the problems share the
+ * smallest tile among their plans.  The autotuner sets it per shape. */
+fastmm_status fastmm_plan_set_tile(fastmm_plan_t plan, int tile);
+
 /* Non-uniform recursion (section 3.4; Examples 4.2 and 4.3): gives every internal node of the
  * plan's recursion tree its own rule.  node_algos[i] is the rule id of node i in breadth-first
  * order: node [l, r_1 .. r_{l-1}] (level l, reached through the 0-based products r_1 ..

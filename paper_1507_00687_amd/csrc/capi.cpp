@@ -253,6 +253,7 @@ struct fastmm_plan_s {
     fastmm_scaling sc{0, 0, 0.0, 0};
     int prec = FASTMM_F64;
     int fuse = FASTMM_FUSE_AUTO;  // fastmm_fusion
+    int tile = 0;  // split precisions: limb-GEMM output tile (0: by the leaf-block shape; 128; 256)
     // Non-uniform recursion: the rule id of every internal node, breadth first (empty: `algo`
     // at every node).
     std::vector<int> tree;
@@ -384,11 +385,16 @@ struct SplitDims {
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-// bm_force (a batch's common tile) overrides the tile chosen for the shape.
-SplitDims split_dims(int prec, const Shape &s, int bm_force = 0) {
+// The limb-GEMM tile of a plan on a shape: the plan's own setting, else by the leaf blocks.
+int plan_tile(const fastmm_plan_s *p, const Shape &s) {
+    return p->tile ? p->tile : limb_gemm_tile(p->prec, s.mb, s.nb);
+}
+
+// bm_force (a batch's common tile) overrides the plan's tile.
+SplitDims split_dims(const fastmm_plan_s *p, const Shape &s, int bm_force = 0) {
     SplitDims d;
-    d.nl = limb_count(prec);
-    d.bm = bm_force ? bm_force : limb_gemm_tile(prec, s.mb, s.nb);
+    d.nl = limb_count(p->prec);
+    d.bm = bm_force ? bm_force : plan_tile(p, s);
     d.mbp = round_up(s.mb, d.bm), d.nbp = round_up(s.nb, d.bm), d.kp = round_up(s.kb, 64);
     return d;
 }
@@ -466,7 +472,7 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
     const size_t es = elem_size(p->prec);
     size_t off = scaling_layout(p, m, k, n, w);
     if (is_split(p->prec)) {
-        const SplitDims d = split_dims(p->prec, s, bm_force);
+        const SplitDims d = split_dims(p, s, bm_force);
         const size_t nleaves = (size_t)plan_leaf_count(p, s.L);
         w.sp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.mbp * d.kp);
         w.tp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.nbp * d.kp);
@@ -811,6 +817,19 @@ fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode) {
     return FASTMM_OK;
 }
 
+fastmm_status fastmm_plan_set_tile(fastmm_plan_t plan, int tile) {
+    if (check_plan(plan)) return FASTMM_EINVAL;
+    if (tile != 0 && tile != 128 && tile != 256) return fail(FASTMM_EINVAL, "tile must be 0, 128 or 256");
+    if (tile != 0 && !is_split(plan->prec)) return fail(FASTMM_EUNSUPPORTED, "the tile applies to split precisions");
+    if (tile == 256 && limb_count(plan->prec) > 2) return fail(FASTMM_EUNSUPPORTED, "256 tiles take at most two limbs");
+    std::lock_guard<std::mutex> g(plan->mu);
+    plan->tile = tile;
+    for (auto &r : plan->rot)
+        if (r) r->tile = tile;
+    plan->node_plans.clear();
+    return FASTMM_OK;
+}
+
 fastmm_status fastmm_plan_set_tree(fastmm_plan_t plan, const int *node_algos, int64_t count) {
     if (check_plan(plan)) return FASTMM_EINVAL;
     const Algo &a = plan_algo(plan);
@@ -1018,7 +1037,7 @@ fastmm_status node_plan(fastmm_plan_s *p, int L, fastmm_plan_s **out) {
         q.reset(new (std::nothrow) fastmm_plan_s());
         if (!q) return fail(FASTMM_ENOMEM, "plan allocation");
         q->algo = p->algo, q->depth = L - 1, q->cutoff = p->cutoff, q->sc = p->sc, q->prec = p->prec;
-        q->fuse = p->fuse;
+        q->fuse = p->fuse, q->tile = p->tile;
         if (!p->levels.empty()) q->levels.assign(p->levels.begin() + 1, p->levels.begin() + L);
     }
     *out = q.get();
@@ -1174,7 +1193,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     if (is_split(plan->prec)) {
         // Split precisions: limb planes of every S_r and T_r^T (k contiguous, zero-padded to
         // the GEMM tiles), then the limb GEMM, then (L >= 1) the W-combination.
-        const SplitDims d = split_dims(plan->prec, s);
+        const SplitDims d = split_dims(plan, s);
         LimbGemm g;
         if ((e = split_form(plan, s, d, A, lda, transA, B, ldb, transB, m, k, n, exps, ws, w, tab, st, g)) != hipSuccess)
             return hip_fail(e, "limb plane formation");
@@ -1279,6 +1298,7 @@ fastmm_status rotated_plan(fastmm_plan_s *p, int times, fastmm_plan_s **out) {
         std::unique_ptr<fastmm_plan_s> q(new (std::nothrow) fastmm_plan_s());
         if (!q) return fail(FASTMM_ENOMEM, "plan allocation");
         q->algo = id, q->depth = p->depth, q->cutoff = p->cutoff, q->sc = p->sc, q->prec = p->prec, q->fuse = p->fuse;
+        q->tile = p->tile;
         for (int lid : p->levels) {  // non-stationary: every level's rule rotated alike
             const int r = algo_rotated(lid, times);
             if (r < 0) return fail(FASTMM_EUNSUPPORTED, "cannot rotate a level's rule");
@@ -1317,7 +1337,7 @@ fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem *pro
         bl.bm = 256;
         for (int i = 0; i < count; ++i) {
             const Shape s = shape_of(plans[i], probs[i].m, probs[i].k, probs[i].n);
-            bl.bm = std::min(bl.bm, limb_gemm_tile(prec, s.mb, s.nb));
+            bl.bm = std::min(bl.bm, plan_tile(plans[i], s));
         }
     }
     for (int i = 0; i < count; ++i) {
@@ -1436,7 +1456,7 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
             it.idx = i;
             it.kb = sh.kb;
             it.combine = sh.L > 0;
-            const SplitDims d = split_dims(p->prec, sh, bl.bm);
+            const SplitDims d = split_dims(p, sh, bl.bm);
             LimbGemm g;
             if ((e = split_form(p, sh, d, q.A, q.k, 0, q.B, q.n, 0, q.m, q.k, q.n, exps, pws, w, tab, s, g)) !=
                 hipSuccess)

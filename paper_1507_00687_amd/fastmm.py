@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
         L.fastmm_plan_set_fusion.argtypes = [vp, i32]
         L.fastmm_plan_set_tree.argtypes = [vp, pi32, i64]
         L.fastmm_plan_set_levels.argtypes = [vp, pi32, i32]
+        L.fastmm_plan_set_tile.argtypes = [vp, i32]
         L.fastmm_plan_path.argtypes = [vp, i64, i64, i64, i32, i32, pi32]
         L.fastmm_gemm.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
         L.fastmm_gemm_ex.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64, i64, i64, i64, vp, sz, vp]
@@ -98,7 +99,7 @@ def lib() -> ctypes.CDLL:
                      "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read", "fastmm_task_table",
                      "fastmm_backward_workspace_size", "fastmm_gemm_backward", "fastmm_batched_workspace_size",
                      "fastmm_gemm_batched", "fastmm_plan_set_fusion", "fastmm_plan_path", "fastmm_plan_set_tree",
-                     "fastmm_algo_stability", "fastmm_plan_set_levels"):
+                     "fastmm_algo_stability", "fastmm_plan_set_levels", "fastmm_plan_set_tile"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -179,6 +180,12 @@ class Plan:
         mode = FUSION[fuse] if isinstance(fuse, str) else (FUSION["auto"] if fuse else FUSION["off"])
         if mode != FUSION["auto"]:
             _check(lib().fastmm_plan_set_fusion(self._h, mode))
+
+    def set_tile(self, tile: int) -> "Plan":
+        """Split precisions: the limb GEMM's output tile, 0 (by the leaf-block shape), 128 or 256."""
+        _check(lib().fastmm_plan_set_tile(self._h, int(tile)))
+        self.tile = int(tile)
+        return self
 
     def set_tree(self, node_algos) -> "Plan":
         """Non-uniform recursion: one rule (name or id) per internal node, breadth first

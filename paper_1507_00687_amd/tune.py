@@ -1,10 +1,13 @@
-"""Autotuner: choose a plan (rule, depth, cutoff) per problem shape by measuring on the GPU.
+"""Autotuner: choose a plan (rule, depth, cutoff and, for the split precisions, the limb GEMM's
+output tile) per problem shape by measuring on the GPU.
 
 Candidates are the built-in rules at depths 0..3 (depth 0 is the classical kernel).  A
 candidate is admitted only if its growth factor relative to classical -- the E^L term of
 Theorem 4.1 over the classical K0^L -- stays within `max_instability` (the relative
 instability (E/K0^2)^L of section 5.3 is the same quantity up to the inner dimension); the
-fastest admitted candidate wins.  Results are cached in a JSON file keyed by shape and
+fastest admitted candidate wins; for a split precision timed alone, the winner is then timed
+with the other output tile (128 x 128 against 256 x 256) and keeps the faster (a batched
+launch runs all its problems on one tile, so batch tuning leaves the tile to the library).  Results are cached in a JSON file keyed by shape and
 precision, so tuning can resume.  The timing itself runs the product through libfastmm.so.
 
 By default a candidate is timed the way a batch runs it: as one fastmm_gemm_batched call over
@@ -20,6 +23,8 @@ from dataclasses import asdict, dataclass
 from typing import Dict, Iterable, List, Optional, Tuple
 
 RULES = ("strassen", "winograd", "f323", "f332", "f233", "f424", "f442", "f244", "laderman333")
+SPLIT = ("bf16", "f16", "bf16x3", "f16x3", "bf16x6")
+LIMBS = {"bf16": 1, "f16": 1, "bf16x3": 2, "f16x3": 2, "bf16x6": 3}
 
 
 @dataclass
@@ -30,6 +35,7 @@ class Choice:
     ms: float
     instability: float  # product over the levels used of E / K0^2 (1 for classical)
     levels: Optional[List[str]] = None  # a rule per level (uniform non-stationary), else None
+    tile: int = 0  # split precisions: limb-GEMM output tile (0: by the leaf-block shape)
 
     def plan(self, precision: str, **kw):
         from .fastmm import Plan
@@ -37,6 +43,8 @@ class Choice:
         p = Plan(self.algo, self.depth, self.cutoff, precision=precision, **kw)
         if self.levels:
             p.set_levels(self.levels)
+        if self.tile:
+            p.set_tile(self.tile)
         return p
 
 
@@ -158,6 +166,21 @@ def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 
         if best is None or ms < best.ms:
             best = Choice(algo, depth if levels else 0, cutoff, ms, inst, list(lv[:levels]) if (lv and levels) else None)
     assert best is not None
+    if precision in SPLIT and LIMBS[precision] <= 2 and not in_batch:
+        # the winner with the other output tile (the library picks one by the leaf-block shape);
+        # not for batches: a batched launch runs all its problems on one tile (the smallest of
+        # their plans'), so a per-shape tile would set it for the whole batch
+        for tile in (128, 256):
+            cand = Choice(best.algo, best.depth, best.cutoff, 0.0, best.instability, best.levels, tile)
+            plan = cand.plan(precision)
+            if in_batch:
+                ms = _time_plan_batched(plan, A, B, Cs, reps)
+            else:
+                ws = torch.empty(max(plan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
+                ms = _time_plan(plan, A, B, C, ws, reps)
+            if ms < best.ms * 0.98:  # a clear gain only: both tiles compute the same products
+                cand.ms = ms
+                best = cand
     return best
 
 

@@ -385,3 +385,20 @@ def test_every_level_scaling_plan_rules(F):
     h = ctypes.c_void_p()
     sc = F.fastmm._Scaling(1, 2, 0.0, 2)
     assert F.lib().fastmm_plan_create(ctypes.byref(h), 1, 2, 1, ctypes.byref(sc), 1) != 0
+
+
+def test_plan_tile_setting(F):
+    # split precisions only; 256 x 256 needs at most two limbs; 0 returns to the shape's choice
+    p = F.Plan("strassen", 1, 1, precision="f16x3")
+    auto = p.workspace_size(600, 600, 600)
+    assert p.set_tile(256).workspace_size(600, 600, 600) == auto  # 304-row leaf blocks take 256 tiles
+    small = p.set_tile(128).workspace_size(600, 600, 600)
+    assert small < auto  # planes padded to 384 rather than 512
+    assert p.set_tile(0).workspace_size(600, 600, 600) == auto
+    with pytest.raises(F.FastmmError):
+        F.Plan("strassen", 1, 1, precision="bf16x6").set_tile(256)
+    F.Plan("strassen", 1, 1, precision="bf16x6").set_tile(128)
+    with pytest.raises(F.FastmmError):
+        F.Plan("strassen", 1, 1, precision="f32").set_tile(128)
+    with pytest.raises(F.FastmmError):
+        F.Plan("strassen", 1, 1, precision="f16x3").set_tile(64)

@@ -163,3 +163,34 @@ def test_autotune_with_per_level_rules():
     assert np.array_equal(C.astype(np.float64), (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64))
     assert ch.levels is None or len(ch.levels) == ch.depth
     print(f"\n  chose {ch}", flush=True)
+
+
+def test_output_tile_forced_and_tuned_split_precision(tmp_path):
+    # the limb GEMM's 128 and 256 tiles give the same exact products, alone and in a batch with
+    # mixed tile settings (the batch runs the smallest); the tuner returns a usable tile choice
+    import torch
+
+    import paper_1507_00687_amd as F
+    from paper_1507_00687_amd import tune
+
+    shape = (600, 520, 700)
+    print(f"\n[tile] {shape} f16x3", flush=True)
+    A, B = make_pair("int8", 5, *shape, dtype=np.float32)
+    exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    outs = []
+    for tile in (0, 128, 256):
+        p = F.Plan("strassen", 1, 1, precision="f16x3").set_tile(tile)
+        outs.append(F.fastmm_gemm(p, tA, tB).cpu().numpy())
+        assert np.array_equal(outs[-1].astype(np.float64), exact)
+    plans = [F.Plan("strassen", 1, 1, precision="f16x3").set_tile(t) for t in (256, 128, 0)]
+    Cs = F.fastmm_gemm_batched(plans, [tA] * 3, [tB] * 3)
+    torch.cuda.synchronize()
+    for c in Cs:
+        assert np.array_equal(c.cpu().numpy().astype(np.float64), exact)
+    res = tune.tune([shape], precision="f16x3", cache=str(tmp_path / "t.json"), max_depth=1, reps=1,
+                    in_batch=False)
+    ch = res[shape]
+    assert ch.tile in (0, 128, 256)
+    got = F.fastmm_gemm(ch.plan("f16x3"), tA, tB).cpu().numpy()
+    assert np.array_equal(got.astype(np.float64), exact)
