@@ -580,32 +580,69 @@ struct NodeDenseArgs {
 // Node operands of the first recursion level written out (eq. (2)): node q is the sum over
 // its source list of coef * block (br, bc) of op(X), each element scaled first.  One thread
 // per column of the node block, rows strided over blockIdx.y, node q = blockIdx.z.
-template <typename T, bool SCALED>
+template <typename T, bool SCALED, int VEC>
 __global__ __launch_bounds__(kThreads) void node_dense_kernel(NodeDenseArgs<T> p) {
     const int q = blockIdx.z;
     const LeafEntry le = p.nodes[q];
     const int begin = p.b_side ? le.b_begin : le.a_begin;
     const int count = p.b_side ? le.b_count : le.a_count;
-    const int64_t col = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t col = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * VEC;  // VEC columns
     if (col >= p.cb) return;
     T *Y = p.Y + (int64_t)q * p.y_stride;
     for (int64_t row = blockIdx.y; row < p.rb; row += gridDim.y) {
-        T acc = T(0);
+        T acc[VEC];
         for (int j = 0; j < count; ++j) {
             const SrcEntry se = p.src[begin + j];
             const int64_t gr = (int64_t)se.br * p.rb + row, gc = (int64_t)se.bc * p.cb + col;
-            T v = T(0);
-            if (gr < p.R && gc < p.K) {
-                v = p.X[gr * p.ld_r + gc * p.ld_c];
-                if (SCALED) v = ldexp_t(v, p.s_r * p.e_r[gr] + p.s_c * p.e_c[gc]);
+            T v[VEC];
+            bool whole = false;
+            if constexpr (VEC > 1) {
+                whole = gr < p.R && gc + VEC <= p.K;
+                if (whole) {  // the whole group inside op(X): one 16-byte load
+                    const typename VecOf<T, VEC>::t w = *reinterpret_cast<const typename VecOf<T, VEC>::t *>(
+                        p.X + gr * p.ld_r + gc);
+                    const T *ws = reinterpret_cast<const T *>(&w);
+                    int ec[VEC];
+                    if (SCALED) load_exps<VEC>(p.e_c + gc, ec);
+                    const int er = SCALED ? p.s_r * p.e_r[gr] : 0;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) v[e] = SCALED ? ldexp_t(ws[e], er + p.s_c * ec[e]) : ws[e];
+                }
             }
-            const T term = (T)se.coef * v;
-            acc = j == 0 ? term : acc + term;
+            if (!whole) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    v[e] = T(0);
+                    if (gr < p.R && gc + e < p.K) {
+                        v[e] = p.X[gr * p.ld_r + (gc + e) * p.ld_c];
+                        if (SCALED) v[e] = ldexp_t(v[e], p.s_r * p.e_r[gr] + p.s_c * p.e_c[gc + e]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const T term = (T)se.coef * v[e];
+                acc[e] = j == 0 ? term : acc[e] + term;
+            }
         }
-        Y[row * p.y_ld + col] = acc;
+        if (count == 0) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] = T(0);
+        }
+        if constexpr (VEC == 1) {
+            Y[row * p.y_ld + col] = acc[0];
+        } else {
+            typename VecOf<T, VEC>::t w;
+            T *ws = reinterpret_cast<T *>(&w);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) ws[e] = acc[e];
+            *reinterpret_cast<typename VecOf<T, VEC>::t *>(Y + row * p.y_ld + col) = w;
+        }
     }
 }
 
+// 16-byte accesses when op(X) has contiguous, 16-byte aligned rows and the node blocks hold
+// whole groups (the planner's leaf blocks are multiples of 8 elements).
 template <typename T>
 hipError_t node_dense_go(const NodeDense &f, int nodes, hipStream_t s) {
     NodeDenseArgs<T> a;
@@ -614,10 +651,20 @@ hipError_t node_dense_go(const NodeDense &f, int nodes, hipStream_t s) {
     a.nodes = f.nodes, a.src = f.src, a.b_side = f.b_side;
     a.e_r = f.e_r, a.e_c = f.e_c, a.s_r = f.s_r, a.s_c = f.s_c;
     a.Y = (T *)f.Y, a.y_stride = f.y_stride, a.y_ld = f.y_ld;
-    const int64_t gx = (f.cb + kThreads - 1) / kThreads;
+    constexpr int VEC = 16 / (int)sizeof(T);
+    const bool vec = f.ld_c == 1 && (uintptr_t)f.X % 16 == 0 && f.ld_r % VEC == 0 && f.cb % VEC == 0 &&
+                     f.y_ld % VEC == 0 && f.y_stride % VEC == 0 && (uintptr_t)f.Y % 16 == 0 &&
+                     (f.e_c == nullptr || (uintptr_t)f.e_c % 16 == 0);
+    const int per = vec ? VEC : 1;
+    const int64_t gx = (f.cb / per + kThreads - 1) / kThreads;
     dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(f.rb, 1024), (unsigned)nodes);
-    if (f.e_r) hipLaunchKernelGGL((node_dense_kernel<T, true>), grid, dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL((node_dense_kernel<T, false>), grid, dim3(kThreads), 0, s, a);
+    if (vec) {
+        if (f.e_r) hipLaunchKernelGGL((node_dense_kernel<T, true, VEC>), grid, dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((node_dense_kernel<T, false, VEC>), grid, dim3(kThreads), 0, s, a);
+    } else {
+        if (f.e_r) hipLaunchKernelGGL((node_dense_kernel<T, true, 1>), grid, dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((node_dense_kernel<T, false, 1>), grid, dim3(kThreads), 0, s, a);
+    }
     return hipGetLastError();
 }
 
