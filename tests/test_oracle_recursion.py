@@ -38,16 +38,18 @@ def test_ragged_shapes_padding(name, shape):
     assert np.array_equal(O.fast(A, B, alg, 2), _int_exact(A, B))
 
 
-def test_brute_force_one_level_exhaustive_small_entries():
-    # Every A, B in {-1,0,1}^{2x2}: one level of Strassen equals the exact product.
-    s = C.strassen()
+@pytest.mark.parametrize("name", ["strassen", "winograd"])
+def test_brute_force_one_level_exhaustive_small_entries(name):
+    # Every pair A, B in {-1,0,1}^{2x2} (all 81 x 81 pairs): one level of the rule equals the
+    # exact product.  A wrong sign, index or dropped term of [U,V,W] shows on some pair.
+    alg = C.get(name)
     vals = [-1.0, 0.0, 1.0]
     combos = np.array(list(itertools.product(vals, repeat=4)))
     for a in combos:
         A = a.reshape(2, 2)
-        for b in combos[::7]:
+        for b in combos:
             B = b.reshape(2, 2)
-            assert np.array_equal(O.fast(A, B, s, 1), A @ B)
+            assert np.array_equal(O.fast(A, B, alg, 1), A @ B), (a, b)
 
 
 def test_one_level_matches_eq1_scalar_formula():
@@ -116,6 +118,60 @@ def test_classical_sequential_within_textbook_bound():
     # |c^ - c| <= K u sum|a||b| (first order), per entry.
     absprod = np.abs(A) @ np.abs(B)
     assert np.all(np.abs(Cc.astype(np.longdouble) - ref) <= 300 * u * absprod * 1.01)
+
+
+def test_thm42_bound_equals_thm41_for_identical_levels():
+    # Theorem 4.2 with the same rule at every level is Theorem 4.1: sum of the levels' Q is
+    # Q L, the product of their E is E^L and of their K0 is K0^L.
+    for name in ["strassen", "winograd", "f323", "f424", "laderman333"]:
+        alg = C.get(name)
+        q = C.quantities(alg)
+        for L in (1, 2, 3):
+            K = 4 * alg.K0 ** L
+            assert O.thm42_bound(K, [alg] * L, 2.0 ** -53) == O.thm41_bound(K, alg.K0, L, q.Q, q.E, 2.0 ** -53)
+
+
+def test_thm42_bound_hand_value():
+    # Strassen (Q 8, E 12, K0 2) above <3,2,3> (Q 10, E 20, K0 2), K = 64 (Table 1's values):
+    # (64/4 + 8 + 10) (64/4) (12 * 20) u = 34 * 16 * 240 u = 130560 u.  A slip such as the
+    # largest Q instead of the sum (26 * 16 * 240), K over one level's K0 (50 * 32 * 240) or
+    # the sum of E instead of the product fails.
+    u = 2.0 ** -53
+    assert O.thm42_bound(64, [C.strassen(), C.f323()], u) == 130560 * u
+    assert O.thm42_bound(64, [C.f323(), C.strassen()], u) == 130560 * u
+    assert O.thm42_bound(64, [], u) == 64 * 64 * u  # no level: the classical K^2 bound
+
+
+def test_two_level_nonstationary_error_within_thm42():
+    levels = [C.strassen(), C.f323()]
+    dims = [(2, 2, 2), (3, 2, 3)]
+    for dist in ("uniform01", "normal"):
+        A, B = make_pair(dist, 6, 6 * 40, 4 * 60, 6 * 40)
+        got = O.fast_tree(A, B, lambda path: levels[len(path)], dims)
+        err = O.normwise_error(got, O.reference_rows(A, B), A, B)
+        assert 0 < err <= O.thm42_bound(4 * 60, levels, 2.0 ** -53)
+
+
+def test_normwise_error_hand_value():
+    # max |C^ - C| / (max|A| max|B|): one entry off by 1/2, max|A| = 2, max|B| = 3 -> 1/12.
+    A = np.array([[1.0, -2.0], [0.0, 1.0]])
+    B = np.array([[3.0, 0.0], [1.0, -1.0]])
+    Cref = np.array([[1.0, 2.0], [3.0, 4.0]], dtype=np.longdouble)
+    Chat = np.array([[1.0, 2.0], [3.0, 4.5]])
+    assert O.normwise_error(Chat, Cref, A, B) == pytest.approx(1.0 / 12.0, rel=1e-15)
+    # sampled rows: Cref holds only the sampled row
+    assert O.normwise_error(Chat, Cref[[1]], A, B, rows=[1]) == pytest.approx(1.0 / 12.0, rel=1e-15)
+    assert O.normwise_error(Chat, Cref[[0]], A, B, rows=[0]) == 0.0
+    # the sign of the difference does not matter; the denominator uses max-abs, not max
+    assert O.normwise_error(-Chat, -Cref, -A, -B) == pytest.approx(1.0 / 12.0, rel=1e-15)
+
+
+def test_componentwise_error_hand_value():
+    # max |c^ - c| / |c| over nonzero c: entries (0,0) off by 1/2 of 1, (1,1) by 1 of 5.
+    Cref = np.array([[1.0, 2.0], [0.0, -5.0]], dtype=np.longdouble)
+    Chat = np.array([[1.5, 2.0], [7.0, -4.0]])  # (1,0) has c = 0 and is skipped
+    assert O.componentwise_error(Chat, Cref) == pytest.approx(0.5, rel=1e-15)
+    assert O.componentwise_error(Chat, Cref[[1]], rows=[1]) == pytest.approx(0.2, rel=1e-15)
 
 
 def test_thm41_special_cases():
