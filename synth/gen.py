@@ -14,6 +14,9 @@ study (section 6.5), and badly scaled products D1*R*D2 with diagonal entries 10^
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
@@ -62,10 +65,10 @@ def normal01(seed: int, tag: int, shape, offset: int = 0) -> np.ndarray:
     return out[:n].reshape(shape)
 
 
-def int_uniform(seed: int, tag: int, shape, lo: int = -8, hi: int = 8) -> np.ndarray:
+def int_uniform(seed: int, tag: int, shape, lo: int = -8, hi: int = 8, offset: int = 0) -> np.ndarray:
     """Integers uniform on {lo..hi} (as doubles); modulo reduction of 64-bit draws."""
     n = int(np.prod(shape))
-    z = splitmix64(seed, tag, n)
+    z = splitmix64(seed, tag, n, offset)
     span = np.uint64(hi - lo + 1)
     return ((z % span).astype(np.int64) + lo).astype(np.float64).reshape(shape)
 
@@ -114,21 +117,50 @@ def fig3_pair(seed: int, n: int, which: int):
 
 DISTRIBUTIONS = ("uniform01", "uniform11", "normal", "int8", "badly_scaled")
 
+_CHUNK = 1 << 22  # elements per work item of the threaded generation (even: whole normal pairs)
+
+
+def _stream(kind: str, seed: int, tag: int, shape) -> np.ndarray:
+    """Element e of the stream `kind` keyed by (seed, tag), for e = 0 .. prod(shape) - 1,
+    generated in chunks on a thread pool (numpy releases the GIL in its loops).  Every element
+    is the same pure function of its index as in the one-piece generation, so the result is
+    bitwise the same."""
+    n = int(np.prod(shape))
+
+    def piece(start: int, cnt: int) -> np.ndarray:
+        if kind == "uniform01":
+            return uniform01(seed, tag, (cnt,), offset=start)
+        if kind == "normal":  # offsets count Box-Muller pairs
+            return normal01(seed, tag, (cnt,), offset=start // 2)
+        return int_uniform(seed, tag, (cnt,), offset=start)
+
+    if n <= _CHUNK:
+        return piece(0, n).reshape(shape)
+    out = np.empty(n, dtype=np.float64)
+
+    def fill(start: int) -> None:
+        cnt = min(_CHUNK, n - start)
+        out[start:start + cnt] = piece(start, cnt)
+
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        list(ex.map(fill, range(0, n, _CHUNK)))
+    return out.reshape(shape)
+
 
 def make_pair(dist: str, seed: int, m: int, k: int, n: int, dtype=np.float64):
     """(A, B) of shapes (m, k) and (k, n), row-major, in the requested dtype."""
     if dist == "uniform01":
-        A = uniform01(seed, TAG_A, (m, k))
-        B = uniform01(seed, TAG_B, (k, n))
+        A = _stream("uniform01", seed, TAG_A, (m, k))
+        B = _stream("uniform01", seed, TAG_B, (k, n))
     elif dist == "uniform11":
-        A = uniform01(seed, TAG_A, (m, k)) * 2.0 - 1.0
-        B = uniform01(seed, TAG_B, (k, n)) * 2.0 - 1.0
+        A = _stream("uniform01", seed, TAG_A, (m, k)) * 2.0 - 1.0
+        B = _stream("uniform01", seed, TAG_B, (k, n)) * 2.0 - 1.0
     elif dist == "normal":
-        A = normal01(seed, TAG_A, (m, k))
-        B = normal01(seed, TAG_B, (k, n))
+        A = _stream("normal", seed, TAG_A, (m, k))
+        B = _stream("normal", seed, TAG_B, (k, n))
     elif dist == "int8":
-        A = int_uniform(seed, TAG_A, (m, k))
-        B = int_uniform(seed, TAG_B, (k, n))
+        A = _stream("int8", seed, TAG_A, (m, k))
+        B = _stream("int8", seed, TAG_B, (k, n))
     elif dist == "badly_scaled":
         A, B = badly_scaled(seed, m, k, n)
     else:
