@@ -3,13 +3,16 @@
 MI355X, beside the classical GEMM built the same way (same precision form, one leaf), with the
 max-norm relative error of both against the long-double CPU reference.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--algo winograd] [--depth 2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--algo winograd] [--depth 1]
                     [--n 8192] [--precision f16x3] [--beside f32] [--scaling none]
-                    [--dist uniform01] [--fuse auto]
+                    [--dist uniform01] [--fuse auto] [--also none]
 
-Default workload: Strassen, depth 1, n = 8192, N(0,1), leaves as FP16 MFMA products with FP32
-accumulation and two-limb split precision (F16X3), the same plan on plain FP32 MFMA reported
-beside it.  Prints one JSON line.  A step is one fastmm_gemm call (scaling reductions, operand
+Default workload (the precision-form configuration): Strassen <2,2,2;7>, depth 2, cutoff 256,
+n = 16384, N(0,1) entries, outside scaling (Algorithm 1, power-of-two factors), leaves as FP16
+MFMA products with FP32 accumulation in the two-limb split form (F16X3).  Beside it in the same
+line: the classical GEMM built the same way (same precision form, same scaling, one leaf), the
+same plan on plain FP32 MFMA, and the <4,2,4;26> rule at the same depth, size, scaling and
+precision.  Prints one JSON line.  A step is one fastmm_gemm call (scaling reductions, operand
 formation, products, W-combination) on inputs already resident in HBM.  The products kernel's
 average duration comes from HIP events the library records on its launch stream.
 """
@@ -41,21 +44,24 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--algo", default="strassen")
-    ap.add_argument("--depth", type=int, default=1)
+    ap.add_argument("--depth", type=int, default=2)
     ap.add_argument("--cutoff", type=int, default=256)
-    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--precision", default="f16x3",
                     help="leaf arithmetic: f64, f32, or a split form (bf16, f16, bf16x3, f16x3, bf16x6)")
     ap.add_argument("--beside", default="f32",
                     help="also time the same plan in this precision (reported beside the headline; none = skip)")
-    ap.add_argument("--scaling", default="none")
+    ap.add_argument("--scaling", default="outside")
     ap.add_argument("--scaling-steps", type=int, default=2)
     ap.add_argument("--per-level", action="store_true",
                     help="run the scaling steps at every inner node of the recursion, not only once")
     ap.add_argument("--dist", default="normal")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--err-rows", type=int, default=16)
-    ap.add_argument("--cpu-n", type=int, default=8192, help="size of the oracle timing sample")
+    ap.add_argument("--cpu-n", type=int, default=4096,
+                    help="size of the oracle timing sample (same algorithm, depth and distribution)")
+    ap.add_argument("--also", default="f424",
+                    help="also time this rule at the same depth, size, scaling and precision (none = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classical", action="store_true")
     ap.add_argument("--fuse", default="auto", choices=["auto", "off", "always"],
@@ -144,15 +150,21 @@ def cpu_baseline_leg(args, A, B, rows):
         n = args.cpu_n
         As, Bs = make_pair(args.dist, args.seed, n, n, n, dtype=np.float64)
         alg = C.get(ORACLE_NAME[args.algo]) if args.algo in ORACLE_NAME else None
+        cutoff = min(args.cutoff, max(1, n // (2 ** args.depth)))
         t0 = time.perf_counter()
         if alg is None or args.depth == 0:
-            O.classical(As, Bs)
+            alg, depth = C.get("strassen"), 0
         else:
-            O.fast(As, Bs, alg, args.depth, min(args.cutoff, max(1, n // (2 ** args.depth))))
+            depth = args.depth
+        if args.scaling != "none":
+            O.scaled_fast(As, Bs, alg, depth, cutoff, mode=args.scaling, steps=args.scaling_steps)
+        else:
+            O.fast(As, Bs, alg, depth, cutoff)
         dt = time.perf_counter() - t0
+        sc = f", {args.scaling} scaling (power-of-two factors)" if args.scaling != "none" else ""
         out["cpu"] = {"value": 2.0 * n ** 3 / dt / 1e12, "unit": "TFLOP/s", "cores": O.num_threads(),
                       "kind": "oracle",
-                      "sample": f"oracle fast FP64 ({args.algo}, depth {args.depth}) on one {n}^3 product "
+                      "sample": f"oracle fast FP64 ({args.algo}, depth {args.depth}{sc}) on one {n}^3 product "
                                 f"of the same distribution, {dt:.2f} s; plain C classical leaves, "
                                 f"sequential summation"}
     return out
@@ -395,6 +407,28 @@ def main():
         beside = {"precision": args.beside, "path": bplan.path(m, k, n), "ms_per_step": ms_b,
                   "value": 2.0 * m * k * n / (ms_b * 1e-3) / 1e12}
 
+    also, also_rows = None, None
+    if args.also and args.also != "none" and args.also != args.algo:
+        aplan = F.Plan(args.also, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
+                       precision=args.precision, fuse=args.fuse, per_level=args.per_level)
+        aws = torch.empty(max(aplan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
+        Ca = torch.empty((m, n), dtype=tA.dtype, device="cuda")
+        run_also = lambda: F.fastmm_gemm(aplan, tA, tB, C=Ca, workspace=aws)
+        ms_a = time_steps(run_also, args.steps, args.warmup)
+        F.fastmm_profile_enable(True)
+        F.fastmm_profile_read()
+        for _ in range(args.steps):
+            run_also()
+        aprof = F.fastmm_profile_read()
+        F.fastmm_profile_enable(False)
+        acalls = max(aprof["calls"], 1)
+        also = {"algo": args.also, "path": aplan.path(m, k, n), "levels_used": aplan.shape(m, k, n)[0],
+                "ms_per_step": ms_a, "value": 2.0 * m * k * n / (ms_a * 1e-3) / 1e12,
+                "phases_ms": {"scaling": aprof["scaling_ms"] / acalls, "form": aprof["form_ms"] / acalls,
+                              "leaf": aprof["leaf_ms"] / acalls, "combine": aprof["combine_ms"] / acalls}}
+        also_rows = Ca  # sampled after the reference rows are chosen
+        del aws
+
     # timed region: K steps between device synchronisations (one GPU: no barrier needed)
     ms = time_steps(run_fast, args.steps, args.warmup)
     value = 2.0 * m * k * n / (ms * 1e-3) / 1e12
@@ -446,6 +480,11 @@ def main():
     if beside is not None:
         Cb_rows = Cb[torch.from_numpy(rows).cuda()].cpu().numpy()
         beside["error"] = float(np.max(np.abs(Cb_rows.astype(np.longdouble) - ref))) / den
+    if also is not None:
+        Ca_rows = also_rows[torch.from_numpy(rows).cuda()].cpu().numpy()
+        also["error"] = float(np.max(np.abs(Ca_rows.astype(np.longdouble) - ref))) / den
+        if classical is not None:
+            also["speedup_vs_classical"] = classical["ms_per_step"] / also["ms_per_step"]
 
     line = {
         "metric": METRIC,
@@ -465,6 +504,7 @@ def main():
                    "precision": args.precision, "scaling": args.scaling, "dist": args.dist, "path": path},
         "classical": classical,
         "beside": beside,
+        "also": also,
         "torch_matmul": torch_ref,
         "speedup_vs_classical": (classical["ms_per_step"] / ms) if classical else None,
         "error": err,

