@@ -282,6 +282,33 @@ fastmm_status fastmm_batched_workspace_size(const fastmm_plan_t *plans, const fa
 fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_problem *probs, int count,
                                   void *workspace, size_t ws_bytes, void *stream);
 
+/* ---- a multiplication that allocates nothing ---------------------------------------- */
+
+/* Bytes of the fixed scratch array behind fastmm_gemm_noalloc (256 MiB per GPU). */
+#define FASTMM_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Computes exactly what fastmm_gemm computes (same
+ * kernels, bitwise the same result), with the workspace taken from a fixed device array inside
+ * the library instead of a caller's buffer: FASTMM_NOALLOC_SCRATCH_BYTES bytes on every GPU the
+ * library runs on, held from its first use on that GPU until the process ends.  Operands as for
+ * fastmm_gemm (contiguous row-major device arrays, C must not overlap A or B); `stream` is a
+ * hipStream_t (NULL = default stream).
+ * The call itself allocates nothing and creates no HIP objects; phase timing records nothing
+ * for it.  Errors, detected before any launch:
+ *   FASTMM_EWORKSPACE    the product needs more workspace (fastmm_workspace_size) than the array
+ *                        holds; nothing is launched (call fastmm_gemm with a workspace instead);
+ *   FASTMM_EUNSUPPORTED  the plan's task tables for this shape's recursion depth are not on
+ *                        this device yet: a plan uploads them (an allocation) on its first
+ *                        fastmm_gemm / fastmm_gemm_ex call at that depth on the device, so run
+ *                        one such call with the plan and shape before using this entry point;
+ *   otherwise as fastmm_gemm.
+ * Every call on one GPU uses that GPU's one array, which keeps the last call's contents (each
+ * call clears what it needs cleared): calls that overlap in time on one GPU (different streams
+ * or threads without ordering between them) race on it and must not be issued. */
+fastmm_status fastmm_gemm_noalloc(fastmm_plan_t plan, const void *A, const void *B, void *C, int64_t m,
+                                  int64_t k, int64_t n, void *stream);
+
 /* ---- differentiation ----------------------------------------------------------------- */
 
 /* Gradients of a loss through C = A B: dA = G B^T and dB = A^T G for G = dLoss/dC (m x n),

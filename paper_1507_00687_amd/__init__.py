@@ -19,6 +19,7 @@ from .fastmm import (  # noqa: F401
     fastmm_gemm_backward,
     fastmm_gemm_batched,
     fastmm_gemm_ex,
+    fastmm_gemm_noalloc,
     fastmm_profile_enable,
     fastmm_profile_read,
     fastmm_scaling_exponents,

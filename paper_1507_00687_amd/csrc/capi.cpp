@@ -51,6 +51,12 @@ thread_local Profiler g_prof;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 namespace {
+thread_local bool g_no_alloc = false;
+}
+void set_no_alloc(bool on) { g_no_alloc = on; }
+bool no_alloc() { return g_no_alloc; }
+
+namespace {
 
 fastmm_status fail(fastmm_status st, const std::string &msg) {
     set_error(msg);
@@ -557,6 +563,10 @@ fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
         *out = it->second.get();
         return FASTMM_OK;
     }
+    if (no_alloc())
+        return fail(FASTMM_EUNSUPPORTED, "the plan's task tables for " + std::to_string(L) +
+                                             " levels are not on this device yet; one fastmm_gemm call with this "
+                                             "plan and shape on the device uploads them");
     HostTables ht;
     std::string err;
     if (!build_plan_tables(p, L, ht, err)) return fail(FASTMM_EUNSUPPORTED, err);
@@ -927,7 +937,7 @@ struct PhaseMarks {
     PhaseEvents pe{};
     hipStream_t st;
     int next = 1;
-    explicit PhaseMarks(hipStream_t s, bool record = true) : prof(g_prof.on && record), st(s) {
+    explicit PhaseMarks(hipStream_t s, bool record = true) : prof(g_prof.on && record && !no_alloc()), st(s) {
         if (!prof) return;
         for (int i = 0; i <= kPhases; ++i) pe.ev[i] = g_prof.get();
         (void)hipEventRecord(pe.ev[0], st);

@@ -41,4 +41,10 @@ Quantities quantities(const Algo &a);
 // Per-thread error message for fastmm_last_error().
 void set_error(const std::string &msg);
 
+// While set on the calling thread, the library allocates no device memory and creates no HIP
+// objects: a call that would upload a plan's task tables (its first call at a recursion depth
+// on a device) fails with FASTMM_EUNSUPPORTED instead, and phase timing records nothing.
+void set_no_alloc(bool on);
+bool no_alloc();
+
 }  // namespace fastmm

@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
         L.fastmm_plan_path.argtypes = [vp, i64, i64, i64, i32, i32, pi32]
         L.fastmm_gemm.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
         L.fastmm_gemm_ex.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64, i64, i64, i64, vp, sz, vp]
+        L.fastmm_gemm_noalloc.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp]
         L.fastmm_scaling_exponents.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp, vp, sz, vp]
         L.fastmm_task_table.argtypes = [vp, i32, pi64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.fastmm_batched_workspace_size.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Problem), i32,
@@ -99,7 +100,8 @@ def lib() -> ctypes.CDLL:
                      "fastmm_gemm_ex", "fastmm_scaling_exponents", "fastmm_profile_enable", "fastmm_profile_read", "fastmm_task_table",
                      "fastmm_backward_workspace_size", "fastmm_gemm_backward", "fastmm_batched_workspace_size",
                      "fastmm_gemm_batched", "fastmm_plan_set_fusion", "fastmm_plan_path", "fastmm_plan_set_tree",
-                     "fastmm_algo_stability", "fastmm_plan_set_levels", "fastmm_plan_set_tile"):
+                     "fastmm_algo_stability", "fastmm_plan_set_levels", "fastmm_plan_set_tile",
+                     "fastmm_gemm_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -277,6 +279,25 @@ def fastmm_gemm(plan: Plan, A, B, C=None, workspace=None, stream=None):
     ws, need = _workspace(plan, m, k, n, A.device, workspace)
     _check(lib().fastmm_gemm(plan.handle, A.data_ptr(), B.data_ptr(), C.data_ptr(), m, k, n, ws.data_ptr(),
                              ws.numel(), _stream_ptr(stream)))
+    return C
+
+
+def fastmm_gemm_noalloc(plan: Plan, A, B, C, stream=None):
+    """C = A @ B with the library's fixed scratch array as workspace (no device allocation in
+    the call; C must be given).  The plan needs one earlier fastmm_gemm call at this shape on
+    the device (which uploads its task tables)."""
+    m, k = A.shape
+    k2, n = B.shape
+    if k != k2:
+        raise ValueError("inner dimensions differ")
+    if A.dtype != plan.dtype or B.dtype != plan.dtype or C.dtype != plan.dtype:
+        raise TypeError(f"plan precision {plan.precision} takes {plan.dtype} operands")
+    if not (A.is_cuda and B.is_cuda and C.is_cuda):
+        raise ValueError("operands must be on the GPU")
+    if not (A.is_contiguous() and B.is_contiguous() and C.is_contiguous()) or tuple(C.shape) != (m, n):
+        raise ValueError("contiguous operands and an m x n C are required")
+    _check(lib().fastmm_gemm_noalloc(plan.handle, A.data_ptr(), B.data_ptr(), C.data_ptr(), m, k, n,
+                                     _stream_ptr(stream)))
     return C
 
 
