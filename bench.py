@@ -108,7 +108,7 @@ def product_kernel(precision: str, path: str):
     """(kernel name, source file) of the launch that computes the products."""
     if path == "fused":
         return "fmm_node222", "node_fused.hip"
-    if precision in ("f64", "f32"):
+    if precision in ("f64", "f32"):  # leaf and written paths
         return "fmm_leaf_pipelined", "leaf_mfma.hip"
     return "fmm_limb_gemm", "limb_gemm.hip"
 
@@ -201,7 +201,7 @@ def batch_main(args):
     Cs = [torch.empty((m, n), dtype=dt, device="cuda") for m, k, n in shapes]
     t0 = time.perf_counter()
     choices = T.tune(shapes, precision=args.precision, cache=args.tune_cache or None, max_depth=2,
-                     cutoffs=(256,), max_instability=args.max_instability, reps=2)
+                     cutoffs=(128, 256, 512), max_instability=args.max_instability, reps=2)
     tune_s = time.perf_counter() - t0
     plans = [choices[sh].plan(args.precision) for sh in shapes]
     cplans = [F.Plan("classical", 0, 1, precision=args.precision) for _ in shapes]

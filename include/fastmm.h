@@ -163,16 +163,23 @@ typedef enum {
     FASTMM_PATH_FUSED = 1, /* the innermost level fused: each work-group forms S_r, T_r, the R
                               products and the W-sums of eq. (1) for one tile of a node of the
                               recursion; the outer L-1 levels as in the leaf path */
-    FASTMM_PATH_EVERY_LEVEL = 2 /* scaling at every level (fastmm_scaling.per_level, depth >= 2):
+    FASTMM_PATH_EVERY_LEVEL = 2, /* scaling at every level (fastmm_scaling.per_level, depth >= 2):
                               the first level's node operands written out, each node product
                               by a call of the remaining levels, then the W-combination */
+    FASTMM_PATH_WRITTEN = 3 /* FP64 / FP32 from depth 2 with a high fan-in (average sources per
+                              leaf operand, (nnz(U)/R)^L and (nnz(V)/R)^L, above 4): every leaf
+                              operand S_r, T_r written out level by level (eq. (1) applied once
+                              per level), one launch over the written-out leaves, then the
+                              W-combination */
 } fastmm_path;
 
 /* Fusion modes (fastmm_plan_set_fusion). */
 typedef enum {
-    FASTMM_FUSE_OFF = 0,    /* always the leaf path */
+    FASTMM_FUSE_OFF = 0,    /* always the leaf path with composite source lists (neither the
+                               fused kernel nor written-out leaf operands) */
     FASTMM_FUSE_AUTO = 1,   /* the default: the fused path where it applies and is the faster one
-                               (FP32 from depth 1, FP64 from depth 2) */
+                               (FP32 from depth 1, FP64 from depth 2), else written-out leaf
+                               operands where FASTMM_PATH_WRITTEN applies, else the leaf path */
     FASTMM_FUSE_ALWAYS = 2  /* the fused path wherever it applies */
 } fastmm_fusion;
 

@@ -79,6 +79,10 @@ struct Tables {
     BlockDests *bdest = nullptr;
     float *ucoef = nullptr, *vcoef = nullptr;  // the rule's U (M0K0 x R) and V (K0N0 x R), row-major
     DestEntry *dest = nullptr;
+    // Leaf r's operands written out as block r of a stacked operand: one source each, (r, 0)
+    // with coefficient 1 (the FP64 / FP32 paths with written-out leaf operands).
+    LeafEntry *wleaves = nullptr;
+    SrcEntry *wsrc = nullptr;
     int device = -1;
     ~Tables() {
         if (device >= 0) {
@@ -92,6 +96,8 @@ struct Tables {
             (void)hipFree(dest);
             (void)hipFree(ucoef);
             (void)hipFree(vcoef);
+            (void)hipFree(wleaves);
+            (void)hipFree(wsrc);
             (void)hipSetDevice(cur);
         }
     }
@@ -434,6 +440,7 @@ struct InnerLevel {
 };
 std::vector<InnerLevel> inner_levels(const fastmm_plan_s *p, const Shape &s, bool side_b) {
     const Algo &a = plan_algo(p);
+    const size_t es = p->prec == FASTMM_F64 ? 8 : 4;
     const int nO = side_b ? a.N0 : a.M0, nK = a.K0;
     const int64_t O = side_b ? s.Np : s.Mp, K = s.Kp;
     std::vector<InnerLevel> v;
@@ -444,7 +451,7 @@ std::vector<InnerLevel> inner_levels(const fastmm_plan_s *p, const Shape &s, boo
         InnerLevel e;
         e.cb_o = O / po, e.cb_k = K / pk, e.y_ld = (e.cb_k + 7) / 8 * 8, e.y_stride = e.cb_o * e.y_ld;
         e.count = count, e.off = off;
-        off = align256(off + 4 * (size_t)count * e.y_stride);
+        off = align256(off + es * (size_t)count * e.y_stride);
         v.push_back(e);
     }
     v.push_back(InnerLevel{0, 0, 0, 0, 0, off});
@@ -455,8 +462,38 @@ std::vector<InnerLevel> inner_levels(const fastmm_plan_s *p, const Shape &s, boo
 // split precisions: [S limb planes][T^T limb planes] 16-bit | [leaf products nleaves * mb * nb]
 // elems.
 struct WsLayout {
-    size_t ea, ep, eb, flags, maxA, maxB, sp, tp, ia, ib, leaves, total;
+    size_t ea, ep, eb, flags, maxA, maxB, sp, tp, ia, ib, xa, xb, leaves, total;
 };
+
+// FP64 / FP32 with a high fan-in: every leaf operand S_r (mb x kb) and T_r (kb x nb) is
+// written out level by level, stacked (leaf r's S_r at rows r mb .. of an R^L mb x xa_ld
+// matrix, T_r likewise at rows r kb of an R^L kb x xb_ld matrix, row strides multiples of 8),
+// and the leaf kernel multiplies the stacked blocks, one source each.  The composite lists
+// would have every work-group re-read (nnz(U)/R)^L source tiles per K stage, ~11 for
+// <4,2,4;26> at depth 2.  Needs every product live (the leaves are then the R^L children, in
+// the composite order) and one rule at every node.
+double plan_fan_in(const fastmm_plan_s *p, int L) {
+    const Algo &a = plan_algo(p);
+    int64_t nu = 0, nv = 0;
+    for (int64_t x : a.U) nu += x != 0;
+    for (int64_t x : a.V) nv += x != 0;
+    return 0.5 * (std::pow((double)nu / a.R, L) + std::pow((double)nv / a.R, L));
+}
+
+bool written_leaves(const fastmm_plan_s *p, const Shape &s) {
+    if (is_split(p->prec) || s.L < 2 || !p->tree.empty() || !p->levels.empty()) return false;
+    if (p->fuse == FASTMM_FUSE_OFF) return false;  // the composite-list leaf path only
+    const Algo &a = plan_algo(p);
+    int64_t all = 1;
+    for (int l = 0; l < s.L; ++l) all *= a.R;
+    if (leaf_count(a, s.L) != all || a.M0 * a.K0 > 16 || a.K0 * a.N0 > 16) return false;
+    return plan_fan_in(p, s.L) > 4.0;
+}
+
+struct WrittenDims {
+    int64_t xa_ld, xb_ld;
+};
+WrittenDims written_dims(const Shape &s) { return WrittenDims{round_up(s.kb, 8), round_up(s.nb, 8)}; }
 
 // The scaling part of a workspace (exponents, flags, maxima); returns its end.
 size_t scaling_layout(const fastmm_plan_s *p, int64_t m, int64_t k, int64_t n, WsLayout &w) {
@@ -486,6 +523,13 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
             w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
             w.ib = off, off = align256(off + inner_levels(p, s, true).back().off);
         }
+    } else if (written_leaves(p, s)) {
+        const WrittenDims wd = written_dims(s);
+        const size_t nleaves = (size_t)plan_leaf_count(p, s.L);
+        w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
+        w.ib = off, off = align256(off + inner_levels(p, s, true).back().off);
+        w.xa = off, off = align256(off + es * nleaves * (size_t)s.mb * wd.xa_ld);
+        w.xb = off, off = align256(off + es * nleaves * (size_t)s.kb * wd.xb_ld);
     }
     w.leaves = off;
     if (s.L > 0) off = align256(off + es * (size_t)plan_leaf_count(p, s.L) * s.mb * s.nb);
@@ -588,6 +632,13 @@ fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
             for (int r = 0; r < a.R; ++r) v[(size_t)j * a.R + r] = (float)a.v(j, r);
         if ((e = upload(&t->ucoef, u)) != hipSuccess || (e = upload(&t->vcoef, v)) != hipSuccess)
             return hip_fail(e, "uploading coefficients");
+    }
+    {
+        std::vector<LeafEntry> wl((size_t)t->nleaves);
+        std::vector<SrcEntry> ws((size_t)t->nleaves);
+        for (int r = 0; r < t->nleaves; ++r) wl[(size_t)r] = LeafEntry{r, 1, r, 1}, ws[(size_t)r] = SrcEntry{r, 0, 1.f, 0};
+        if ((e = upload(&t->wleaves, wl)) != hipSuccess || (e = upload(&t->wsrc, ws)) != hipSuccess)
+            return hip_fail(e, "uploading tables");
     }
     *out = t.get();
     p->tables[key] = std::move(t);
@@ -912,6 +963,7 @@ fastmm_status fastmm_plan_path(fastmm_plan_t plan, int64_t m, int64_t k, int64_t
     uint32_t masks[6];
     *path = every_level(plan, s)                         ? FASTMM_PATH_EVERY_LEVEL
             : fused_path(plan, s, transA, transB, masks) ? FASTMM_PATH_FUSED
+            : written_leaves(plan, s)                    ? FASTMM_PATH_WRITTEN
                                                          : FASTMM_PATH_LEAF;
     return FASTMM_OK;
 }
@@ -1030,6 +1082,60 @@ hipError_t split_form(fastmm_plan_s *plan, const Shape &s, const SplitDims &d, c
     g.mb = s.mb, g.nb = s.nb, g.m = m, g.n = n, g.sc = exps, g.post_exp = -2 * pre;
     g.tiles_m = (int)(d.mbp / d.bm), g.tiles_n = (int)(d.nbp / d.bm);
     return hipSuccess;
+}
+
+// FP64 / FP32 with written-out leaf operands: the leaf operands of both sides level by level
+// (the first level scaled), S_r stacked at ws + xa (o-major), T_r at ws + xb (k-major, B's own
+// orientation), so that the leaf kernel reads each as one row-major source block.
+hipError_t form_written(fastmm_plan_s *plan, const Shape &s, const void *A, int64_t lda, int transA, const void *B,
+                        int64_t ldb, int transB, int64_t m, int64_t k, int64_t n, const ScaleExps &exps, char *ws,
+                        const WsLayout &w, const Tables *tab, hipStream_t st) {
+    const Algo &al = plan_algo(plan);
+    const WrittenDims wd = written_dims(s);
+    auto form_side = [&](bool side_b) -> hipError_t {
+        const std::vector<InnerLevel> lv = inner_levels(plan, s, side_b);
+        char *ibase = ws + (side_b ? w.ib : w.ia);
+        int64_t nodes = 1;
+        for (int l = 1; l <= s.L; ++l) {
+            NodeForm nf{};
+            if (l == 1) {
+                if (side_b) {
+                    nf.X = B, nf.ld_o = transB ? ldb : 1, nf.ld_k = transB ? 1 : ldb, nf.R = n;
+                    nf.e_o = exps.eb, nf.s_o = -1, nf.s_k = -1;  // 2^(-ep_kk - eb_j)
+                } else {
+                    nf.X = A, nf.ld_o = transA ? 1 : lda, nf.ld_k = transA ? lda : 1, nf.R = m;
+                    nf.e_o = exps.ea, nf.s_o = -1, nf.s_k = 1;  // 2^(ep_kk - ea_i)
+                }
+                nf.K = k, nf.first = 1, nf.e_k = exps.ep, nf.pre_exp = 0;
+            } else {
+                const InnerLevel &in = lv[l - 2];
+                nf.X = ibase + in.off, nf.ld_o = in.y_ld, nf.ld_k = 1;
+                nf.node_stride = in.y_stride, nf.first = 0;
+            }
+            nf.nO = side_b ? al.N0 : al.M0, nf.nK = al.K0, nf.side_b = side_b ? 1 : 0, nf.R_ = al.R;
+            nf.coef = side_b ? tab->vcoef : tab->ucoef;
+            nf.last = 0;
+            if (l == s.L) {
+                nf.cb_o = side_b ? s.nb : s.mb, nf.cb_k = s.kb;
+                if (side_b) {
+                    nf.Y = ws + w.xb, nf.y_ld = wd.xb_ld, nf.y_stride = s.kb * wd.xb_ld, nf.kmajor = 1;
+                } else {
+                    nf.Y = ws + w.xa, nf.y_ld = wd.xa_ld, nf.y_stride = s.mb * wd.xa_ld;
+                }
+            } else {
+                const InnerLevel &out = lv[l - 1];
+                nf.cb_o = out.cb_o, nf.cb_k = out.cb_k;
+                nf.Y = ibase + out.off, nf.y_ld = out.y_ld, nf.y_stride = out.y_stride;
+            }
+            if (nodes > 65535) return hipErrorInvalidValue;
+            hipError_t er = launch_form_node(plan->prec, nf, (int)nodes, st);
+            if (er != hipSuccess) return er;
+            nodes *= al.R;
+        }
+        return hipSuccess;
+    };
+    hipError_t e = form_side(false);
+    return e != hipSuccess ? e : form_side(true);
 }
 
 // ---- scaling at every level
@@ -1232,9 +1338,40 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
         return FASTMM_OK;
     }
-    fin.mark();  // no operand formation pass on the FP64 / FP32 paths
     uint32_t masks[6];
-    if (fused_path(plan, s, transA, transB, masks)) {
+    const bool fused = fused_path(plan, s, transA, transB, masks);
+    if (!fused && written_leaves(plan, s)) {
+        // leaf operands written out level by level, then one launch over the stacked blocks
+        // (one source per leaf, unscaled: the formation applied the factors), then the
+        // W-combination with D_A, D_B
+        if ((e = form_written(plan, s, A, lda, transA, B, ldb, transB, m, k, n, exps, ws, w, tab, st)) != hipSuccess)
+            return hip_fail(e, "leaf operand formation");
+        fin.mark();
+        const WrittenDims wd = written_dims(s);
+        LeafLaunch X = L;
+        X.A = ws + w.xa, X.lda = wd.xa_ld, X.transA = 0;
+        X.B = ws + w.xb, X.ldb = wd.xb_ld, X.transB = 0;
+        X.m = (int64_t)tab->nleaves * s.mb, X.k = (int64_t)tab->nleaves * s.kb, X.n = s.nb;
+        X.leaves = tab->wleaves, X.asrc = tab->wsrc, X.bsrc = tab->wsrc;
+        X.sc = ScaleExps{nullptr, nullptr, nullptr};
+        X.out = ws + w.leaves, X.ldo = s.nb, X.leaf_stride = s.mb * s.nb, X.direct = 0;
+        e = launch_leaf(X, st);
+        fin.mark();
+        if (e != hipSuccess) return hip_fail(e, "leaf kernel");
+        CombineLaunch Cb;
+        Cb.elem = el;
+        Cb.M = ws + w.leaves;
+        Cb.leaf_stride = s.mb * s.nb;
+        Cb.C = C, Cb.ldc = ldc, Cb.m = m, Cb.n = n, Cb.mb = s.mb, Cb.nb = s.nb;
+        Cb.NB = tab->NB;
+        Cb.bdest = tab->bdest, Cb.dest = tab->dest;
+        Cb.sc = exps;
+        set_kron(plan, s.L, tab->nleaves, Cb);
+        if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
+        return FASTMM_OK;
+    }
+    fin.mark();  // no operand formation pass on the other FP64 / FP32 paths
+    if (fused) {
         // The innermost level runs fused; the L-1 outer levels supply the node operands and,
         // for L >= 2, the W-combination of the node products.
         Tables *outer = nullptr;

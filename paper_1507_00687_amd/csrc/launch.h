@@ -164,18 +164,20 @@ struct LimbGemm {
     int tiles_m, tiles_n;
     int direct;
 };
-// Split precisions, pass 1 level by level: one recursion level of the operand formation.  The
+// Operand formation level by level (split precisions; written-out leaf operands of the FP64 /
+// FP32 paths): one recursion level.  Elements are double for FP64, float otherwise.  The
 // node operand of node q is op(X) itself on the first level (element (o, kk) at
 // X[o * ld_o + kk * ld_k], zero outside R x K, scaled by 2^(s_o e_o[o] + s_k e_k[kk] + pre_exp)
-// when e_o is not null) or, below it, the FP32 block X + q * node_stride (element (o, kk) at
+// when e_o is not null) or, below it, the block X + q * node_stride (element (o, kk) at
 // o * ld_o + kk).  It has nO x nK sub-blocks of cb_o x cb_k; sub-block s sits at o-block
 // (side_b ? s / nK : s % nO) and k-block (side_b ? s % nK : s / nO) (eq. (1): A and B blocks
 // column-major).  Child c = sum_s coef[s * R_ + c] X_s of node q gets index q * R_ + c and is
 // written either as limb planes (last: same layout as PlaneForm, rowsp x kp, blocked by bt) or as
-// an FP32 block Y + index * y_stride with row stride y_ld (a multiple of 8, >= cb_k; columns
-// cb_k .. y_ld-1 written as zeros).
+// a block Y + index * y_stride: o-major with row stride y_ld (a multiple of 8, >= cb_k; columns
+// cb_k .. y_ld-1 written as zeros) or, with kmajor, k-major (cb_k rows of y_ld >= cb_o, a
+// multiple of 8; columns cb_o .. y_ld-1 written as zeros).
 struct NodeForm {
-    const float *X;
+    const void *X;  // float (split precisions, FP32) or double (FP64) elements
     int64_t ld_o, ld_k, R, K;
     int64_t node_stride;
     int first;
@@ -185,8 +187,9 @@ struct NodeForm {
     const int32_t *e_o, *e_k;
     int s_o, s_k, pre_exp;
     int last;
-    float *Y;
+    void *Y;
     int64_t y_stride, y_ld;
+    int kmajor;  // FP blocks written k-major (element (o, kk) at kk * y_ld + o; y_ld a multiple of 8)
     unsigned short *planes;
     int64_t rowsp, kp, bt, plane_stride, leaf_stride;
     int nl, half;  // set by launch_form_node from the precision

@@ -131,25 +131,30 @@ __global__ __launch_bounds__(256) void form_planes(PlaneForm a) {
 }
 
 // ------------------------------------------------------------------ pass 1, all leaves at once
-// The same limb planes, with every source element read from HBM once: a work-group takes one
-// 64 x 64 tile position inside the leaf blocks, loads that tile of every block of op(X) (the
-// nbo x nbk leaf-block grid) into registers, then forms each leaf's S_r from them in turn.
-// A leaf's coefficients sit in a dense leaves x blocks table in LDS (zero where a block is not
-// one of its sources); blocks are summed in the order of the rule's single block index at
-// depth 1 (column-major for A, row-major over (n-block, k-block) for B), which is the order of
-// the source lists there.  EPT elements per thread and block; at most 64 / EPT blocks.  The
-// table takes nleaves x blocks floats of dynamic LDS (sized per launch, so that small tables
-// leave the occupancy of a streaming kernel).
-constexpr int kAllMaxCoef = 4096;  // leaves x blocks entries of the coefficient table
+constexpr int kAllMaxCoef = 4096;  // leaves x blocks entries of the coefficient table (dynamic LDS)
 
-template <bool HALF, int NL, bool SCALED, bool KCONTIG, int EPT>
-__global__ __launch_bounds__(4096 / EPT) void form_all(PlaneForm a, int nleaves) {
-    constexpr int NT = 4096 / EPT, NB = 64 / EPT, RP = NT / 64;
-    __shared__ float tile[kFT][kFT + 1];
-    extern __shared__ float coef[];  // nleaves x nblk
+// The limb planes of every leaf with every source element read from HBM once: a work-group
+// takes one TR x 64 tile position inside the leaf blocks; each thread owns one 8-element k chunk
+// there (eight consecutive k of one plane row, i.e. 16 bytes of every limb plane), holds that
+// chunk of every block of op(X) (the nbo x nbk leaf-block grid, NB >= blocks) in registers, and
+// for each leaf sums the leaf's blocks with its coefficients (a dense leaves x blocks table in
+// LDS, zero where a block is not one of its sources), splits and writes its 16-byte limb chunks
+// directly, with no LDS round trip and no barrier per leaf.  Blocks are summed in the order of
+// the rule's single block index at depth 1 (column-major for A, row-major over (n-block,
+// k-block) for B), which is the order of the source lists there.  Thread layout: k-contiguous
+// operands (KCONTIG): eight consecutive lanes take the eight chunks of one row; otherwise (B, n
+// contiguous) lanes 4i + c take rows i of a 16-row group and chunks c of a 32-k piece, so loads
+// read 64-byte row segments and each wave writes 16 whole 64-byte rows of one plane piece.
+// Two-wave work-groups (TR = 16) let several run per CU out of phase (one loading while
+// another writes); a 512-thread version with one 64 x 64 tile per work-group, and the earlier
+// LDS-transposing version with a barrier per leaf, both ran 5 % slower.
+template <bool HALF, int NL, bool SCALED, bool KCONTIG, int NB, int TR>
+__global__ __launch_bounds__(TR * 8) void form_regs(PlaneForm a, int nleaves) {
+    constexpr int NT = TR * 8;
+    extern __shared__ float rcoef[];  // nleaves x nblk
     const int t = threadIdx.x;
     const int nbo = a.nbo, nbk = a.nbk, nblk = nbo * nbk;
-    for (int i = t; i < nleaves * nblk; i += NT) coef[i] = 0.f;
+    for (int i = t; i < nleaves * nblk; i += NT) rcoef[i] = 0.f;
     __syncthreads();
     for (int leaf = t; leaf < nleaves; leaf += NT) {
         const LeafEntry le = a.leaves[leaf];
@@ -157,99 +162,89 @@ __global__ __launch_bounds__(4096 / EPT) void form_all(PlaneForm a, int nleaves)
         for (int q = 0; q < count; ++q) {
             const SrcEntry se = a.src[begin + q];
             const int bo = a.b_side ? se.bc : se.br, bk = a.b_side ? se.br : se.bc;
-            coef[leaf * nblk + (a.b_side ? bo * nbk + bk : bk * nbo + bo)] += se.coef;
+            rcoef[leaf * nblk + (a.b_side ? bo * nbk + bk : bk * nbo + bo)] += se.coef;
         }
     }
-    const int64_t o0 = (int64_t)blockIdx.y * kFT, k0 = (int64_t)blockIdx.x * kFT;
-    // scaling exponents of the work-group's rows and columns in every block (staged in LDS)
-    __shared__ int32_t eo_s[SCALED ? NB * kFT : 1], ek_s[SCALED ? NB * kFT : 1];
-    if (SCALED) {
-        for (int i = t; i < nbo * kFT; i += NT) {
-            const int64_t ob = o0 + i % kFT, o = (i / kFT) * a.rb + ob;
-            eo_s[i] = (ob < a.rb && o < a.R) ? a.s_o * a.e_o[o] + a.pre_exp : 0;
-        }
-        for (int i = t; i < nbk * kFT; i += NT) {
-            const int64_t kb = k0 + i % kFT, kk = (i / kFT) * a.kb + kb;
-            ek_s[i] = (kb < a.kb && kk < a.K) ? a.s_k * a.e_k[kk] : 0;
-        }
+    static_assert(TR % 16 == 0 && TR <= 64, "tile rows");
+    int ol, kc;  // the thread's row and 8-wide k chunk in the TR x 64 tile
+    if (KCONTIG) {
+        ol = t >> 3, kc = t & 7;
+    } else {
+        const int wave = t >> 6, lane = t & 63;
+        ol = (lane >> 2) + 16 * (wave % (TR / 16)), kc = (lane & 3) + 4 * (wave / (TR / 16));
     }
-    __syncthreads();  // coefficient table and exponents complete
-    int lo[EPT], lk[EPT];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        if (KCONTIG) lo[e] = e * RP + t / 64, lk[e] = t % 64;
-        else lk[e] = e * RP + t / 64, lo[e] = t % 64;
-    }
-    float x[NB][EPT];
+    // work-group (row tile x, k tile y): consecutive work-groups take consecutive TR-row slices
+    // of the same 32-k plane pieces, so the work-groups in flight write whole pieces together
+    const int64_t ob = (int64_t)blockIdx.x * TR + ol, kb0 = (int64_t)blockIdx.y * 64 + 8 * kc;  // in the leaf block
+    const bool vec = KCONTIG && (a.ld_o & 3) == 0 && ((uintptr_t)a.X & 15) == 0;
+    float x[NB][8];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int bo = a.b_side ? b / nbk : b % nbo, bk = a.b_side ? b % nbk : b / nbo;
+        const int64_t o = (int64_t)bo * a.rb + ob, kk0 = (int64_t)bk * a.kb + kb0;  // in op(X)
+        const bool row_ok = b < nblk && ob < a.rb && o < a.R;
+        if (vec && row_ok && kb0 + 8 <= a.kb && kk0 + 8 <= a.K) {
+            const float4 *p = reinterpret_cast<const float4 *>(a.X + o * a.ld_o + kk0);
+            const float4 u = p[0], w = p[1];
+            x[b][0] = u.x, x[b][1] = u.y, x[b][2] = u.z, x[b][3] = u.w;
+            x[b][4] = w.x, x[b][5] = w.y, x[b][6] = w.z, x[b][7] = w.w;
+        } else {
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int64_t ob = o0 + lo[e], kb = k0 + lk[e];  // inside the leaf block
-            const int64_t o = bo * a.rb + ob, kk = bk * a.kb + kb;  // inside op(X)
-            const bool ok = b < nblk && ob < a.rb && kb < a.kb && o < a.R && kk < a.K;
-            const float y = *(ok ? a.X + o * a.ld_o + kk * a.ld_k : a.X);
-            float v = ok ? y : 0.f;
-            x[b][e] = v;
+            for (int j = 0; j < 8; ++j) {
+                const bool ok = row_ok && kb0 + j < a.kb && kk0 + j < a.K;
+                const float y = *(ok ? a.X + o * a.ld_o + (kk0 + j) * a.ld_k : a.X);
+                x[b][j] = ok ? y : 0.f;
+            }
         }
-    }
-    if (SCALED) {  // once per element, not once per leaf that uses it (exact: powers of two)
+        if (SCALED && row_ok) {  // once per element, not once per leaf that uses it (exact: powers of two)
+            const int eo = a.s_o * a.e_o[o] + a.pre_exp;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int bo = a.b_side ? b / nbk : b % nbo, bk = a.b_side ? b % nbk : b / nbo;
-            if (b < nblk) {
-#pragma unroll
-                for (int e = 0; e < EPT; ++e) x[b][e] = ldexpf(x[b][e], eo_s[bo * kFT + lo[e]] + ek_s[bk * kFT + lk[e]]);
+            for (int j = 0; j < 8; ++j) {
+                const int64_t kk = kk0 + j;
+                const int ek = (kb0 + j < a.kb && kk < a.K) ? a.s_k * a.e_k[kk] : 0;
+                x[b][j] = ldexpf(x[b][j], eo + ek);
             }
         }
     }
+    __syncthreads();  // coefficient table complete
+    const int64_t o = ob, kk = kb0;  // plane row and k
+    unsigned short *dst0 =
+        a.planes + ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 + kk % 32;
     for (int leaf = 0; leaf < nleaves; ++leaf) {
-        float v[EPT];
+        float v[8];
         bool first = true;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const float c = b < nblk ? coef[leaf * nblk + b] : 0.f;
+            const float c = b < nblk ? rcoef[leaf * nblk + b] : 0.f;
             if (c != 0.f) {
 #pragma unroll
-                for (int e = 0; e < EPT; ++e) v[e] = first ? c * x[b][e] : v[e] + c * x[b][e];
+                for (int j = 0; j < 8; ++j) v[j] = first ? c * x[b][j] : v[j] + c * x[b][j];
                 first = false;
             }
         }
         if (first) {
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) v[e] = 0.f;
+            for (int j = 0; j < 8; ++j) v[j] = 0.f;
         }
-        if (leaf > 0) __syncthreads();  // the previous leaf's chunks have been read
+        unsigned short h[NL][8];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) tile[lo[e]][lk[e]] = v[e];
-        __syncthreads();
-        // 64 rows x 8 chunks of 8 k: split and write 16 bytes per limb
-        for (int cidx = t; cidx < kFT * 8; cidx += NT) {
-            const int ro = cidx / 8, rk = (cidx % 8) * 8;
-            unsigned short h[NL][8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                float r = tile[ro][rk + j];
-#pragma unroll
-                for (int l = 0; l < NL; ++l) {
-                    float back;
-                    h[l][j] = LimbT<HALF>::split(r, back);
-                    r = r - back;
-                }
-            }
+        for (int j = 0; j < 8; ++j) {
+            float r = v[j];
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
-                uint4 w;
-                w.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
-                w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
-                w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
-                w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
-                const int64_t o = o0 + ro, kk = k0 + rk;
-                *reinterpret_cast<uint4 *>(a.planes + (int64_t)leaf * a.leaf_stride + l * a.plane_stride +
-                                           ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 +
-                                           kk % 32) = w;
+                float back;
+                h[l][j] = LimbT<HALF>::split(r, back);
+                r = r - back;
             }
+        }
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            uint4 w;
+            w.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
+            w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
+            w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
+            w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
+            *reinterpret_cast<uint4 *>(dst0 + (int64_t)leaf * a.leaf_stride + l * a.plane_stride) = w;
         }
     }
 }
@@ -257,20 +252,24 @@ __global__ __launch_bounds__(4096 / EPT) void form_all(PlaneForm a, int nleaves)
 // ------------------------------------------------------------------ pass 1, level by level
 // One recursion level of the operand formation for a node operand X (eq. (1)): the node's nS
 // sub-blocks X_s are read once and all R children C_c = sum_s coef[s][c] X_s are written, as
-// FP32 blocks (inner levels) or as limb planes (last level).  Each work-group handles a TO x 64
-// tile position (o, kk) of the child blocks: it stages the nS sub-block tiles in LDS, then forms
-// every child tile from them.  Children of node q are numbered q R + c, the order of the
-// composite leaves (first level most significant).
-template <int TO>
+// blocks of the element type T (inner levels, and every level of the FP64 / FP32 paths) or as
+// limb planes (last level of the split precisions, T = float).  Each work-group handles a
+// TO x 64 tile position (o, kk) of the child blocks: it stages the nS sub-block tiles in LDS,
+// then forms every child tile from them.  Children of node q are numbered q R + c, the order of
+// the composite leaves (first level most significant).  Blocks are written o-major (element
+// (o, kk) at o * y_ld + kk) or, with kmajor, k-major (element (o, kk) at kk * y_ld + o: a
+// B-side operand written back in its own row-major k x n orientation).
+template <typename T, int TO>
 __global__ __launch_bounds__(256) void form_node(NodeForm a) {
-    extern __shared__ float ntile[];  // [nS][TO][65], then the nS x R_ coefficients
+    extern __shared__ __attribute__((aligned(16))) unsigned char node_lds[];
+    T *ntile = reinterpret_cast<T *>(node_lds);  // [nS][TO][65], then the nS x R_ coefficients
     const int t = threadIdx.x;
     const int q = blockIdx.z;
     const int64_t o0 = (int64_t)blockIdx.y * TO, k0 = (int64_t)blockIdx.x * 64;
     const int nS = a.nO * a.nK;
     const bool kc = a.ld_k == 1;
-    const float *X = a.X + (a.first ? 0 : (int64_t)q * a.node_stride);
-    float *coef = ntile + nS * TO * 65;
+    const T *X = reinterpret_cast<const T *>(a.X) + (a.first ? 0 : (int64_t)q * a.node_stride);
+    float *coef = reinterpret_cast<float *>(ntile + nS * TO * 65);
     for (int i = t; i < nS * a.R_; i += 256) coef[i] = a.coef[i];
     for (int sb = 0; sb < nS; ++sb) {
         const int ob = a.side_b ? sb / a.nK : sb % a.nO, kbk = a.side_b ? sb % a.nK : sb / a.nO;
@@ -281,13 +280,49 @@ __global__ __launch_bounds__(256) void form_node(NodeForm a) {
             const int64_t o = ob * a.cb_o + oc, kk = kbk * a.cb_k + kcn;  // inside the node operand
             bool ok = oc < a.cb_o && kcn < a.cb_k;
             if (a.first) ok = ok && o < a.R && kk < a.K;
-            const float y = *(ok ? X + o * a.ld_o + kk * a.ld_k : X);
-            float x = ok ? y : 0.f;
-            if (a.first && a.e_o) x = ldexpf(x, a.s_o * a.e_o[ok ? o : 0] + a.s_k * a.e_k[ok ? kk : 0] + a.pre_exp);
+            const T y = *(ok ? X + o * a.ld_o + kk * a.ld_k : X);
+            T x = ok ? y : T(0);
+            if (a.first && a.e_o) x = ldexp(x, a.s_o * a.e_o[ok ? o : 0] + a.s_k * a.e_k[ok ? kk : 0] + a.pre_exp);
             ntile[(sb * TO + lo) * 65 + lk] = x;
         }
     }
     __syncthreads();
+    T *Y = reinterpret_cast<T *>(a.Y);
+    if (!a.last && a.kmajor) {
+        // (child, k row, 8-wide o chunk): eight consecutive o of one k row per thread, read down
+        // a column of the staged tiles (row stride 65: distinct banks)
+        constexpr int OC = TO / 8;
+        for (int w = t; w < a.R_ * 64 * OC; w += 256) {
+            const int c = w / (64 * OC), task = w - c * (64 * OC);
+            const int rk = task / OC, ro = (task % OC) * 8;
+            T v[8];
+            bool first = true;
+            for (int sb = 0; sb < nS; ++sb) {
+                const float u = coef[sb * a.R_ + c];
+                if (u == 0.f) continue;
+                const T *src = &ntile[(sb * TO + ro) * 65 + rk];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = first ? (T)u * src[j * 65] : v[j] + (T)u * src[j * 65];
+                first = false;
+            }
+            if (first) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = T(0);
+            }
+            const int64_t child = (int64_t)q * a.R_ + c, o = o0 + ro, kk = k0 + rk;
+            if (kk < a.cb_k && o < a.y_ld) {
+                T *dst = Y + child * a.y_stride + kk * a.y_ld + o;
+                if constexpr (sizeof(T) == 4) {
+                    *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                    *reinterpret_cast<float4 *>(dst + 4) = make_float4(v[4], v[5], v[6], v[7]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 8; j += 2) *reinterpret_cast<double2 *>(dst + j) = make_double2(v[j], v[j + 1]);
+                }
+            }
+        }
+        return;
+    }
     // (child, task) pairs flattened, so that every thread has work when TO x 8 < 256
     for (int w = t; w < a.R_ * TO * 8; w += 256) {
         const int c = w / (TO * 8), task = w - c * (TO * 8);
@@ -296,49 +331,58 @@ __global__ __launch_bounds__(256) void form_node(NodeForm a) {
         // a piece are adjacent).  The LDS row stride of 65 words keeps the reads at most
         // two-way bank conflicted.
         const int ro = task / 8, rk = (task % 8) * 8;
-        float v[8];
+        T v[8];
         bool first = true;
         for (int sb = 0; sb < nS; ++sb) {
             const float u = coef[sb * a.R_ + c];
             if (u == 0.f) continue;
-            const float *src = &ntile[(sb * TO + ro) * 65 + rk];
+            const T *src = &ntile[(sb * TO + ro) * 65 + rk];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = first ? u * src[j] : v[j] + u * src[j];
+            for (int j = 0; j < 8; ++j) v[j] = first ? (T)u * src[j] : v[j] + (T)u * src[j];
             first = false;
         }
         if (first) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = 0.f;
+            for (int j = 0; j < 8; ++j) v[j] = T(0);
         }
         const int64_t child = (int64_t)q * a.R_ + c, o = o0 + ro, kk = k0 + rk;
-        if (a.last) {
-            unsigned short h[3][8];
+        if constexpr (sizeof(T) == 4) {
+            if (a.last) {
+                unsigned short h[3][8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                float r = v[j];
+                for (int j = 0; j < 8; ++j) {
+                    float r = v[j];
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) {
+                        float back;
+                        h[l][j] = a.half ? LimbT<true>::split(r, back) : LimbT<false>::split(r, back);
+                        r = r - back;
+                    }
+                }
 #pragma unroll
                 for (int l = 0; l < 3; ++l) {
-                    float back;
-                    h[l][j] = a.half ? LimbT<true>::split(r, back) : LimbT<false>::split(r, back);
-                    r = r - back;
+                    if (l >= a.nl) break;
+                    uint4 w;
+                    w.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
+                    w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
+                    w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
+                    w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
+                    *reinterpret_cast<uint4 *>(a.planes + child * a.leaf_stride + l * a.plane_stride +
+                                               ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 +
+                                               kk % 32) = w;
                 }
+                continue;
             }
+        }
+        if (o < a.cb_o && kk < a.y_ld) {
+            T *dst = Y + child * a.y_stride + o * a.y_ld + kk;
+            if constexpr (sizeof(T) == 4) {
+                *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                *reinterpret_cast<float4 *>(dst + 4) = make_float4(v[4], v[5], v[6], v[7]);
+            } else {
 #pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                if (l >= a.nl) break;
-                uint4 w;
-                w.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
-                w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
-                w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
-                w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
-                *reinterpret_cast<uint4 *>(a.planes + child * a.leaf_stride + l * a.plane_stride +
-                                           ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 +
-                                           kk % 32) = w;
+                for (int j = 0; j < 8; j += 2) *reinterpret_cast<double2 *>(dst + j) = make_double2(v[j], v[j + 1]);
             }
-        } else if (o < a.cb_o && kk < a.y_ld) {
-            float *dst = a.Y + child * a.y_stride + o * a.y_ld + kk;
-            *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-            *reinterpret_cast<float4 *>(dst + 4) = make_float4(v[4], v[5], v[6], v[7]);
         }
     }
 }
@@ -558,15 +602,17 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm_batched(const L
     limb_tile<HALF, NL, BM, BN, WM, WN, true, true, true>(a, leaf, tm, tn, sm);
 }
 
-template <bool HALF, int NL, int EPT>
-hipError_t form_all_go(const PlaneForm &f, int nleaves, hipStream_t s) {
-    const dim3 grid((unsigned)(f.kp / kFT), (unsigned)(f.rowsp / kFT)), block(4096 / EPT);
+template <bool HALF, int NL, int NB>
+hipError_t form_regs_go(const PlaneForm &f, int nleaves, hipStream_t s) {
+    constexpr int TR = 16;  // small work-groups (two waves): several per CU, out of phase
+    if (f.kp / kFT > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(f.rowsp / TR), (unsigned)(f.kp / kFT)), block(TR * 8);
     const bool scaled = f.e_o != nullptr, kc = f.ld_k == 1;
     const size_t lds = (size_t)nleaves * f.nbo * f.nbk * sizeof(float);
-    if (scaled && kc) hipLaunchKernelGGL((form_all<HALF, NL, true, true, EPT>), grid, block, lds, s, f, nleaves);
-    else if (scaled) hipLaunchKernelGGL((form_all<HALF, NL, true, false, EPT>), grid, block, lds, s, f, nleaves);
-    else if (kc) hipLaunchKernelGGL((form_all<HALF, NL, false, true, EPT>), grid, block, lds, s, f, nleaves);
-    else hipLaunchKernelGGL((form_all<HALF, NL, false, false, EPT>), grid, block, lds, s, f, nleaves);
+    if (scaled && kc) hipLaunchKernelGGL((form_regs<HALF, NL, true, true, NB, TR>), grid, block, lds, s, f, nleaves);
+    else if (scaled) hipLaunchKernelGGL((form_regs<HALF, NL, true, false, NB, TR>), grid, block, lds, s, f, nleaves);
+    else if (kc) hipLaunchKernelGGL((form_regs<HALF, NL, false, true, NB, TR>), grid, block, lds, s, f, nleaves);
+    else hipLaunchKernelGGL((form_regs<HALF, NL, false, false, NB, TR>), grid, block, lds, s, f, nleaves);
     return hipGetLastError();
 }
 
@@ -579,9 +625,9 @@ hipError_t form_go(const PlaneForm &f, int nleaves, hipStream_t s) {
     // holds fewer registers and streams faster)
     const int64_t nblk = (int64_t)f.nbo * f.nbk;
     if (f.nbo > 0 && f.nbk > 0 && nblk > 1 && nblk <= 16 && nblk * nleaves <= kAllMaxCoef) {
-        if (nblk <= 4) return form_all_go<HALF, NL, 16>(f, nleaves, s);
-        if (nblk <= 8) return form_all_go<HALF, NL, 8>(f, nleaves, s);
-        return form_all_go<HALF, NL, 4>(f, nleaves, s);
+        if (nblk <= 4) return form_regs_go<HALF, NL, 4>(f, nleaves, s);
+        if (nblk <= 8) return form_regs_go<HALF, NL, 8>(f, nleaves, s);
+        return form_regs_go<HALF, NL, 16>(f, nleaves, s);
     }
     const dim3 grid((unsigned)(f.kp / kFT), (unsigned)(f.rowsp / kFT), (unsigned)nleaves);
     const bool scaled = f.e_o != nullptr, kc = f.ld_k == 1;
@@ -655,18 +701,31 @@ hipError_t launch_form_node(int prec, const NodeForm &f, int nodes, hipStream_t 
     NodeForm a = f;
     a.nl = limb_count(prec);
     a.half = (prec == FASTMM_F16 || prec == FASTMM_F16X3) ? 1 : 0;
+    const bool dbl = prec == FASTMM_F64;
+    if (a.last && (dbl || prec == FASTMM_F32)) return hipErrorInvalidValue;  // planes: split precisions only
     const int nS = a.nO * a.nK;
     if (nS < 1 || nS > 16 || nodes <= 0) return nodes <= 0 ? hipSuccess : hipErrorInvalidValue;
     const int TO = nS <= 4 ? 32 : (nS <= 8 ? 16 : 8);
-    const int64_t ext_o = a.last ? a.rowsp : a.cb_o, ext_k = a.last ? a.kp : a.y_ld;
+    // extent of the child blocks the grid covers: planes (rowsp x kp), o-major blocks
+    // (cb_o x y_ld) or k-major blocks (y_ld x cb_k, o along the rows' contiguous direction)
+    const int64_t ext_o = a.last ? a.rowsp : (a.kmajor ? a.y_ld : a.cb_o);
+    const int64_t ext_k = a.last ? a.kp : (a.kmajor ? a.cb_k : a.y_ld);
     const int64_t gx = (ext_k + 63) / 64, gy = (ext_o + TO - 1) / TO;
     if (gx <= 0 || gy <= 0) return hipSuccess;
     if (gx > 0x7fffffffLL || gy > 65535 || nodes > 65535) return hipErrorInvalidValue;
+    if (a.kmajor && (a.y_ld % 8 != 0)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)nodes);
-    const size_t lds = ((size_t)nS * TO * 65 + (size_t)nS * a.R_) * sizeof(float);
-    if (TO == 32) hipLaunchKernelGGL(form_node<32>, grid, dim3(256), lds, s, a);
-    else if (TO == 16) hipLaunchKernelGGL(form_node<16>, grid, dim3(256), lds, s, a);
-    else hipLaunchKernelGGL(form_node<8>, grid, dim3(256), lds, s, a);
+    const size_t es = dbl ? sizeof(double) : sizeof(float);
+    const size_t lds = (size_t)nS * TO * 65 * es + (size_t)nS * a.R_ * sizeof(float);
+    if (dbl) {
+        if (TO == 32) hipLaunchKernelGGL((form_node<double, 32>), grid, dim3(256), lds, s, a);
+        else if (TO == 16) hipLaunchKernelGGL((form_node<double, 16>), grid, dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((form_node<double, 8>), grid, dim3(256), lds, s, a);
+    } else {
+        if (TO == 32) hipLaunchKernelGGL((form_node<float, 32>), grid, dim3(256), lds, s, a);
+        else if (TO == 16) hipLaunchKernelGGL((form_node<float, 16>), grid, dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((form_node<float, 8>), grid, dim3(256), lds, s, a);
+    }
     return hipGetLastError();
 }
 

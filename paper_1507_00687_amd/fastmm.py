@@ -209,10 +209,11 @@ class Plan:
         return self
 
     def path(self, m: int, k: int, n: int, transA: bool = False, transB: bool = False) -> str:
-        """'leaf', 'fused' or 'every_level': the execution path of an m x k by k x n product."""
+        """'leaf', 'fused', 'every_level' or 'written': the execution path of an m x k by k x n
+        product."""
         v = ctypes.c_int()
         _check(lib().fastmm_plan_path(self._h, m, k, n, int(transA), int(transB), ctypes.byref(v)))
-        return {0: "leaf", 1: "fused", 2: "every_level"}[v.value]
+        return {0: "leaf", 1: "fused", 2: "every_level", 3: "written"}[v.value]
 
     @property
     def handle(self):

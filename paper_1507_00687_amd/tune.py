@@ -57,7 +57,7 @@ def relative_instability(algo: str, levels: int) -> float:
     return fastmm_algo_stability(algo, levels)["rel_instability"]
 
 
-def candidates(max_depth: int = 3, cutoffs: Iterable[int] = (256,), non_stationary: bool = False):
+def candidates(max_depth: int = 3, cutoffs: Iterable[int] = (128, 256, 512), non_stationary: bool = False):
     """(rule, depth, cutoff, levels) tuples: classical, every rule stationary at depths
     1..max_depth and, with non_stationary, every ordered pair of distinct rules as two levels
     (section 3.3; shapes far from square are where mixed base cases pay)."""
@@ -125,7 +125,7 @@ def _key(m, k, n, precision, in_batch=True):
     return f"{m}x{k}x{n}:{precision}" + (":batch" if in_batch else "")
 
 
-def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 3, cutoffs=(256,),
+def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 3, cutoffs=(128, 256, 512),
                max_instability: float = float("inf"), reps: int = 3, A=None, B=None, in_batch: bool = True,
                non_stationary: bool = False) -> Choice:
     """Measure every admitted candidate on (m, k, n) and return the fastest (timed inside a
@@ -173,11 +173,8 @@ def tune_shape(m: int, k: int, n: int, precision: str = "f32", max_depth: int = 
         for tile in (128, 256):
             cand = Choice(best.algo, best.depth, best.cutoff, 0.0, best.instability, best.levels, tile)
             plan = cand.plan(precision)
-            if in_batch:
-                ms = _time_plan_batched(plan, A, B, Cs, reps)
-            else:
-                ws = torch.empty(max(plan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
-                ms = _time_plan(plan, A, B, C, ws, reps)
+            ws = torch.empty(max(plan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
+            ms = _time_plan(plan, A, B, C, ws, reps)
             if ms < best.ms * 0.98:  # a clear gain only: both tiles compute the same products
                 cand.ms = ms
                 best = cand

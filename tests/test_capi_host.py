@@ -162,6 +162,25 @@ def test_fused_path_selection(F, precision):
     assert F.Plan("strassen", 1, 1, precision="bf16x3").path(256, 256, 256) == "leaf"
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_written_path_selection(F, precision):
+    """From depth 2, rules whose leaf operands average more than 4 sources (nnz(U)/R)^L,
+    (nnz(V)/R)^L write their leaf operands out level by level; <2,2,2> rules keep the fused
+    kernel; split precisions form limb planes instead; one level, fusion off and trees stay on
+    the leaf path."""
+    P = lambda name, depth, cutoff=1, **kw: F.Plan(name, depth, cutoff, precision=precision, **kw)
+    assert P("f424", 2).path(256, 128, 256) == "written"          # fan-in 11.0
+    assert P("f323", 2).path(198, 200, 180) == "written"          # 4.55
+    assert P("laderman333", 2).path(135, 100, 81) == "written"    # 4.92
+    assert P("f424", 2).path(256, 128, 256, transA=True, transB=True) == "written"
+    assert P("f424", 1).path(256, 128, 256) == "leaf"             # one level: 3.31
+    assert P("f424", 2, 200).path(256, 128, 256) == "leaf"        # the cutoff leaves one level
+    assert P("f424", 2, fuse="off").path(256, 128, 256) == "leaf"  # fusion off: composite lists only
+    assert P("laderman333", 3).path(270, 270, 270) == "written"     # 10.9
+    assert P("strassen", 3).path(256, 256, 256) == "fused"          # 5.04, but <2,2,2> fused first
+    assert F.Plan("f424", 2, 1, precision="f16x3").path(256, 128, 256) == "leaf"
+
+
 def test_fused_path_matches_rules_by_coefficients(F):
     # Cyclic rotations (the rules of the backward pass) and user rules equal to a built-in
     # one take the fused path; a rule with its products reordered does not.
