@@ -108,6 +108,8 @@ def product_kernel(precision: str, path: str):
     """(kernel name, source file) of the launch that computes the products."""
     if path == "fused":
         return "fmm_node222", "node_fused.hip"
+    if path == "fused_loads":
+        return "fmm_limb_fused", "limb_gemm.hip"
     if precision in ("f64", "f32"):  # leaf and written paths
         return "fmm_leaf_pipelined", "leaf_mfma.hip"
     return "fmm_limb_gemm", "limb_gemm.hip"

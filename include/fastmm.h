@@ -166,6 +166,12 @@ typedef enum {
     FASTMM_PATH_EVERY_LEVEL = 2, /* scaling at every level (fastmm_scaling.per_level, depth >= 2):
                               the first level's node operands written out, each node product
                               by a call of the remaining levels, then the W-combination */
+    FASTMM_PATH_FUSED_LOADS = 4, /* split precisions with FASTMM_FUSE_ALWAYS, 256 x 256 limb-GEMM
+                              tiles, at most two limbs, every product live and at most two
+                              nonzeros per column of U and V (Strassen's rule, classical): the
+                              outer levels' node operands written out in FP32 level by level
+                              (none at depth <= 1), the innermost level's S_r, T_r formed in the
+                              limb GEMM's tile loads (no limb planes), then the W-combination */
     FASTMM_PATH_WRITTEN = 3 /* FP64 / FP32 from depth 2 with a high fan-in (average sources per
                               leaf operand, (nnz(U)/R)^L and (nnz(V)/R)^L, above 4): every leaf
                               operand S_r, T_r written out level by level (eq. (1) applied once
@@ -176,11 +182,14 @@ typedef enum {
 /* Fusion modes (fastmm_plan_set_fusion). */
 typedef enum {
     FASTMM_FUSE_OFF = 0,    /* always the leaf path with composite source lists (neither the
-                               fused kernel nor written-out leaf operands) */
+                               fused kernels nor written-out leaf operands; split precisions
+                               through limb planes) */
     FASTMM_FUSE_AUTO = 1,   /* the default: the fused path where it applies and is the faster one
                                (FP32 from depth 1, FP64 from depth 2), else written-out leaf
                                operands where FASTMM_PATH_WRITTEN applies, else the leaf path */
-    FASTMM_FUSE_ALWAYS = 2  /* the fused path wherever it applies */
+    FASTMM_FUSE_ALWAYS = 2  /* the fused path wherever it applies; for the split precisions the
+                               innermost level formed in the limb GEMM's loads
+                               (FASTMM_PATH_FUSED_LOADS) where it applies */
 } fastmm_fusion;
 
 /* Set the fusion mode (fastmm_fusion) of this plan and of the rotated sub-plans of its backward

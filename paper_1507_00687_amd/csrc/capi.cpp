@@ -83,6 +83,7 @@ struct Tables {
     // with coefficient 1 (the FP64 / FP32 paths with written-out leaf operands).
     LeafEntry *wleaves = nullptr;
     SrcEntry *wsrc = nullptr;
+    float *unit = nullptr;  // the 1 x 1 x 1 rule's U = V = [1]
     int device = -1;
     ~Tables() {
         if (device >= 0) {
@@ -98,6 +99,7 @@ struct Tables {
             (void)hipFree(vcoef);
             (void)hipFree(wleaves);
             (void)hipFree(wsrc);
+            (void)hipFree(unit);
             (void)hipSetDevice(cur);
         }
     }
@@ -495,6 +497,48 @@ struct WrittenDims {
 };
 WrittenDims written_dims(const Shape &s) { return WrittenDims{round_up(s.kb, 8), round_up(s.nb, 8)}; }
 
+int max_col_nnz(const std::vector<int64_t> &X, int rows, int R) {
+    int mx = 0;
+    for (int r = 0; r < R; ++r) {
+        int c = 0;
+        for (int i = 0; i < rows; ++i) c += X[(size_t)i * R + r] != 0;
+        mx = std::max(mx, c);
+    }
+    return mx;
+}
+
+// Split precisions with the innermost recursion level formed in the limb GEMM's tile loads
+// (fmm_limb_fused): the node operands of the outer levels are written out in FP32 level by level
+// (at depth <= 1 the operands themselves, B read transposed, copied only when their layout needs
+// it), the GEMM forms each leaf's S_r and T_r^T from them while staging; no limb planes.  For
+// one rule at every node with every product live, at most 2 sources per column of U and V
+// (the raw chunks of a stage sit in registers beside the accumulators; 4 spill), at most two
+// limbs and 256 x 256 output tiles.
+//
+// Measured on MI355X, this path is slower than limb planes: Strassen depth 2 at n = 16384 F16X3
+// took 26.7 ms in fmm_limb_fused against 17.2 ms in fmm_limb_gemm (plus 2.8 ms of plane formation;
+// the FP32 node operands of depth 2 cost as much, 2.8 ms); classical 28.0 against 21.9.  The
+// fused GEMM keeps every stage's raw FP32 chunks in registers beside the accumulators (256
+// VGPRs, a few spills), so it runs the 32 x 32 x 16 MFMA form and leaves the per-stage sums and
+// splits unoverlapped.  It is therefore taken only when asked for (FASTMM_FUSE_ALWAYS).
+bool fused_split(const fastmm_plan_s *p, const Shape &s) {
+    if (!is_split(p->prec) || limb_count(p->prec) > 2 || p->fuse != FASTMM_FUSE_ALWAYS) return false;
+    if (!p->tree.empty() || !p->levels.empty()) return false;
+    if (plan_tile(p, s) != 256) return false;
+    if (s.L >= 1) {
+        const Algo &a = plan_algo(p);
+        int64_t all = 1;
+        for (int l = 0; l < s.L; ++l) all *= a.R;
+        if (leaf_count(a, s.L) != all) return false;
+        if (max_col_nnz(a.U, a.M0 * a.K0, a.R) > 2 || max_col_nnz(a.V, a.K0 * a.N0, a.R) > 2) return false;
+    }
+    // 32-bit element offsets inside one node operand (rows x row length, both sides)
+    const Algo &a = plan_algo(p);
+    const int64_t pm = s.L >= 1 ? s.mb * a.M0 : s.Mp, pn = s.L >= 1 ? s.nb * a.N0 : s.Np;
+    const int64_t pk = round_up(s.L >= 1 ? s.kb * a.K0 : s.Kp, 8);
+    return pm * pk < ((int64_t)1 << 31) && pn * pk < ((int64_t)1 << 31);
+}
+
 // The scaling part of a workspace (exponents, flags, maxima); returns its end.
 size_t scaling_layout(const fastmm_plan_s *p, int64_t m, int64_t k, int64_t n, WsLayout &w) {
     const size_t es = elem_size(p->prec);
@@ -514,7 +558,18 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
     WsLayout w{};
     const size_t es = elem_size(p->prec);
     size_t off = scaling_layout(p, m, k, n, w);
-    if (is_split(p->prec)) {
+    if (is_split(p->prec) && bm_force == 0 && fused_split(p, s)) {
+        // node operands: depth <= 1 the copies of op(A) and op(B)^T (used when their layout
+        // needs one), deeper the FP32 children of the outer levels
+        if (s.L <= 1) {
+            const int64_t kt = round_up(s.Kp, 8);
+            w.xa = off, off = align256(off + 4 * (size_t)s.Mp * kt);
+            w.xb = off, off = align256(off + 4 * (size_t)s.Np * kt);
+        } else {
+            w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
+            w.ib = off, off = align256(off + inner_levels(p, s, true).back().off);
+        }
+    } else if (is_split(p->prec)) {
         const SplitDims d = split_dims(p, s, bm_force);
         const size_t nleaves = (size_t)plan_leaf_count(p, s.L);
         w.sp = off, off = align256(off + 2 * nleaves * d.nl * (size_t)d.mbp * d.kp);
@@ -637,7 +692,8 @@ fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
         std::vector<LeafEntry> wl((size_t)t->nleaves);
         std::vector<SrcEntry> ws((size_t)t->nleaves);
         for (int r = 0; r < t->nleaves; ++r) wl[(size_t)r] = LeafEntry{r, 1, r, 1}, ws[(size_t)r] = SrcEntry{r, 0, 1.f, 0};
-        if ((e = upload(&t->wleaves, wl)) != hipSuccess || (e = upload(&t->wsrc, ws)) != hipSuccess)
+        if ((e = upload(&t->wleaves, wl)) != hipSuccess || (e = upload(&t->wsrc, ws)) != hipSuccess ||
+            (e = upload(&t->unit, std::vector<float>{1.f})) != hipSuccess)
             return hip_fail(e, "uploading tables");
     }
     *out = t.get();
@@ -964,6 +1020,7 @@ fastmm_status fastmm_plan_path(fastmm_plan_t plan, int64_t m, int64_t k, int64_t
     *path = every_level(plan, s)                         ? FASTMM_PATH_EVERY_LEVEL
             : fused_path(plan, s, transA, transB, masks) ? FASTMM_PATH_FUSED
             : written_leaves(plan, s)                    ? FASTMM_PATH_WRITTEN
+            : fused_split(plan, s)                       ? FASTMM_PATH_FUSED_LOADS
                                                          : FASTMM_PATH_LEAF;
     return FASTMM_OK;
 }
@@ -1081,6 +1138,107 @@ hipError_t split_form(fastmm_plan_s *plan, const Shape &s, const SplitDims &d, c
     g.s_plane = fa.plane_stride, g.s_leaf = fa.leaf_stride, g.t_plane = fb.plane_stride, g.t_leaf = fb.leaf_stride;
     g.mb = s.mb, g.nb = s.nb, g.m = m, g.n = n, g.sc = exps, g.post_exp = -2 * pre;
     g.tiles_m = (int)(d.mbp / d.bm), g.tiles_n = (int)(d.nbp / d.bm);
+    return hipSuccess;
+}
+
+// Split precisions with the innermost level formed in the limb GEMM's loads (fused_split): the
+// node operands of both sides (FP32, k contiguous; B's stored transposed), then fmm_limb_fused
+// over all leaves x tiles.  Fills f except the output fields.
+hipError_t fused_split_operands(fastmm_plan_s *plan, const Shape &s, const void *A, int64_t lda, int transA,
+                                const void *B, int64_t ldb, int transB, int64_t m, int64_t k, int64_t n,
+                                const ScaleExps &exps, int pre, char *ws, const WsLayout &w, const Tables *tab,
+                                hipStream_t st, LimbFused &f) {
+    const Algo &al = plan_algo(plan);
+    const bool i_step = schedule_of(plan->sc).find('I') != std::string::npos;
+    f = LimbFused{};
+    if (s.L <= 1) {
+        // The operands themselves are the node operand: op(A) (m x k) and op(B)^T (n x k), read in
+        // place when k-contiguous, 16-byte aligned, k a multiple of 8 and without inside factors
+        // (the row factors of an O step are applied while loading); else copied once by a 1 x 1
+        // level of form_node, which applies every factor.
+        const int64_t kt = round_up(s.Kp, 8);
+        auto side = [&](bool side_b) -> hipError_t {
+            const void *X = side_b ? B : A;
+            const int64_t ld = side_b ? ldb : lda;
+            const bool krow = side_b ? transB != 0 : transA == 0;  // stored rows of op(X) with k contiguous
+            const int64_t rows = side_b ? n : m;
+            FusedSide &fs = side_b ? f.b : f.a;
+            // (32-bit element offsets: the stored operand must span less than 2^31 elements)
+            if (krow && !i_step && k % 8 == 0 && ld % 4 == 0 && ((uintptr_t)X & 15) == 0 &&
+                rows * ld < ((int64_t)1 << 31)) {
+                fs.X = (const float *)X, fs.ld = ld, fs.rows = rows, fs.cols = k;
+                fs.e_row = side_b ? exps.eb : exps.ea, fs.s_row = -1, fs.pre_exp = pre;
+                return hipSuccess;
+            }
+            NodeForm nf{};
+            nf.X = X;
+            if (side_b) nf.ld_o = transB ? ldb : 1, nf.ld_k = transB ? 1 : ldb;
+            else nf.ld_o = transA ? 1 : lda, nf.ld_k = transA ? lda : 1;
+            nf.R = rows, nf.K = k, nf.first = 1;
+            nf.e_o = side_b ? exps.eb : exps.ea, nf.e_k = exps.ep, nf.s_o = -1, nf.s_k = side_b ? -1 : 1;
+            nf.pre_exp = exps.ea ? pre : 0;
+            nf.nO = 1, nf.nK = 1, nf.side_b = side_b ? 1 : 0, nf.R_ = 1, nf.coef = tab->unit;
+            nf.cb_o = rows, nf.cb_k = kt, nf.last = 0;
+            nf.Y = ws + (side_b ? w.xb : w.xa), nf.y_ld = kt, nf.y_stride = rows * kt;
+            fs.X = (const float *)nf.Y, fs.ld = kt, fs.rows = rows, fs.cols = kt, fs.e_row = nullptr;
+            return launch_form_node(FASTMM_F32, nf, 1, st);
+        };
+        hipError_t e = side(false);
+        if (e == hipSuccess) e = side(true);
+        if (e != hipSuccess) return e;
+        f.a.node_stride = f.b.node_stride = 0;
+    } else {
+        // levels 1 .. L-1 written out (the first one scaled); the innermost level in the GEMM
+        auto side = [&](bool side_b) -> hipError_t {
+            const std::vector<InnerLevel> lv = inner_levels(plan, s, side_b);
+            char *ibase = ws + (side_b ? w.ib : w.ia);
+            int64_t nodes = 1;
+            for (int l = 1; l < s.L; ++l) {
+                NodeForm nf{};
+                if (l == 1) {
+                    nf.X = side_b ? B : A;
+                    if (side_b) nf.ld_o = transB ? ldb : 1, nf.ld_k = transB ? 1 : ldb, nf.R = n;
+                    else nf.ld_o = transA ? 1 : lda, nf.ld_k = transA ? lda : 1, nf.R = m;
+                    nf.K = k, nf.first = 1;
+                    nf.e_o = side_b ? exps.eb : exps.ea, nf.e_k = exps.ep, nf.s_o = -1, nf.s_k = side_b ? -1 : 1;
+                    nf.pre_exp = exps.ea ? pre : 0;
+                } else {
+                    const InnerLevel &in = lv[(size_t)l - 2];
+                    nf.X = ibase + in.off, nf.ld_o = in.y_ld, nf.ld_k = 1;
+                    nf.node_stride = in.y_stride, nf.first = 0;
+                }
+                nf.nO = side_b ? al.N0 : al.M0, nf.nK = al.K0, nf.side_b = side_b ? 1 : 0, nf.R_ = al.R;
+                nf.coef = side_b ? tab->vcoef : tab->ucoef;
+                const InnerLevel &out = lv[(size_t)l - 1];
+                nf.cb_o = out.cb_o, nf.cb_k = out.cb_k, nf.last = 0;
+                nf.Y = ibase + out.off, nf.y_ld = out.y_ld, nf.y_stride = out.y_stride;
+                if (nodes > 65535) return hipErrorInvalidValue;
+                hipError_t er = launch_form_node(plan->prec, nf, (int)nodes, st);
+                if (er != hipSuccess) return er;
+                nodes *= al.R;
+            }
+            const InnerLevel &last = lv[(size_t)s.L - 2];
+            FusedSide &fs = side_b ? f.b : f.a;
+            fs.X = (const float *)(ibase + last.off), fs.ld = last.y_ld, fs.node_stride = last.y_stride;
+            fs.rows = last.cb_o, fs.cols = last.cb_k, fs.e_row = nullptr;
+            return hipSuccess;
+        };
+        hipError_t e = side(false);
+        if (e == hipSuccess) e = side(true);
+        if (e != hipSuccess) return e;
+    }
+    f.a.sb_rows = s.mb, f.b.sb_rows = s.nb;
+    if (s.L >= 1) {
+        f.ucoef = tab->ucoef, f.vcoef = tab->vcoef, f.M0 = al.M0, f.K0 = al.K0, f.N0 = al.N0, f.R = al.R;
+        f.qa = max_col_nnz(al.U, al.M0 * al.K0, al.R), f.qb = max_col_nnz(al.V, al.K0 * al.N0, al.R);
+    } else {
+        f.ucoef = f.vcoef = tab->unit, f.M0 = f.K0 = f.N0 = f.R = 1, f.qa = f.qb = 1;
+    }
+    // leaf inner dimension in whole 8-element chunks (a multiple of 8 from depth 1; at depth 0
+    // the copies are zero-padded to it and a direct operand has k % 8 == 0)
+    f.kb = round_up(s.kb, 8), f.nk = (f.kb + 31) / 32;
+    f.mb = s.mb, f.nb = s.nb, f.m = m, f.n = n, f.sc = exps, f.post_exp = -2 * pre;
+    f.tiles_m = (int)((s.mb + 255) / 256), f.tiles_n = (int)((s.nb + 255) / 256);
     return hipSuccess;
 }
 
@@ -1309,6 +1467,37 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     L.leaves = tab->leaves, L.asrc = tab->asrc, L.bsrc = tab->bsrc;
     L.sc = exps;
     hipError_t e;
+    if (is_split(plan->prec) && fused_split(plan, s)) {
+        // Split precisions, innermost level fused into the limb GEMM's loads: node operands,
+        // then the fused limb GEMM over all leaves, then (L >= 1) the W-combination.
+        const bool f16 = plan->prec == FASTMM_F16 || plan->prec == FASTMM_F16X3;
+        const int pre = (f16 && exps.ea && schedule_of(plan->sc).find('O') != std::string::npos) ? 8 : 0;
+        LimbFused f;
+        if ((e = fused_split_operands(plan, s, A, lda, transA, B, ldb, transB, m, k, n, exps, pre, ws, w, tab, st,
+                                      f)) != hipSuccess)
+            return hip_fail(e, "node operand formation");
+        fin.mark();
+        if (s.L == 0) {
+            f.out = (float *)C, f.ldo = ldc, f.leaf_stride = 0, f.direct = 1;
+        } else {
+            f.out = (float *)(ws + w.leaves), f.ldo = s.nb, f.leaf_stride = s.mb * s.nb, f.direct = 0;
+        }
+        e = launch_limb_fused(plan->prec, f, tab->nleaves, st);
+        fin.mark();
+        if (e != hipSuccess) return hip_fail(e, "fused limb GEMM kernel");
+        if (s.L == 0) return FASTMM_OK;
+        CombineLaunch Cb;
+        Cb.elem = el;
+        Cb.M = ws + w.leaves;
+        Cb.leaf_stride = s.mb * s.nb;
+        Cb.C = C, Cb.ldc = ldc, Cb.m = m, Cb.n = n, Cb.mb = s.mb, Cb.nb = s.nb;
+        Cb.NB = tab->NB;
+        Cb.bdest = tab->bdest, Cb.dest = tab->dest;
+        Cb.sc = exps;
+        set_kron(plan, s.L, tab->nleaves, Cb);
+        if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
+        return FASTMM_OK;
+    }
     if (is_split(plan->prec)) {
         // Split precisions: limb planes of every S_r and T_r^T (k contiguous, zero-padded to
         // the GEMM tiles), then the limb GEMM, then (L >= 1) the W-combination.

@@ -164,6 +164,37 @@ struct LimbGemm {
     int tiles_m, tiles_n;
     int direct;
 };
+// Split precisions with the innermost recursion level formed in the GEMM's tile loads (eq. (1)
+// applied while staging).  Leaf (node q = leaf / R, innermost product r = leaf % R) multiplies
+// S_r = sum_i U_ir X_i by T_r = sum_j V_jr Y_j, where X_i are the sub-blocks of node q's A operand
+// and Y_j those of its B operand.  Both operands are FP32 with k contiguous: the A operand row-
+// major (rows of m), the B operand stored transposed (rows of n).  Sub-block i of the A operand
+// sits at row block i % M0, k block i / M0; sub-block j of the B operand at row block j / K0, k
+// block j % K0 (eq. (1): blocks column-major).  S_r and T_r^T are formed in FP32 from the loaded
+// tiles, sources in increasing index order, split into limbs and staged in LDS for the limb
+// products, so no limb planes are written.
+struct FusedSide {
+    const float *X;             // node q's operand at X + q * node_stride, row stride ld
+    int64_t ld, node_stride;
+    int64_t rows, cols;         // valid extent of a node operand (zero beyond: virtual padding)
+    int64_t sb_rows;            // rows of a sub-block (mb or nb); its k extent is LimbFused::kb
+    const int32_t *e_row;       // outside scaling: row r of the operand times 2^(s_row e_row[r] + pre_exp)
+    int s_row, pre_exp;
+};
+struct LimbFused {
+    FusedSide a, b;
+    const float *ucoef, *vcoef;  // innermost rule: U (M0 K0 x R) and V (K0 N0 x R), row-major
+    int M0, K0, N0, R;
+    int qa, qb;                  // most nonzeros in a column of U, of V (<= 2)
+    int64_t kb, nk;              // leaf inner dimension, and its 32-k stages
+    float *out;
+    int64_t ldo, leaf_stride, mb, nb, m, n;
+    ScaleExps sc;
+    int post_exp;
+    int tiles_m, tiles_n;
+    int direct;
+};
+hipError_t launch_limb_fused(int prec, const LimbFused &f, int nleaves, hipStream_t s);
 // Operand formation level by level (split precisions; written-out leaf operands of the FP64 /
 // FP32 paths): one recursion level.  Elements are double for FP64, float otherwise.  The
 // node operand of node q is op(X) itself on the first level (element (o, kk) at

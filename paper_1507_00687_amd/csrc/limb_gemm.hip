@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "devtypes.h"
 #include "fastmm.h"
@@ -26,6 +27,7 @@ namespace fastmm {
 namespace {
 
 typedef float g4v __attribute__((ext_vector_type(4)));
+typedef float g16v __attribute__((ext_vector_type(16)));
 typedef __bf16 gbf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 gh8 __attribute__((ext_vector_type(8)));
 typedef short gs8 __attribute__((ext_vector_type(8)));
@@ -46,6 +48,13 @@ struct LimbT<false> {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(gbf8, a), __builtin_bit_cast(gbf8, b), c,
                                                        0, 0, 0);
     }
+    // D(32x32) += A(32x16) B(16x32): lane l supplies A[l%32][8(l/32) .. 8(l/32)+7] and
+    // B[8(l/32) .. 8(l/32)+7][l%32]; accumulator element v of lane l is
+    // D[8(v/4) + 4(l/32) + v%4][l%32].
+    __device__ static g16v mma32(gs8 a, gs8 b, g16v c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(gbf8, a), __builtin_bit_cast(gbf8, b), c,
+                                                       0, 0, 0);
+    }
 };
 template <>
 struct LimbT<true> {
@@ -56,6 +65,10 @@ struct LimbT<true> {
     }
     __device__ static g4v mma(gs8 a, gs8 b, g4v c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(gh8, a), __builtin_bit_cast(gh8, b), c, 0, 0,
+                                                      0);
+    }
+    __device__ static g16v mma32(gs8 a, gs8 b, g16v c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(gh8, a), __builtin_bit_cast(gh8, b), c, 0, 0,
                                                       0);
     }
 };
@@ -143,11 +156,11 @@ constexpr int kAllMaxCoef = 4096;  // leaves x blocks entries of the coefficient
 // the rule's single block index at depth 1 (column-major for A, row-major over (n-block,
 // k-block) for B), which is the order of the source lists there.  Thread layout: k-contiguous
 // operands (KCONTIG): eight consecutive lanes take the eight chunks of one row; otherwise (B, n
-// contiguous) lanes 4i + c take rows i of a 16-row group and chunks c of a 32-k piece, so loads
-// read 64-byte row segments and each wave writes 16 whole 64-byte rows of one plane piece.
-// Two-wave work-groups (TR = 16) let several run per CU out of phase (one loading while
-// another writes); a 512-thread version with one 64 x 64 tile per work-group, and the earlier
-// LDS-transposing version with a barrier per leaf, both ran 5 % slower.
+// contiguous) 32 consecutive lanes take 32 consecutive rows of one chunk, so loads read whole
+// 128-byte lines.  Small work-groups (TR = 16 or 32 rows) let several run per CU out of phase
+// (one loading while another writes); a 512-thread version with one 64 x 64 tile per
+// work-group, and the earlier LDS-transposing version with a barrier per leaf, both ran 5 %
+// slower.
 template <bool HALF, int NL, bool SCALED, bool KCONTIG, int NB, int TR>
 __global__ __launch_bounds__(TR * 8) void form_regs(PlaneForm a, int nleaves) {
     constexpr int NT = TR * 8;
@@ -165,13 +178,15 @@ __global__ __launch_bounds__(TR * 8) void form_regs(PlaneForm a, int nleaves) {
             rcoef[leaf * nblk + (a.b_side ? bo * nbk + bk : bk * nbo + bo)] += se.coef;
         }
     }
-    static_assert(TR % 16 == 0 && TR <= 64, "tile rows");
+    static_assert(TR % 16 == 0 && TR <= 64 && (KCONTIG || TR % 32 == 0), "tile rows");
     int ol, kc;  // the thread's row and 8-wide k chunk in the TR x 64 tile
     if (KCONTIG) {
         ol = t >> 3, kc = t & 7;
     } else {
+        // 32 consecutive lanes on 32 consecutive rows (o contiguous in op(X)): every load reads
+        // whole 128-byte lines; a wave writes 32 bytes of 32 rows, its neighbour the rest
         const int wave = t >> 6, lane = t & 63;
-        ol = (lane >> 2) + 16 * (wave % (TR / 16)), kc = (lane & 3) + 4 * (wave / (TR / 16));
+        ol = (lane & 31) + 32 * (wave % (TR / 32)), kc = (lane >> 5) + 2 * (wave / (TR / 32));
     }
     // work-group (row tile x, k tile y): consecutive work-groups take consecutive TR-row slices
     // of the same 32-k plane pieces, so the work-groups in flight write whole pieces together
@@ -560,6 +575,275 @@ __device__ __forceinline__ void limb_tile(const LimbGemm &a, int leaf, int64_t t
         }
 }
 
+// ------------------------------------------------------------------ limb GEMM, innermost level fused
+// As limb_tile, with the limb tiles formed while staging instead of read from limb planes: every
+// stage each thread loads its chunks (eight consecutive k of one row; 16-byte loads) of the up to
+// Q source sub-blocks of its leaf's S_r and T_r^T (loads for stage k+1 issued before the MFMA
+// work of stage k), sums them with the coefficients (times the row's outside-scaling factor, a
+// power of two, so each term is exact and each sum rounds once, in source order), splits the
+// sums into limbs and writes the 16-byte limb chunks to LDS.  The limb products, their order and
+// the output are those of limb_tile.
+template <bool HALF, int NL, int BM, int BN, int WM, int WN, int QA, int QB, bool M32>
+__device__ __forceinline__ void limb_tile_fused(const LimbFused &a, int leaf, int64_t tm, int64_t tn,
+                                                LimbSmem<NL, BM, BN> &sm) {
+    constexpr int BK = 32, NT = 64 * WM * WN, RS = 32;
+    constexpr int MS = M32 ? 32 : 16;  // MFMA block: 32 x 32 x 16 or 16 x 16 x 32
+    constexpr int TI = BM / (MS * WM), TJ = BN / (MS * WN);
+    typedef typename std::conditional<M32, g16v, g4v>::type acc_t;
+    constexpr int NV = M32 ? 16 : 4;
+    constexpr int CA = BM * 4 / NT, CB = BN * 4 / NT;  // 8-k chunks per thread and stage
+    static_assert(CA * NT == BM * 4 && CB * NT == BN * 4, "chunk split");
+    typedef Products<NL> P;
+    auto &As = sm.As;
+    auto &Bs = sm.Bs;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    auto swz = [](int r, int c) { return c ^ ((r >> 1) & 3); };
+
+    // The leaf's sources: the nonzeros of column r of the innermost U (A side) and V (B side),
+    // in increasing index order; slot q holds the q-th (uniform values, found by a scan per slot).
+    const int node = leaf / a.R, r = leaf - node * a.R;
+    const int nsa = a.M0 * a.K0, nsb = a.K0 * a.N0;
+    int na = 0, nb = 0;
+    float ca[QA], cb[QB];
+    int64_t ra0[QA], ka0[QA], rb0[QB], kb0[QB];  // first row and k offset of each source sub-block
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+        int idx = -1, cnt = 0;
+        for (int i = 0; i < nsa; ++i)
+            if (a.ucoef[i * a.R + r] != 0.f) {
+                if (cnt == q) idx = i;
+                ++cnt;
+            }
+        na = cnt < QA ? cnt : QA;
+        ca[q] = idx >= 0 ? a.ucoef[idx * a.R + r] : 0.f;
+        ra0[q] = idx >= 0 ? (int64_t)(idx % a.M0) * a.a.sb_rows : 0;
+        ka0[q] = idx >= 0 ? (int64_t)(idx / a.M0) * a.kb : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        int idx = -1, cnt = 0;
+        for (int j = 0; j < nsb; ++j)
+            if (a.vcoef[j * a.R + r] != 0.f) {
+                if (cnt == q) idx = j;
+                ++cnt;
+            }
+        nb = cnt < QB ? cnt : QB;
+        cb[q] = idx >= 0 ? a.vcoef[idx * a.R + r] : 0.f;
+        rb0[q] = idx >= 0 ? (int64_t)(idx / a.K0) * a.b.sb_rows : 0;
+        kb0[q] = idx >= 0 ? (int64_t)(idx % a.K0) * a.kb : 0;
+    }
+    const float *XA = a.a.X + (int64_t)node * a.a.node_stride;
+    const float *XB = a.b.X + (int64_t)node * a.b.node_stride;
+    // Per source: element offset (32-bit) of the thread's first chunk inside the node operand;
+    // chunk u lies 128 u rows further (rows r0 + 128 u of the tile, k chunk kc).  Bit u Q + q of
+    // vmask: chunk u of source q lies inside the operand.  Factors: the coefficient times the
+    // row's outside-scaling factor (a power of two), per chunk and source.
+    static_assert(NT == 512 && CA == 2 && CB == 2, "thread layout");
+    const int r0 = t >> 2, kc = t & 3;
+    uint32_t ba[QA], bb[QB];
+    uint32_t ma = 0, mbm = 0;
+    float fa_[CA][QA], fb_[CB][QB];
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+        ba[q] = (uint32_t)((ra0[q] + tm * BM + r0) * a.a.ld + ka0[q] + 8 * kc);
+#pragma unroll
+        for (int u = 0; u < CA; ++u) {
+            const int64_t lr = tm * BM + r0 + 128 * u, row = ra0[q] + lr;
+            const bool ok = q < na && lr < a.mb && row < a.a.rows;
+            ma |= ok ? 1u << (u * QA + q) : 0u;
+            fa_[u][q] = (ok && a.a.e_row) ? ldexpf(ca[q], a.a.s_row * a.a.e_row[row] + a.a.pre_exp) : ca[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        bb[q] = (uint32_t)((rb0[q] + tn * BN + r0) * a.b.ld + kb0[q] + 8 * kc);
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            const int64_t lr = tn * BN + r0 + 128 * u, row = rb0[q] + lr;
+            const bool ok = q < nb && lr < a.nb && row < a.b.rows;
+            mbm |= ok ? 1u << (u * QB + q) : 0u;
+            fb_[u][q] = (ok && a.b.e_row) ? ldexpf(cb[q], a.b.s_row * a.b.e_row[row] + a.b.pre_exp) : cb[q];
+        }
+    }
+    const uint32_t stepa = (uint32_t)(128 * a.a.ld), stepb = (uint32_t)(128 * a.b.ld);
+    // Raw source chunks of the next stage, as vector values (not arrays) so that they stay in
+    // VGPRs: element 8 (u QA + q) + e of xa is element e of chunk u, source q.
+    typedef float rawA_t __attribute__((ext_vector_type(8 * CA * QA)));
+    typedef float rawB_t __attribute__((ext_vector_type(8 * CB * QB)));
+    rawA_t xa;
+    rawB_t xb;
+#define FUSED_LOAD_SIDE(X, Q, BASE, MASK, STEP, OFF0, COLS, XP, k0)                                    \
+    _Pragma("unroll") for (int u = 0; u < 2; ++u) {                                                    \
+        const int64_t kk = (k0) + 8 * kc;                                                              \
+        _Pragma("unroll") for (int q = 0; q < Q; ++q) {                                                \
+            const bool ok = ((MASK >> (u * Q + q)) & 1u) && kk + 8 <= a.kb && OFF0[q] + kk + 8 <= COLS; \
+            float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0;                                      \
+            if (ok) {                                                                                  \
+                const float4 *p4 = reinterpret_cast<const float4 *>(XP + BASE[q] + u * STEP + (k0));   \
+                w0 = p4[0], w1 = p4[1];                                                                \
+            }                                                                                          \
+            const int b8 = 8 * (u * Q + q);                                                            \
+            X[b8] = w0.x, X[b8 + 1] = w0.y, X[b8 + 2] = w0.z, X[b8 + 3] = w0.w;                        \
+            X[b8 + 4] = w1.x, X[b8 + 5] = w1.y, X[b8 + 6] = w1.z, X[b8 + 7] = w1.w;                    \
+        }                                                                                              \
+    }
+#define FUSED_LOAD(k0)                                                       \
+    FUSED_LOAD_SIDE(xa, QA, ba, ma, stepa, ka0, a.a.cols, XA, k0)            \
+    FUSED_LOAD_SIDE(xb, QB, bb, mbm, stepb, kb0, a.b.cols, XB, k0)
+    const int rowa[2] = {r0, r0 + 128}, kca[2] = {kc, kc}, rowb[2] = {r0, r0 + 128}, kcb[2] = {kc, kc};
+    // Sum each chunk's sources (v = f0 x0, then v = fma(f_q, x_q, v): every f x is exact, a
+    // signed power of two or half of one, so each step rounds once, as a separate add would),
+    // split into limbs and write the 16-byte limb chunks to LDS buffer st.
+#define FUSED_STORE_SIDE(X, Q, NS, F, ROW, KC, S, st)                                                  \
+    _Pragma("unroll") for (int u = 0; u < 2; ++u) {                                                    \
+        float v[8];                                                                                    \
+        _Pragma("unroll") for (int e = 0; e < 8; ++e) v[e] = F[u][0] * X[8 * (u * Q) + e];             \
+        _Pragma("unroll") for (int q = 1; q < Q; ++q) {                                                \
+            if (q < NS) {                                                                              \
+                _Pragma("unroll") for (int e = 0; e < 8; ++e) v[e] =                                   \
+                    __builtin_fmaf(F[u][q], X[8 * (u * Q + q) + e], v[e]);                             \
+            }                                                                                          \
+        }                                                                                              \
+        unsigned short h[NL][8];                                                                       \
+        _Pragma("unroll") for (int e = 0; e < 8; ++e) {                                                \
+            float rr = v[e];                                                                           \
+            _Pragma("unroll") for (int l = 0; l < NL; ++l) {                                           \
+                float back;                                                                            \
+                h[l][e] = LimbT<HALF>::split(rr, back);                                                \
+                rr = rr - back;                                                                        \
+            }                                                                                          \
+        }                                                                                              \
+        _Pragma("unroll") for (int l = 0; l < NL; ++l)                                                 \
+            *reinterpret_cast<uint4 *>(&S[st][l][ROW[u] * RS + 8 * swz(ROW[u], KC[u])]) =              \
+                uint4{(uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16), (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16), \
+                      (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16), (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16)}; \
+    }
+#define FUSED_STORE(st)                                   \
+    FUSED_STORE_SIDE(xa, QA, na, fa_, rowa, kca, As, st) \
+    FUSED_STORE_SIDE(xb, QB, nb, fb_, rowb, kcb, Bs, st)
+
+    acc_t acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[i][j][v] = 0.f;
+    const int g = lane >> 4, l16 = lane & 15;
+    const int64_t nk = a.nk;
+    FUSED_LOAD(0)
+    FUSED_STORE(0)
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        const bool more = kt + 1 < nk;
+        if (more) {
+            FUSED_LOAD((kt + 1) * BK)
+        }
+        // one limb product at a time, its two fragment sets read from LDS just before use (the
+        // raw chunks of the next stage take the registers that all products' fragments at once
+        // would need)
+        if constexpr (M32) {
+            // two 16-k halves per stage; lane l reads row l % 32, chunk 2 h + l / 32
+            const int l32 = lane & 31, hh = lane >> 5;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int p = 0; p < P::n; ++p) {
+                    gs8 fa[TI], fb[TJ];
+#pragma unroll
+                    for (int i = 0; i < TI; ++i) {
+                        const int rr = wm * (BM / WM) + i * 32 + l32;
+                        fa[i] = *reinterpret_cast<const gs8 *>(&As[cur][P::a[p]][rr * RS + 8 * swz(rr, 2 * h + hh)]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < TJ; ++j) {
+                        const int rr = wn * (BN / WN) + j * 32 + l32;
+                        fb[j] = *reinterpret_cast<const gs8 *>(&Bs[cur][P::b[p]][rr * RS + 8 * swz(rr, 2 * h + hh)]);
+                    }
+#pragma unroll
+                    for (int i = 0; i < TI; ++i)
+#pragma unroll
+                        for (int j = 0; j < TJ; ++j) acc[i][j] = LimbT<HALF>::mma32(fa[i], fb[j], acc[i][j]);
+                }
+        } else {
+#pragma unroll
+            for (int p = 0; p < P::n; ++p) {
+                gs8 fa[TI], fb[TJ];
+#pragma unroll
+                for (int i = 0; i < TI; ++i) {
+                    const int rr = wm * (BM / WM) + i * 16 + l16;
+                    fa[i] = *reinterpret_cast<const gs8 *>(&As[cur][P::a[p]][rr * RS + 8 * swz(rr, g)]);
+                }
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) {
+                    const int rr = wn * (BN / WN) + j * 16 + l16;
+                    fb[j] = *reinterpret_cast<const gs8 *>(&Bs[cur][P::b[p]][rr * RS + 8 * swz(rr, g)]);
+                }
+#pragma unroll
+                for (int i = 0; i < TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < TJ; ++j) acc[i][j] = LimbT<HALF>::mma(fa[i], fb[j], acc[i][j]);
+            }
+        }
+        if (more) {  // the other buffer was last read before the previous barrier
+            FUSED_STORE(cur ^ 1)
+        }
+        __syncthreads();
+    }
+#undef FUSED_LOAD
+#undef FUSED_LOAD_SIDE
+#undef FUSED_STORE_SIDE
+#undef FUSED_STORE
+
+    // Output: the leaf workspace, or (a single classical leaf) C with 2^(ea_i + eb_j) applied.
+    const bool direct = a.direct != 0, scaled = a.sc.ea != nullptr;
+    int ebj[TJ];
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+        const int64_t col = tn * BN + wn * (BN / WN) + j * MS + (M32 ? (lane & 31) : l16);
+        ebj[j] = (direct && scaled && col < a.n) ? a.sc.eb[col] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int64_t row = tm * BM + wm * (BM / WM) + i * MS +
+                                (M32 ? 8 * (v / 4) + 4 * (lane >> 5) + v % 4 : 4 * (lane >> 4) + v);
+            const int eai = (direct && scaled && row < a.m) ? a.post_exp + a.sc.ea[row] : 0;
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) {
+                const int64_t col = tn * BN + wn * (BN / WN) + j * MS + (M32 ? (lane & 31) : l16);
+                float val = acc[i][j][v];
+                if (direct) {
+                    if (row < a.m && col < a.n) {  // one power-of-two factor: exact unless it underflows
+                        if (scaled) val = ldexpf(val, eai + ebj[j]);
+                        a.out[row * a.ldo + col] = val;
+                    }
+                } else if (row < a.mb && col < a.nb) {
+                    if (a.post_exp) val = ldexpf(val, a.post_exp);
+                    a.out[(int64_t)leaf * a.leaf_stride + row * a.ldo + col] = val;
+                }
+            }
+        }
+}
+
+template <bool HALF, int NL, int BM, int BN, int WM, int WN, int QA, int QB, bool M32>
+__global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_fused(LimbFused a) {
+    __shared__ LimbSmem<NL, BM, BN> sm;
+    const int64_t tiles = (int64_t)a.tiles_m * a.tiles_n;
+    const int64_t item = xcd_remap_g(blockIdx.x, gridDim.x);
+    const int leaf = __builtin_amdgcn_readfirstlane((int)(item / tiles));
+    const int rem = __builtin_amdgcn_readfirstlane((int)(item - (int64_t)leaf * tiles));
+    const int grp = rem / (8 * a.tiles_n);
+    const int gsz = min(8, a.tiles_m - grp * 8);
+    const int gidx = rem - grp * 8 * a.tiles_n;
+    const int64_t tm = __builtin_amdgcn_readfirstlane(grp * 8 + gidx % gsz);
+    const int64_t tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
+    limb_tile_fused<HALF, NL, BM, BN, WM, WN, QA, QB, M32>(a, leaf, tm, tn, sm);
+}
+
 // Item `item` (leaf-major, tiles in groups of 8 tile rows) of one problem -> (leaf, tm, tn).
 __device__ __forceinline__ void limb_item(const LimbGemm &a, int64_t item, int &leaf, int64_t &tm, int64_t &tn) {
     const int64_t tiles = (int64_t)a.tiles_m * a.tiles_n;
@@ -604,15 +888,18 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void fmm_limb_gemm_batched(const L
 
 template <bool HALF, int NL, int NB>
 hipError_t form_regs_go(const PlaneForm &f, int nleaves, hipStream_t s) {
-    constexpr int TR = 16;  // small work-groups (two waves): several per CU, out of phase
+    // small work-groups (two waves when k is contiguous, four otherwise): several per CU, out
+    // of phase (one loading while another writes)
+    constexpr int TRK = 16, TRO = 32;
     if (f.kp / kFT > 65535) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(f.rowsp / TR), (unsigned)(f.kp / kFT)), block(TR * 8);
     const bool scaled = f.e_o != nullptr, kc = f.ld_k == 1;
+    const int tr = kc ? TRK : TRO;
+    const dim3 grid((unsigned)(f.rowsp / tr), (unsigned)(f.kp / kFT)), block(tr * 8);
     const size_t lds = (size_t)nleaves * f.nbo * f.nbk * sizeof(float);
-    if (scaled && kc) hipLaunchKernelGGL((form_regs<HALF, NL, true, true, NB, TR>), grid, block, lds, s, f, nleaves);
-    else if (scaled) hipLaunchKernelGGL((form_regs<HALF, NL, true, false, NB, TR>), grid, block, lds, s, f, nleaves);
-    else if (kc) hipLaunchKernelGGL((form_regs<HALF, NL, false, true, NB, TR>), grid, block, lds, s, f, nleaves);
-    else hipLaunchKernelGGL((form_regs<HALF, NL, false, false, NB, TR>), grid, block, lds, s, f, nleaves);
+    if (scaled && kc) hipLaunchKernelGGL((form_regs<HALF, NL, true, true, NB, TRK>), grid, block, lds, s, f, nleaves);
+    else if (scaled) hipLaunchKernelGGL((form_regs<HALF, NL, true, false, NB, TRO>), grid, block, lds, s, f, nleaves);
+    else if (kc) hipLaunchKernelGGL((form_regs<HALF, NL, false, true, NB, TRK>), grid, block, lds, s, f, nleaves);
+    else hipLaunchKernelGGL((form_regs<HALF, NL, false, false, NB, TRO>), grid, block, lds, s, f, nleaves);
     return hipGetLastError();
 }
 
@@ -680,7 +967,38 @@ hipError_t gemm_tile(int bm, const LimbGemm &g, int nleaves, hipStream_t s) {
     return gemm_go<HALF, NL, 128, 128, 2, 2>(g, nleaves, s);
 }
 
+template <bool HALF, int NL, int QA, int QB>
+hipError_t fused_go(const LimbFused &f, int nleaves, hipStream_t s) {
+    const int64_t blocks = (int64_t)f.tiles_m * f.tiles_n * nleaves;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if constexpr (NL < 3) {
+        hipLaunchKernelGGL((fmm_limb_fused<HALF, NL, 256, 256, 2, 4, QA, QB, true>), dim3((unsigned)blocks), dim3(512), 0,
+                           s, f);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+template <bool HALF, int NL>
+hipError_t fused_q(const LimbFused &f, int qa, int qb, int nleaves, hipStream_t s) {
+    if (qa <= 1 && qb <= 1) return fused_go<HALF, NL, 1, 1>(f, nleaves, s);
+    if (qa <= 2 && qb <= 2) return fused_go<HALF, NL, 2, 2>(f, nleaves, s);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+hipError_t launch_limb_fused(int prec, const LimbFused &f, int nleaves, hipStream_t s) {
+    const int qa = f.qa, qb = f.qb;  // most sources of a leaf on each side (the kernel's bound)
+    switch (prec) {
+        case FASTMM_BF16: return fused_q<false, 1>(f, qa, qb, nleaves, s);
+        case FASTMM_F16: return fused_q<true, 1>(f, qa, qb, nleaves, s);
+        case FASTMM_BF16X3: return fused_q<false, 2>(f, qa, qb, nleaves, s);
+        case FASTMM_F16X3: return fused_q<true, 2>(f, qa, qb, nleaves, s);
+    }
+    return hipErrorInvalidValue;
+}
 
 int limb_count(int prec) {
     switch (prec) {

@@ -209,11 +209,11 @@ class Plan:
         return self
 
     def path(self, m: int, k: int, n: int, transA: bool = False, transB: bool = False) -> str:
-        """'leaf', 'fused', 'every_level' or 'written': the execution path of an m x k by k x n
-        product."""
+        """'leaf', 'fused', 'every_level', 'written' or 'fused_loads': the execution path of an
+        m x k by k x n product."""
         v = ctypes.c_int()
         _check(lib().fastmm_plan_path(self._h, m, k, n, int(transA), int(transB), ctypes.byref(v)))
-        return {0: "leaf", 1: "fused", 2: "every_level", 3: "written"}[v.value]
+        return {0: "leaf", 1: "fused", 2: "every_level", 3: "written", 4: "fused_loads"}[v.value]
 
     @property
     def handle(self):

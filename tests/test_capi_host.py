@@ -181,6 +181,29 @@ def test_written_path_selection(F, precision):
     assert F.Plan("f424", 2, 1, precision="f16x3").path(256, 128, 256) == "leaf"
 
 
+def test_fused_loads_path_selection(F):
+    """With fusion "always", split precisions with 256-wide leaf blocks, at most two limbs and a
+    rule with at most two nonzeros per column of U and V (Strassen's; classical) form the
+    innermost level in the limb GEMM's loads; other rules, 128 tiles, three limbs, fusion off
+    and the default mode (the faster limb planes) take limb planes."""
+    P = lambda name, depth, prec="f16x3", fuse="always", **kw: F.Plan(name, depth, 1, precision=prec, fuse=fuse,
+                                                                       **kw)
+    assert P("strassen", 2, fuse="auto").path(1024, 1024, 1024) == "leaf"  # limb planes are faster
+    assert P("strassen", 2).path(1024, 1024, 1024) == "fused_loads"
+    assert P("strassen", 1).path(520, 1032, 600) == "fused_loads"
+    assert P("classical", 0).path(600, 520, 300) == "fused_loads"
+    assert P("strassen", 2, "bf16").path(1024, 1024, 1024) == "fused_loads"
+    assert P("strassen", 1).path(600, 520, 300) == "leaf"            # 150-wide blocks: 128 tiles
+    assert P("winograd", 1).path(1024, 1024, 1024) == "leaf"         # four nonzeros in a U column
+    assert P("f424", 2).path(4096, 4096, 4096) == "leaf"
+    assert P("strassen", 2, "bf16x6").path(1024, 1024, 1024) == "leaf"  # three limbs
+    assert P("strassen", 2, fuse="off").path(1024, 1024, 1024) == "leaf"
+    assert P("strassen", 2).set_tile(128).path(1024, 1024, 1024) == "leaf"
+    # the fused path needs no limb planes: its workspace is far smaller
+    assert P("strassen", 2).workspace_size(4096, 4096, 4096) < P("strassen", 2, fuse="off").workspace_size(
+        4096, 4096, 4096)
+
+
 def test_fused_path_matches_rules_by_coefficients(F):
     # Cyclic rotations (the rules of the backward pass) and user rules equal to a built-in
     # one take the fused path; a rule with its products reordered does not.
@@ -408,7 +431,8 @@ def test_every_level_scaling_plan_rules(F):
 
 def test_plan_tile_setting(F):
     # split precisions only; 256 x 256 needs at most two limbs; 0 returns to the shape's choice
-    p = F.Plan("strassen", 1, 1, precision="f16x3")
+    # (through limb planes, fusion off: the planes' padding follows the tile)
+    p = F.Plan("strassen", 1, 1, precision="f16x3", fuse="off")
     auto = p.workspace_size(600, 600, 600)
     assert p.set_tile(256).workspace_size(600, 600, 600) == auto  # 304-row leaf blocks take 256 tiles
     small = p.set_tile(128).workspace_size(600, 600, 600)
