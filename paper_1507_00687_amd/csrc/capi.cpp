@@ -467,6 +467,19 @@ struct WsLayout {
     size_t ea, ep, eb, flags, maxA, maxB, sp, tp, ia, ib, xa, xb, leaves, total;
 };
 
+// Whether a product takes the fused one-level kernel: FP64/FP32, at least one level, row-major
+// operands and a rule with a compiled sign pattern.  FASTMM_FUSE_AUTO leaves FP64 at depth 1
+// on the leaf path, whose 128x128 tiles run faster there (measured on MI355X: 44 against 40
+// effective TFLOP/s for Strassen at n = 8192); from depth 2 on, saving the leaf products'
+// round trip through memory wins.
+bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, uint32_t masks[6]) {
+    if (p->fuse == FASTMM_FUSE_OFF || s.L < 1 || transA || transB) return false;
+    if (!p->tree.empty() || !p->levels.empty()) return false;  // the fused kernel: one rule, every level
+    if (p->prec != FASTMM_F64 && p->prec != FASTMM_F32) return false;
+    if (p->fuse == FASTMM_FUSE_AUTO && p->prec == FASTMM_F64 && s.L < 2) return false;
+    return rule_masks_222(plan_algo(p), masks) && node222_supported(masks);
+}
+
 // FP64 / FP32 with a high fan-in: every leaf operand S_r (mb x kb) and T_r (kb x nb) is
 // written out level by level, stacked (leaf r's S_r at rows r mb .. of an R^L mb x xa_ld
 // matrix, T_r likewise at rows r kb of an R^L kb x xb_ld matrix, row strides multiples of 8),
@@ -490,6 +503,13 @@ bool written_leaves(const fastmm_plan_s *p, const Shape &s) {
     for (int l = 0; l < s.L; ++l) all *= a.R;
     if (leaf_count(a, s.L) != all || a.M0 * a.K0 > 16 || a.K0 * a.N0 > 16) return false;
     return plan_fan_in(p, s.L) > 4.0;
+}
+
+// The written path is taken where it applies and the fused kernel does not (the fused kernel,
+// where it applies to row-major operands, comes first; transposed operands are copied).
+bool written_taken(const fastmm_plan_s *p, const Shape &s) {
+    uint32_t masks[6];
+    return written_leaves(p, s) && !fused_path(p, s, 0, 0, masks);
 }
 
 struct WrittenDims {
@@ -578,7 +598,12 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
             w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
             w.ib = off, off = align256(off + inner_levels(p, s, true).back().off);
         }
-    } else if (written_leaves(p, s)) {
+    } else if (!is_split(p->prec) && !written_taken(p, s)) {
+        // FP64 / FP32: row-major copies of op(A) and op(B), scaled, for scaled plans with a
+        // level and for transposed operands (prescale_operands)
+        w.xa = off, off = align256(off + es * (size_t)s.Mp * round_up(s.Kp, 8));
+        w.xb = off, off = align256(off + es * (size_t)s.Kp * round_up(s.Np, 8));
+    } else if (written_taken(p, s)) {
         const WrittenDims wd = written_dims(s);
         const size_t nleaves = (size_t)plan_leaf_count(p, s.L);
         w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
@@ -590,19 +615,6 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
     if (s.L > 0) off = align256(off + es * (size_t)plan_leaf_count(p, s.L) * s.mb * s.nb);
     w.total = off;
     return w;
-}
-
-// Whether a product takes the fused one-level kernel: FP64/FP32, at least one level, row-major
-// operands and a rule with a compiled sign pattern.  FASTMM_FUSE_AUTO leaves FP64 at depth 1
-// on the leaf path, whose 128x128 tiles run faster there (measured on MI355X: 44 against 40
-// effective TFLOP/s for Strassen at n = 8192); from depth 2 on, saving the leaf products'
-// round trip through memory wins.
-bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, uint32_t masks[6]) {
-    if (p->fuse == FASTMM_FUSE_OFF || s.L < 1 || transA || transB) return false;
-    if (!p->tree.empty() || !p->levels.empty()) return false;  // the fused kernel: one rule, every level
-    if (p->prec != FASTMM_F64 && p->prec != FASTMM_F32) return false;
-    if (p->fuse == FASTMM_FUSE_AUTO && p->prec == FASTMM_F64 && s.L < 2) return false;
-    return rule_masks_222(plan_algo(p), masks) && node222_supported(masks);
 }
 
 std::string schedule_of(const fastmm_scaling &sc) {
@@ -1017,9 +1029,12 @@ fastmm_status fastmm_plan_path(fastmm_plan_t plan, int64_t m, int64_t k, int64_t
     if (!path || m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "bad arguments");
     const Shape s = shape_of(plan, m, k, n);
     uint32_t masks[6];
+    // FP64 / FP32 transposed operands are copied to row-major first (gemm_ex), so the fused
+    // kernel's choice does not depend on the transposition flags
+    (void)transA, (void)transB;
     *path = every_level(plan, s)                         ? FASTMM_PATH_EVERY_LEVEL
-            : fused_path(plan, s, transA, transB, masks) ? FASTMM_PATH_FUSED
-            : written_leaves(plan, s)                    ? FASTMM_PATH_WRITTEN
+            : fused_path(plan, s, 0, 0, masks)           ? FASTMM_PATH_FUSED
+            : written_taken(plan, s)                     ? FASTMM_PATH_WRITTEN
             : fused_split(plan, s)                       ? FASTMM_PATH_FUSED_LOADS
                                                          : FASTMM_PATH_LEAF;
     return FASTMM_OK;
@@ -1240,6 +1255,40 @@ hipError_t fused_split_operands(fastmm_plan_s *plan, const Shape &s, const void 
     f.mb = s.mb, f.nb = s.nb, f.m = m, f.n = n, f.sc = exps, f.post_exp = -2 * pre;
     f.tiles_m = (int)((s.mb + 255) / 256), f.tiles_n = (int)((s.nb + 255) / 256);
     return hipSuccess;
+}
+
+// FP64 / FP32: row-major copies A2 = op(A) (m x lda2) and B2 = op(B) (k x ldb2) in the workspace,
+// with the scaling factors applied when `scale` (A' = diag(2^-ea) op(A) diag(2^ep),
+// B' = diag(2^-ep) op(B) diag(2^-eb)), by a 1 x 1 level of form_node.  The product kernels then
+// read plain row-major operands: a scaled product applies each factor once here instead of once
+// per source in every K stage of every tile that reads the element, and transposed operands
+// take the fast row-major kernels.
+hipError_t prescale_operands(fastmm_plan_s *plan, const Shape &s, const void *A, int64_t lda, int transA,
+                             const void *B, int64_t ldb, int transB, int64_t m, int64_t k, int64_t n,
+                             const ScaleExps &exps, bool scale, char *ws, const WsLayout &w, const Tables *tab,
+                             hipStream_t st, const void **A2, int64_t *lda2, const void **B2, int64_t *ldb2) {
+    (void)s;
+    // Without scaling only a transposed operand is copied; the other is used in place.
+    const bool copy_a = scale || transA, copy_b = scale || transB;
+    const int prec = plan->prec == FASTMM_F64 ? FASTMM_F64 : FASTMM_F32;
+    const int64_t ka = round_up(k, 8), nbl = round_up(n, 8);
+    NodeForm fa{};
+    fa.X = A, fa.ld_o = transA ? 1 : lda, fa.ld_k = transA ? lda : 1, fa.R = m, fa.K = k, fa.first = 1;
+    if (scale) fa.e_o = exps.ea, fa.e_k = exps.ep, fa.s_o = -1, fa.s_k = 1;
+    fa.nO = 1, fa.nK = 1, fa.side_b = 0, fa.R_ = 1, fa.coef = tab->unit;
+    fa.cb_o = m, fa.cb_k = k, fa.last = 0, fa.Y = ws + w.xa, fa.y_ld = ka, fa.y_stride = m * ka;
+    NodeForm fb{};
+    fb.X = B, fb.ld_o = transB ? ldb : 1, fb.ld_k = transB ? 1 : ldb, fb.R = n, fb.K = k, fb.first = 1;
+    if (scale) fb.e_o = exps.eb, fb.e_k = exps.ep, fb.s_o = -1, fb.s_k = -1;
+    fb.nO = 1, fb.nK = 1, fb.side_b = 1, fb.R_ = 1, fb.coef = tab->unit;
+    fb.cb_o = n, fb.cb_k = k, fb.last = 0, fb.Y = ws + w.xb, fb.y_ld = nbl, fb.y_stride = k * nbl, fb.kmajor = 1;
+    hipError_t e = copy_a ? launch_form_node(prec, fa, 1, st) : hipSuccess;
+    if (e == hipSuccess && copy_b) e = launch_form_node(prec, fb, 1, st);
+    if (copy_a) *A2 = ws + w.xa, *lda2 = ka;
+    else *A2 = A, *lda2 = lda;
+    if (copy_b) *B2 = ws + w.xb, *ldb2 = nbl;
+    else *B2 = B, *ldb2 = ldb;
+    return e;
 }
 
 // FP64 / FP32 with written-out leaf operands: the leaf operands of both sides level by level
@@ -1527,9 +1576,21 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
         return FASTMM_OK;
     }
+    // FP64 / FP32 outside the written path: scaled plans with a level and transposed operands
+    // run on row-major (scaled) copies of the operands
+    const bool written = written_taken(plan, s);
+    const bool scaled_copy = !written && exps.ea != nullptr && s.L >= 1;
+    if (!written && (scaled_copy || transA || transB)) {
+        if ((e = prescale_operands(plan, s, A, lda, transA, B, ldb, transB, m, k, n, exps, scaled_copy, ws, w, tab,
+                                   st, &A, &lda, &B, &ldb)) != hipSuccess)
+            return hip_fail(e, "operand copies");
+        transA = transB = 0;
+        L.A = A, L.B = B, L.lda = lda, L.ldb = ldb, L.transA = L.transB = 0;
+        if (scaled_copy) L.sc = ScaleExps{nullptr, nullptr, nullptr};  // the products read scaled copies
+    }
     uint32_t masks[6];
     const bool fused = fused_path(plan, s, transA, transB, masks);
-    if (!fused && written_leaves(plan, s)) {
+    if (written) {
         // leaf operands written out level by level, then one launch over the stacked blocks
         // (one source per leaf, unscaled: the formation applied the factors), then the
         // W-combination with D_A, D_B
@@ -1573,7 +1634,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         N.mb = s.mb, N.kb = s.kb, N.nb = s.nb;
         N.nnodes = outer->nleaves;
         N.outer = outer->leaves, N.asrc = outer->asrc, N.bsrc = outer->bsrc;
-        N.sc = exps;
+        N.sc = exps, N.scale_in = scaled_copy ? 0 : 1;
         for (int i = 0; i < 6; ++i) N.masks[i] = masks[i];
         if (s.L == 1) {
             N.out = C, N.ldo = ldc, N.node_stride = 0;

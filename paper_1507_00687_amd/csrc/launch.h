@@ -120,6 +120,8 @@ struct NodeLaunch {
     const SrcEntry *asrc;
     const SrcEntry *bsrc;
     ScaleExps sc;
+    int scale_in = 1;   // with sc: 1 scales the operands while loading, 0 takes them as already
+                        // scaled (sc then only scales the depth-1 output)
     uint32_t masks[6];  // (U+, U-, V+, V-, W+, W-): bit s*7+r marks coefficient +1 / -1
 };
 // Whether a compiled fused kernel exists for this sign pattern.

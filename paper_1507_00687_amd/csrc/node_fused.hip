@@ -104,7 +104,8 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t G) {
     return ((x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + j;
 }
 
-template <typename T, bool SCALED, uint32_t UP, uint32_t UN, uint32_t VP, uint32_t VN, uint32_t WP, uint32_t WN>
+template <typename T, bool SCALED, bool SCALED_OUT, uint32_t UP, uint32_t UN, uint32_t VP, uint32_t VN, uint32_t WP,
+          uint32_t WN>
 __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
     typedef NCore<T> C;
     typedef typename C::vec_t vec_t;
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
                     const int64_t row = rsub + lr, col = csub + lc;  // inside the node's output
                     if (p.node_stride == 0) {  // depth 1: the node is the whole product
                         if (row < p.m && col < p.n) {
-                            if (SCALED) val = C::scale(val, p.sc.ea[row] + p.sc.eb[col]);
+                            if (SCALED_OUT) val = C::scale(val, p.sc.ea[row] + p.sc.eb[col]);
                             p.out[row * p.ldo + col] = val;
                         }
                     } else {
@@ -435,12 +436,16 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
     X(0xe385a83u, 0x0020000u, 0x7019845u, 0x0802220u, 0xd840129u, 0x01a0410u)          \
     X(0xd840129u, 0x01a0410u, 0xe385a83u, 0x0020000u, 0x7019845u, 0x0802220u)
 
+// scaled_in: the operands are scaled while loading; scaled: the depth-1 output takes
+// 2^(ea_i + eb_j) (operands already scaled when !scaled_in)
 template <typename T, uint32_t UP, uint32_t UN, uint32_t VP, uint32_t VN, uint32_t WP, uint32_t WN>
-hipError_t node_launch(const NArgs<T> &a, unsigned blocks, bool scaled, hipStream_t s) {
-    if (scaled)
-        hipLaunchKernelGGL((fmm_node222<T, true, UP, UN, VP, VN, WP, WN>), dim3(blocks), dim3(kNT), 0, s, a);
+hipError_t node_launch(const NArgs<T> &a, unsigned blocks, bool scaled, bool scaled_in, hipStream_t s) {
+    if (scaled && scaled_in)
+        hipLaunchKernelGGL((fmm_node222<T, true, true, UP, UN, VP, VN, WP, WN>), dim3(blocks), dim3(kNT), 0, s, a);
+    else if (scaled)
+        hipLaunchKernelGGL((fmm_node222<T, false, true, UP, UN, VP, VN, WP, WN>), dim3(blocks), dim3(kNT), 0, s, a);
     else
-        hipLaunchKernelGGL((fmm_node222<T, false, UP, UN, VP, VN, WP, WN>), dim3(blocks), dim3(kNT), 0, s, a);
+        hipLaunchKernelGGL((fmm_node222<T, false, false, UP, UN, VP, VN, WP, WN>), dim3(blocks), dim3(kNT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -471,7 +476,7 @@ hipError_t node_go(const NodeLaunch &L, hipStream_t s) {
     const uint32_t *m = L.masks;
 #define FASTMM_NODE_TRY(up, un, vp, vn, wp, wn)                                                        \
     if (m[0] == up && m[1] == un && m[2] == vp && m[3] == vn && m[4] == wp && m[5] == wn)             \
-        return node_launch<T, up, un, vp, vn, wp, wn>(a, (unsigned)blocks, scaled, s);
+        return node_launch<T, up, un, vp, vn, wp, wn>(a, (unsigned)blocks, scaled, scaled && L.scale_in, s);
     FASTMM_NODE222_PATTERNS(FASTMM_NODE_TRY)
 #undef FASTMM_NODE_TRY
     return hipErrorInvalidValue;

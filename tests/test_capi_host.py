@@ -147,9 +147,10 @@ def test_fused_path_selection(F, precision):
     assert P("strassen", 1, fuse="always").path(256, 256, 256) == "fused"
     assert P("winograd", 3).path(300, 200, 100) == "fused"
     assert P("strassen", 2).path(17, 300, 41) == "fused"
-    # transposed operands, no level, cutoff stopping at depth 0, other rules, fusion off
-    assert P("strassen", 1).path(256, 256, 256, transB=True) == "leaf"
-    assert P("strassen", 1).path(256, 256, 256, transA=True) == "leaf"
+    # transposed operands are copied to row-major and take the fused kernel too; no level,
+    # cutoff stopping at depth 0, other rules, fusion off take the leaf path
+    assert P("strassen", 2).path(256, 256, 256, transB=True) == "fused"
+    assert P("strassen", 2).path(256, 256, 256, transA=True) == "fused"
     assert P("strassen", 0).path(256, 256, 256) == "leaf"
     assert P("strassen", 2, 512).path(256, 256, 256) == "leaf"
     assert P("f323", 1).path(300, 200, 300) == "leaf"
