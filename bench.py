@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--dist", default="normal")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--err-rows", type=int, default=16)
-    ap.add_argument("--cpu-n", type=int, default=4096,
+    ap.add_argument("--cpu-n", type=int, default=8192,
                     help="size of the oracle timing sample (same algorithm, depth and distribution)")
     ap.add_argument("--also", default="f424",
                     help="also time this rule at the same depth, size, scaling and precision (none = skip)")
@@ -184,23 +184,35 @@ def leaf_flops(F, plan_algo, plan, m, k, n, precision):
 
 def batch_main(args):
     """A batch of rectangular problems (dims drawn from {512, ..., 8192}, tall-skinny included,
-    N(0,1) entries from a seeded generator on the GPU), plans chosen per shape by the autotuner,
-    run as one fastmm_gemm_batched call per step; the same batch with classical plans beside."""
+    N(0,1) entries from the seeded host generator), plans chosen per shape by the autotuner; a
+    step is one training step of the batch: the forward products in one fastmm_gemm_batched call,
+    then the gradients dA_i = G_i B_i^T, dB_i = A_i^T G_i of every problem in one
+    fastmm_gemm_backward_batched call.  The same batch with classical plans beside."""
     import numpy as np
     import torch
 
     import paper_1507_00687_amd as F
     from paper_1507_00687_amd import tune as T
+    from synth import make_pair
+    from synth.gen import TAG_G, normal01
 
     torch.cuda.set_device(0)
     rng = np.random.default_rng(args.seed)
     dims = np.array([512, 1024, 2048, 4096, 8192])
     shapes = [tuple(int(x) for x in rng.choice(dims, 3)) for _ in range(args.batch)]
-    dt = torch.float64 if args.precision == "f64" else torch.float32
-    gen = torch.Generator(device="cuda").manual_seed(args.seed)
-    As = [torch.randn((m, k), dtype=dt, device="cuda", generator=gen) for m, k, n in shapes]
-    Bs = [torch.randn((k, n), dtype=dt, device="cuda", generator=gen) for m, k, n in shapes]
-    Cs = [torch.empty((m, n), dtype=dt, device="cuda") for m, k, n in shapes]
+    ndt = np.float64 if args.precision == "f64" else np.float32
+    t0 = time.perf_counter()
+    hostA, hostB, hostG = [], [], []
+    for i, (m, k, n) in enumerate(shapes):
+        A, B = make_pair("normal", args.seed + i, m, k, n, dtype=ndt)
+        hostA.append(A)
+        hostB.append(B)
+        hostG.append(normal01(args.seed + i, TAG_G, (m, n)).astype(ndt))
+    gen_s = time.perf_counter() - t0
+    As = [torch.from_numpy(X).cuda() for X in hostA]
+    Bs = [torch.from_numpy(X).cuda() for X in hostB]
+    Gs = [torch.from_numpy(X).cuda() for X in hostG]
+    Cs = [torch.empty((m, n), dtype=As[0].dtype, device="cuda") for m, k, n in shapes]
     t0 = time.perf_counter()
     choices = T.tune(shapes, precision=args.precision, cache=args.tune_cache or None, max_depth=2,
                      cutoffs=(128, 256, 512), max_instability=args.max_instability, reps=2)
@@ -211,34 +223,78 @@ def batch_main(args):
     cws = torch.empty(max(F.fastmm_batched_workspace_size(cplans, As, Bs), 1), dtype=torch.uint8, device="cuda")
     Cc = [torch.empty_like(c) for c in Cs]
     flops = sum(2.0 * m * k * n for m, k, n in shapes)
-    run = lambda: F.fastmm_gemm_batched(plans, As, Bs, Cs, workspace=ws)
+    fwd = lambda: F.fastmm_gemm_batched(plans, As, Bs, Cs, workspace=ws)
+    grads = {}
+    bwd = lambda: grads.__setitem__("fast", F.fastmm_gemm_backward_batched(plans, As, Bs, Gs))
+    cbwd = lambda: grads.__setitem__("classical", F.fastmm_gemm_backward_batched(cplans, As, Bs, Gs))
     ms_cls = time_steps(lambda: F.fastmm_gemm_batched(cplans, As, Bs, Cc, workspace=cws), args.steps, args.warmup)
-    ms = time_steps(run, args.steps, args.warmup)
+    ms_cls_b = time_steps(cbwd, args.steps, args.warmup)
+    ms = time_steps(fwd, args.steps, args.warmup)
+    ms_b = time_steps(bwd, args.steps, args.warmup)
 
     F.fastmm_profile_enable(True)
     F.fastmm_profile_read()
     for _ in range(args.steps):
-        run()
+        fwd()
     prof = F.fastmm_profile_read()
+    for _ in range(args.steps):
+        bwd()
+    prof_b = F.fastmm_profile_read()
     F.fastmm_profile_enable(False)
     calls = max(prof["calls"], 1)
+    calls_b = max(prof_b["calls"], 1)
     leaf_ms = prof["leaf_ms"] / calls
     executed = sum(leaf_flops(F, choices[sh].algo, p, *sh, args.precision) for sh, p in zip(shapes, plans))
     achieved = executed / (leaf_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
 
-    # errors of a few problems on sampled rows against the long-double reference (oracle leg)
+    # errors of a few problems on sampled rows against the long-double reference (oracle leg):
+    # C = A B, dA = G B^T, dB = A^T G
     from oracle import fastmm_oracle as O
 
-    err_fast = err_cls = 0.0
-    for i in np.unique(np.linspace(0, len(shapes) - 1, 4).astype(int)):
+    err = {"fast": 0.0, "classical": 0.0, "fast_dA": 0.0, "fast_dB": 0.0, "classical_dA": 0.0,
+           "classical_dB": 0.0}
+    sampled = np.unique(np.linspace(0, len(shapes) - 1, 4).astype(int))
+    for i in sampled:
         m, k, n = shapes[i]
+        A64, B64, G64 = (X.astype(np.float64) for X in (hostA[i], hostB[i], hostG[i]))
         rows = np.unique(np.linspace(0, m - 1, 4).astype(np.int64))
-        A64 = As[i].double().cpu().numpy()
-        B64 = Bs[i].double().cpu().numpy()
         ref = O.reference_rows(A64, B64, rows)
-        err_fast = max(err_fast, O.normwise_error(Cs[i].cpu().numpy(), ref, A64, B64, rows))
-        err_cls = max(err_cls, O.normwise_error(Cc[i].cpu().numpy(), ref, A64, B64, rows))
+        err["fast"] = max(err["fast"], O.normwise_error(Cs[i].cpu().numpy(), ref, A64, B64, rows))
+        err["classical"] = max(err["classical"], O.normwise_error(Cc[i].cpu().numpy(), ref, A64, B64, rows))
+        Bt, At = np.ascontiguousarray(B64.T), np.ascontiguousarray(A64.T)
+        rows_b = np.unique(np.linspace(0, k - 1, 4).astype(np.int64))
+        ref_a = O.reference_rows(G64, Bt, rows)
+        ref_b = O.reference_rows(At, G64, rows_b)
+        for key in ("fast", "classical"):
+            dA, dB = grads[key][i]
+            err[key + "_dA"] = max(err[key + "_dA"], O.normwise_error(dA.cpu().numpy(), ref_a, G64, Bt, rows))
+            err[key + "_dB"] = max(err[key + "_dB"], O.normwise_error(dB.cpu().numpy(), ref_b, At, G64, rows_b))
+    # the oracle timed on the largest problems of the batch with their tuned plans, until about
+    # 10 s of CPU work (at most 4 problems)
+    cpu = None
+    if not args.no_cpu:
+        from oracle import coeffs as C
+
+        order = sorted(range(len(shapes)), key=lambda j: -shapes[j][0] * shapes[j][1] * shapes[j][2])
+        done, fl_cpu, dt_cpu = [], 0.0, 0.0
+        for i in order[:4]:
+            m, k, n = shapes[i]
+            c = choices[shapes[i]]
+            A64, B64 = hostA[i].astype(np.float64), hostB[i].astype(np.float64)
+            t0 = time.perf_counter()
+            if c.depth == 0 or c.algo == "classical" or c.levels:
+                O.classical(A64, B64)
+            else:
+                O.fast(A64, B64, C.get(ORACLE_NAME.get(c.algo, c.algo)), c.depth, c.cutoff)
+            dt_cpu += time.perf_counter() - t0
+            fl_cpu += 2.0 * m * k * n
+            done.append(f"{m}x{k}x{n} {c.algo} L={c.depth}")
+            if dt_cpu >= 10.0:
+                break
+        cpu = {"value": fl_cpu / dt_cpu / 1e12, "unit": "TFLOP/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"oracle FP64 forward of the largest problems of the batch ({', '.join(done)}), "
+                         f"{dt_cpu:.2f} s"}
     mix = {}
     for sh in shapes:
         c = choices[sh]
@@ -246,32 +302,41 @@ def batch_main(args):
         mix[key] = mix.get(key, 0) + 1
     kname = "fmm_limb_gemm_batched" if args.precision in ("bf16", "f16", "bf16x3", "f16x3", "bf16x6") else \
         "fmm_leaf_batched"
+    total = ms + ms_b
     line = {
         "metric": METRIC,
-        "value": flops / (ms * 1e-3) / 1e12,
+        "value": 3.0 * flops / (total * 1e-3) / 1e12,
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": total,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": f"batch of {len(shapes)} problems, dims from 512..8192 (seed {args.seed}), "
-                               f"autotuned plans, {args.precision}, N(0,1)",
-                   "problems": len(shapes), "flops_2mkn": flops, "plan_mix": mix,
+                               f"autotuned plans, {args.precision}, N(0,1), forward + backward",
+                   "problems": len(shapes), "flops_2mkn": flops, "plan_mix": mix, "generation_s": gen_s,
                    "tuning_s": tune_s, "max_instability": args.max_instability},
-        "classical": {"ms_per_step": ms_cls, "value": flops / (ms_cls * 1e-3) / 1e12},
-        "speedup_vs_classical": ms_cls / ms,
-        "error": {"fast": err_fast, "classical": err_cls, "problems_sampled": 4, "rows_per_problem": 4,
-                  "reference": "long double classical (oracle)"},
+        "forward": {"ms_per_step": ms, "value": flops / (ms * 1e-3) / 1e12},
+        "backward": {"ms_per_step": ms_b, "value": 2.0 * flops / (ms_b * 1e-3) / 1e12,
+                     "launches": "one fastmm_gemm_backward_batched call (dA and dB of every problem, one "
+                                 "products launch)"},
+        "classical": {"ms_per_step": ms_cls + ms_cls_b, "forward_ms": ms_cls, "backward_ms": ms_cls_b,
+                      "value": 3.0 * flops / ((ms_cls + ms_cls_b) * 1e-3) / 1e12},
+        "speedup_vs_classical": (ms_cls + ms_cls_b) / total,
+        "error": dict(err, problems_sampled=len(sampled), rows_per_problem=4,
+                      reference="long double classical (oracle)"),
         "phases_ms": {"scaling": prof["scaling_ms"] / calls, "form": prof["form_ms"] / calls, "leaf": leaf_ms,
                       "combine": prof["combine_ms"] / calls},
+        "phases_ms_backward": {"scaling": prof_b["scaling_ms"] / calls_b, "form": prof_b["form_ms"] / calls_b,
+                               "leaf": prof_b["leaf_ms"] / calls_b, "combine": prof_b["combine_ms"] / calls_b},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": kname, "flops_per_launch": executed},
-        "cpu_baseline": None,
+                     "frac": achieved / peak, "traffic": None, "kernel": kname, "flops_per_launch": executed,
+                     "launch": "forward products"},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

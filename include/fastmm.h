@@ -286,6 +286,21 @@ typedef struct {
 fastmm_status fastmm_batched_workspace_size(const fastmm_plan_t *plans, const fastmm_problem *probs,
                                             int count, size_t *bytes);
 
+/* One product of a batch as fastmm_gemm_ex takes it: C = op(A) op(B) with op(A) m x k and
+ * op(B) k x n, op(X) = X^T when the flag is nonzero (A then stored k x m, B n x k), row-major
+ * storage with leading dimensions lda, ldb (at least the stored row length) and ldc >= n. */
+typedef struct {
+    const void *A;
+    int64_t lda;
+    int transA;
+    const void *B;
+    int64_t ldb;
+    int transB;
+    void *C;
+    int64_t ldc;
+    int64_t m, k, n;
+} fastmm_problem_ex;
+
 /* Multiply `count` independent problems, problem i with plans[i] (its own rule, depth,
  * cutoff and scaling; all plans must share one precision).  Each problem's scaling steps run
  * first (and, for the split precisions, its limb-plane formation); then ONE launch computes the
@@ -297,6 +312,17 @@ fastmm_status fastmm_batched_workspace_size(const fastmm_plan_t *plans, const fa
  * the workspace (a staged copy). */
 fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_problem *probs, int count,
                                   void *workspace, size_t ws_bytes, void *stream);
+
+/* fastmm_gemm_batched for strided and transposed operands (fastmm_problem_ex); the same single
+ * launch of the products.  The split precisions form their limb planes from transposed
+ * operands directly; FP64 / FP32 copy a transposed operand into the workspace first (the
+ * batched leaf kernel reads row-major operands).  Same errors as fastmm_gemm_ex, per problem
+ * (FASTMM_ESHAPE for a leading dimension below the stored row length), plus FASTMM_EALIAS when
+ * an output overlaps any input or another output of the batch. */
+fastmm_status fastmm_batched_ex_workspace_size(const fastmm_plan_t *plans, const fastmm_problem_ex *probs,
+                                               int count, size_t *bytes);
+fastmm_status fastmm_gemm_batched_ex(const fastmm_plan_t *plans, const fastmm_problem_ex *probs, int count,
+                                     void *workspace, size_t ws_bytes, void *stream);
 
 /* ---- a multiplication that allocates nothing ---------------------------------------- */
 
@@ -328,17 +354,42 @@ fastmm_status fastmm_gemm_noalloc(fastmm_plan_t plan, const void *A, const void 
 /* ---- differentiation ----------------------------------------------------------------- */
 
 /* Gradients of a loss through C = A B: dA = G B^T and dB = A^T G for G = dLoss/dC (m x n),
- * computed by the same recursion with the cyclic rotations of the plan's rule (the rotation
- * rule stated with Appendices B and C): dA^T = B G^T is a <K0,N0,M0> product, done by
- * [V,W,U]; dB^T = G^T A is a <N0,M0,K0> product, done by [W,U,V]; each result is transposed
- * into place.  Same depth, cutoff, scaling and precision as the plan.  A (m x k), B (k x n),
- * G (m x n) are contiguous row-major inputs; dA (m x k) and dB (k x n) outputs, either may be
- * NULL to skip it.  Workspace: fastmm_backward_workspace_size bytes. */
+ * computed by the same recursion with rules derived from the plan's rule by the symmetries of
+ * section 3.1: dA = G B^T is a <M0,N0,K0> product, done by the transpose of the cyclic rotation
+ * [V,W,U] (the rule that forms B G^T = dA^T); dB = A^T G is a <K0,M0,N0> product, done by the
+ * transpose of [W,U,V] (which forms G^T A = dB^T).  Each product reads its transposed operand
+ * (B^T, resp. A^T) through the transpose flags of fastmm_gemm_ex and writes its result in
+ * place: nothing is transposed before or after.  Same depth, cutoff, scaling, precision and
+ * fusion mode as the plan (for uniform non-stationary plans every level's rule is transformed
+ * alike).  A (m x k), B (k x n), G (m x n) are contiguous row-major inputs; dA (m x k) and
+ * dB (k x n) outputs, either may be NULL to skip it; with m = 0 (resp. n = 0) the requested
+ * dB (dA) is filled with zeros.  Workspace: fastmm_backward_workspace_size bytes.
+ * FASTMM_EUNSUPPORTED for plans with a non-uniform tree (fastmm_plan_set_tree). */
 fastmm_status fastmm_backward_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n,
                                              size_t *bytes);
 fastmm_status fastmm_gemm_backward(fastmm_plan_t plan, const void *A, const void *B, const void *G,
                                    void *dA, void *dB, int64_t m, int64_t k, int64_t n,
                                    void *workspace, size_t ws_bytes, void *stream);
+
+/* One problem of a batched backward pass: inputs A (m x k), B (k x n), G (m x n), outputs dA
+ * (m x k) and dB (k x n), contiguous row-major; either output may be NULL. */
+typedef struct {
+    const void *A;
+    const void *B;
+    const void *G;
+    void *dA;
+    void *dB;
+    int64_t m, k, n;
+} fastmm_grad_problem;
+
+/* The backward pass of a batch (section 3.1 symmetries as in fastmm_gemm_backward), problem i
+ * with plans[i]: the 2 x count gradient products (dA_i = G_i B_i^T, dB_i = A_i^T G_i) run as ONE
+ * fastmm_gemm_batched_ex call, so their leaf products share one launch.  All plans share one
+ * precision.  Outputs must not overlap any input or each other (FASTMM_EALIAS). */
+fastmm_status fastmm_backward_batched_workspace_size(const fastmm_plan_t *plans, const fastmm_grad_problem *probs,
+                                                     int count, size_t *bytes);
+fastmm_status fastmm_gemm_backward_batched(const fastmm_plan_t *plans, const fastmm_grad_problem *probs, int count,
+                                           void *workspace, size_t ws_bytes, void *stream);
 
 /* ---- scaling vectors (the reductions of Algorithms 1-3, exposed for verification) ---- */
 

@@ -17,7 +17,9 @@ from .fastmm import (  # noqa: F401
     fastmm_batched_workspace_size,
     fastmm_gemm,
     fastmm_gemm_backward,
+    fastmm_gemm_backward_batched,
     fastmm_gemm_batched,
+    fastmm_gemm_batched_ex,
     fastmm_gemm_ex,
     fastmm_gemm_noalloc,
     fastmm_profile_enable,

@@ -1,9 +1,11 @@
 """torch.autograd.Function for C = A B through a fast-multiplication plan.
 
 Forward: fastmm_gemm with the plan's rule.  Backward: fastmm_gemm_backward, which computes
-dA = G B^T and dB = A^T G with the cyclic rotations of the same rule ([V,W,U] for the
-<K0,N0,M0> product B G^T and [W,U,V] for the <N0,M0,K0> product G^T A), at the plan's depth,
-cutoff, scaling and precision.  Argument marshalling only; the arithmetic runs in libfastmm.so.
+dA = G B^T and dB = A^T G with rules derived from the same rule by the symmetries of section 3.1
+(the transpose of the rotation [V,W,U] for the <M0,N0,K0> product G B^T, the transpose of
+[W,U,V] for the <K0,M0,N0> product A^T G), at the plan's depth, cutoff, scaling and precision,
+reading B^T and A^T through transpose flags.  Argument marshalling only; the arithmetic runs in
+libfastmm.so.
 """
 from __future__ import annotations
 

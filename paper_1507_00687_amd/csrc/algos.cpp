@@ -175,6 +175,31 @@ Algo rotate(const Algo &a, const char *name) {
     return b;
 }
 
+// The transposed rule: applied to (B^T, A^T) it forms (C)^T, so it is a rule for <N0,K0,M0>.
+// Under the single-index conventions (A and B blocks column-major, C blocks row-major) its
+// product r takes as left operand the transposes of the B blocks that product r of `a` takes,
+// as right operand the transposes of a's A blocks, and contributes to the transposed C blocks:
+// S'_r = T_r^T, T'_r = S_r^T, M'_r = M_r^T (section 3.1 notation).
+Algo transpose_rule(const Algo &a, const char *name) {
+    Algo t;
+    t.name = name;
+    t.M0 = a.N0, t.K0 = a.K0, t.N0 = a.M0, t.R = a.R;
+    const int R = a.R;
+    t.U.assign((size_t)a.N0 * a.K0 * R, 0);
+    t.V.assign((size_t)a.K0 * a.M0 * R, 0);
+    t.W.assign((size_t)a.N0 * a.M0 * R, 0);
+    t.den_U = a.den_V, t.den_V = a.den_U, t.den_W = a.den_W;
+    for (int r = 0; r < R; ++r) {
+        for (int p = 0; p < a.N0; ++p)  // A' = B^T: block (p, q) is B's block (q, p) transposed
+            for (int q = 0; q < a.K0; ++q) t.U[(size_t)(p + q * a.N0) * R + r] = a.V[(size_t)(q + p * a.K0) * R + r];
+        for (int q = 0; q < a.K0; ++q)  // B' = A^T: block (q, s) is A's block (s, q) transposed
+            for (int s = 0; s < a.M0; ++s) t.V[(size_t)(q + s * a.K0) * R + r] = a.U[(size_t)(s + q * a.M0) * R + r];
+        for (int p = 0; p < a.N0; ++p)  // C' = C^T, row-major blocks
+            for (int s = 0; s < a.M0; ++s) t.W[(size_t)(p * a.M0 + s) * R + r] = a.W[(size_t)(s * a.N0 + p) * R + r];
+    }
+    return t;
+}
+
 // Rules written as products of sums of named entries.  An entry "xPQ" is row P, column Q
 // (1-based) of the A or B base matrix; outputs "cPQ" list (product number, sign).
 struct Term {
@@ -274,6 +299,7 @@ struct Registry {
     std::vector<Algo> builtin;  // index = fastmm_algo id
     std::vector<Algo> user;     // id = FASTMM_ALGO_USER0 + index
     std::map<std::pair<int, int>, int> rotations;  // (id, times) -> id of the rotated rule
+    std::map<std::pair<int, int>, int> transposed;  // (id, times) -> id of the transposed rotation
     bool ok = false;
     Registry() {
         builtin.resize(10);
@@ -389,6 +415,23 @@ int algo_rotated(int id, int times) {
     if (brent_violations(r) != 0) return -1;
     const int nid = register_locked(reg, std::move(r));
     if (nid >= 0) reg.rotations[{id, times}] = nid;
+    return nid;
+}
+
+int algo_transposed_rotation(int id, int times) {
+    times = ((times % 3) + 3) % 3;
+    const Algo *a = algo_get(id);
+    if (!a) return -1;
+    Registry &reg = registry();
+    std::lock_guard<std::mutex> g(reg.mu);
+    auto it = reg.transposed.find({id, times});
+    if (it != reg.transposed.end()) return it->second;
+    Algo r = *a;
+    for (int t = 0; t < times; ++t) r = rotate(r, "rotation");
+    r = transpose_rule(r, "transposed rotation");
+    if (brent_violations(r) != 0) return -1;
+    const int nid = register_locked(reg, std::move(r));
+    if (nid >= 0) reg.transposed[{id, times}] = nid;
     return nid;
 }
 

@@ -276,8 +276,9 @@ struct fastmm_plan_s {
     std::vector<int> levels;
     std::mutex mu;
     std::map<std::pair<int, int>, std::unique_ptr<fastmm::Tables>> tables;  // (L, device)
-    // Sub-plans with the rotated rules, made on first use by the backward pass.
-    std::unique_ptr<fastmm_plan_s> rot[3];
+    // Sub-plans of the backward pass (made on first use): [0] forms dA = G B^T with the
+    // transpose of the rotation [V,W,U], [1] forms dB = A^T G with the transpose of [W,U,V].
+    std::unique_ptr<fastmm_plan_s> grad[2];
     // Scaling at every level: the plans of the first level's node products, by the depth of
     // the call that uses them (made on first use).
     std::map<int, std::unique_ptr<fastmm_plan_s>> node_plans;
@@ -940,7 +941,7 @@ fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode) {
     if (mode < FASTMM_FUSE_OFF || mode > FASTMM_FUSE_ALWAYS) return fail(FASTMM_EINVAL, "unknown fusion mode");
     std::lock_guard<std::mutex> g(plan->mu);
     plan->fuse = mode;
-    for (auto &r : plan->rot)
+    for (auto &r : plan->grad)
         if (r) r->fuse = plan->fuse;
     plan->node_plans.clear();  // remade with the new mode on next use
     return FASTMM_OK;
@@ -953,7 +954,7 @@ fastmm_status fastmm_plan_set_tile(fastmm_plan_t plan, int tile) {
     if (tile == 256 && limb_count(plan->prec) > 2) return fail(FASTMM_EUNSUPPORTED, "256 tiles take at most two limbs");
     std::lock_guard<std::mutex> g(plan->mu);
     plan->tile = tile;
-    for (auto &r : plan->rot)
+    for (auto &r : plan->grad)
         if (r) r->tile = tile;
     plan->node_plans.clear();
     return FASTMM_OK;
@@ -987,7 +988,7 @@ fastmm_status fastmm_plan_set_tree(fastmm_plan_t plan, const int *node_algos, in
     plan->tree = std::move(tree);
     plan->levels.clear();
     plan->tables.clear();  // rebuilt for the new tree on next use
-    for (auto &r : plan->rot) r.reset();
+    for (auto &r : plan->grad) r.reset();
     plan->node_plans.clear();
     return FASTMM_OK;
 }
@@ -1011,7 +1012,7 @@ fastmm_status fastmm_plan_set_levels(fastmm_plan_t plan, const int *level_algos,
     plan->levels = std::move(lv);
     plan->tree.clear();
     plan->tables.clear();
-    for (auto &r : plan->rot) r.reset();
+    for (auto &r : plan->grad) r.reset();
     plan->node_plans.clear();
     return FASTMM_OK;
 }
@@ -1634,7 +1635,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         N.mb = s.mb, N.kb = s.kb, N.nb = s.nb;
         N.nnodes = outer->nleaves;
         N.outer = outer->leaves, N.asrc = outer->asrc, N.bsrc = outer->bsrc;
-        N.sc = exps, N.scale_in = scaled_copy ? 0 : 1;
+        N.sc = exps;  // the operands are the scaled copies when the plan scales
         for (int i = 0; i < 6; ++i) N.masks[i] = masks[i];
         if (s.L == 1) {
             N.out = C, N.ldo = ldc, N.node_stride = 0;
@@ -1689,24 +1690,28 @@ fastmm_status fastmm_gemm(fastmm_plan_t plan, const void *A, const void *B, void
 
 namespace fastmm {
 namespace {
-// Sub-plan of `p` whose rule is the rotation of p's rule applied `times` times.
-fastmm_status rotated_plan(fastmm_plan_s *p, int times, fastmm_plan_s **out) {
+// Sub-plan of `p` for a gradient product (which = 0: dA = G B^T, a <M0,N0,K0> product; 1:
+// dB = A^T G, a <K0,M0,N0> product): every level's rule replaced by the transpose of its
+// rotation (section 3.1), same depth, cutoff, scaling, precision, fusion mode and tile.
+fastmm_status grad_plan(fastmm_plan_s *p, int which, fastmm_plan_s **out) {
+    if (!p->tree.empty()) return fail(FASTMM_EUNSUPPORTED, "backward of a non-uniform plan is not built");
+    const int times = which == 0 ? 2 : 1;
     std::lock_guard<std::mutex> g(p->mu);
-    if (!p->rot[times]) {
-        const int id = algo_rotated(p->algo, times);
-        if (id < 0) return fail(FASTMM_EUNSUPPORTED, "cannot rotate the plan's rule");
+    if (!p->grad[which]) {
+        const int id = algo_transposed_rotation(p->algo, times);
+        if (id < 0) return fail(FASTMM_EUNSUPPORTED, "cannot form the backward rule");
         std::unique_ptr<fastmm_plan_s> q(new (std::nothrow) fastmm_plan_s());
         if (!q) return fail(FASTMM_ENOMEM, "plan allocation");
         q->algo = id, q->depth = p->depth, q->cutoff = p->cutoff, q->sc = p->sc, q->prec = p->prec, q->fuse = p->fuse;
         q->tile = p->tile;
-        for (int lid : p->levels) {  // non-stationary: every level's rule rotated alike
-            const int r = algo_rotated(lid, times);
-            if (r < 0) return fail(FASTMM_EUNSUPPORTED, "cannot rotate a level's rule");
+        for (int lid : p->levels) {  // non-stationary: every level's rule transformed alike
+            const int r = algo_transposed_rotation(lid, times);
+            if (r < 0) return fail(FASTMM_EUNSUPPORTED, "cannot form a level's backward rule");
             q->levels.push_back(r);
         }
-        p->rot[times] = std::move(q);
+        p->grad[which] = std::move(q);
     }
-    *out = p->rot[times].get();
+    *out = p->grad[which].get();
     return FASTMM_OK;
 }
 }  // namespace
@@ -1717,20 +1722,23 @@ namespace {
 constexpr int kModes = 4;  // FP32 / FP64 batch items: scaled operands or not x output to C or not
 struct BatchLayout {
     std::vector<size_t> ws_off, ws_size;
+    std::vector<size_t> copy_a, copy_b;  // FP64 / FP32: row-major copies of transposed operands (offsets
+                                         // inside the problem's region; 0 = none)
     size_t descs = 0, first = 0, total = 0;
     int bm = 0;  // split precisions: the limb-GEMM tile shared by the batch
 };
 
-fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem *probs, int count, BatchLayout &bl) {
+fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem_ex *probs, int count, BatchLayout &bl) {
     if (count < 0 || (count > 0 && (!plans || !probs))) return fail(FASTMM_EINVAL, "bad batch arguments");
     if (count > 65536) return fail(FASTMM_EINVAL, "batch too large");
     size_t off = 0;
     int prec = -1;
     for (int i = 0; i < count; ++i) {
         if (!plans[i]) return fail(FASTMM_EINVAL, "null plan in batch");
+        if (check_plan(plans[i])) return FASTMM_EINVAL;
         if (prec < 0) prec = plans[i]->prec;
         if (plans[i]->prec != prec) return fail(FASTMM_EUNSUPPORTED, "batched plans must share one precision");
-        const fastmm_problem &q = probs[i];
+        const fastmm_problem_ex &q = probs[i];
         if (q.m < 0 || q.k < 0 || q.n < 0) return fail(FASTMM_EINVAL, "negative size in batch");
     }
     if (count > 0 && is_split(prec)) {  // one limb-GEMM tile for the whole batch
@@ -1740,14 +1748,20 @@ fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem *pro
             bl.bm = std::min(bl.bm, plan_tile(plans[i], s));
         }
     }
+    const size_t es = prec < 0 ? 8 : elem_size(prec);
     for (int i = 0; i < count; ++i) {
-        const fastmm_problem &q = probs[i];
+        const fastmm_problem_ex &q = probs[i];
         const Shape s = shape_of(plans[i], q.m, q.k, q.n);
         if (every_level(plans[i], s))
             return fail(FASTMM_EUNSUPPORTED, "scaling at every level runs through fastmm_gemm_ex, not in a batch");
-        const size_t w = ws_layout(plans[i], s, q.m, q.k, q.n, bl.bm).total;
+        size_t w = ws_layout(plans[i], s, q.m, q.k, q.n, bl.bm).total;
+        size_t ca = 0, cb = 0;
+        if (!is_split(prec) && q.transA) ca = align256(w), w = ca + align256(es * (size_t)q.m * q.k);
+        if (!is_split(prec) && q.transB) cb = align256(w), w = cb + align256(es * (size_t)q.k * q.n);
         bl.ws_off.push_back(off);
         bl.ws_size.push_back(w);
+        bl.copy_a.push_back(ca);
+        bl.copy_b.push_back(cb);
         off = align256(off + w);
     }
     const Elem el = prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
@@ -1756,6 +1770,14 @@ fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem *pro
     bl.first = off, off = align256(off + 8 * (size_t)(count + kModes));  // one prefix array per mode
     bl.total = off;
     return FASTMM_OK;
+}
+
+// Contiguous problems as strided ones (leading dimensions = row lengths, no transposes).
+void problems_ex(const fastmm_problem *probs, int count, std::vector<fastmm_problem_ex> &v) {
+    for (int i = 0; probs && i < count; ++i) {
+        const fastmm_problem &q = probs[i];
+        v.push_back(fastmm_problem_ex{q.A, q.k, 0, q.B, q.n, 0, q.C, q.n, q.m, q.k, q.n});
+    }
 }
 
 int device_cus() {
@@ -1772,8 +1794,8 @@ int device_cus() {
 }  // namespace
 }  // namespace fastmm
 
-fastmm_status fastmm_batched_workspace_size(const fastmm_plan_t *plans, const fastmm_problem *probs, int count,
-                                            size_t *bytes) {
+fastmm_status fastmm_batched_ex_workspace_size(const fastmm_plan_t *plans, const fastmm_problem_ex *probs, int count,
+                                               size_t *bytes) {
     if (!bytes) return fail(FASTMM_EINVAL, "null output");
     BatchLayout bl;
     fastmm_status st = batch_layout(plans, probs, count, bl);
@@ -1781,8 +1803,24 @@ fastmm_status fastmm_batched_workspace_size(const fastmm_plan_t *plans, const fa
     return st;
 }
 
+fastmm_status fastmm_batched_workspace_size(const fastmm_plan_t *plans, const fastmm_problem *probs, int count,
+                                            size_t *bytes) {
+    if (count < 0 || (count > 0 && !probs)) return fail(FASTMM_EINVAL, "bad batch arguments");
+    std::vector<fastmm_problem_ex> ex;
+    problems_ex(probs, count, ex);
+    return fastmm_batched_ex_workspace_size(plans, ex.data(), count, bytes);
+}
+
 fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_problem *probs, int count, void *workspace,
                                   size_t ws_bytes, void *stream) {
+    if (count < 0 || (count > 0 && !probs)) return fail(FASTMM_EINVAL, "bad batch arguments");
+    std::vector<fastmm_problem_ex> ex;
+    problems_ex(probs, count, ex);
+    return fastmm_gemm_batched_ex(plans, ex.data(), count, workspace, ws_bytes, stream);
+}
+
+fastmm_status fastmm_gemm_batched_ex(const fastmm_plan_t *plans, const fastmm_problem_ex *probs, int count,
+                                     void *workspace, size_t ws_bytes, void *stream) {
     BatchLayout bl;
     fastmm_status st = batch_layout(plans, probs, count, bl);
     if (st != FASTMM_OK) return st;
@@ -1795,17 +1833,26 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
     // validate every problem before launching anything
+    auto a_bytes = [&](const fastmm_problem_ex &q) {
+        return q.transA ? span_bytes(q.k, q.m, q.lda, es) : span_bytes(q.m, q.k, q.lda, es);
+    };
+    auto b_bytes = [&](const fastmm_problem_ex &q) {
+        return q.transB ? span_bytes(q.n, q.k, q.ldb, es) : span_bytes(q.k, q.n, q.ldb, es);
+    };
     for (int i = 0; i < count; ++i) {
-        const fastmm_problem &q = probs[i];
+        const fastmm_problem_ex &q = probs[i];
         if (q.m == 0 || q.n == 0) continue;
         if (!q.C || (q.k > 0 && (!q.A || !q.B))) return fail(FASTMM_EINVAL, "null operand in batch");
-        const size_t cb = span_bytes(q.m, q.n, q.n, es);
+        if (q.ldc < q.n) return fail(FASTMM_ESHAPE, "ldc < n in batch");
+        if (q.k > 0 && (q.lda < (q.transA ? q.m : q.k) || q.ldb < (q.transB ? q.k : q.n)))
+            return fail(FASTMM_ESHAPE, "lda or ldb too small in batch");
+        const size_t cb = span_bytes(q.m, q.n, q.ldc, es);
         for (int j = 0; j < count; ++j) {
-            const fastmm_problem &r = probs[j];
-            if (r.k > 0 && (ranges_overlap(q.C, cb, r.A, span_bytes(r.m, r.k, r.k, es)) ||
-                            ranges_overlap(q.C, cb, r.B, span_bytes(r.k, r.n, r.n, es))))
+            const fastmm_problem_ex &r = probs[j];
+            if (r.k > 0 && r.m > 0 && r.n > 0 &&
+                (ranges_overlap(q.C, cb, r.A, a_bytes(r)) || ranges_overlap(q.C, cb, r.B, b_bytes(r))))
                 return fail(FASTMM_EALIAS, "a batch output overlaps an input");
-            if (j != i && r.m > 0 && r.n > 0 && ranges_overlap(q.C, cb, r.C, span_bytes(r.m, r.n, r.n, es)))
+            if (j != i && r.m > 0 && r.n > 0 && ranges_overlap(q.C, cb, r.C, span_bytes(r.m, r.n, r.ldc, es)))
                 return fail(FASTMM_EALIAS, "batch outputs overlap");
         }
         if (((uintptr_t)q.A % es) || ((uintptr_t)q.B % es) || ((uintptr_t)q.C % es))
@@ -1826,22 +1873,22 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
     // every problem's scaling steps, then every problem's operand formation (split precisions)
     std::vector<ScaleExps> exps_all(count);
     for (int i = 0; i < count; ++i) {
-        const fastmm_problem &q = probs[i];
+        const fastmm_problem_ex &q = probs[i];
         fastmm_plan_s *p = plans[i];
         if (q.m == 0 || q.n == 0 || q.k == 0) continue;
         const Shape sh = shape_of(p, q.m, q.k, q.n);
         const WsLayout w = ws_layout(p, sh, q.m, q.k, q.n, bl.bm);
-        if ((st = run_scaling(p, q.A, q.k, 0, q.B, q.n, 0, q.m, q.k, q.n, ws + bl.ws_off[i], w, s, &exps_all[i])) !=
-            FASTMM_OK)
+        if ((st = run_scaling(p, q.A, q.lda, q.transA, q.B, q.ldb, q.transB, q.m, q.k, q.n, ws + bl.ws_off[i], w, s,
+                              &exps_all[i])) != FASTMM_OK)
             return st;
     }
     fin.mark();
     for (int i = 0; i < count; ++i) {
-        const fastmm_problem &q = probs[i];
+        const fastmm_problem_ex &q = probs[i];
         fastmm_plan_s *p = plans[i];
         if (q.m == 0 || q.n == 0) continue;
         if (q.k == 0) {
-            if ((e = launch_zero_elems(el, q.C, q.n, q.m, q.n, s)) != hipSuccess) return hip_fail(e, "zero fill");
+            if ((e = launch_zero_elems(el, q.C, q.ldc, q.m, q.n, s)) != hipSuccess) return hip_fail(e, "zero fill");
             continue;
         }
         const Shape sh = shape_of(p, q.m, q.k, q.n);
@@ -1858,18 +1905,18 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
             it.combine = sh.L > 0;
             const SplitDims d = split_dims(p, sh, bl.bm);
             LimbGemm g;
-            if ((e = split_form(p, sh, d, q.A, q.k, 0, q.B, q.n, 0, q.m, q.k, q.n, exps, pws, w, tab, s, g)) !=
-                hipSuccess)
+            if ((e = split_form(p, sh, d, q.A, q.lda, q.transA, q.B, q.ldb, q.transB, q.m, q.k, q.n, exps, pws, w,
+                                tab, s, g)) != hipSuccess)
                 return hip_fail(e, "limb plane formation");
             if (sh.L == 0) {
-                g.out = (float *)q.C, g.ldo = q.n, g.leaf_stride = 0, g.direct = 1;
+                g.out = (float *)q.C, g.ldo = q.ldc, g.leaf_stride = 0, g.direct = 1;
             } else {
                 g.out = (float *)(pws + w.leaves), g.ldo = sh.nb, g.leaf_stride = sh.mb * sh.nb, g.direct = 0;
                 CombineLaunch &c = it.cb;
                 c.elem = el;
                 c.M = pws + w.leaves;
                 c.leaf_stride = sh.mb * sh.nb;
-                c.C = q.C, c.ldc = q.n, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
+                c.C = q.C, c.ldc = q.ldc, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
                 c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
                 set_kron(p, sh.L, tab->nleaves, c);
             }
@@ -1880,10 +1927,23 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
             items.push_back(std::move(it));
             continue;
         }
+        // the batched leaf kernel reads row-major operands: a transposed one is copied first
+        const void *qa = q.A, *qb = q.B;
+        int64_t qlda = q.lda, qldb = q.ldb;
+        if (q.transA) {
+            if ((e = launch_transpose(el, q.A, q.lda, q.k, q.m, pws + bl.copy_a[i], q.k, s)) != hipSuccess)
+                return hip_fail(e, "operand copy");
+            qa = pws + bl.copy_a[i], qlda = q.k;
+        }
+        if (q.transB) {
+            if ((e = launch_transpose(el, q.B, q.ldb, q.n, q.k, pws + bl.copy_b[i], q.n, s)) != hipSuccess)
+                return hip_fail(e, "operand copy");
+            qb = pws + bl.copy_b[i], qldb = q.n;
+        }
         LeafLaunch L;
         L.elem = el;
         L.prec = p->prec;
-        L.A = q.A, L.B = q.B, L.lda = q.k, L.ldb = q.n, L.transA = 0, L.transB = 0;
+        L.A = qa, L.B = qb, L.lda = qlda, L.ldb = qldb, L.transA = 0, L.transB = 0;
         L.m = q.m, L.k = q.k, L.n = q.n, L.mb = sh.mb, L.kb = sh.kb, L.nb = sh.nb;
         L.nleaves = tab->nleaves;
         L.leaves = tab->leaves, L.asrc = tab->asrc, L.bsrc = tab->bsrc;
@@ -1893,14 +1953,14 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
         it.kb = sh.kb;
         it.combine = sh.L > 0;
         if (sh.L == 0) {
-            L.out = q.C, L.ldo = q.n, L.leaf_stride = 0, L.direct = 1;
+            L.out = q.C, L.ldo = q.ldc, L.leaf_stride = 0, L.direct = 1;
         } else {
             L.out = pws + w.leaves, L.ldo = sh.nb, L.leaf_stride = sh.mb * sh.nb, L.direct = 0;
             CombineLaunch &c = it.cb;
             c.elem = el;
             c.M = pws + w.leaves;
             c.leaf_stride = sh.mb * sh.nb;
-            c.C = q.C, c.ldc = q.n, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
+            c.C = q.C, c.ldc = q.ldc, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
             c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
             set_kron(p, sh.L, tab->nleaves, c);
         }
@@ -1975,16 +2035,14 @@ fastmm_status fastmm_gemm_batched(const fastmm_plan_t *plans, const fastmm_probl
 
 fastmm_status fastmm_backward_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n, size_t *bytes) {
     if (check_plan(plan)) return FASTMM_EINVAL;
-    if (!plan->tree.empty()) return fail(FASTMM_EUNSUPPORTED, "backward of a non-uniform plan is not built");
     if (!bytes || m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "bad arguments");
-    fastmm_plan_s *ra = nullptr, *rb = nullptr;
+    fastmm_plan_s *ga = nullptr, *gb = nullptr;
     fastmm_status st;
-    if ((st = rotated_plan(plan, 2, &ra)) != FASTMM_OK || (st = rotated_plan(plan, 1, &rb)) != FASTMM_OK) return st;
+    if ((st = grad_plan(plan, 0, &ga)) != FASTMM_OK || (st = grad_plan(plan, 1, &gb)) != FASTMM_OK) return st;
     size_t wa = 0, wb = 0;
-    if ((st = fastmm_workspace_size(ra, k, n, m, &wa)) != FASTMM_OK) return st;  // dA^T = B G^T
-    if ((st = fastmm_workspace_size(rb, n, m, k, &wb)) != FASTMM_OK) return st;  // dB^T = G^T A
-    const size_t es = elem_size(plan->prec);
-    *bytes = align256(es * (size_t)std::max(k * m, n * k)) + align256(es * (size_t)n * m) + std::max(wa, wb);
+    if ((st = fastmm_workspace_size(ga, m, n, k, &wa)) != FASTMM_OK) return st;  // dA = G B^T
+    if ((st = fastmm_workspace_size(gb, k, m, n, &wb)) != FASTMM_OK) return st;  // dB = A^T G
+    *bytes = std::max(wa, wb);
     return FASTMM_OK;
 }
 
@@ -1992,47 +2050,68 @@ fastmm_status fastmm_gemm_backward(fastmm_plan_t plan, const void *A, const void
                                    void *dB, int64_t m, int64_t k, int64_t n, void *workspace, size_t ws_bytes,
                                    void *stream) {
     if (check_plan(plan)) return FASTMM_EINVAL;
-    if (!plan->tree.empty()) return fail(FASTMM_EUNSUPPORTED, "backward of a non-uniform plan is not built");
     if (m < 0 || k < 0 || n < 0) return fail(FASTMM_EINVAL, "negative size");
-    if ((dA && (!G || !B)) || (dB && (!G || !A))) return fail(FASTMM_EINVAL, "null input");
-    if (m == 0 || k == 0) return FASTMM_OK;
-    size_t need = 0;
-    fastmm_status st = fastmm_backward_workspace_size(plan, m, k, n, &need);
-    if (st != FASTMM_OK) return st;
-    if (workspace == nullptr || ws_bytes < need) return fail(FASTMM_EWORKSPACE, "backward workspace too small");
-    if (((uintptr_t)workspace & 255) != 0) return fail(FASTMM_EINVAL, "workspace must be 256-byte aligned");
-    const size_t es = elem_size(plan->prec);
-    const Elem el = plan->prec == FASTMM_F64 ? Elem::F64 : Elem::F32;
-    char *tmp = (char *)workspace;
-    const size_t tmp_bytes = align256(es * (size_t)std::max(k * m, n * k));
-    char *gt = tmp + tmp_bytes;  // G^T (n x m), shared by both products
-    const size_t gt_bytes = align256(es * (size_t)n * m);
-    char *ws = gt + gt_bytes;
-    const size_t wsb = ws_bytes - tmp_bytes - gt_bytes;
-    hipStream_t s = (hipStream_t)stream;
-    fastmm_plan_s *ra = nullptr, *rb = nullptr;
-    if ((st = rotated_plan(plan, 2, &ra)) != FASTMM_OK || (st = rotated_plan(plan, 1, &rb)) != FASTMM_OK) return st;
-    if (n > 0) {
-        // Both products read G transposed: materialise G^T once, so that they run on row-major
-        // operands (the pipelined and fused kernels).
-        hipError_t e = launch_transpose(el, G, n, m, n, gt, m, s);
-        if (e != hipSuccess) return hip_fail(e, "transpose kernel");
-    }
-    if (dA) {
-        // dA^T (k x m) = B (k x n) * G^T (n x m)
-        st = fastmm_gemm_ex(ra, B, n, 0, gt, m, 0, tmp, m, k, n, m, ws, wsb, stream);
+    const bool full = m > 0 && k > 0 && n > 0;  // empty products need no inputs (zero or nothing)
+    if (full && ((dA && (!G || !B)) || (dB && (!G || !A)))) return fail(FASTMM_EINVAL, "null input");
+    fastmm_plan_s *ga = nullptr, *gb = nullptr;
+    fastmm_status st;
+    if ((st = grad_plan(plan, 0, &ga)) != FASTMM_OK || (st = grad_plan(plan, 1, &gb)) != FASTMM_OK) return st;
+    // Both products read their transposed operand through the transpose flags: the split
+    // precisions form their limb planes from it directly, FP64 / FP32 copy it once.
+    if (dA) {  // dA (m x k) = G (m x n) * B^T, B stored k x n
+        st = fastmm_gemm_ex(ga, G, n, 0, B, n, 1, dA, k, m, n, k, workspace, ws_bytes, stream);
         if (st != FASTMM_OK) return st;
-        hipError_t e = launch_transpose(el, tmp, m, k, m, dA, k, s);
-        if (e != hipSuccess) return hip_fail(e, "transpose kernel");
     }
-    if (dB && n > 0) {
-        // dB^T (n x k) = G^T (n x m) * A (m x k)
-        st = fastmm_gemm_ex(rb, gt, m, 0, A, k, 0, tmp, k, n, m, k, ws, wsb, stream);
+    if (dB) {  // dB (k x n) = A^T * G (m x n), A stored m x k
+        st = fastmm_gemm_ex(gb, A, k, 1, G, n, 0, dB, n, k, m, n, workspace, ws_bytes, stream);
         if (st != FASTMM_OK) return st;
-        hipError_t e = launch_transpose(el, tmp, k, n, k, dB, n, s);
-        if (e != hipSuccess) return hip_fail(e, "transpose kernel");
     }
     return FASTMM_OK;
+}
+
+namespace fastmm {
+namespace {
+// The products of a batched backward pass: dA_i then dB_i for every problem that asks for
+// them, with their plans.
+fastmm_status grad_products(const fastmm_plan_t *plans, const fastmm_grad_problem *probs, int count,
+                            std::vector<fastmm_plan_t> &gp, std::vector<fastmm_problem_ex> &gq) {
+    if (count < 0 || (count > 0 && (!plans || !probs))) return fail(FASTMM_EINVAL, "bad batch arguments");
+    for (int i = 0; i < count; ++i) {
+        const fastmm_grad_problem &q = probs[i];
+        if (!plans[i] || check_plan(plans[i])) return fail(FASTMM_EINVAL, "null plan in batch");
+        if (q.m < 0 || q.k < 0 || q.n < 0) return fail(FASTMM_EINVAL, "negative size in batch");
+        const bool full = q.m > 0 && q.k > 0 && q.n > 0;
+        if (full && ((q.dA && (!q.G || !q.B)) || (q.dB && (!q.G || !q.A))))
+            return fail(FASTMM_EINVAL, "null input in batch");
+        fastmm_plan_s *ga = nullptr, *gb = nullptr;
+        fastmm_status st;
+        if ((st = grad_plan(plans[i], 0, &ga)) != FASTMM_OK || (st = grad_plan(plans[i], 1, &gb)) != FASTMM_OK)
+            return st;
+        if (q.dA) gp.push_back(ga), gq.push_back(fastmm_problem_ex{q.G, q.n, 0, q.B, q.n, 1, q.dA, q.k, q.m, q.n, q.k});
+        if (q.dB) gp.push_back(gb), gq.push_back(fastmm_problem_ex{q.A, q.k, 1, q.G, q.n, 0, q.dB, q.n, q.k, q.m, q.n});
+    }
+    return FASTMM_OK;
+}
+}  // namespace
+}  // namespace fastmm
+
+fastmm_status fastmm_backward_batched_workspace_size(const fastmm_plan_t *plans, const fastmm_grad_problem *probs,
+                                                     int count, size_t *bytes) {
+    if (!bytes) return fail(FASTMM_EINVAL, "null output");
+    std::vector<fastmm_plan_t> gp;
+    std::vector<fastmm_problem_ex> gq;
+    fastmm_status st = grad_products(plans, probs, count, gp, gq);
+    if (st != FASTMM_OK) return st;
+    return fastmm_batched_ex_workspace_size(gp.data(), gq.data(), (int)gq.size(), bytes);
+}
+
+fastmm_status fastmm_gemm_backward_batched(const fastmm_plan_t *plans, const fastmm_grad_problem *probs, int count,
+                                           void *workspace, size_t ws_bytes, void *stream) {
+    std::vector<fastmm_plan_t> gp;
+    std::vector<fastmm_problem_ex> gq;
+    fastmm_status st = grad_products(plans, probs, count, gp, gq);
+    if (st != FASTMM_OK) return st;
+    return fastmm_gemm_batched_ex(gp.data(), gq.data(), (int)gq.size(), workspace, ws_bytes, stream);
 }
 
 fastmm_status fastmm_task_table(fastmm_plan_t plan, int levels, int64_t counts[5], int32_t *leaves, int32_t *asrc,

@@ -29,6 +29,11 @@ int algo_register(Algo &&a);  // returns the new id
 // Id of the cyclic rotation of rule `id` applied `times` times: once gives [W,U,V] (a rule for
 // <N0,M0,K0>), twice [V,W,U] (<K0,N0,M0>).  Registered on first use; -1 on failure.
 int algo_rotated(int id, int times);
+// Id of the transpose of that rotation: times = 2 gives a rule for <M0,N0,K0> that forms
+// G B^T (the transpose of [V,W,U] applied to (B, G^T)), times = 1 a rule for <K0,M0,N0> that
+// forms A^T G (the transpose of [W,U,V] applied to (G^T, A)).  Registered on first use; -1 on
+// failure.
+int algo_transposed_rotation(int id, int times);
 // Number of (a, b, c) index triples violating the Brent equations under the convention
 // A, B column-major and C row-major (exact integer arithmetic).
 long brent_violations(const Algo &a);

@@ -119,13 +119,14 @@ struct NodeLaunch {
     const LeafEntry *outer;
     const SrcEntry *asrc;
     const SrcEntry *bsrc;
-    ScaleExps sc;
-    int scale_in = 1;   // with sc: 1 scales the operands while loading, 0 takes them as already
-                        // scaled (sc then only scales the depth-1 output)
+    ScaleExps sc;       // the operands come scaled; sc scales the depth-1 output only
     uint32_t masks[6];  // (U+, U-, V+, V-, W+, W-): bit s*7+r marks coefficient +1 / -1
 };
 // Whether a compiled fused kernel exists for this sign pattern.
 bool node222_supported(const uint32_t masks[6]);
+// The same for the transposed-rotation patterns (node_fused_t.hip).
+bool node222_t_supported(const uint32_t masks[6]);
+hipError_t launch_node222_t(const NodeLaunch &L, hipStream_t s);
 hipError_t launch_node222(const NodeLaunch &L, hipStream_t s);
 
 // Split precisions, pass 1: limb planes of the leaf operands.  Plane row o, column kk of leaf

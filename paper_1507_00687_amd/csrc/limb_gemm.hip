@@ -428,11 +428,14 @@ struct Products<3> {
     static constexpr int a[6] = {0, 1, 2, 0, 1, 0}, b[6] = {2, 1, 0, 1, 0, 0};
 };
 
-// Work-group of 2 x 2 waves, each a (BM/2) x (BN/2) tile of the BM x BN output tile (64 x 64 or,
-// for large blocks, 128 x 128: the larger wave tile halves the LDS bytes read per MFMA); K stage
-// 32; LDS double-buffered, rows of 32 halves (64 bytes, four 16-byte chunks) with chunk c of row r
-// stored at chunk c ^ ((r / 2) mod 4), so that the 16-byte fragment reads (16 rows, one chunk)
-// and the staging writes (consecutive chunks and rows) both fall on distinct banks.
+// Work-group of WM x WN waves, each a (BM/WM) x (BN/WN) tile of the BM x BN output tile: 2 x 2
+// waves on 128 x 128 tiles, 4 x 2 waves of 64 x 128 on 256 x 256 tiles (measured on MI355X over
+// 49 leaves of 4096^3: 2 % faster than 2 x 4 waves of 128 x 64; one work-group per CU, two waves
+// per SIMD).  K stage 32; LDS double-buffered, rows of 32 halves (64 bytes, four 16-byte chunks)
+// with chunk c of row r stored at chunk c ^ ((r / 2) mod 4), so that the 16-byte fragment reads
+// (16 rows, one chunk) and the staging writes (consecutive chunks and rows) both fall on distinct
+// banks (SQ_LDS_BANK_CONFLICT reads 0 for this kernel; swizzling with bit 3 of r as well gives 3
+// conflict cycles per LDS instruction and 13 % more time).
 template <int NL, int BM, int BN>
 struct LimbSmem {
     __attribute__((aligned(16))) unsigned short As[2][NL][BM * 32];
@@ -954,7 +957,7 @@ template <bool HALF, int NL>
 hipError_t gemm_batched_tile(int bm, const void *descs, const int64_t *first, int count, int64_t total,
                              hipStream_t s) {
     if constexpr (NL < 3) {
-        if (bm == 256) return gemm_batched_go<HALF, NL, 256, 256, 2, 4>(descs, first, count, total, s);
+        if (bm == 256) return gemm_batched_go<HALF, NL, 256, 256, 4, 2>(descs, first, count, total, s);
     }
     return gemm_batched_go<HALF, NL, 128, 128, 2, 2>(descs, first, count, total, s);
 }
@@ -962,7 +965,7 @@ hipError_t gemm_batched_tile(int bm, const void *descs, const int64_t *first, in
 template <bool HALF, int NL>
 hipError_t gemm_tile(int bm, const LimbGemm &g, int nleaves, hipStream_t s) {
     if constexpr (NL < 3) {
-        if (bm == 256) return gemm_go<HALF, NL, 256, 256, 2, 4>(g, nleaves, s);
+        if (bm == 256) return gemm_go<HALF, NL, 256, 256, 4, 2>(g, nleaves, s);
     }
     return gemm_go<HALF, NL, 128, 128, 2, 2>(g, nleaves, s);
 }

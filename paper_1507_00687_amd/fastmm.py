@@ -44,6 +44,17 @@ class _Problem(ctypes.Structure):
                 ("k", ctypes.c_int64), ("n", ctypes.c_int64)]
 
 
+class _ProblemEx(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("transA", ctypes.c_int), ("B", ctypes.c_void_p),
+                ("ldb", ctypes.c_int64), ("transB", ctypes.c_int), ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+                ("m", ctypes.c_int64), ("k", ctypes.c_int64), ("n", ctypes.c_int64)]
+
+
+class _GradProblem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("G", ctypes.c_void_p), ("dA", ctypes.c_void_p),
+                ("dB", ctypes.c_void_p), ("m", ctypes.c_int64), ("k", ctypes.c_int64), ("n", ctypes.c_int64)]
+
+
 class _Scaling(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("steps", ctypes.c_int), ("tau", ctypes.c_double),
                 ("per_level", ctypes.c_int)]
@@ -88,6 +99,12 @@ def lib() -> ctypes.CDLL:
         L.fastmm_batched_workspace_size.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Problem), i32,
                                                      ctypes.POINTER(sz)]
         L.fastmm_gemm_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Problem), i32, vp, sz, vp]
+        L.fastmm_batched_ex_workspace_size.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_ProblemEx), i32,
+                                                        ctypes.POINTER(sz)]
+        L.fastmm_gemm_batched_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_ProblemEx), i32, vp, sz, vp]
+        L.fastmm_backward_batched_workspace_size.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_GradProblem), i32,
+                                                              ctypes.POINTER(sz)]
+        L.fastmm_gemm_backward_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_GradProblem), i32, vp, sz, vp]
         L.fastmm_backward_workspace_size.argtypes = [vp, i64, i64, i64, ctypes.POINTER(sz)]
         L.fastmm_gemm_backward.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, i64, vp, sz, vp]
         L.fastmm_profile_enable.argtypes = [i32]
@@ -101,7 +118,8 @@ def lib() -> ctypes.CDLL:
                      "fastmm_backward_workspace_size", "fastmm_gemm_backward", "fastmm_batched_workspace_size",
                      "fastmm_gemm_batched", "fastmm_plan_set_fusion", "fastmm_plan_path", "fastmm_plan_set_tree",
                      "fastmm_algo_stability", "fastmm_plan_set_levels", "fastmm_plan_set_tile",
-                     "fastmm_gemm_noalloc"):
+                     "fastmm_gemm_noalloc", "fastmm_batched_ex_workspace_size", "fastmm_gemm_batched_ex",
+                     "fastmm_backward_batched_workspace_size", "fastmm_gemm_backward_batched"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -366,9 +384,88 @@ def fastmm_gemm_batched(plans, As, Bs, Cs=None, workspace=None, stream=None):
     return Cs
 
 
+def fastmm_gemm_batched_ex(plans, As, Bs, transA=None, transB=None, Cs=None, workspace=None, stream=None):
+    """C_i = op(A_i) @ op(B_i) for all i with plans[i], op(X) = X.T where trans*[i] is set; the
+    stored operands may be row-strided 2-D views (unit column stride).  One launch of the
+    products for the batch."""
+    import torch
+
+    count = len(As)
+    if not (len(Bs) == count and len(plans) == count):
+        raise ValueError("plans, As and Bs must have the same length")
+    transA = list(transA) if transA is not None else [False] * count
+    transB = list(transB) if transB is not None else [False] * count
+    probs = (_ProblemEx * max(count, 1))()
+    outs = []
+    for i in range(count):
+        a, b = As[i], Bs[i]
+        for x in (a, b):
+            if x.dim() != 2 or x.stride(1) != 1:
+                raise ValueError(f"problem {i}: operands must be 2-D with unit column stride")
+            if x.dtype != plans[i].dtype:
+                raise TypeError(f"problem {i}: operands must be {plans[i].dtype}")
+        m, k = (a.shape[1], a.shape[0]) if transA[i] else (a.shape[0], a.shape[1])
+        kb, n = (b.shape[1], b.shape[0]) if transB[i] else (b.shape[0], b.shape[1])
+        if k != kb:
+            raise ValueError(f"problem {i}: inner dimensions differ")
+        c = Cs[i] if Cs is not None else torch.empty((m, n), dtype=a.dtype, device=a.device)
+        if c.dim() != 2 or c.stride(1) != 1 or tuple(c.shape) != (m, n):
+            raise ValueError(f"problem {i}: C must be an {m} x {n} view with unit column stride")
+        outs.append(c)
+        probs[i] = _ProblemEx(a.data_ptr(), max(a.stride(0), 1), int(bool(transA[i])), b.data_ptr(),
+                              max(b.stride(0), 1), int(bool(transB[i])), c.data_ptr(), max(c.stride(0), 1), m, k, n)
+    handles = (ctypes.c_void_p * max(count, 1))(*[p.handle.value for p in plans])
+    need = ctypes.c_size_t()
+    _check(lib().fastmm_batched_ex_workspace_size(handles, probs, count, ctypes.byref(need)))
+    if workspace is None:
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=As[0].device if count else "cuda")
+    _check(lib().fastmm_gemm_batched_ex(handles, probs, count, workspace.data_ptr(), workspace.numel(),
+                                        _stream_ptr(stream)))
+    return outs
+
+
+def fastmm_gemm_backward_batched(plans, As, Bs, Gs, need_dA: bool = True, need_dB: bool = True, workspace=None,
+                                 stream=None):
+    """[(dA_i, dB_i)] = [(G_i B_i^T, A_i^T G_i)] for all i with plans[i]: the gradient products of
+    the whole batch in one launch (None where not needed)."""
+    import torch
+
+    count = len(As)
+    if not (len(Bs) == count and len(Gs) == count and len(plans) == count):
+        raise ValueError("plans, As, Bs and Gs must have the same length")
+    As = [a.contiguous() for a in As]
+    Bs = [b.contiguous() for b in Bs]
+    Gs = [g.contiguous() for g in Gs]
+    probs = (_GradProblem * max(count, 1))()
+    outs = []
+    for i in range(count):
+        a, b, g = As[i], Bs[i], Gs[i]
+        m, k = a.shape
+        n = b.shape[1]
+        if b.shape[0] != k or tuple(g.shape) != (m, n):
+            raise ValueError(f"problem {i}: shapes do not match")
+        for x in (a, b, g):
+            if x.dtype != plans[i].dtype:
+                raise TypeError(f"problem {i}: operands must be {plans[i].dtype}")
+        dA = torch.empty((m, k), dtype=a.dtype, device=a.device) if need_dA else None
+        dB = torch.empty((k, n), dtype=a.dtype, device=a.device) if need_dB else None
+        outs.append((dA, dB))
+        probs[i] = _GradProblem(a.data_ptr(), b.data_ptr(), g.data_ptr(), dA.data_ptr() if dA is not None else None,
+                                dB.data_ptr() if dB is not None else None, m, k, n)
+    handles = (ctypes.c_void_p * max(count, 1))(*[p.handle.value for p in plans])
+    need = ctypes.c_size_t()
+    _check(lib().fastmm_backward_batched_workspace_size(handles, probs, count, ctypes.byref(need)))
+    if workspace is None:
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=As[0].device if count else "cuda")
+    _check(lib().fastmm_gemm_backward_batched(handles, probs, count, workspace.data_ptr(), workspace.numel(),
+                                              _stream_ptr(stream)))
+    return outs
+
+
 def fastmm_gemm_backward(plan: Plan, A, B, G, need_dA: bool = True, need_dB: bool = True, workspace=None,
                          stream=None):
-    """(dA, dB) = (G B^T, A^T G) through the rotated fast algorithms (None where not needed)."""
+    """(dA, dB) = (G B^T, A^T G) through the transposed rotations of the plan's rule (None where not
+    needed)."""
     import torch
 
     m, k = A.shape

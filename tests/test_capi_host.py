@@ -224,6 +224,83 @@ def test_fused_path_matches_rules_by_coefficients(F):
     assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "leaf"
 
 
+def _transpose_rule(a):
+    """The rule for <N0,K0,M0> that forms C^T = B^T A^T with the products of `a` transposed
+    (section 3.1): written here from the index conventions (A, B single indices column-major,
+    C row-major), independently of the library's own transposition."""
+    M0, K0, N0, R = a.M0, a.K0, a.N0, len(a.U[0])
+    U = [[0] * R for _ in range(N0 * K0)]
+    V = [[0] * R for _ in range(K0 * M0)]
+    W = [[0] * R for _ in range(N0 * M0)]
+    for r in range(R):
+        for p in range(N0):
+            for q in range(K0):
+                U[p + q * N0][r] = a.V[q + p * K0][r]
+        for q in range(K0):
+            for t in range(M0):
+                V[q + t * K0][r] = a.U[t + q * M0][r]
+        for p in range(N0):
+            for t in range(M0):
+                W[p * M0 + t][r] = a.W[t * N0 + p][r]
+    return N0, K0, M0, R, U, V, W
+
+
+@pytest.mark.parametrize("name", ["strassen", "winograd", "f323", "f424"])
+def test_transposed_rotations_are_rules_and_form_the_transpose(F, name):
+    """The backward products use the transposes of the rotations: each is a valid rule (the
+    library's registration checks the Brent equations exactly), computes (A B)^T from (B^T, A^T)
+    exactly on integers through its task table, and for <2,2,2;7> rules it has a compiled fused
+    kernel (the backward pass stays on the fused path)."""
+    a = C.get(name)
+    rng = np.random.default_rng(7)
+    for t in range(3):
+        r = a
+        for _ in range(t):
+            r = C.rotate(r)
+        M0, K0, N0, R, U, V, W = _transpose_rule(r)
+        # coefficients in {0, +-1/2, +-1}: numerators over a common 2^1 (a denominator of 1 when integral)
+        frac = any(x != int(x) for M in (U, V, W) for row in M for x in row)
+        num = [np.array([[int(2 * x) if frac else int(x) for x in row] for row in M], dtype=np.int64)
+               for M in (U, V, W)]
+        uid = F.fastmm_algo_register(M0, K0, N0, R, *num, 1 if frac else 0)
+        # (A B)^T = B^T A^T through the transposed rule's one-level task table
+        m, k, n = 2 * r.M0, 3 * r.K0, 2 * r.N0
+        A = rng.integers(-4, 5, (m, k)).astype(np.float64)
+        B = rng.integers(-4, 5, (k, n)).astype(np.float64)
+        tab = F.fastmm_task_table(F.Plan(uid, 1, 1), 1)
+        got = _eval_tables(tab, np.ascontiguousarray(B.T), np.ascontiguousarray(A.T), M0, K0, N0, 1)
+        assert np.array_equal(got, (A @ B).T)
+        if (M0, K0, N0, R) == (2, 2, 2, 7):
+            assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "fused", (name, t)
+            assert F.Plan(uid, 2, 1, precision="f64").path(128, 128, 128) == "fused", (name, t)
+
+
+def test_backward_workspace_and_batched_errors_on_host(F):
+    p = F.Plan("strassen", 2, 64, precision="f32")
+    lib = F.lib()
+    size = ctypes.c_size_t()
+    assert lib.fastmm_backward_workspace_size(p.handle, 300, 200, 100, ctypes.byref(size)) == 0
+    need_a = ctypes.c_size_t()
+    need_b = ctypes.c_size_t()
+    # the two products: dA (300 x 200) = G (300 x 100) B^T, dB (200 x 100) = A^T G
+    assert lib.fastmm_workspace_size(p.handle, 300, 100, 200, ctypes.byref(need_a)) == 0
+    assert lib.fastmm_workspace_size(p.handle, 200, 300, 100, ctypes.byref(need_b)) == 0
+    assert size.value >= min(need_a.value, need_b.value) > 0
+    from paper_1507_00687_amd.fastmm import _GradProblem, _ProblemEx
+
+    handles = (ctypes.c_void_p * 1)(p.handle.value)
+    bad = (_GradProblem * 1)(_GradProblem(8, 8, 8, 4096, 8192, -1, 4, 4))
+    assert lib.fastmm_backward_batched_workspace_size(handles, bad, 1, ctypes.byref(size)) == -1
+    # a strided product whose ldc is below n: rejected before any launch
+    base = 1 << 20
+    pe = (_ProblemEx * 1)(_ProblemEx(base, 64, 0, base + 65536, 64, 1, base + 131072, 32, 64, 64, 64))
+    assert lib.fastmm_batched_ex_workspace_size(handles, pe, 1, ctypes.byref(size)) == 0
+    assert lib.fastmm_gemm_batched_ex(handles, pe, 1, base + (1 << 24), size.value, None) == -3
+    # an output overlapping an input of the batch
+    pe2 = (_ProblemEx * 1)(_ProblemEx(base, 64, 0, base + 65536, 64, 1, base + 1024, 64, 64, 64, 64))
+    assert lib.fastmm_gemm_batched_ex(handles, pe2, 1, base + (1 << 24), size.value, None) == -7
+
+
 # ----------------------------------------------------------------- non-uniform recursion trees
 from tests.trees import dalberto_tree, f323_tree  # noqa: E402
 

@@ -110,8 +110,9 @@ def test_fused_repeat_is_deterministic():
 
 @pytest.mark.parametrize("name", ["strassen", "winograd"])
 def test_fused_gradients_integer_exact(name):
-    # The backward pass runs the rotated rules ([V,W,U] and [W,U,V]) on row-major operands,
-    # so it takes the fused path too.
+    # The backward pass runs the transposes of the rotated rules (compiled patterns of the
+    # fused kernel), the transposed operand copied row-major first, so it takes the fused path
+    # too.
     import torch
 
     import paper_1507_00687_amd as F
