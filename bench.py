@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 METRIC = "effective TFLOP/s (2mkn/t) and max-norm rel error vs FP64 oracle, fast vs classical"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500.0, "f16x3": 2500.0,
                "bf16x6": 2500.0}
+PEAK_TFLOPS_BY_DTYPE = {"float64": 78.6, "float32": 157.3, "float16": 2500.0, "bfloat16": 2500.0}
 PRODUCTS = {"f64": 1, "f32": 1, "bf16": 1, "f16": 1, "bf16x3": 3, "f16x3": 3, "bf16x6": 6}
 HBM_PEAK_GBS = 8000.0
 ORACLE_NAME = {"strassen": "strassen", "winograd": "winograd", "f323": "f323", "f332": "f332", "f233": "f233",
@@ -66,6 +67,8 @@ def parse():
     ap.add_argument("--no-classical", action="store_true")
     ap.add_argument("--fuse", default="auto", choices=["auto", "off", "always"],
                     help="fusion mode of the plan (off: leaf products + W-combination)")
+    ap.add_argument("--no-vendor", action="store_true",
+                    help="skip timing torch.bmm (hipBLASLt) on the leaf products' shape")
     ap.add_argument("--torch-ref", action="store_true",
                     help="also time torch.matmul (vendor BLAS) on the same operands, as context")
     ap.add_argument("--batch", type=int, default=0,
@@ -86,6 +89,11 @@ def parse():
     ap.add_argument("--tune-cache", default="", help="JSON cache of the autotuner's choices (batch mode)")
     ap.add_argument("--max-instability", type=float, default=16.0,
                     help="autotuner admission cap on (E/K0^2)^L (batch mode)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the product kernel's HBM bytes per launch for this workload into "
+                         "profiles/traffic.json from two rocprofv3 counter runs (--pmc FETCH_SIZE, then "
+                         "--pmc WRITE_SIZE) of this command with --no-classical --beside none --also none "
+                         "--calib-copy-mb MB; runs on the host only")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB (calibrates rocprofv3 byte counters)")
     return ap.parse_args()
@@ -170,6 +178,27 @@ def cpu_baseline_leg(args, A, B, rows):
                                 f"of the same distribution, {dt:.2f} s; plain C classical leaves, "
                                 f"sequential summation"}
     return out
+
+
+def vendor_leaf_gemm(args, nleaves, mb, kb, nb, achieved):
+    """The vendor library on the leaf products' shape, for context: torch.bmm (hipBLASLt) over
+    nleaves independent mb x kb x nb products of N(0,1) data in the MFMA input type of the
+    precision (fp16 for the fp16 limb forms, bf16 for the bf16 ones, else the precision itself).
+    The MFMA rate depends on the data (operands of few significant bits draw less power and run
+    at higher clocks), so the comparison uses full-mantissa values, as the limb planes are."""
+    import torch
+
+    dt = {"f16": torch.float16, "f16x3": torch.float16, "bf16": torch.bfloat16, "bf16x3": torch.bfloat16,
+          "bf16x6": torch.bfloat16, "f32": torch.float32, "f64": torch.float64}[args.precision]
+    g = torch.Generator(device="cuda").manual_seed(args.seed)
+    X = torch.randn((nleaves, mb, kb), dtype=torch.float32, device="cuda", generator=g).to(dt)
+    Y = torch.randn((nleaves, kb, nb), dtype=torch.float32, device="cuda", generator=g).to(dt).contiguous()
+    ms_v = time_steps(lambda: torch.bmm(X, Y), args.steps, args.warmup)
+    v = 2.0 * nleaves * mb * kb * nb / (ms_v * 1e-3) / 1e12
+    del X, Y
+    return {"what": f"torch.bmm {str(dt).replace('torch.', '')} (hipBLASLt), {nleaves} x {mb}x{kb}x{nb}, N(0,1)",
+            "ms": ms_v, "value": v, "frac": v / PEAK_TFLOPS_BY_DTYPE[str(dt).replace("torch.", "")],
+            "product_kernel_over_vendor": achieved / v}
 
 
 def leaf_flops(F, plan_algo, plan, m, k, n, precision):
@@ -419,8 +448,66 @@ def scaling_study(args):
     print(json.dumps(line), flush=True)
 
 
+def record_traffic(args):
+    """Median FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the product kernel in two rocprofv3
+    counter runs, each scaled by what the counter reads for the calibration copy of
+    --calib-copy-mb MiB (its true bytes read and written), into profiles/traffic.json under this
+    workload's key, with the hash of the kernel's source (bench lines report the bytes only while
+    the source is unchanged)."""
+    import csv
+    import statistics
+
+    import paper_1507_00687_amd as F
+
+    if args.calib_copy_mb <= 0:
+        sys.exit("--record-traffic needs --calib-copy-mb (the copy the counters are scaled by)")
+    n = args.n
+    plan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
+                  precision=args.precision, fuse=args.fuse, per_level=args.per_level)
+    path = plan.path(n, n, n)
+    kname, ksource = product_kernel(args.precision, path)
+    workload = (f"{args.algo} L={args.depth} cutoff={args.cutoff} n={n} {args.precision} {args.dist} "
+                f"scaling={args.scaling}{' per-level' if args.per_level else ''} path={path}")
+    calib_kib = (args.calib_copy_mb << 20) / 1024.0
+
+    def per_dispatch(fname, counter):
+        vals = {}
+        copies = {}
+        for r in csv.DictReader(open(fname)):
+            if r["Counter_Name"] != counter:
+                continue
+            d, v = r["Dispatch_Id"], float(r["Counter_Value"])
+            if r["Kernel_Name"].split("(")[0].split("<")[0].endswith(kname):
+                vals[d] = vals.get(d, 0.0) + v
+            elif "copyBuffer" in r["Kernel_Name"]:
+                copies[d] = copies.get(d, 0.0) + v
+        if not vals or not copies:
+            sys.exit(f"{fname}: no {counter} rows for {kname} or for the calibration copy")
+        return statistics.median(vals.values()), max(copies.values()), len(vals)
+
+    fetch, fcopy, nd = per_dispatch(args.record_traffic[0], "FETCH_SIZE")
+    write, wcopy, _ = per_dispatch(args.record_traffic[1], "WRITE_SIZE")
+    fs, wsc = calib_kib / fcopy, calib_kib / wcopy
+    rec = {"kernel": kname, "source": ksource, "source_hash": kernel_source_hash(ksource), "fetch_kib": fetch,
+           "write_kib": write, "fetch_scale": round(fs, 3), "write_scale": round(wsc, 3),
+           "bytes_per_launch": int((fetch * fs + write * wsc) * 1024), "dispatches": nd}
+    path_json = os.path.join(ROOT, "profiles", "traffic.json")
+    data = json.load(open(path_json)) if os.path.exists(path_json) else {}
+    old = data.get(workload, {})
+    if "summary" in old:
+        rec["summary"] = old["summary"]
+    data[workload] = rec
+    with open(path_json, "w") as f:
+        json.dump(data, f, indent=1)
+        f.write("\n")
+    print(json.dumps({workload: rec}))
+
+
 def main():
     args = parse()
+    if args.record_traffic:
+        record_traffic(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built",
               file=sys.stderr)
@@ -525,6 +612,9 @@ def main():
     if args.torch_ref:
         ms_t = time_steps(lambda: torch.matmul(tA, tB), args.steps, args.warmup)
         torch_ref = {"ms_per_step": ms_t, "value": 2.0 * m * k * n / (ms_t * 1e-3) / 1e12}
+    vendor = None
+    if not args.no_vendor and L > 0 and path != "every_level":
+        vendor = vendor_leaf_gemm(args, nleaves, mb, kb, nb, achieved)
     if args.calib_copy_mb > 0:
         nbytes = args.calib_copy_mb << 20
         src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -573,6 +663,7 @@ def main():
         "beside": beside,
         "also": also,
         "torch_matmul": torch_ref,
+        "vendor_leaf_gemm": vendor,
         "speedup_vs_classical": (classical["ms_per_step"] / ms) if classical else None,
         "error": err,
         "phases_ms": {"scaling": prof["scaling_ms"] / calls, "form": prof["form_ms"] / calls, "leaf": leaf_ms,
