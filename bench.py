@@ -8,7 +8,8 @@ max-norm relative error of both against the long-double CPU reference.
                     [--dist uniform01] [--fuse auto] [--also none]
 
 Default workload (the precision-form configuration): Strassen <2,2,2;7>, depth 2, cutoff 256,
-n = 16384, N(0,1) entries, outside scaling (Algorithm 1, power-of-two factors), leaves as FP16
+n = 16384, N(0,1) entries, outside scaling (Algorithm 1, each factor the power of two nearest to
+the row's or column's max-abs), leaves as FP16
 MFMA products with FP32 accumulation in the two-limb split form (F16X3).  Beside it in the same
 line: the classical GEMM built the same way (same precision form, same scaling, one leaf), the
 same plan on plain FP32 MFMA, and the <4,2,4;26> rule at the same depth, size, scaling and
@@ -54,6 +55,9 @@ def parse():
                     help="also time the same plan in this precision (reported beside the headline; none = skip)")
     ap.add_argument("--scaling", default="outside")
     ap.add_argument("--scaling-steps", type=int, default=2)
+    ap.add_argument("--o-round", default="nearest", choices=["up", "nearest"],
+                    help="O-step factors: the nearest power of two to the max (default), or the smallest "
+                         "one >= it")
     ap.add_argument("--per-level", action="store_true",
                     help="run the scaling steps at every inner node of the recursion, not only once")
     ap.add_argument("--dist", default="normal")
@@ -167,7 +171,8 @@ def cpu_baseline_leg(args, A, B, rows):
         else:
             depth = args.depth
         if args.scaling != "none":
-            O.scaled_fast(As, Bs, alg, depth, cutoff, mode=args.scaling, steps=args.scaling_steps)
+            O.scaled_fast(As, Bs, alg, depth, cutoff, mode=args.scaling, steps=args.scaling_steps,
+                          o_round=args.o_round)
         else:
             O.fast(As, Bs, alg, depth, cutoff)
         dt = time.perf_counter() - t0
@@ -463,11 +468,12 @@ def record_traffic(args):
         sys.exit("--record-traffic needs --calib-copy-mb (the copy the counters are scaled by)")
     n = args.n
     plan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
-                  precision=args.precision, fuse=args.fuse, per_level=args.per_level)
+                  precision=args.precision, fuse=args.fuse, per_level=args.per_level, o_round=args.o_round)
     path = plan.path(n, n, n)
     kname, ksource = product_kernel(args.precision, path)
     workload = (f"{args.algo} L={args.depth} cutoff={args.cutoff} n={n} {args.precision} {args.dist} "
-                f"scaling={args.scaling}{' per-level' if args.per_level else ''} path={path}")
+                f"scaling={args.scaling}{' per-level' if args.per_level else ''}"
+                f"{' o-round=nearest' if args.o_round == 'nearest' else ''} path={path}")
     calib_kib = (args.calib_copy_mb << 20) / 1024.0
 
     def per_dispatch(fname, counter):
@@ -532,7 +538,7 @@ def main():
     tA = torch.from_numpy(A).cuda()
     tB = torch.from_numpy(B).cuda()
     plan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
-                  precision=args.precision, fuse=args.fuse, per_level=args.per_level)
+                  precision=args.precision, fuse=args.fuse, per_level=args.per_level, o_round=args.o_round)
     L, Mp, Kp, Np = plan.shape(m, k, n)
     path = plan.path(m, k, n)
     kname, ksource = product_kernel(args.precision, path)
@@ -542,7 +548,8 @@ def main():
 
     classical = None
     if not args.no_classical:
-        cplan = F.Plan("classical", 0, 1, scaling=args.scaling, steps=args.scaling_steps, precision=args.precision)
+        cplan = F.Plan("classical", 0, 1, scaling=args.scaling, steps=args.scaling_steps, precision=args.precision,
+                       o_round=args.o_round)
         cws = torch.empty(max(cplan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
         Cc = torch.empty((m, n), dtype=tA.dtype, device="cuda")
         run_cls = lambda: F.fastmm_gemm(cplan, tA, tB, C=Cc, workspace=cws)
@@ -554,7 +561,7 @@ def main():
         bdt = torch.float64 if args.beside == "f64" else torch.float32
         bA, bB = (tA, tB) if bdt == tA.dtype else (tA.to(bdt), tB.to(bdt))
         bplan = F.Plan(args.algo, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
-                       precision=args.beside, fuse=args.fuse, per_level=args.per_level)
+                       precision=args.beside, fuse=args.fuse, per_level=args.per_level, o_round=args.o_round)
         bws = torch.empty(max(bplan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
         Cb = torch.empty((m, n), dtype=bdt, device="cuda")
         ms_b = time_steps(lambda: F.fastmm_gemm(bplan, bA, bB, C=Cb, workspace=bws), args.steps, args.warmup)
@@ -564,7 +571,7 @@ def main():
     also, also_rows = None, None
     if args.also and args.also != "none" and args.also != args.algo:
         aplan = F.Plan(args.also, args.depth, args.cutoff, scaling=args.scaling, steps=args.scaling_steps,
-                       precision=args.precision, fuse=args.fuse, per_level=args.per_level)
+                       precision=args.precision, fuse=args.fuse, per_level=args.per_level, o_round=args.o_round)
         aws = torch.empty(max(aplan.workspace_size(m, k, n), 1), dtype=torch.uint8, device="cuda")
         Ca = torch.empty((m, n), dtype=tA.dtype, device="cuda")
         run_also = lambda: F.fastmm_gemm(aplan, tA, tB, C=Ca, workspace=aws)
@@ -606,7 +613,8 @@ def main():
     achieved = flops_per_launch / (leaf_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     workload = (f"{args.algo} L={args.depth} cutoff={args.cutoff} n={n} {args.precision} {args.dist} "
-                f"scaling={args.scaling}{' per-level' if args.per_level else ''} path={path}")
+                f"scaling={args.scaling}{' per-level' if args.per_level else ''}"
+                f"{' o-round=nearest' if args.o_round == 'nearest' else ''} path={path}")
 
     torch_ref = None
     if args.torch_ref:
@@ -658,7 +666,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "algo": args.algo, "depth": args.depth, "levels_used": L,
                    "cutoff": args.cutoff, "m": m, "k": k, "n": n, "padded": [Mp, Kp, Np],
-                   "precision": args.precision, "scaling": args.scaling, "dist": args.dist, "path": path},
+                   "precision": args.precision, "scaling": args.scaling, "o_round": args.o_round, "dist": args.dist,
+                   "path": path},
         "classical": classical,
         "beside": beside,
         "also": also,

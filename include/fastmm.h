@@ -108,7 +108,20 @@ typedef struct {
                    them and for the nested products).  Stationary and uniform non-stationary
                    plans; not with fastmm_plan_set_tree or fastmm_gemm_batched
                    (FASTMM_EUNSUPPORTED). */
+    int o_round;   /* fastmm_o_round: the power of two an O step (Algorithm 1) takes for a row
+                   or column whose max-abs is x.  Section 6 rounds the factors to powers of
+                   two (so that scaling is exact) without fixing which one:
+                   FASTMM_O_ROUND_UP (0, default) the smallest power of two >= x (scaled
+                   maxima in (1/2, 1]); FASTMM_O_ROUND_NEAREST (1) 2^j with j the integer
+                   nearest to log2 x (scaled maxima in [2^-1/2, 2^1/2); never a tie).  The
+                   nearer factor keeps rows whose maxima are alike on one factor, so the
+                   cancelling cross-block terms of a fast rule are not amplified by the factor
+                   ratio 2 when the product is unscaled (N(0,1) inputs: errors of unscaled
+                   products instead of about twice those). */
 } fastmm_scaling;
+
+/* O-step factor rounding (fastmm_scaling.o_round). */
+typedef enum { FASTMM_O_ROUND_UP = 0, FASTMM_O_ROUND_NEAREST = 1 } fastmm_o_round;
 
 typedef struct fastmm_plan_s *fastmm_plan_t;
 

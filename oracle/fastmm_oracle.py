@@ -218,6 +218,16 @@ def pow2_ceil(x: np.ndarray) -> np.ndarray:
     return np.ldexp(1.0, np.where(f == 0.5, e - 1, e)).astype(np.float64)
 
 
+def pow2_nearest(x: np.ndarray) -> np.ndarray:
+    """2^j with j the integer nearest to log2 x, for finite x > 0 (exact, via the binary
+    exponent).  With x = f 2^e, f in [1/2, 1): log2 x = e + log2 f lies in [e-1, e), nearer e
+    exactly when f > 2^-1/2.  No double equals the irrational 2^-1/2, so f > 2^-1/2 is
+    f >= the smallest double above it, and there are no ties."""
+    f, e = np.frexp(x)
+    above = float.fromhex("0x1.6a09e667f3bcdp-1")  # smallest double > 2^-1/2
+    return np.ldexp(1.0, np.where(f >= above, e, e - 1)).astype(np.float64)
+
+
 def pow2_sqrt_ratio(b: np.ndarray, a: np.ndarray) -> np.ndarray:
     """2^j with j the nearest integer to log2(b/a)/2, ties to even; exact for finite b, a > 0.
 
@@ -250,18 +260,21 @@ class ScalingResult:
     stopped_early: bool = False
 
 
-def o_step(A1, B1, pow2: bool):
+def o_step(A1, B1, pow2: bool, o_round: str = "up"):
     """Outside step (Algorithm 1; Algorithm 3 'O step'): divide rows of A' by their max-abs and
     columns of B' by theirs.  Returns new A', B', the applied factors and the unrounded ones.
-    All-zero rows/columns (and non-finite maxima) get factor 1."""
+    All-zero rows/columns (and non-finite maxima) get factor 1.  With pow2 each factor is
+    rounded to a power of two (section 6): the smallest one >= the max (o_round 'up') or the
+    one nearest to it in log scale ('nearest')."""
+    rnd = {"up": pow2_ceil, "nearest": pow2_nearest}[o_round]
     ra = np.max(np.abs(A1), axis=1) if A1.shape[1] else np.zeros(A1.shape[0])
     sb = np.max(np.abs(B1), axis=0) if B1.shape[0] else np.zeros(B1.shape[1])
     ra_ok, sb_ok = _safe_positive(ra), _safe_positive(sb)
     ra_u = np.where(ra_ok, ra, 1.0)
     sb_u = np.where(sb_ok, sb, 1.0)
     if pow2:
-        rp = np.where(ra_ok, pow2_ceil(ra_u), 1.0)
-        sp = np.where(sb_ok, pow2_ceil(sb_u), 1.0)
+        rp = np.where(ra_ok, rnd(ra_u), 1.0)
+        sp = np.where(sb_ok, rnd(sb_u), 1.0)
     else:
         rp, sp = ra_u, sb_u
     A2 = A1 / rp.astype(A1.dtype)[:, None]
@@ -285,10 +298,11 @@ def i_step(A1, B1, pow2: bool):
 
 
 def scale(A: np.ndarray, B: np.ndarray, schedule: str, tau: Optional[float] = None,
-          pow2: bool = True) -> ScalingResult:
+          pow2: bool = True, o_round: str = "up") -> ScalingResult:
     """Run a sequence of O and I steps (e.g. 'O' = Algorithm 1, 'I' = Algorithm 2, 'OI',
     'IO', 'OIOI' = Algorithm 3 with 4 steps).  With tau, the stopping test of Theorem 6.5 is
-    applied to every step after the first O step, on the unrounded factors."""
+    applied to every step after the first O step, on the unrounded factors.  o_round: the
+    power of two an O step rounds to (o_step)."""
     A1 = np.array(A, copy=True)
     B1 = np.array(B, copy=True)
     r = np.ones(A.shape[0])
@@ -298,7 +312,7 @@ def scale(A: np.ndarray, B: np.ndarray, schedule: str, tau: Optional[float] = No
     seen_o = False
     for kind in schedule:
         if kind == "O":
-            A1, B1, rp, sp, ru, su = o_step(A1, B1, pow2)
+            A1, B1, rp, sp, ru, su = o_step(A1, B1, pow2, o_round)
             r = r * rp  # D_A <- D_A D_A'
             s = sp * s  # D_B <- D_B' D_B
             res.steps.append("O")
@@ -344,16 +358,17 @@ def schedule_for(mode: str, steps: int = 2) -> str:
 
 def scaled_fast(A, B, alg: Bilinear, depth: int, cutoff: int = 1, mode: str = "none",
                 steps: int = 2, tau: Optional[float] = None, pow2: bool = True,
-                leaf: Optional[Callable] = None) -> np.ndarray:
+                leaf: Optional[Callable] = None, o_round: str = "up") -> np.ndarray:
     """C = D_A fast(A', B') D_B after the chosen scaling steps (Algorithms 1-3)."""
-    sc = scale(A, B, schedule_for(mode, steps), tau, pow2)
+    sc = scale(A, B, schedule_for(mode, steps), tau, pow2, o_round)
     Cp = fast(sc.A, sc.B, alg, depth, cutoff, leaf)
     return (sc.r.astype(Cp.dtype)[:, None] * Cp) * sc.s.astype(Cp.dtype)[None, :]
 
 
 def scaled_fast_every_level(A, B, rules: Sequence[Bilinear], cutoff: int = 1, mode: str = "none",
                             steps: int = 2, tau: Optional[float] = None, pow2: bool = True,
-                            leaf: Optional[Callable] = None, trace: Optional[list] = None) -> np.ndarray:
+                            leaf: Optional[Callable] = None, trace: Optional[list] = None,
+                            o_round: str = "up") -> np.ndarray:
     """Diagonal scaling applied at every level (a reading: the paper scales once, before the
     multiplication).  `rules` holds one rule per level (the same rule repeated for a
     stationary algorithm); the cutoff may stop the recursion earlier.  Every node of the
@@ -373,7 +388,7 @@ def scaled_fast_every_level(A, B, rules: Sequence[Bilinear], cutoff: int = 1, mo
     def node(X, Y, level):
         if level == L:
             return leaf(X, Y)
-        sc = scale(X, Y, schedule, tau, pow2)
+        sc = scale(X, Y, schedule, tau, pow2, o_round)
         if trace is not None:
             trace.append((level, sc))
         alg = rules[level]
@@ -381,7 +396,7 @@ def scaled_fast_every_level(A, B, rules: Sequence[Bilinear], cutoff: int = 1, mo
         return (sc.r.astype(Cp.dtype)[:, None] * Cp) * sc.s.astype(Cp.dtype)[None, :]
 
     if L == 0:  # the root is the only node: one scaling around the classical product
-        sc = scale(A, B, schedule, tau, pow2)
+        sc = scale(A, B, schedule, tau, pow2, o_round)
         Cp = leaf(sc.A, sc.B)
         return (sc.r.astype(Cp.dtype)[:, None] * Cp) * sc.s.astype(Cp.dtype)[None, :]
     Mp, Kp, Np = padded_dims(m, k, n, dims[:L])

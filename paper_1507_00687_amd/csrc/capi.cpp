@@ -264,7 +264,7 @@ struct fastmm_plan_s {
     int algo = 0;
     int depth = 0;
     int cutoff = 1;
-    fastmm_scaling sc{0, 0, 0.0, 0};
+    fastmm_scaling sc{0, 0, 0.0, 0, 0};
     int prec = FASTMM_F64;
     int fuse = FASTMM_FUSE_AUTO;  // fastmm_fusion
     int tile = 0;  // split precisions: limb-GEMM output tile (0: by the leaf-block shape; 128; 256)
@@ -748,6 +748,7 @@ fastmm_status run_scaling(fastmm_plan_s *p, const void *A, int64_t lda, int tran
         S.maxA = ws + w.maxA, S.maxB = ws + w.maxB;
         S.flags = flags;
         S.tau = p->sc.tau;
+        S.o_nearest = p->sc.o_round == FASTMM_O_ROUND_NEAREST ? 1 : 0;
         // The stopping test of Theorem 6.5 applies to every step after the first O step.
         S.test = (p->sc.tau > 0.0 && seen_o) ? 1 : 0;
         if (kind == 'O') seen_o = true;
@@ -898,7 +899,7 @@ fastmm_status fastmm_plan_create(fastmm_plan_t *out, int algo, int depth, int cu
     if (depth < 0 || depth > 8) return fail(FASTMM_EINVAL, "depth must be in [0, 8]");
     if (cutoff < 1) return fail(FASTMM_EINVAL, "cutoff must be >= 1");
     if (precision < FASTMM_F64 || precision > FASTMM_BF16X6) return fail(FASTMM_EINVAL, "unknown precision");
-    fastmm_scaling sc{FASTMM_SCALE_NONE, 0, 0.0, 0};
+    fastmm_scaling sc{FASTMM_SCALE_NONE, 0, 0.0, 0, FASTMM_O_ROUND_UP};
     if (scaling) {
         sc = *scaling;
         if (sc.mode < FASTMM_SCALE_NONE || sc.mode > FASTMM_SCALE_REPEATED)
@@ -907,6 +908,8 @@ fastmm_status fastmm_plan_create(fastmm_plan_t *out, int algo, int depth, int cu
             return fail(FASTMM_EINVAL, "repeated scaling needs 1 <= steps <= 256");
         if (!(sc.tau >= 0.0) || std::isinf(sc.tau)) return fail(FASTMM_EINVAL, "tau must be finite and >= 0");
         if (sc.per_level != 0 && sc.per_level != 1) return fail(FASTMM_EINVAL, "per_level must be 0 or 1");
+        if (sc.o_round != FASTMM_O_ROUND_UP && sc.o_round != FASTMM_O_ROUND_NEAREST)
+            return fail(FASTMM_EINVAL, "unknown O-step rounding");
     }
     fastmm_plan_s *p = new (std::nothrow) fastmm_plan_s();
     if (!p) return fail(FASTMM_ENOMEM, "plan allocation");

@@ -851,6 +851,16 @@ __device__ inline int ceil_log2(T x) {
     return (f == T(0.5)) ? e - 1 : e;
 }
 
+// Nearest integer to log2(x), for finite x > 0.  With x = f 2^e, f in [1/2, 1): e when
+// f > 2^-1/2, else e - 1.  2^-1/2 is irrational, so no f equals it: comparing with the double
+// just above it decides exactly (also for float f, whose values are doubles).
+template <typename T>
+__device__ inline int nearest_log2(T x) {
+    int e;
+    const T f = frexp(x, &e);
+    return ((double)f >= 0x1.6a09e667f3bcdp-1) ? e : e - 1;
+}
+
 // Nearest integer to log2(b/a)/2, ties to even, for finite a, b > 0 (exact: mantissas of b
 // and a compared directly).
 template <typename T>
@@ -865,16 +875,16 @@ __device__ inline int half_log2_ratio(T b, T a) {
     return (lo & 1) == 0 ? lo : hi;
 }
 
-// O-step finalisation: e[i] += ceil_log2(max[i]) where the max is finite and positive.
-// Stopping test (tau > 0): fail unless every unrounded factor max[i] >= thr.
+// O-step finalisation: e[i] += ceil_log2(max[i]) (or nearest_log2) where the max is finite
+// and positive.  Stopping test (tau > 0): fail unless every unrounded factor max[i] >= thr.
 template <typename T>
 __global__ void o_finalize_kernel(const T *mx, int64_t count, int32_t *e, const int32_t *flags, int32_t *fail,
-                                  int test, double thr) {
+                                  int test, double thr, int nearest) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (flags[0] != 0 || i >= count) return;  // flags[0]: iteration already stopped
     const T v = mx[i];
     if (finite_pos(v)) {
-        e[i] += ceil_log2(v);
+        e[i] += nearest ? nearest_log2(v) : ceil_log2(v);
         if (test && (double)v < thr) atomicOr(fail, 1);
     }
 }
@@ -1135,9 +1145,9 @@ hipError_t scale_step_t(const ScaleStep &S, hipStream_t s) {
         if (err != hipSuccess) return err;
         const double thr = S.test ? std::pow(1.0 + S.tau, -0.5) : 0.0;
         hipLaunchKernelGGL(o_finalize_kernel<T>, dim3(grid1d(S.m, kThreads)), dim3(kThreads), 0, s, mA, S.m,
-                           S.ea, S.flags, S.flags + 1, S.test, thr);
+                           S.ea, S.flags, S.flags + 1, S.test, thr, S.o_nearest);
         hipLaunchKernelGGL(o_finalize_kernel<T>, dim3(grid1d(S.n, kThreads)), dim3(kThreads), 0, s, mB, S.n,
-                           S.eb, S.flags, S.flags + 1, S.test, thr);
+                           S.eb, S.flags, S.flags + 1, S.test, thr, S.o_nearest);
     } else {
         // columns of A' and rows of B'
         err = reduce_cols<T>(A, S.lda, S.transA, S.m, S.k, S.ea, -1, S.ep, +1, mA, s);

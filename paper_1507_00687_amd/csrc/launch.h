@@ -95,7 +95,8 @@ struct ScaleStep {
     void *maxA, *maxB;
     int32_t *flags;
     double tau;
-    int test;  // apply the stopping test at this step
+    int test;       // apply the stopping test at this step
+    int o_nearest;  // O step: power of two nearest to the max (else the smallest >= it)
 };
 
 // Fused one-level launch for <2,2,2;7> rules with coefficients in {0, +1, -1}: every

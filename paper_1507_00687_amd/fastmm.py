@@ -57,7 +57,10 @@ class _GradProblem(ctypes.Structure):
 
 class _Scaling(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("steps", ctypes.c_int), ("tau", ctypes.c_double),
-                ("per_level", ctypes.c_int)]
+                ("per_level", ctypes.c_int), ("o_round", ctypes.c_int)]
+
+
+O_ROUNDS = {"up": 0, "nearest": 1}
 
 
 _lib = None
@@ -189,12 +192,12 @@ class Plan:
 
     def __init__(self, algo="strassen", depth: int = 1, cutoff: int = 1, scaling: str = "none",
                  steps: int = 2, tau: float = 0.0, precision: str = "f64", fuse="auto",
-                 per_level: bool = False):
+                 per_level: bool = False, o_round: str = "up"):
         self.algo, self.depth, self.cutoff = algo, depth, cutoff
         self.scaling, self.steps, self.tau, self.precision = scaling, steps, tau, precision
-        self.fuse, self.per_level = fuse, per_level
+        self.fuse, self.per_level, self.o_round = fuse, per_level, o_round
         self._h = ctypes.c_void_p()
-        sc = _Scaling(_id(SCALE_MODES, scaling), steps, tau, int(bool(per_level)))
+        sc = _Scaling(_id(SCALE_MODES, scaling), steps, tau, int(bool(per_level)), _id(O_ROUNDS, o_round))
         _check(lib().fastmm_plan_create(ctypes.byref(self._h), _id(ALGOS, algo), depth, cutoff, ctypes.byref(sc),
                                         _id(PRECISIONS, precision)))
         mode = FUSION[fuse] if isinstance(fuse, str) else (FUSION["auto"] if fuse else FUSION["off"])

@@ -93,10 +93,10 @@ def test_fullsize_f64_sampled_rows():
 N4 = 16384
 
 
-def _config4_plan(precision, name="strassen", depth=2):
+def _config4_plan(precision, name="strassen", depth=2, scaling="outside", o_round="up"):
     import paper_1507_00687_amd as F
 
-    return F.Plan(name, depth, 256, scaling="outside", precision=precision)
+    return F.Plan(name, depth, 256, scaling=scaling, precision=precision, o_round=o_round)
 
 
 def test_config4_f16x3_strassen_L2_outside_n16384_sampled_rows():
@@ -152,3 +152,26 @@ def test_config4_f16x3_f424_L2_outside_n16384_sampled_rows():
     print(f"  error f16x3 {err:.3e}, f32 {err_f32:.3e}", flush=True)
     assert err <= theorem_bound("f424", n, n, n, 2, 256, 2.0 ** -22)
     assert err <= 1.5 * err_f32
+
+
+@pytest.mark.parametrize("n,depth", [(8192, 1), (16384, 2)])
+def test_outside_scaling_nearest_rounding_keeps_unscaled_accuracy(n, depth):
+    """F16X3 Strassen with outside scaling whose O-step factors are the nearest powers of two:
+    on N(0,1) inputs at these sizes every row and column maximum (about 3.5 to 5.5) lies between
+    the rounding boundaries 2^1.5 and 2^2.5, so all factors are 4 and the fast product keeps
+    the accuracy of the unscaled one (within 1.2x on the same rows); rounding the factors up
+    splits the maxima at 4 and costs about a factor 2 (reported)."""
+    print(f"\n[o-round] strassen L={depth} n={n} f16x3: generating inputs", flush=True)
+    A, B = make_pair("normal", 24, n, n, n, dtype=np.float32)
+    rows = _rows(n)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ref = O.reference_rows(A64, B64, rows)
+    e = {}
+    for key, sc, rnd in (("none", "none", "up"), ("up", "outside", "up"), ("nearest", "outside", "nearest")):
+        got = run_gpu(_config4_plan("f16x3", depth=depth, scaling=sc, o_round=rnd), A, B)
+        e[key] = O.normwise_error(got, ref, A64, B64, rows)
+        del got
+    print(f"  error unscaled {e['none']:.3e}, outside up {e['up']:.3e}, outside nearest {e['nearest']:.3e}",
+          flush=True)
+    assert e["nearest"] <= 1.2 * e["none"]
+    assert e["nearest"] <= theorem_bound("strassen", n, n, n, depth, 256, 2.0 ** -22)

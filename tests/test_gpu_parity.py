@@ -135,19 +135,20 @@ def test_deterministic_repeat():
 MODES = {"outside": "O", "inside": "I", "out_in": "OI", "in_out": "IO"}
 
 
+@pytest.mark.parametrize("o_round", ["up", "nearest"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("mode,steps", [("outside", 1), ("inside", 1), ("out_in", 2), ("in_out", 2),
                                         ("repeated", 4), ("repeated", 7)])
-def test_scaling_exponents_bit_exact(precision, mode, steps):
+def test_scaling_exponents_bit_exact(precision, mode, steps, o_round):
     import torch
 
     import paper_1507_00687_amd as F
 
     A, B = make_pair("badly_scaled", 2, 96, 130, 70, dtype=np_dtype(precision))
-    p = _plan("strassen", 1, 1, precision, scaling=mode, steps=steps)
+    p = _plan("strassen", 1, 1, precision, scaling=mode, steps=steps, o_round=o_round)
     ea, eb, ep = F.fastmm_scaling_exponents(p, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
     sched = MODES.get(mode) or O.schedule_for("repeated", steps)
-    sc = O.scale(A.astype(np.float64), B.astype(np.float64), sched, pow2=True)
+    sc = O.scale(A.astype(np.float64), B.astype(np.float64), sched, pow2=True, o_round=o_round)
     assert np.array_equal(ea.cpu().numpy(), np.log2(sc.r).astype(np.int32))
     assert np.array_equal(eb.cpu().numpy(), np.log2(sc.s).astype(np.int32))
     assert np.array_equal(ep.cpu().numpy(), np.log2(sc.p).astype(np.int32))
@@ -172,6 +173,41 @@ def test_scaled_gemm_against_scaled_oracle(precision, mode):
                         mode=mode if mode != "repeated" else "repeated", steps=4)
     rel_or = np.max(np.abs(Cor.astype(np.longdouble) - ref) / bound_mat)
     assert float(rel) <= 4 * float(rel_or) + 4 * u
+
+
+def test_nearest_rounding_boundary_exponents_bit_exact():
+    """Row and column maxima on both sides of the rounding boundary 2^(j + 1/2): the doubles
+    just above and just below 2^-1/2, scaled by powers of two, in FP64; and the floats just
+    above and below it in FP32."""
+    import torch
+
+    import paper_1507_00687_amd as F
+
+    above = float.fromhex("0x1.6a09e667f3bcdp-1")
+    below = float(np.nextafter(above, 0.0))
+    f_above = float(np.float32(above)) if np.float32(above) > above else float(np.nextafter(np.float32(above), np.float32(1)))
+    f_below = float(np.nextafter(np.float32(f_above), np.float32(0)))
+    for precision, pair in (("f64", (above, below)), ("f32", (f_above, f_below))):
+        dt = np_dtype(precision)
+        vals = np.array([pair[i % 2] * 2.0 ** (i % 7 - 3) for i in range(64)], dtype=dt)
+        A = np.full((64, 48), 0.125, dtype=dt)
+        A[:, 5] = vals  # row maxima on both sides of the boundary
+        B = np.full((48, 64), 0.125, dtype=dt)
+        B[7, :] = vals[::-1]
+        p = _plan("strassen", 1, 1, precision, scaling="outside", o_round="nearest")
+        ea, eb, ep = F.fastmm_scaling_exponents(p, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+        sc = O.scale(A.astype(np.float64), B.astype(np.float64), "O", pow2=True, o_round="nearest")
+        assert np.array_equal(ea.cpu().numpy(), np.log2(sc.r).astype(np.int32))
+        assert np.array_equal(eb.cpu().numpy(), np.log2(sc.s).astype(np.int32))
+
+
+@pytest.mark.parametrize("precision,name,depth", [("f32", "strassen", 2), ("f64", "winograd", 2),
+                                                  ("f16x3", "strassen", 2), ("f32", "f424", 2),
+                                                  ("bf16x3", "f424", 1)])
+def test_nearest_rounding_integer_exact(precision, name, depth):
+    A, B = make_pair("int8", 9, 260, 300, 228, dtype=np_dtype(precision))
+    got = run_gpu(_plan(name, depth, 1, precision, scaling="out_in", o_round="nearest"), A, B)
+    assert np.array_equal(got.astype(np.float64), (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64))
 
 
 def test_scaling_with_tau_stops_early_like_oracle():

@@ -264,3 +264,67 @@ def test_every_level_scaling_with_cutoff_and_no_levels():
     assert np.array_equal(got, want)
     ref = O.reference_rows(A, B)
     assert O.componentwise_error(got, ref) < 1e-13
+
+
+def test_pow2_nearest_hand_values_and_boundary():
+    from fractions import Fraction
+
+    above = float.fromhex("0x1.6a09e667f3bcdp-1")  # smallest double above 2^-1/2
+    below = float(np.nextafter(above, 0.0))
+    assert Fraction(below) ** 2 < Fraction(1, 2) < Fraction(above) ** 2  # exact
+    x = np.array([1.0, 0.75, 0.7, 3.0, 2.8, 1.5, 1.4, above, below, 4.0 * above, 4.0 * below, 2.0 ** -30 * 1.5])
+    want = [1.0, 1.0, 0.5, 4.0, 2.0, 2.0, 1.0, 1.0, 0.5, 4.0, 2.0, 2.0 ** -29]
+    assert np.array_equal(O.pow2_nearest(x), want)
+
+
+def test_pow2_nearest_against_log2_rounding():
+    """Brute force over many magnitudes, away from the half-way points where float log2 could
+    round either way."""
+    rng = np.random.default_rng(11)
+    x = 2.0 ** rng.uniform(-60, 60, 20000)
+    l2 = np.log2(x)
+    keep = np.abs(l2 - np.floor(l2) - 0.5) > 1e-9
+    assert np.array_equal(O.pow2_nearest(x[keep]), 2.0 ** np.round(l2[keep]))
+
+
+def test_outside_nearest_rounding_range_and_exact_round_trip():
+    A, B = badly_scaled(6, 40, 24, 36)
+    so = O.scale(A, B, "O", pow2=True, o_round="nearest")
+    rm = np.max(np.abs(so.A), axis=1)
+    cm = np.max(np.abs(so.B), axis=0)
+    for m_ in (rm, cm):
+        assert np.all((m_ >= 2.0 ** -0.5) & (m_ < 2.0 ** 0.5))
+    for x in list(so.r) + list(so.s):
+        assert np.frexp(x)[0] == 0.5
+    assert np.array_equal(so.r[:, None] * so.A, A)
+    assert np.array_equal(so.B * so.s[None, :], B)
+    # exact on dyadic inputs through a fast rule, like the other rounding
+    Ad, Bd = dyadic_pair(3, 48, 40, 56)
+    got = O.scaled_fast(Ad, Bd, C.strassen(), 2, 1, "out_in", o_round="nearest")
+    assert np.array_equal(got, exact_product(Ad, Bd))
+
+
+def test_outside_rounding_and_the_cancelling_terms():
+    """Why the O-step rounding matters for a fast rule: rows whose maxima straddle a rounding
+    boundary get factors a ratio 2 apart, and Strassen's cancelling cross-block terms (e.g. the
+    A22 terms of M1 and M4 in C11) then carry rounding errors up to twice their unscaled size
+    after the product is unscaled.  Row and column maxima spread over [3, 5]: rounding up
+    splits them at 4 (factors 4 and 8); the nearest power of two puts them all on 4 (the
+    boundaries are 2^1.5 and 2^2.5), a uniform exact scaling, so the error equals the unscaled
+    one.  FP32 arithmetic, Strassen depth 2, n = 256."""
+    n = 256
+    errs = {"none": [], "up": [], "nearest": []}
+    for seed in range(4):
+        rng = np.random.default_rng(100 + seed)
+        A = rng.standard_normal((n, n))
+        B = rng.standard_normal((n, n))
+        A = (A / np.abs(A).max(1)[:, None] * rng.uniform(3, 5, n)[:, None]).astype(np.float32)
+        B = (B / np.abs(B).max(0)[None, :] * rng.uniform(3, 5, n)[None, :]).astype(np.float32)
+        A64, B64 = A.astype(np.float64), B.astype(np.float64)
+        ref = O.reference_rows(A64, B64)
+        err = lambda X: O.normwise_error(X.astype(np.float64), ref, A64, B64)
+        errs["none"].append(err(O.fast(A, B, C.strassen(), 2)))
+        for r in ("up", "nearest"):
+            errs[r].append(err(O.scaled_fast(A, B, C.strassen(), 2, 1, "outside", o_round=r)))
+    assert errs["nearest"] == errs["none"]
+    assert np.mean(errs["up"]) >= 1.4 * np.mean(errs["none"])
