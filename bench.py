@@ -200,10 +200,15 @@ def vendor_leaf_gemm(args, nleaves, mb, kb, nb, achieved):
     Y = torch.randn((nleaves, kb, nb), dtype=torch.float32, device="cuda", generator=g).to(dt).contiguous()
     ms_v = time_steps(lambda: torch.bmm(X, Y), args.steps, args.warmup)
     v = 2.0 * nleaves * mb * kb * nb / (ms_v * 1e-3) / 1e12
-    del X, Y
+    # its error on the first product (max-norm, relative to max|X| max|Y|) against FP64: shows
+    # the arithmetic the library used (a reduced-precision internal type would show here)
+    Z = torch.bmm(X[:1], Y[:1])[0].double()
+    Zr = X[0].double() @ Y[0].double()
+    err = ((Z - Zr).abs().max() / (X[0].double().abs().max() * Y[0].double().abs().max())).item()
+    del X, Y, Z, Zr
     return {"what": f"torch.bmm {str(dt).replace('torch.', '')} (hipBLASLt), {nleaves} x {mb}x{kb}x{nb}, N(0,1)",
             "ms": ms_v, "value": v, "frac": v / PEAK_TFLOPS_BY_DTYPE[str(dt).replace("torch.", "")],
-            "product_kernel_over_vendor": achieved / v}
+            "product_kernel_over_vendor": achieved / v, "first_product_error": err}
 
 
 def leaf_flops(F, plan_algo, plan, m, k, n, precision):
