@@ -94,8 +94,8 @@ typedef enum {
 typedef struct {
     int mode;   /* fastmm_scale_mode */
     int steps;  /* number of O/I steps for FASTMM_SCALE_REPEATED (>= 1) */
-    double tau; /* > 0: stop early by the test of Theorem 6.5, applied to every step after
-                   the first O step on the unrounded factors; evaluated on the device (the
+    double tau; /* > 0: stop early by the test of the stopping-criterion theorem (section
+                   6.3), applied to every step after the first O step on the unrounded factors; evaluated on the device (the
                    remaining steps become no-ops), no host synchronisation; 0: run all steps */
     int per_level; /* 0: the steps run once, on A and B (section 6).  1: also on the operands
                    S_r, T_r of every inner node of the recursion (a reading of scaling "at
@@ -221,13 +221,13 @@ fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode);
  * smallest tile among their plans.  The autotuner sets it per shape. */
 fastmm_status fastmm_plan_set_tile(fastmm_plan_t plan, int tile);
 
-/* Non-uniform recursion (section 3.4; Examples 4.2 and 4.3): gives every internal node of the
- * plan's recursion tree its own rule.  node_algos[i] is the rule id of node i in breadth-first
+/* Non-uniform recursion (section 3.4; the two non-uniform examples of section 5.2): gives every
+ * internal node of the plan's recursion tree its own rule.  node_algos[i] is the rule id of node i in breadth-first
  * order: node [l, r_1 .. r_{l-1}] (level l, reached through the 0-based products r_1 ..
  * r_{l-1}) is entry (R^(l-1) - 1) / (R - 1) + (r_1 .. r_{l-1} read as a base-R number), so
  * count = 1 + R + ... + R^(depth-1).  Every rule must have the plan rule's <M0,K0,N0;R> (for
- * instance the permutation variants [U, (P x I) V, (I x P) W] of Example 4.2, registered with
- * fastmm_algo_register) and every product live.  count = 0 restores the plan's rule at every
+ * instance the permutation variants [U, (P x I) V, (I x P) W] of the non-uniform Strassen
+ * example, registered with fastmm_algo_register) and every product live.  count = 0 restores the plan's rule at every
  * node.  When the cutoff leaves fewer levels, the tree's first levels apply.  Such plans take
  * the leaf path (and the limb planes of the split precisions); fastmm_gemm_backward rejects
  * them (FASTMM_EUNSUPPORTED).  Must not be called while calls using the plan are in flight

@@ -6,7 +6,7 @@ the CPU-baseline leg of the benchmark may import it; the product library never d
 the two share no code.
 
 Parity pins (tests/test_oracle_*.py) tie it to the paper: Brent equations in exact
-arithmetic, Table 1 quantities, the stability vectors of Examples 4.2 and 4.3, exact
+arithmetic, Table 1 quantities, the stability vectors of the two non-uniform examples of section 5.2, exact
 agreement with integer matrix products, the worked scaling examples 6.1-6.5, the closed
 form of Lemma D.5 and the invariants of Lemma D.1.  Scaling at every level (a reading; the
 paper prints no values for it) is pinned by exact integer products, its reduction to one

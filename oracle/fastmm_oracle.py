@@ -15,7 +15,8 @@ What it computes, each piece following the paper:
   * fast_tree(...)          -- uniform and non-uniform non-stationary recursion
                                (sections 3.3, 3.4): one rule per level or per tree node.
   * outside/inside/repeated scaling -- Algorithms 1, 2, 3 (section 6), with the stopping
-                               test of Theorem 6.5 and an exact power-of-two variant;
+                               test of the stopping-criterion theorem (section 6.3)
+                               and an exact power-of-two variant;
                                applied once (scaled_fast) or at every inner node of the
                                recursion (scaled_fast_every_level, a reading).
   * bounds                  -- Theorems 4.1 and 4.2 and the non-uniform quantities of
@@ -300,7 +301,8 @@ def i_step(A1, B1, pow2: bool):
 def scale(A: np.ndarray, B: np.ndarray, schedule: str, tau: Optional[float] = None,
           pow2: bool = True, o_round: str = "up") -> ScalingResult:
     """Run a sequence of O and I steps (e.g. 'O' = Algorithm 1, 'I' = Algorithm 2, 'OI',
-    'IO', 'OIOI' = Algorithm 3 with 4 steps).  With tau, the stopping test of Theorem 6.5 is
+    'IO', 'OIOI' = Algorithm 3 with 4 steps).  With tau, the stopping test of the
+    stopping-criterion theorem (section 6.3) is
     applied to every step after the first O step, on the unrounded factors.  o_round: the
     power of two an O step rounds to (o_step)."""
     A1 = np.array(A, copy=True)

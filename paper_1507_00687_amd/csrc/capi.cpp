@@ -749,7 +749,8 @@ fastmm_status run_scaling(fastmm_plan_s *p, const void *A, int64_t lda, int tran
         S.flags = flags;
         S.tau = p->sc.tau;
         S.o_nearest = p->sc.o_round == FASTMM_O_ROUND_NEAREST ? 1 : 0;
-        // The stopping test of Theorem 6.5 applies to every step after the first O step.
+        // The stopping test (stopping-criterion theorem, section 6.3) applies to every step after
+        // the first O step.
         S.test = (p->sc.tau > 0.0 && seen_o) ? 1 : 0;
         if (kind == 'O') seen_o = true;
         if ((e = launch_scale_step(S, st)) != hipSuccess) return hip_fail(e, "scaling step");

@@ -163,7 +163,8 @@ def test_scaled_gemm_against_scaled_oracle(precision, mode):
     ref = O.reference_rows(A64, B64)
     sched = {"none": "", "outside": "O", "repeated": "OIOI"}[mode]
     sc = O.scale(A64, B64, sched, pow2=True)
-    # Error of the scaled computation, measured as Proposition 6.3 states it: relative to
+    # Error of the scaled computation, measured as the scaled-error bound of
+    # section 6.3 (repeated outside-inside scaling) states it: relative to
     # r_i s_j ||A'|| ||B'|| entry by entry.
     bound_mat = np.outer(sc.r, sc.s) * O.maxabs(sc.A) * O.maxabs(sc.B)
     rel = np.max(np.abs(got.astype(np.longdouble) - ref) / bound_mat)

@@ -1,4 +1,5 @@
-"""GPU tests of non-uniform recursion (section 3.4): the trees of Examples 4.2 and 4.3 on the
+"""GPU tests of non-uniform recursion (section 3.4): the trees of the two non-uniform examples of section 5.2
+(Examples 4.2 and 4.3 here) on the
 leaf path (FP64, FP32) and the split-precision path, single and batched, against the oracle's
 per-node recursion."""
 import numpy as np

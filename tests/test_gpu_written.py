@@ -64,7 +64,7 @@ def test_written_float_against_oracle(precision, name, depth, shape):
 @pytest.mark.parametrize("scaling,steps", [("outside", 1), ("inside", 1), ("out_in", 2), ("repeated", 4)])
 def test_written_scaled_against_oracle(precision, scaling, steps):
     """Badly scaled inputs: the error of the scaled written path entry by entry relative to
-    r_i s_j ||A'|| ||B'|| (Proposition 6.3), within Theorem 4.1 and within 4x the oracle's own
+    r_i s_j ||A'|| ||B'|| (the scaled-error bound of section 6.3), within Theorem 4.1 and within 4x the oracle's own
     scaled product in the same precision; integers times powers of two stay bit-exact."""
     name, depth, shape = "f424", 2, (160, 96, 200)
     print(f"\n[written-scaled] {name} L={depth} {shape} {precision} {scaling}", flush=True)

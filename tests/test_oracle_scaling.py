@@ -1,6 +1,7 @@
-"""Pins for the oracle's diagonal scaling: Algorithms 1-3, Examples 6.1-6.5 (the worked 2x2
-examples of section 6), Lemma D.1 invariants, Lemma D.5 closed form and the stopping test of
-Theorem 6.5.  CPU only.  The symbolic small entry z of the examples is a power of two here so
+"""Pins for the oracle's diagonal scaling: Algorithms 1-3, the worked 2x2 examples of section 6
+(numbered 6.1-6.5 here in the paper's order: outside scaling, inside scaling, inside-outside
+against outside-inside (two), scaling not always enough), the invariants of Lemma D.1, the
+closed form of Lemma D.5 (Appendix D) and the stopping-criterion theorem of section 6.3.  CPU only.  The symbolic small entry z of the examples is a power of two here so
 that the power-of-two variant and the exact variant coincide."""
 import numpy as np
 import pytest
@@ -117,7 +118,7 @@ def test_lemma_d5_linear_rate_one_half():
 
 
 def test_stopping_criterion_guarantee_on_lemma_d5():
-    # Theorem 6.5: when the test passes after step t+1 (I) or t+2 (O), the relative distance
+    # Stopping-criterion theorem (section 6.3): when the test passes after step t+1 (I) or t+2 (O), the relative distance
     # to the limit is at most tau.  Checked against the closed-form limit of Lemma D.5.
     v = 4
     A, B = _lemma_d5(v)

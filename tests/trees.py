@@ -1,6 +1,7 @@
-"""Recursion trees of section 3.4 used by the tests: the non-uniform Strassen tree of Example
-4.2 and the three-variant <3,2,3;15> tree of Example 4.3, registered with the library as user
-rules (exact Brent check) from the oracle's coefficient tables."""
+"""Recursion trees of section 3.4 used by the tests: the non-uniform Strassen tree and the
+three-variant <3,2,3;15> tree of the two non-uniform examples of section 5.2 (numbered 4.2 and
+4.3 in these tests), registered with the library as user rules (exact Brent check) from the
+oracle's coefficient tables."""
 import numpy as np
 
 from oracle import coeffs as C
