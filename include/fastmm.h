@@ -222,15 +222,15 @@ fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode);
 fastmm_status fastmm_plan_set_tile(fastmm_plan_t plan, int tile);
 
 /* Non-uniform recursion (section 3.4; the two non-uniform examples of section 5.2): gives every
- * internal node of the plan's recursion tree its own rule.  node_algos[i] is the rule id of node i in breadth-first
- * order: node [l, r_1 .. r_{l-1}] (level l, reached through the 0-based products r_1 ..
- * r_{l-1}) is entry (R^(l-1) - 1) / (R - 1) + (r_1 .. r_{l-1} read as a base-R number), so
- * count = 1 + R + ... + R^(depth-1).  Every rule must have the plan rule's <M0,K0,N0;R> (for
- * instance the permutation variants [U, (P x I) V, (I x P) W] of the non-uniform Strassen
- * example, registered with fastmm_algo_register) and every product live.  count = 0 restores the plan's rule at every
- * node.  When the cutoff leaves fewer levels, the tree's first levels apply.  Such plans take
- * the leaf path (and the limb planes of the split precisions); fastmm_gemm_backward rejects
- * them (FASTMM_EUNSUPPORTED).  Must not be called while calls using the plan are in flight
+ * internal node of the plan's recursion tree its own rule.  node_algos[i] is the rule id of
+ * node i in breadth-first order: node [l, r_1 .. r_{l-1}] (level l, reached through the 0-based
+ * products r_1 .. r_{l-1}) is entry (R^(l-1) - 1) / (R - 1) + (r_1 .. r_{l-1} read as a base-R
+ * number), so count = 1 + R + ... + R^(depth-1).  Every rule must have the plan rule's
+ * <M0,K0,N0;R> (for instance the permutation variants [U, (P x I) V, (I x P) W] of the
+ * non-uniform Strassen example, registered with fastmm_algo_register) and every product live.
+ * count = 0 restores the plan's rule at every node.  When the cutoff leaves fewer levels, the
+ * tree's first levels apply.  Such plans take the leaf path (and the limb planes of the split
+ * precisions), forward, batched and backward.  Must not be called while calls using the plan are in flight
  * (the plan's cached task tables are rebuilt).  Errors: FASTMM_EINVAL (null list, unknown
  * id), FASTMM_ESHAPE (wrong count, a rule of another shape), FASTMM_EUNSUPPORTED (a rule with
  * a product that never reaches C). */
@@ -376,8 +376,9 @@ fastmm_status fastmm_gemm_noalloc(fastmm_plan_t plan, const void *A, const void 
  * fusion mode as the plan (for uniform non-stationary plans every level's rule is transformed
  * alike).  A (m x k), B (k x n), G (m x n) are contiguous row-major inputs; dA (m x k) and
  * dB (k x n) outputs, either may be NULL to skip it; with m = 0 (resp. n = 0) the requested
- * dB (dA) is filled with zeros.  Workspace: fastmm_backward_workspace_size bytes.
- * FASTMM_EUNSUPPORTED for plans with a non-uniform tree (fastmm_plan_set_tree). */
+ * dB (dA) is filled with zeros.  Workspace: fastmm_backward_workspace_size bytes.  Plans with
+ * a non-uniform tree (fastmm_plan_set_tree) transform every node's rule alike and run on the
+ * leaf path. */
 fastmm_status fastmm_backward_workspace_size(fastmm_plan_t plan, int64_t m, int64_t k, int64_t n,
                                              size_t *bytes);
 fastmm_status fastmm_gemm_backward(fastmm_plan_t plan, const void *A, const void *B, const void *G,

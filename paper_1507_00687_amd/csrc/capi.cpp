@@ -1581,17 +1581,20 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
         return FASTMM_OK;
     }
-    // FP64 / FP32 outside the written path: scaled plans with a level and transposed operands
-    // run on row-major (scaled) copies of the operands
+    // FP64 / FP32 outside the written path: scaled plans and transposed operands run on
+    // row-major (scaled) copies of the operands (one pass, cheaper than applying the factors to
+    // every loaded element: the products kernels re-read each operand element many times)
     const bool written = written_taken(plan, s);
-    const bool scaled_copy = !written && exps.ea != nullptr && s.L >= 1;
+    const bool scaled_copy = !written && exps.ea != nullptr;
     if (!written && (scaled_copy || transA || transB)) {
         if ((e = prescale_operands(plan, s, A, lda, transA, B, ldb, transB, m, k, n, exps, scaled_copy, ws, w, tab,
                                    st, &A, &lda, &B, &ldb)) != hipSuccess)
             return hip_fail(e, "operand copies");
         transA = transB = 0;
         L.A = A, L.B = B, L.lda = lda, L.ldb = ldb, L.transA = L.transB = 0;
-        if (scaled_copy) L.sc = ScaleExps{nullptr, nullptr, nullptr};  // the products read scaled copies
+        // the products read scaled copies; a single leaf still scales its output
+        if (scaled_copy && s.L >= 1) L.sc = ScaleExps{nullptr, nullptr, nullptr};
+        if (scaled_copy && s.L == 0) L.scale_in = 0;
     }
     uint32_t masks[6];
     const bool fused = fused_path(plan, s, transA, transB, masks);
@@ -1695,10 +1698,11 @@ fastmm_status fastmm_gemm(fastmm_plan_t plan, const void *A, const void *B, void
 namespace fastmm {
 namespace {
 // Sub-plan of `p` for a gradient product (which = 0: dA = G B^T, a <M0,N0,K0> product; 1:
-// dB = A^T G, a <K0,M0,N0> product): every level's rule replaced by the transpose of its
-// rotation (section 3.1), same depth, cutoff, scaling, precision, fusion mode and tile.
+// dB = A^T G, a <K0,M0,N0> product): every level's (or tree node's) rule replaced by the
+// transpose of its rotation (section 3.1), same depth, cutoff, scaling, precision, fusion mode
+// and tile.  Rotation and transposition keep the product indices, so a tree keeps its node
+// numbering.
 fastmm_status grad_plan(fastmm_plan_s *p, int which, fastmm_plan_s **out) {
-    if (!p->tree.empty()) return fail(FASTMM_EUNSUPPORTED, "backward of a non-uniform plan is not built");
     const int times = which == 0 ? 2 : 1;
     std::lock_guard<std::mutex> g(p->mu);
     if (!p->grad[which]) {
@@ -1712,6 +1716,11 @@ fastmm_status grad_plan(fastmm_plan_s *p, int which, fastmm_plan_s **out) {
             const int r = algo_transposed_rotation(lid, times);
             if (r < 0) return fail(FASTMM_EUNSUPPORTED, "cannot form a level's backward rule");
             q->levels.push_back(r);
+        }
+        for (int nid : p->tree) {  // non-uniform: every node's rule transformed alike
+            const int r = algo_transposed_rotation(nid, times);
+            if (r < 0) return fail(FASTMM_EUNSUPPORTED, "cannot form a tree node's backward rule");
+            q->tree.push_back(r);
         }
         p->grad[which] = std::move(q);
     }

@@ -34,6 +34,8 @@ struct LeafLaunch {
     const SrcEntry *bsrc;
     ScaleExps sc;
     int direct;
+    int scale_in = 1;  // with sc and a direct output: 0 takes the operands as already scaled
+                       // (only the output takes 2^(ea_i + eb_j)); row-major operands only
 };
 
 // W-combination: C_block(P,S) = sum over its DestEntry list of coef * M_leaf, then

@@ -91,7 +91,9 @@ struct Tile {
 };
 
 // One 128x128 output tile (tile row tm, tile column tn) of leaf `leaf` of the problem p.
-template <typename T, bool SCALED, bool DIRECT>
+// SCALED: the loads apply the scaling factors to the operands; SCALED_OUT: a direct output takes
+// 2^(ea_i + eb_j) (with SCALED both, without SCALED only the output: operands already scaled).
+template <typename T, bool SCALED, bool DIRECT, bool SCALED_OUT = SCALED>
 __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t tm, int64_t tn,
                                           typename Tile<T>::Smem &sm) {
     typedef Core<T> C;
@@ -419,7 +421,7 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
                 T val = acc[i][j][v];
                 if (DIRECT) {
                     if (row < p.m && col < p.n) {
-                        if (SCALED) val = C::scale(val, p.sc.ea[row] + p.sc.eb[col]);
+                        if (SCALED_OUT) val = C::scale(val, p.sc.ea[row] + p.sc.eb[col]);
                         p.out[row * p.ldo + col] = val;
                     }
                 } else {
@@ -440,7 +442,7 @@ __device__ __forceinline__ void tile_coords(int rem, int tiles_m, int tiles_n, i
     tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
 }
 
-template <typename T, bool SCALED, bool DIRECT>
+template <typename T, bool SCALED, bool DIRECT, bool SCALED_OUT = SCALED>
 __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T> p) {
     __shared__ typename Tile<T>::Smem sm;
     const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T>
     const int rem = __builtin_amdgcn_readfirstlane((int)(bid - (int64_t)leaf * tiles));
     int64_t tm, tn;
     tile_coords(rem, p.tiles_m, p.tiles_n, tm, tn);
-    leaf_tile<T, SCALED, DIRECT>(p, leaf, tm, tn, sm);
+    leaf_tile<T, SCALED, DIRECT, SCALED_OUT>(p, leaf, tm, tn, sm);
 }
 
 // Batched launch over several problems of one output mode (each with its own plan tables):
@@ -512,7 +514,9 @@ hipError_t go(const LeafLaunch &L, hipStream_t s) {
     const bool scaled = L.sc.ea != nullptr;
     dim3 grid((unsigned)blocks), block(kNT);
     if (L.direct) {
-        if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, true>), grid, block, 0, s, a);
+        if (scaled && !L.scale_in)
+            hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, true, true>), grid, block, 0, s, a);
+        else if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, true>), grid, block, 0, s, a);
     } else {
         if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, false>), grid, block, 0, s, a);

@@ -54,7 +54,7 @@ def test_tree_float_against_oracle_tree(precision, tree):
     assert err <= (1e-13 if precision == "f64" else 5e-5)
 
 
-def test_tree_in_a_batch_and_backward_rejected():
+def test_tree_in_a_batch_and_backward():
     import torch
 
     import paper_1507_00687_amd as F
@@ -70,5 +70,19 @@ def test_tree_in_a_batch_and_backward_rejected():
     torch.cuda.synchronize()
     for (a, b), c in zip(host, Cs):
         assert np.array_equal(c.cpu().numpy().astype(np.float64), (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
-    with pytest.raises(F.FastmmError):
-        F.fastmm_gemm_backward(tplan, As[0], Bs[0], torch.ones((256, 192), device="cuda"))
+    # backward: every node's rule transposed and rotated alike (section 3.1), exact on integers,
+    # single and batched
+    from synth.gen import TAG_G, int_uniform
+
+    i64 = lambda X: X.astype(np.int64)
+    Gs = [int_uniform(60 + i, TAG_G, (s[0], s[2])).astype(np.float32) for i, s in enumerate(shapes)]
+    tGs = [torch.from_numpy(g).cuda() for g in Gs]
+    dA, dB = F.fastmm_gemm_backward(tplan, As[0], Bs[0], tGs[0])
+    batched = F.fastmm_gemm_backward_batched(plans, As, Bs, tGs)
+    torch.cuda.synchronize()
+    a, b = host[0]
+    assert np.array_equal(dA.cpu().numpy().astype(np.float64), (i64(Gs[0]) @ i64(b).T).astype(np.float64))
+    assert np.array_equal(dB.cpu().numpy().astype(np.float64), (i64(a).T @ i64(Gs[0])).astype(np.float64))
+    for (a, b), g, (ga, gb) in zip(host, Gs, batched):
+        assert np.array_equal(ga.cpu().numpy().astype(np.float64), (i64(g) @ i64(b).T).astype(np.float64))
+        assert np.array_equal(gb.cpu().numpy().astype(np.float64), (i64(a).T @ i64(g)).astype(np.float64))
