@@ -119,7 +119,7 @@ def time_steps(fn, steps, warmup):
 def product_kernel(precision: str, path: str):
     """(kernel name, source file) of the launch that computes the products."""
     if path == "fused":
-        return "fmm_node222", "node_fused.hip"
+        return "fmm_node222", "node_fused.h"
     if path == "fused_loads":
         return "fmm_limb_fused", "limb_gemm.hip"
     if precision in ("f64", "f32"):  # leaf and written paths
@@ -478,7 +478,7 @@ def record_traffic(args):
     kname, ksource = product_kernel(args.precision, path)
     workload = (f"{args.algo} L={args.depth} cutoff={args.cutoff} n={n} {args.precision} {args.dist} "
                 f"scaling={args.scaling}{' per-level' if args.per_level else ''}"
-                f"{' o-round=nearest' if args.o_round == 'nearest' else ''} path={path}")
+                f"{' o-round=nearest' if args.o_round == 'nearest' and args.scaling != 'none' else ''} path={path}")
     calib_kib = (args.calib_copy_mb << 20) / 1024.0
 
     def per_dispatch(fname, counter):
@@ -619,7 +619,7 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     workload = (f"{args.algo} L={args.depth} cutoff={args.cutoff} n={n} {args.precision} {args.dist} "
                 f"scaling={args.scaling}{' per-level' if args.per_level else ''}"
-                f"{' o-round=nearest' if args.o_round == 'nearest' else ''} path={path}")
+                f"{' o-round=nearest' if args.o_round == 'nearest' and args.scaling != 'none' else ''} path={path}")
 
     torch_ref = None
     if args.torch_ref:
