@@ -175,7 +175,9 @@ typedef enum {
                               while loading, eq. (2)), then one W-combination launch */
     FASTMM_PATH_FUSED = 1, /* the innermost level fused: each work-group forms S_r, T_r, the R
                               products and the W-sums of eq. (1) for one tile of a node of the
-                              recursion; the outer L-1 levels as in the leaf path */
+                              recursion; from depth 2 the node operands of the outer L-1 levels
+                              are written level by level first (with the scaling factors and
+                              transposes applied), and their W-combination follows the kernel */
     FASTMM_PATH_EVERY_LEVEL = 2, /* scaling at every level (fastmm_scaling.per_level, depth >= 2):
                               the first level's node operands written out, each node product
                               by a call of the remaining levels, then the W-combination */

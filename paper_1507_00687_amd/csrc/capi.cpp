@@ -513,6 +513,16 @@ bool written_taken(const fastmm_plan_s *p, const Shape &s) {
     return written_leaves(p, s) && !fused_path(p, s, 0, 0, masks);
 }
 
+// The fused path from depth 2: the node operands of the L-1 outer levels are written level by
+// level first (the scaling factors and transposes applied at the first level), so that the fused
+// kernel reads one source per node operand.  Summing the two or more sources of every node
+// operand in the kernel's load stage doubled its loads per MFMA (Strassen depth 2 FP32 at
+// n=8192: 0.47 of the FP32 peak, against 0.61 at depth 1).
+bool fused_written(const fastmm_plan_s *p, const Shape &s) {
+    uint32_t masks[6];
+    return s.L >= 2 && fused_path(p, s, 0, 0, masks);
+}
+
 struct WrittenDims {
     int64_t xa_ld, xb_ld;
 };
@@ -599,9 +609,14 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
             w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
             w.ib = off, off = align256(off + inner_levels(p, s, true).back().off);
         }
+    } else if (!is_split(p->prec) && fused_written(p, s)) {
+        // FP64 / FP32 fused from depth 2: the outer levels' node operands (the last of them
+        // stacked as the fused kernel's operands)
+        w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
+        w.ib = off, off = align256(off + inner_levels(p, s, true).back().off);
     } else if (!is_split(p->prec) && !written_taken(p, s)) {
-        // FP64 / FP32: row-major copies of op(A) and op(B), scaled, for scaled plans with a
-        // level and for transposed operands (prescale_operands)
+        // FP64 / FP32: row-major copies of op(A) and op(B), scaled, for scaled plans and for
+        // transposed operands (prescale_operands)
         w.xa = off, off = align256(off + es * (size_t)s.Mp * round_up(s.Kp, 8));
         w.xb = off, off = align256(off + es * (size_t)s.Kp * round_up(s.Np, 8));
     } else if (written_taken(p, s)) {
@@ -1299,16 +1314,20 @@ hipError_t prescale_operands(fastmm_plan_s *plan, const Shape &s, const void *A,
 // FP64 / FP32 with written-out leaf operands: the leaf operands of both sides level by level
 // (the first level scaled), S_r stacked at ws + xa (o-major), T_r at ws + xb (k-major, B's own
 // orientation), so that the leaf kernel reads each as one row-major source block.
+// With upto = s.L - 1 (the fused path from depth 2) the levels stop at the node operands of the
+// innermost level's nodes, written where inner_levels puts level L-1, the A side o-major (node q
+// at rows q cb_o) and the B side k-major (node q at rows q cb_k, row stride cb_o): stacked
+// row-major operands with one source per node.
 hipError_t form_written(fastmm_plan_s *plan, const Shape &s, const void *A, int64_t lda, int transA, const void *B,
                         int64_t ldb, int transB, int64_t m, int64_t k, int64_t n, const ScaleExps &exps, char *ws,
-                        const WsLayout &w, const Tables *tab, hipStream_t st) {
+                        const WsLayout &w, const Tables *tab, hipStream_t st, int upto) {
     const Algo &al = plan_algo(plan);
     const WrittenDims wd = written_dims(s);
     auto form_side = [&](bool side_b) -> hipError_t {
         const std::vector<InnerLevel> lv = inner_levels(plan, s, side_b);
         char *ibase = ws + (side_b ? w.ib : w.ia);
         int64_t nodes = 1;
-        for (int l = 1; l <= s.L; ++l) {
+        for (int l = 1; l <= upto; ++l) {
             NodeForm nf{};
             if (l == 1) {
                 if (side_b) {
@@ -1338,6 +1357,9 @@ hipError_t form_written(fastmm_plan_s *plan, const Shape &s, const void *A, int6
                 const InnerLevel &out = lv[l - 1];
                 nf.cb_o = out.cb_o, nf.cb_k = out.cb_k;
                 nf.Y = ibase + out.off, nf.y_ld = out.y_ld, nf.y_stride = out.y_stride;
+                if (l == upto && side_b) {  // the fused kernel's B operand: k-major, same bytes
+                    nf.y_ld = out.cb_o, nf.y_stride = out.cb_k * out.cb_o, nf.kmajor = 1;
+                }
             }
             if (nodes > 65535) return hipErrorInvalidValue;
             hipError_t er = launch_form_node(plan->prec, nf, (int)nodes, st);
@@ -1585,8 +1607,9 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     // row-major (scaled) copies of the operands (one pass, cheaper than applying the factors to
     // every loaded element: the products kernels re-read each operand element many times)
     const bool written = written_taken(plan, s);
-    const bool scaled_copy = !written && exps.ea != nullptr;
-    if (!written && (scaled_copy || transA || transB)) {
+    const bool fw = !written && fused_written(plan, s);  // outer levels written, then fused
+    const bool scaled_copy = !written && !fw && exps.ea != nullptr;
+    if (!written && !fw && (scaled_copy || transA || transB)) {
         if ((e = prescale_operands(plan, s, A, lda, transA, B, ldb, transB, m, k, n, exps, scaled_copy, ws, w, tab,
                                    st, &A, &lda, &B, &ldb)) != hipSuccess)
             return hip_fail(e, "operand copies");
@@ -1597,12 +1620,18 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         if (scaled_copy && s.L == 0) L.scale_in = 0;
     }
     uint32_t masks[6];
-    const bool fused = fused_path(plan, s, transA, transB, masks);
+    const bool fused = fw ? fused_path(plan, s, 0, 0, masks) : fused_path(plan, s, transA, transB, masks);
+    if (fw) {
+        if ((e = form_written(plan, s, A, lda, transA, B, ldb, transB, m, k, n, exps, ws, w, tab, st, s.L - 1)) !=
+            hipSuccess)
+            return hip_fail(e, "node operand formation");
+    }
     if (written) {
         // leaf operands written out level by level, then one launch over the stacked blocks
         // (one source per leaf, unscaled: the formation applied the factors), then the
         // W-combination with D_A, D_B
-        if ((e = form_written(plan, s, A, lda, transA, B, ldb, transB, m, k, n, exps, ws, w, tab, st)) != hipSuccess)
+        if ((e = form_written(plan, s, A, lda, transA, B, ldb, transB, m, k, n, exps, ws, w, tab, st, s.L)) !=
+            hipSuccess)
             return hip_fail(e, "leaf operand formation");
         fin.mark();
         const WrittenDims wd = written_dims(s);
@@ -1643,6 +1672,16 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         N.nnodes = outer->nleaves;
         N.outer = outer->leaves, N.asrc = outer->asrc, N.bsrc = outer->bsrc;
         N.sc = exps;  // the operands are the scaled copies when the plan scales
+        if (fw) {
+            // node q's operands: rows q cb_o of the stacked A side, rows q cb_k of the k-major B
+            // side (one source each, block row q); bounds over the stacks
+            const InnerLevel la = inner_levels(plan, s, false)[(size_t)s.L - 2];
+            const InnerLevel lb = inner_levels(plan, s, true)[(size_t)s.L - 2];
+            N.A = ws + w.ia + la.off, N.lda = la.y_ld;
+            N.B = ws + w.ib + lb.off, N.ldb = lb.cb_o;
+            N.m = (int64_t)outer->nleaves * la.cb_o, N.k = (int64_t)outer->nleaves * la.cb_k, N.n = lb.cb_o;
+            N.outer = outer->wleaves, N.asrc = outer->wsrc, N.bsrc = outer->wsrc;
+        }
         for (int i = 0; i < 6; ++i) N.masks[i] = masks[i];
         if (s.L == 1) {
             N.out = C, N.ldo = ldc, N.node_stride = 0;
