@@ -7,8 +7,10 @@
 // 64x64 (FP32) or 64x32 (FP64) tile position (tm, tn) of the four output sub-blocks of one node
 // of the recursion tree (the node is the whole problem at depth 1; at depth L it is one of the
 // R^(L-1) products of the outer levels).  Per K stage it loads the matching tiles of the node's
-// four A sub-blocks and four B sub-blocks into LDS once -- each node operand being the sum of
-// its outer-level sources, formed while loading -- and then, for every product r, forms the
+// four A sub-blocks and four B sub-blocks into LDS once -- each node operand the sum of its
+// sources in the outer tables, formed while loading; the library hands it one source per node
+// operand (the operands themselves at depth 1, the written node operands from depth 2) -- and
+// then, for every product r, forms the
 // MFMA fragments of S_r = sum_i u_ir A_i and T_r = sum_j v_jr B_j (eq. (1)) from those LDS
 // tiles and accumulates M_r = S_r T_r in registers.  The epilogue forms C_k = sum_r w_kr M_r
 // (eq. (1)) and writes each element of the node's output once: into C with the outside-scaling
@@ -122,9 +124,16 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
     // 16-byte LDS write per column; consecutive lanes take consecutive k-blocks, which keeps
     // both the global reads (whole row segments) and the LDS writes free of conflicts.
     constexpr int KBV = BK / VEC, CBV = BN / VEC, NBT = 4 * KBV * CBV / kNT;  // B: blocks per thread
-    // LDS tiles are k-contiguous for both operands (B stored transposed), rows padded to a
-    // 16-byte multiple that spreads consecutive rows over the banks.
-    constexpr int LDS_K = BK + 16 / (int)sizeof(T);
+    // LDS tiles are k-contiguous for both operands (B stored transposed).  FP32: rows of 16
+    // floats (64 bytes, four 16-byte chunks), chunk c of row r stored at chunk c ^ ((r / 2) mod 4),
+    // the layout under which the limb GEMM's 16-row fragment reads and row-major staging writes
+    // measure no bank conflicts; FP64: rows padded to a 16-byte multiple that spreads consecutive
+    // rows over the banks.  lidx(r, k): element (row r, k) for k a multiple of VEC.
+    constexpr bool SWZ = sizeof(T) == 4;
+    constexpr int LDS_K = SWZ ? BK : BK + 16 / (int)sizeof(T);
+    auto lidx = [](int r, int k) {
+        return SWZ ? r * LDS_K + (((k / VEC) ^ ((r >> 1) & 3)) * VEC) : r * LDS_K + k;
+    };
     static_assert(NPA * RPPA == BM && NBT * kNT == 4 * KBV * CBV, "tile shape");
     static_assert((LDS_K * sizeof(T)) % 16 == 0 && KPL % VEC == 0, "row alignment");
 
@@ -280,7 +289,7 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
                 T *xs = reinterpret_cast<T *>(&x);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) xs[e] = va[s][pa][e];
-                *reinterpret_cast<vec_t *>(&As[st][s][(pa * RPPA + ra) * LDS_K + ka]) = x;
+                *reinterpret_cast<vec_t *>(&As[st][s][lidx(pa * RPPA + ra, ka)]) = x;
             }
         }
 #pragma unroll
@@ -291,7 +300,7 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
                 T *xs = reinterpret_cast<T *>(&x);
 #pragma unroll
                 for (int vr = 0; vr < VEC; ++vr) xs[vr] = vb[u][vr][e];
-                *reinterpret_cast<vec_t *>(&Bs[st][sB[u]][(cB[u] + e) * LDS_K + kB[u]]) = x;
+                *reinterpret_cast<vec_t *>(&Bs[st][sB[u]][lidx(cB[u] + e, kB[u])]) = x;
             }
     };
 
@@ -327,7 +336,7 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
 #pragma unroll
                 for (int i = 0; i < TM; ++i) {
                     const vec_t w = *reinterpret_cast<const vec_t *>(
-                        &As[cur][s][(wm * 16 * TM + i * 16 + l16) * LDS_K + g4 + jh * VEC]);
+                        &As[cur][s][lidx(wm * 16 * TM + i * 16 + l16, g4 + jh * VEC)]);
                     const T *ws = reinterpret_cast<const T *>(&w);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) ea[i][s][e] = ws[e];
@@ -335,7 +344,7 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
 #pragma unroll
                 for (int j = 0; j < TN; ++j) {
                     const vec_t w = *reinterpret_cast<const vec_t *>(
-                        &Bs[cur][s][(wn * 16 * TN + j * 16 + l16) * LDS_K + g4 + jh * VEC]);
+                        &Bs[cur][s][lidx(wn * 16 * TN + j * 16 + l16, g4 + jh * VEC)]);
                     const T *ws = reinterpret_cast<const T *>(&w);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) eb[j][s][e] = ws[e];
