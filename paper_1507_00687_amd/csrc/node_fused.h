@@ -7,10 +7,9 @@
 // 64x64 (FP32) or 64x32 (FP64) tile position (tm, tn) of the four output sub-blocks of one node
 // of the recursion tree (the node is the whole problem at depth 1; at depth L it is one of the
 // R^(L-1) products of the outer levels).  Per K stage it loads the matching tiles of the node's
-// four A sub-blocks and four B sub-blocks into LDS once -- each node operand the sum of its
-// sources in the outer tables, formed while loading; the library hands it one source per node
-// operand (the operands themselves at depth 1, the written node operands from depth 2) -- and
-// then, for every product r, forms the
+// four A sub-blocks and four B sub-blocks into LDS once -- one source block per node operand:
+// the operands themselves at depth 1, the node operands written by the outer levels' formation
+// from depth 2 -- and then, for every product r, forms the
 // MFMA fragments of S_r = sum_i u_ir A_i and T_r = sum_j v_jr B_j (eq. (1)) from those LDS
 // tiles and accumulates M_r = S_r T_r in registers.  The epilogue forms C_k = sum_r w_kr M_r
 // (eq. (1)) and writes each element of the node's output once: into C with the outside-scaling
@@ -74,7 +73,8 @@ struct NArgs {
     int64_t m, k, n;
     int64_t mb, kb, nb;  // sub-block sizes (the leaf block of the full recursion)
     int tiles_m, tiles_n;
-    const LeafEntry *outer;  // per node: its operand sources (blocks of 2mb x 2kb, 2kb x 2nb)
+    const LeafEntry *outer;  // per node: its one A and one B source (blocks of 2mb x 2kb, 2kb x 2nb),
+                             // coefficient 1
     const SrcEntry *asrc;
     const SrcEntry *bsrc;
     int64_t node_stride;  // elements between node products in the workspace
@@ -103,6 +103,13 @@ __device__ __forceinline__ T psum(int r, const T (&e)[4]) {
         first = false;
     }
     return a;
+}
+
+// A wave-uniform 64-bit value, kept in scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 __device__ inline int64_t xcd_remap(int64_t b, int64_t G) {
@@ -152,11 +159,12 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
     const int gidx = rem - grp * 8 * p.tiles_n;
     const int64_t tm = __builtin_amdgcn_readfirstlane(grp * 8 + gidx % gsz);
     const int64_t tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
-    LeafEntry le = p.outer[node];
-    le.a_begin = __builtin_amdgcn_readfirstlane(le.a_begin);
-    le.a_count = __builtin_amdgcn_readfirstlane(le.a_count);
-    le.b_begin = __builtin_amdgcn_readfirstlane(le.b_begin);
-    le.b_count = __builtin_amdgcn_readfirstlane(le.b_count);
+    // The node's one A source and one B source (coefficient 1): block row / column of the node
+    // operand in the stacked or plain operand.
+    const LeafEntry le = p.outer[node];
+    const SrcEntry sa = p.asrc[le.a_begin], sbs = p.bsrc[le.b_begin];
+    const int64_t abr = __builtin_amdgcn_readfirstlane(sa.br), abc = __builtin_amdgcn_readfirstlane(sa.bc);
+    const int64_t bbr = __builtin_amdgcn_readfirstlane(sbs.br), bbc = __builtin_amdgcn_readfirstlane(sbs.bc);
 
     const int ra = t / TPRA, ka = (t % TPRA) * VEC;   // A: row within pass, k offset
     int sB[NBT], kB[NBT], cB[NBT];  // B: the thread's blocks (sub-block, k offset, column offset)
@@ -166,37 +174,120 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
         sB[u] = idx / (KBV * CBV), kB[u] = (b % KBV) * VEC, cB[u] = (b / KBV) * VEC;
     }
     const int64_t mb2 = 2 * p.mb, kb2 = 2 * p.kb, nb2 = 2 * p.nb;
+    // first row and column of the work-group's tile in sub-block s4 (A: s4 = p + 2q for
+    // sub-block (p, q); B likewise), k offset 0; uniform, recomputed where used
+    auto rowA = [&](int s4) { return abr * mb2 + (s4 & 1) * p.mb + tm * BM; };
+    auto colA = [&](int s4) { return abc * kb2 + (s4 >> 1) * p.kb; };
+    auto rowB = [&](int s4) { return bbr * kb2 + (s4 & 1) * p.kb; };
+    auto colB = [&](int s4) { return bbc * nb2 + (s4 >> 1) * p.nb + tn * BN; };
 
     // Stages with k0 + BK <= kfast read whole tiles with vector loads and no bounds checks:
-    // every source tile of this work-group lies inside its sub-block and inside the operand.
+    // every tile of this work-group lies inside its sub-block and inside the operand.
     int64_t kfast = (p.vec_a && p.vec_b && p.small_ld && tm * BM + BM <= p.mb && tn * BN + BN <= p.nb) ? p.kb : 0;
-    for (int q = 0; q < le.a_count && kfast > 0; ++q) {
-        const SrcEntry se = p.asrc[le.a_begin + q];
-        for (int s = 0; s < 4; ++s) {
-            if ((int64_t)se.br * mb2 + (s & 1) * p.mb + tm * BM + BM > p.m) kfast = 0;
-            kfast = min(kfast, p.k - ((int64_t)se.bc * kb2 + (s >> 1) * p.kb));
-        }
-    }
-    for (int q = 0; q < le.b_count && kfast > 0; ++q) {
-        const SrcEntry se = p.bsrc[le.b_begin + q];
-        for (int s = 0; s < 4; ++s) {
-            if ((int64_t)se.bc * nb2 + (s >> 1) * p.nb + tn * BN + BN > p.n) kfast = 0;
-            kfast = min(kfast, p.k - ((int64_t)se.br * kb2 + (s & 1) * p.kb));
-        }
-    }
+    if (rowA(1) + BM > p.m || colB(2) + BN > p.n) kfast = 0;  // the last sub-block row / column
+    kfast = min(kfast, min(p.k - colA(2), p.k - rowB(1)));
     kfast = __builtin_amdgcn_readfirstlane(kfast);
-    // byte offsets of the thread's vectors inside a tile (the same for every source, sub-block
-    // and K stage)
+    // byte offsets of the thread's vectors inside a tile (the same for every sub-block and K
+    // stage)
     uint32_t voA[NPA], voB[NBT];
 #pragma unroll
     for (int pa = 0; pa < NPA; ++pa) voA[pa] = (uint32_t)(((pa * RPPA + ra) * p.lda + ka) * sizeof(T));
 #pragma unroll
     for (int u = 0; u < NBT; ++u) voB[u] = (uint32_t)((kB[u] * p.ldb + cB[u]) * sizeof(T));
 
+    // The thread's part of the A tiles of the four node sub-blocks at K offset k0, zero outside
+    // A and the sub-block.
+    auto load_a_one = [&](int64_t k0, T (&v)[4][NPA][VEC]) {
+        const bool fast = k0 + BK <= kfast;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int64_t row0 = rowA(s4), cbase = colA(s4) + k0;
+            if (fast) {
+                const char *base = reinterpret_cast<const char *>(p.A + uniform64(row0 * p.lda + cbase));
+#pragma unroll
+                for (int pa = 0; pa < NPA; ++pa) {
+                    const vec_t w = *reinterpret_cast<const vec_t *>(__builtin_assume_aligned(base + voA[pa], 16));
+                    const T *ws = reinterpret_cast<const T *>(&w);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) v[s4][pa][e] = ws[e];
+                }
+            } else {
+#pragma unroll
+                for (int pa = 0; pa < NPA; ++pa) {
+                    const int r = pa * RPPA + ra;
+                    const bool rok = (tm * BM + r < p.mb) && (row0 + r < p.m);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const bool ok = rok && (k0 + ka + e < p.kb) && (cbase + ka + e < p.k);
+                        const T y = *(ok ? p.A + (row0 + r) * p.lda + cbase + ka + e : p.A);
+                        v[s4][pa][e] = ok ? y : T(0);
+                    }
+                }
+            }
+        }
+    };
+    // The thread's B blocks at K offset k0, zero outside B and the sub-block.
+    auto load_b_one = [&](int64_t k0, T (&v)[NBT][VEC][VEC]) {
+        const bool fast = k0 + BK <= kfast;
+#pragma unroll
+        for (int u = 0; u < NBT; ++u) {
+            const int sb = sB[u];
+            const int64_t row0 = rowB(sb) + k0, cbase = colB(sb);  // k-row of block row 0, tile column 0
+            if (fast) {
+                const char *base = reinterpret_cast<const char *>(p.B + uniform64(row0 * p.ldb + cbase)) + voB[u];
+#pragma unroll
+                for (int vr = 0; vr < VEC; ++vr) {
+                    const vec_t w = *reinterpret_cast<const vec_t *>(
+                        __builtin_assume_aligned(base + (size_t)vr * p.ldb * sizeof(T), 16));
+                    const T *ws = reinterpret_cast<const T *>(&w);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) v[u][vr][e] = ws[e];
+                }
+            } else {
+#pragma unroll
+                for (int vr = 0; vr < VEC; ++vr) {
+                    const int kr = kB[u] + vr;
+                    const bool rok = (k0 + kr < p.kb) && (row0 + kr < p.k);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const int cc = cB[u] + e;
+                        const bool ok = rok && (tn * BN + cc < p.nb) && (cbase + cc < p.n);
+                        const T y = *(ok ? p.B + (row0 + kr) * p.ldb + cbase + cc : p.B);
+                        v[u][vr][e] = ok ? y : T(0);
+                    }
+                }
+            }
+        }
+    };
+    // FP64 keeps the source-list form of the load stage (table entries read per stage): with the
+    // tile origins kept across the loop, as in the FP32 form, its register budget (224 AGPR
+    // accumulators) spills (measured 10-19 % slower); for FP32 the origins in scalar registers and
+    // no per-stage table reads took the kernel from 0.61 to 0.72 of the FP32 peak.
+    // Stages with k0 + BK <= kfast read whole tiles with vector loads and no bounds checks:
+    // every source tile of this work-group lies inside its sub-block and inside the operand.
+    int64_t kfast_l = (p.vec_a && p.vec_b && p.small_ld && tm * BM + BM <= p.mb && tn * BN + BN <= p.nb) ? p.kb : 0;
+    for (int q = 0; q < le.a_count && kfast_l > 0; ++q) {
+        const SrcEntry se = p.asrc[le.a_begin + q];
+        for (int s = 0; s < 4; ++s) {
+            if ((int64_t)se.br * mb2 + (s & 1) * p.mb + tm * BM + BM > p.m) kfast_l = 0;
+            kfast_l = min(kfast_l, p.k - ((int64_t)se.bc * kb2 + (s >> 1) * p.kb));
+        }
+    }
+    for (int q = 0; q < le.b_count && kfast_l > 0; ++q) {
+        const SrcEntry se = p.bsrc[le.b_begin + q];
+        for (int s = 0; s < 4; ++s) {
+            if ((int64_t)se.bc * nb2 + (s >> 1) * p.nb + tn * BN + BN > p.n) kfast_l = 0;
+            kfast_l = min(kfast_l, p.k - ((int64_t)se.br * kb2 + (s & 1) * p.kb));
+        }
+    }
+    kfast_l = __builtin_amdgcn_readfirstlane(kfast_l);
+    // byte offsets of the thread's vectors inside a tile (the same for every source, sub-block
+    // and K stage)
+
     // The thread's part of the A tiles of the four node sub-blocks at K offset k0: the sum over
     // the node's sources of coef * A, zero outside A and the sub-block.
-    auto load_a = [&](int64_t k0, T (&v)[4][NPA][VEC]) {
-        const bool fast = k0 + BK <= kfast;
+    auto load_a_list = [&](int64_t k0, T (&v)[4][NPA][VEC]) {
+        const bool fast = k0 + BK <= kfast_l;
         for (int q = 0; q < le.a_count; ++q) {
             const SrcEntry se = p.asrc[le.a_begin + q];
             const T c = (T)se.coef;
@@ -237,8 +328,8 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
     };
     // The thread's B blocks at K offset k0: the sum over the node's sources of coef * B, zero
     // outside B and the sub-block.
-    auto load_b = [&](int64_t k0, T (&v)[NBT][VEC][VEC]) {
-        const bool fast = k0 + BK <= kfast;
+    auto load_b_list = [&](int64_t k0, T (&v)[NBT][VEC][VEC]) {
+        const bool fast = k0 + BK <= kfast_l;
         for (int q = 0; q < le.b_count; ++q) {
             const SrcEntry se = p.bsrc[le.b_begin + q];
             const T c = (T)se.coef;
@@ -279,6 +370,14 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
                         v[u][vr][e] = (q == 0) ? c * x[vr][e] : v[u][vr][e] + c * x[vr][e];
             }
         }
+    };
+    auto load_a = [&](int64_t k0, T (&v)[4][NPA][VEC]) {
+        if constexpr (SWZ) load_a_one(k0, v);
+        else load_a_list(k0, v);
+    };
+    auto load_b = [&](int64_t k0, T (&v)[NBT][VEC][VEC]) {
+        if constexpr (SWZ) load_b_one(k0, v);
+        else load_b_list(k0, v);
     };
     auto store = [&](int st, const T (&va)[4][NPA][VEC], const T (&vb)[NBT][VEC][VEC]) {
 #pragma unroll
