@@ -1642,6 +1642,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         X.leaves = tab->wleaves, X.asrc = tab->wsrc, X.bsrc = tab->wsrc;
         X.sc = ScaleExps{nullptr, nullptr, nullptr};
         X.out = ws + w.leaves, X.ldo = s.nb, X.leaf_stride = s.mb * s.nb, X.direct = 0;
+        X.one = 1;
         e = launch_leaf(X, st);
         fin.mark();
         if (e != hipSuccess) return hip_fail(e, "leaf kernel");
@@ -1707,6 +1708,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     auto leaf_launch = [&]() { return launch_leaf(L, st); };
     if (s.L == 0) {
         L.out = C, L.ldo = ldc, L.leaf_stride = 0, L.direct = 1;
+        L.one = 1;  // a single leaf: the operands themselves
         e = leaf_launch();
         fin.mark();
         if (e != hipSuccess) return hip_fail(e, "leaf kernel");

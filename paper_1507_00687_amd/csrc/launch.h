@@ -36,6 +36,7 @@ struct LeafLaunch {
     int direct;
     int scale_in = 1;  // with sc and a direct output: 0 takes the operands as already scaled
                        // (only the output takes 2^(ea_i + eb_j)); row-major operands only
+    int one = 0;       // every leaf has one A and one B source, coefficient 1 (row-major operands)
 };
 
 // W-combination: C_block(P,S) = sum over its DestEntry list of coef * M_leaf, then

@@ -93,7 +93,11 @@ struct Tile {
 // One 128x128 output tile (tile row tm, tile column tn) of leaf `leaf` of the problem p.
 // SCALED: the loads apply the scaling factors to the operands; SCALED_OUT: a direct output takes
 // 2^(ea_i + eb_j) (with SCALED both, without SCALED only the output: operands already scaled).
-template <typename T, bool SCALED, bool DIRECT, bool SCALED_OUT = SCALED>
+// ONE: every leaf has one A and one B source with coefficient 1 (a single classical leaf, or the
+// written leaf operands): the source blocks are read from the tables once, and each stage's
+// loads go straight to the registers that are stored to LDS (no per-stage table reads, no
+// coefficient products).
+template <typename T, bool SCALED, bool DIRECT, bool SCALED_OUT = SCALED, bool ONE = false>
 __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t tm, int64_t tn,
                                           typename Tile<T>::Smem &sm) {
     typedef Core<T> C;
@@ -274,8 +278,20 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
                 for (int e = 0; e < VEC; ++e) sb[i][e] = (q == 0) ? c * xb0[i][e] : sb[i][e] + c * xb0[i][e];
         }
     };
-    // Issue the raw loads of sources 0 and 1 (those exist) of the stage at k0.
+    SrcEntry one_a{}, one_b{};  // ONE: the leaf's sources, read once (uniform)
+    if constexpr (ONE) {
+        one_a = p.asrc[le.a_begin], one_b = p.bsrc[le.b_begin];
+        one_a.br = __builtin_amdgcn_readfirstlane(one_a.br), one_a.bc = __builtin_amdgcn_readfirstlane(one_a.bc);
+        one_b.br = __builtin_amdgcn_readfirstlane(one_b.br), one_b.bc = __builtin_amdgcn_readfirstlane(one_b.bc);
+    }
+    // Issue the raw loads of sources 0 and 1 (those exist) of the stage at k0 (ONE: straight
+    // into the registers stored next).
     auto prefetch = [&](int64_t k0) {
+        if constexpr (ONE) {
+            load_a(one_a, k0, sa);
+            load_b(one_b, k0, sb);
+            return;
+        }
         load_a(p.asrc[le.a_begin], k0, xa0);
         if (le.a_count > 1) load_a(p.asrc[le.a_begin + 1], k0, xa1);
         load_b(p.bsrc[le.b_begin], k0, xb0);
@@ -283,6 +299,7 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
     };
     // Combine the prefetched sources (in source order) and gather the remaining ones.
     auto finish = [&](int64_t k0) {
+        if constexpr (ONE) return;
         const T ca0 = (T)p.asrc[le.a_begin].coef, cb0 = (T)p.bsrc[le.b_begin].coef;
 #pragma unroll
         for (int i = 0; i < NPA; ++i)
@@ -356,7 +373,8 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
         for (int j = 0; j < TN; ++j) acc[i][j] = typename C::acc_t{};
 
     const int64_t nk = (p.kb + BK - 1) / BK;
-    gather_rest(0, 0);
+    if constexpr (ONE) prefetch(0);
+    else gather_rest(0, 0);
     store(0);
     __syncthreads();
     for (int64_t kt = 0; kt < nk; ++kt) {
@@ -442,7 +460,7 @@ __device__ __forceinline__ void tile_coords(int rem, int tiles_m, int tiles_n, i
     tn = __builtin_amdgcn_readfirstlane(gidx / gsz);
 }
 
-template <typename T, bool SCALED, bool DIRECT, bool SCALED_OUT = SCALED>
+template <typename T, bool SCALED, bool DIRECT, bool SCALED_OUT = SCALED, bool ONE = false>
 __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T> p) {
     __shared__ typename Tile<T>::Smem sm;
     const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
@@ -451,7 +469,7 @@ __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T>
     const int rem = __builtin_amdgcn_readfirstlane((int)(bid - (int64_t)leaf * tiles));
     int64_t tm, tn;
     tile_coords(rem, p.tiles_m, p.tiles_n, tm, tn);
-    leaf_tile<T, SCALED, DIRECT, SCALED_OUT>(p, leaf, tm, tn, sm);
+    leaf_tile<T, SCALED, DIRECT, SCALED_OUT, ONE>(p, leaf, tm, tn, sm);
 }
 
 // Batched launch over several problems of one output mode (each with its own plan tables):
@@ -513,13 +531,18 @@ hipError_t go(const LeafLaunch &L, hipStream_t s) {
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const bool scaled = L.sc.ea != nullptr;
     dim3 grid((unsigned)blocks), block(kNT);
-    if (L.direct) {
+    // The single-source form only without scaled loads (with them the FP32 variant spills).
+    if (L.direct && L.one && !(scaled && L.scale_in)) {
+        if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, true, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, true, false, true>), grid, block, 0, s, a);
+    } else if (L.direct) {
         if (scaled && !L.scale_in)
             hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, true, true>), grid, block, 0, s, a);
         else if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, true>), grid, block, 0, s, a);
     } else {
         if (scaled) hipLaunchKernelGGL((fmm_leaf_pipelined<T, true, false>), grid, block, 0, s, a);
+        else if (L.one) hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, false, false, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((fmm_leaf_pipelined<T, false, false>), grid, block, 0, s, a);
     }
     return hipGetLastError();
