@@ -77,13 +77,24 @@ __device__ inline int64_t xcd_remap_tile(int64_t b, int64_t G) {
     return ((x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + j;
 }
 
-template <typename T>
+// Both tiles are k-contiguous (B stored transposed).  SWZ (FP32 without scaled loads): rows of
+// 32 floats (128 bytes, eight 16-byte chunks), chunk c of row r kept at chunk c ^ (r mod 8);
+// measured with SQ_LDS_BANK_CONFLICT on MI355X, the fragment reads (16 consecutive rows, one
+// chunk per 16 lanes), the row-major A writes and the transposed B writes are all free of bank
+// conflicts.  Otherwise rows padded by 16 bytes (one extra cycle per FP32 fragment read, but one
+// lane offset fewer: the FP32 variants with scaled loads are short of registers).  idx(r, k):
+// element (row r, k) for k a multiple of VEC; for r16 a multiple of 16,
+// idx(r16 + r, k) = r16 LDS_K + idx(r, k).
+template <typename T, bool SCALED>
 struct Tile {
     typedef Core<T> C;
     static constexpr int BM = 128, BN = 128, BK = C::BK, VEC = C::VEC;
-    // Both tiles are k-contiguous (B stored transposed), rows padded by 16 bytes: 16-byte
-    // reads of consecutive rows fall on distinct banks.
-    static constexpr int LDS_K = BK + 16 / (int)sizeof(T);
+    static constexpr bool SWZ = sizeof(T) == 4 && !SCALED;
+    static constexpr int LDS_K = SWZ ? BK : BK + 16 / (int)sizeof(T);
+    __device__ static __forceinline__ int idx(int r, int k) {
+        if constexpr (SWZ) return r * LDS_K + (((k / VEC) ^ (r & 7)) * VEC);
+        else return r * LDS_K + k;
+    }
     struct Smem {
         __attribute__((aligned(16))) T As[2][BM * LDS_K];
         __attribute__((aligned(16))) T Bs[2][BN * LDS_K];
@@ -99,14 +110,15 @@ struct Tile {
 // coefficient products).
 template <typename T, bool SCALED, bool DIRECT, bool SCALED_OUT = SCALED, bool ONE = false>
 __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t tm, int64_t tn,
-                                          typename Tile<T>::Smem &sm) {
+                                          typename Tile<T, SCALED>::Smem &sm) {
     typedef Core<T> C;
     constexpr int BM = 128, BN = 128, BK = C::BK, VEC = C::VEC;
     constexpr int TPRA = BK / VEC, RPPA = kNT / TPRA, NPA = BM / RPPA;  // A: threads/row, rows/pass
     // B is loaded in VEC x VEC blocks (VEC k-rows by VEC columns, consecutive lanes on
     // consecutive k-blocks) and written transposed, one 16-byte LDS write per column.
     constexpr int KBV = BK / VEC, NBT = KBV * (BN / VEC) / kNT, NPB = NBT * VEC;  // B: blocks, rows
-    constexpr int LDS_K = Tile<T>::LDS_K;
+    typedef Tile<T, SCALED> TL;
+    constexpr int LDS_K = TL::LDS_K;
     constexpr int WM = 64, WN = 64, TM = WM / 16, TN = WN / 16;
     static_assert(NPA * RPPA == BM && NBT * kNT == KBV * (BN / VEC) && BK % 16 == 0, "tile shape");
     auto &As = sm.As;
@@ -345,6 +357,13 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
             }
         }
     };
+    static_assert(RPPA % 16 == 0, "pass rows");
+    const int sto_a = TL::idx(ra, ka);
+    int sto_b[NBT][VEC];
+#pragma unroll
+    for (int u = 0; u < NBT; ++u)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) sto_b[u][e] = TL::idx(cB[u] + e, kB[u]);
     auto store = [&](int s) {
 #pragma unroll
         for (int pa = 0; pa < NPA; ++pa) {
@@ -352,7 +371,7 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
             T *xs = reinterpret_cast<T *>(&x);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) xs[e] = sa[pa][e];
-            *reinterpret_cast<typename C::vec_t *>(&As[s][(pa * RPPA + ra) * LDS_K + ka]) = x;
+            *reinterpret_cast<typename C::vec_t *>(&As[s][pa * RPPA * LDS_K + sto_a]) = x;
         }
 #pragma unroll
         for (int u = 0; u < NBT; ++u)
@@ -362,7 +381,7 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
                 T *xs = reinterpret_cast<T *>(&x);
 #pragma unroll
                 for (int vr = 0; vr < VEC; ++vr) xs[vr] = sb[u * VEC + vr][e];
-                *reinterpret_cast<typename C::vec_t *>(&Bs[s][(cB[u] + e) * LDS_K + kB[u]]) = x;
+                *reinterpret_cast<typename C::vec_t *>(&Bs[s][sto_b[u][e]]) = x;
             }
     };
 
@@ -395,7 +414,7 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
 #pragma unroll
                 for (int c = 0; c < 4; c += VEC) {
                     const typename C::vec_t x = *reinterpret_cast<const typename C::vec_t *>(
-                        &as[(wm * WM + i * 16 + l16) * LDS_K + 16 * h + g4 + c]);
+                        &as[(wm * WM + i * 16) * LDS_K + TL::idx(l16, 16 * h + g4 + c)]);
                     const T *xs = reinterpret_cast<const T *>(&x);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) ea[i][c + e] = xs[e];
@@ -405,7 +424,7 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
 #pragma unroll
                 for (int c = 0; c < 4; c += VEC) {
                     const typename C::vec_t x = *reinterpret_cast<const typename C::vec_t *>(
-                        &bs[(wn * WN + j * 16 + l16) * LDS_K + 16 * h + g4 + c]);
+                        &bs[(wn * WN + j * 16) * LDS_K + TL::idx(l16, 16 * h + g4 + c)]);
                     const T *xs = reinterpret_cast<const T *>(&x);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) eb[j][c + e] = xs[e];
@@ -462,7 +481,7 @@ __device__ __forceinline__ void tile_coords(int rem, int tiles_m, int tiles_n, i
 
 template <typename T, bool SCALED, bool DIRECT, bool SCALED_OUT = SCALED, bool ONE = false>
 __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T> p) {
-    __shared__ typename Tile<T>::Smem sm;
+    __shared__ typename Tile<T, SCALED>::Smem sm;
     const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
     const int bid = __builtin_amdgcn_readfirstlane((int)xcd_remap_tile(blockIdx.x, gridDim.x));
     const int leaf = __builtin_amdgcn_readfirstlane((int)(bid / tiles));
@@ -481,7 +500,7 @@ template <typename T, bool SCALED, bool DIRECT>
 __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_batched(const PArgs<T> *__restrict__ probs,
                                                                      const int64_t *__restrict__ first, int count,
                                                                      int64_t total) {
-    __shared__ typename Tile<T>::Smem sm;
+    __shared__ typename Tile<T, SCALED>::Smem sm;
     const int64_t w = blockIdx.x;
     int lo = 0, hi = count - 1;
     while (lo < hi) {  // last q with first[q] <= w

@@ -132,20 +132,36 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
     // both the global reads (whole row segments) and the LDS writes free of conflicts.
     constexpr int KBV = BK / VEC, CBV = BN / VEC, NBT = 4 * KBV * CBV / kNT;  // B: blocks per thread
     // LDS tiles are k-contiguous for both operands (B stored transposed).  FP32: rows of 16
-    // floats (64 bytes, four 16-byte chunks), chunk c of row r stored at chunk c ^ ((r / 2) mod 4),
-    // the layout under which the limb GEMM's 16-row fragment reads and row-major staging writes
-    // measure no bank conflicts; FP64: rows padded to a 16-byte multiple that spreads consecutive
-    // rows over the banks.  lidx(r, k): element (row r, k) for k a multiple of VEC.
+    // floats (64 bytes, four 16-byte chunks); row r is kept at row q = r ^ ((r / 4) mod 4) (a
+    // permutation inside each aligned group of four rows) with its chunk c at chunk
+    // c ^ ((q / 2) mod 4).  Measured with SQ_LDS_BANK_CONFLICT on MI355X, this layout is free of
+    // bank conflicts for the three access patterns here: the 16-row fragment reads (one chunk per
+    // 16 lanes), the row-major A writes (four lanes per row) and the transposed B writes (rows
+    // c, c + 4, c + 8, ... of one column offset); without the row permutation the B writes take
+    // two extra cycles each, and with padded rows the reads take one.  FP64: rows padded to a
+    // 16-byte multiple that spreads consecutive rows over the banks.  lidx(r, k): element (row r,
+    // k) for k a multiple of VEC.
     constexpr bool SWZ = sizeof(T) == 4;
     constexpr int LDS_K = SWZ ? BK : BK + 16 / (int)sizeof(T);
     auto lidx = [](int r, int k) {
-        return SWZ ? r * LDS_K + (((k / VEC) ^ ((r >> 1) & 3)) * VEC) : r * LDS_K + k;
+        if constexpr (SWZ) {
+            const int q = r ^ ((r >> 2) & 3);
+            return q * LDS_K + (((k / VEC) ^ ((q >> 1) & 3)) * VEC);
+        } else {
+            return r * LDS_K + k;
+        }
     };
-    static_assert(NPA * RPPA == BM && NBT * kNT == 4 * KBV * CBV, "tile shape");
+    // lidx(r16 + r, k) = lbase(r16) + lidx(r, k) for r16 a multiple of 16: the lane parts are
+    // computed once, the rest is a constant offset.
+    auto lbase = [](int r16) { return r16 * LDS_K; };
     static_assert((LDS_K * sizeof(T)) % 16 == 0 && KPL % VEC == 0, "row alignment");
 
-    __shared__ __attribute__((aligned(16))) T As[2][4][BM * LDS_K];
-    __shared__ __attribute__((aligned(16))) T Bs[2][4][BN * LDS_K];
+    // one stage's A and B tiles side by side
+    struct Stage {
+        __attribute__((aligned(16))) T a[4][BM * LDS_K];
+        __attribute__((aligned(16))) T b[4][BN * LDS_K];
+    };
+    __shared__ Stage stg[2];
 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -379,6 +395,13 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
         if constexpr (SWZ) load_b_one(k0, v);
         else load_b_list(k0, v);
     };
+    static_assert(RPPA % 16 == 0, "pass rows");
+    const int sto_a = lidx(ra, ka);
+    int sto_b[NBT][VEC];
+#pragma unroll
+    for (int u = 0; u < NBT; ++u)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) sto_b[u][e] = lidx(cB[u] + e, kB[u]);
     auto store = [&](int st, const T (&va)[4][NPA][VEC], const T (&vb)[NBT][VEC][VEC]) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -388,7 +411,7 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
                 T *xs = reinterpret_cast<T *>(&x);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) xs[e] = va[s][pa][e];
-                *reinterpret_cast<vec_t *>(&As[st][s][lidx(pa * RPPA + ra, ka)]) = x;
+                *reinterpret_cast<vec_t *>(&stg[st].a[s][lbase(pa * RPPA) + sto_a]) = x;
             }
         }
 #pragma unroll
@@ -399,7 +422,7 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
                 T *xs = reinterpret_cast<T *>(&x);
 #pragma unroll
                 for (int vr = 0; vr < VEC; ++vr) xs[vr] = vb[u][vr][e];
-                *reinterpret_cast<vec_t *>(&Bs[st][sB[u]][lidx(cB[u] + e, kB[u])]) = x;
+                *reinterpret_cast<vec_t *>(&stg[st].b[sB[u]][sto_b[u][e]]) = x;
             }
     };
 
@@ -429,13 +452,14 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
         }
 #pragma unroll
         for (int jh = 0; jh < KPL / VEC; ++jh) {
+            const int rdo = lidx(l16, g4 + jh * VEC);
             T ea[TM][4][VEC], eb[TN][4][VEC];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
 #pragma unroll
                 for (int i = 0; i < TM; ++i) {
                     const vec_t w = *reinterpret_cast<const vec_t *>(
-                        &As[cur][s][lidx(wm * 16 * TM + i * 16 + l16, g4 + jh * VEC)]);
+                        &stg[cur].a[s][lbase(wm * 16 * TM + i * 16) + rdo]);
                     const T *ws = reinterpret_cast<const T *>(&w);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) ea[i][s][e] = ws[e];
@@ -443,7 +467,7 @@ __global__ __launch_bounds__(kNT, NCore<T>::OCC) void fmm_node222(NArgs<T> p) {
 #pragma unroll
                 for (int j = 0; j < TN; ++j) {
                     const vec_t w = *reinterpret_cast<const vec_t *>(
-                        &Bs[cur][s][lidx(wn * 16 * TN + j * 16 + l16, g4 + jh * VEC)]);
+                        &stg[cur].b[s][lbase(wn * 16 * TN + j * 16) + rdo]);
                     const T *ws = reinterpret_cast<const T *>(&w);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) eb[j][s][e] = ws[e];
