@@ -147,11 +147,11 @@ __global__ __launch_bounds__(256) void form_planes(PlaneForm a) {
 constexpr int kAllMaxCoef = 4096;  // leaves x blocks entries of the coefficient table (dynamic LDS)
 
 // The limb planes of every leaf with every source element read from HBM once: a work-group
-// takes one TR x 64 tile position inside the leaf blocks; each thread owns one 8-element k chunk
-// there (eight consecutive k of one plane row, i.e. 16 bytes of every limb plane), holds that
-// chunk of every block of op(X) (the nbo x nbk leaf-block grid, NB >= blocks) in registers, and
-// for each leaf sums the leaf's blocks with its coefficients (a dense leaves x blocks table in
-// LDS, zero where a block is not one of its sources), splits and writes its 16-byte limb chunks
+// takes one TR x 8 KW tile position inside the leaf blocks; each thread owns one KW-element k
+// chunk there (KW consecutive k of one plane row, i.e. 2 KW bytes of every limb plane), holds
+// that chunk of every block of op(X) (the nbo x nbk leaf-block grid, NB >= blocks) in registers,
+// and for each leaf sums the leaf's blocks with its coefficients (a dense leaves x blocks table in
+// LDS, zero where a block is not one of its sources), splits and writes its limb chunks
 // directly, with no LDS round trip and no barrier per leaf.  Blocks are summed in the order of
 // the rule's single block index at depth 1 (column-major for A, row-major over (n-block,
 // k-block) for B), which is the order of the source lists there.  Thread layout: k-contiguous
@@ -161,7 +161,7 @@ constexpr int kAllMaxCoef = 4096;  // leaves x blocks entries of the coefficient
 // (one loading while another writes); a 512-thread version with one 64 x 64 tile per
 // work-group, and the earlier LDS-transposing version with a barrier per leaf, both ran 5 %
 // slower.
-template <bool HALF, int NL, bool SCALED, bool KCONTIG, int NB, int TR>
+template <bool HALF, int NL, bool SCALED, bool KCONTIG, int NB, int TR, int KW>
 __global__ __launch_bounds__(TR * 8) void form_regs(PlaneForm a, int nleaves) {
     constexpr int NT = TR * 8;
     extern __shared__ float rcoef[];  // nleaves x nblk
@@ -179,7 +179,8 @@ __global__ __launch_bounds__(TR * 8) void form_regs(PlaneForm a, int nleaves) {
         }
     }
     static_assert(TR % 16 == 0 && TR <= 64 && (KCONTIG || TR % 32 == 0), "tile rows");
-    int ol, kc;  // the thread's row and 8-wide k chunk in the TR x 64 tile
+    static_assert(KW == 8 || KW == 4, "chunk width");
+    int ol, kc;  // the thread's row and KW-wide k chunk in the TR x 8 KW tile
     if (KCONTIG) {
         ol = t >> 3, kc = t & 7;
     } else {
@@ -190,22 +191,24 @@ __global__ __launch_bounds__(TR * 8) void form_regs(PlaneForm a, int nleaves) {
     }
     // work-group (row tile x, k tile y): consecutive work-groups take consecutive TR-row slices
     // of the same 32-k plane pieces, so the work-groups in flight write whole pieces together
-    const int64_t ob = (int64_t)blockIdx.x * TR + ol, kb0 = (int64_t)blockIdx.y * 64 + 8 * kc;  // in the leaf block
+    const int64_t ob = (int64_t)blockIdx.x * TR + ol, kb0 = (int64_t)blockIdx.y * (8 * KW) + KW * kc;  // in the leaf block
     const bool vec = KCONTIG && (a.ld_o & 3) == 0 && ((uintptr_t)a.X & 15) == 0;
-    float x[NB][8];
+    float x[NB][KW];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int bo = a.b_side ? b / nbk : b % nbo, bk = a.b_side ? b % nbk : b / nbo;
         const int64_t o = (int64_t)bo * a.rb + ob, kk0 = (int64_t)bk * a.kb + kb0;  // in op(X)
         const bool row_ok = b < nblk && ob < a.rb && o < a.R;
-        if (vec && row_ok && kb0 + 8 <= a.kb && kk0 + 8 <= a.K) {
+        if (vec && row_ok && kb0 + KW <= a.kb && kk0 + KW <= a.K) {
             const float4 *p = reinterpret_cast<const float4 *>(a.X + o * a.ld_o + kk0);
-            const float4 u = p[0], w = p[1];
-            x[b][0] = u.x, x[b][1] = u.y, x[b][2] = u.z, x[b][3] = u.w;
-            x[b][4] = w.x, x[b][5] = w.y, x[b][6] = w.z, x[b][7] = w.w;
+#pragma unroll
+            for (int h = 0; h < KW / 4; ++h) {
+                const float4 u = p[h];
+                x[b][4 * h] = u.x, x[b][4 * h + 1] = u.y, x[b][4 * h + 2] = u.z, x[b][4 * h + 3] = u.w;
+            }
         } else {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < KW; ++j) {
                 const bool ok = row_ok && kb0 + j < a.kb && kk0 + j < a.K;
                 const float y = *(ok ? a.X + o * a.ld_o + (kk0 + j) * a.ld_k : a.X);
                 x[b][j] = ok ? y : 0.f;
@@ -214,7 +217,7 @@ __global__ __launch_bounds__(TR * 8) void form_regs(PlaneForm a, int nleaves) {
         if (SCALED && row_ok) {  // once per element, not once per leaf that uses it (exact: powers of two)
             const int eo = a.s_o * a.e_o[o] + a.pre_exp;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < KW; ++j) {
                 const int64_t kk = kk0 + j;
                 const int ek = (kb0 + j < a.kb && kk < a.K) ? a.s_k * a.e_k[kk] : 0;
                 x[b][j] = ldexpf(x[b][j], eo + ek);
@@ -226,40 +229,38 @@ __global__ __launch_bounds__(TR * 8) void form_regs(PlaneForm a, int nleaves) {
     unsigned short *dst0 =
         a.planes + ((o / a.bt) * (a.kp / 32) + kk / 32) * (a.bt * 32) + (o % a.bt) * 32 + kk % 32;
     for (int leaf = 0; leaf < nleaves; ++leaf) {
-        float v[8];
+        float v[KW];
         bool first = true;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const float c = b < nblk ? rcoef[leaf * nblk + b] : 0.f;
             if (c != 0.f) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = first ? c * x[b][j] : v[j] + c * x[b][j];
+                for (int j = 0; j < KW; ++j) v[j] = first ? c * x[b][j] : v[j] + c * x[b][j];
                 first = false;
             }
         }
         if (first) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = 0.f;
+            for (int j = 0; j < KW; ++j) v[j] = 0.f;
         }
-        unsigned short h[NL][8];
+        uint32_t h[NL][KW / 2];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < KW; ++j) {
             float r = v[j];
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
                 float back;
-                h[l][j] = LimbT<HALF>::split(r, back);
+                const uint32_t bits = LimbT<HALF>::split(r, back);
                 r = r - back;
+                h[l][j / 2] = (j & 1) ? (h[l][j / 2] | (bits << 16)) : bits;
             }
         }
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
-            uint4 w;
-            w.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
-            w.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
-            w.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
-            w.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
-            *reinterpret_cast<uint4 *>(dst0 + (int64_t)leaf * a.leaf_stride + l * a.plane_stride) = w;
+            unsigned short *dst = dst0 + (int64_t)leaf * a.leaf_stride + l * a.plane_stride;
+            if constexpr (KW == 8) *reinterpret_cast<uint4 *>(dst) = uint4{h[l][0], h[l][1], h[l][2], h[l][3]};
+            else *reinterpret_cast<uint2 *>(dst) = uint2{h[l][0], h[l][1]};
         }
     }
 }
@@ -893,16 +894,18 @@ template <bool HALF, int NL, int NB>
 hipError_t form_regs_go(const PlaneForm &f, int nleaves, hipStream_t s) {
     // small work-groups (two waves when k is contiguous, four otherwise): several per CU, out
     // of phase (one loading while another writes)
-    constexpr int TRK = 16, TRO = 32;
-    if (f.kp / kFT > 65535) return hipErrorInvalidValue;
+    // four-element k chunks: a wave's limb writes cover eight whole 64-byte plane rows of one
+    // 32-k piece (eight-element chunks, 7 % slower, split them over two pieces)
+    constexpr int TRK = 16, TRO = 32, KW = 4;
+    if (f.kp / (8 * KW) > 65535) return hipErrorInvalidValue;
     const bool scaled = f.e_o != nullptr, kc = f.ld_k == 1;
     const int tr = kc ? TRK : TRO;
-    const dim3 grid((unsigned)(f.rowsp / tr), (unsigned)(f.kp / kFT)), block(tr * 8);
+    const dim3 grid((unsigned)(f.rowsp / tr), (unsigned)(f.kp / (8 * KW))), block(tr * 8);
     const size_t lds = (size_t)nleaves * f.nbo * f.nbk * sizeof(float);
-    if (scaled && kc) hipLaunchKernelGGL((form_regs<HALF, NL, true, true, NB, TRK>), grid, block, lds, s, f, nleaves);
-    else if (scaled) hipLaunchKernelGGL((form_regs<HALF, NL, true, false, NB, TRO>), grid, block, lds, s, f, nleaves);
-    else if (kc) hipLaunchKernelGGL((form_regs<HALF, NL, false, true, NB, TRK>), grid, block, lds, s, f, nleaves);
-    else hipLaunchKernelGGL((form_regs<HALF, NL, false, false, NB, TRO>), grid, block, lds, s, f, nleaves);
+    if (scaled && kc) hipLaunchKernelGGL((form_regs<HALF, NL, true, true, NB, TRK, KW>), grid, block, lds, s, f, nleaves);
+    else if (scaled) hipLaunchKernelGGL((form_regs<HALF, NL, true, false, NB, TRO, KW>), grid, block, lds, s, f, nleaves);
+    else if (kc) hipLaunchKernelGGL((form_regs<HALF, NL, false, true, NB, TRK, KW>), grid, block, lds, s, f, nleaves);
+    else hipLaunchKernelGGL((form_regs<HALF, NL, false, false, NB, TRO, KW>), grid, block, lds, s, f, nleaves);
     return hipGetLastError();
 }
 
