@@ -2018,7 +2018,9 @@ fastmm_status fastmm_gemm_batched_ex(const fastmm_plan_t *plans, const fastmm_pr
             c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
             set_kron(p, sh.L, tab->nleaves, c);
         }
-        it.mode = 2 * (exps.ea != nullptr ? 1 : 0) + (L.direct ? 1 : 0);
+        // mode bits: one source per leaf (a classical product, unscaled), scaled loads, output to C
+        const bool one = sh.L == 0 && exps.ea == nullptr;
+        it.mode = 4 * (one ? 1 : 0) + 2 * (exps.ea != nullptr ? 1 : 0) + (L.direct ? 1 : 0);
         it.desc.resize(leaf_desc_bytes(el));
         it.tiles = leaf_desc_build(L, it.desc.data());
         items.push_back(std::move(it));
@@ -2077,7 +2079,7 @@ fastmm_status fastmm_gemm_batched_ex(const fastmm_plan_t *plans, const fastmm_pr
         if (split) {
             if ((e = launch_limb_gemm_batched(plans[0]->prec, bl.bm, gd, gf, gc, g.total, s)) != hipSuccess)
                 return hip_fail(e, "batched limb GEMM kernel");
-        } else if ((e = launch_leaf_batched(el, g.mode >> 1, g.mode & 1, gd, gf, gc, g.total, s)) != hipSuccess) {
+        } else if ((e = launch_leaf_batched(el, (g.mode >> 1) & 1, g.mode & 1, g.mode >> 2, gd, gf, gc, g.total, s)) != hipSuccess) {
             return hip_fail(e, "batched leaf kernel");
         }
     }

@@ -249,13 +249,13 @@ hipError_t launch_leaf_pipelined(const LeafLaunch &L, hipStream_t s);
 // Batched version (row-major operands, FP64/FP32): leaf_desc_build writes the device
 // descriptor of one problem's launch to `dst` (leaf_desc_bytes(e) bytes, host memory) and
 // returns its number of work items; launch_leaf_batched runs `total` items of `count` problems
-// that share one mode (scaled operands or not, output to C or to the leaf workspace), with the
-// descriptors and the item prefix offsets first[count + 1] in device memory, one work-group
-// per item.
+// that share one mode (scaled operands or not, output to C or to the leaf workspace, one: every
+// leaf with one source of coefficient 1, unscaled), with the descriptors and the item prefix
+// offsets first[count + 1] in device memory, one work-group per item.
 size_t leaf_desc_bytes(Elem e);
 int64_t leaf_desc_build(const LeafLaunch &L, void *dst);
-hipError_t launch_leaf_batched(Elem e, int scaled, int direct, const void *descs, const int64_t *first, int count,
-                               int64_t total, hipStream_t s);
+hipError_t launch_leaf_batched(Elem e, int scaled, int direct, int one, const void *descs, const int64_t *first,
+                               int count, int64_t total, hipStream_t s);
 // out (C x R) = in^T for a row-major R x C matrix (FP32 or FP64).
 hipError_t launch_transpose(Elem e, const void *in, int64_t ldi, int64_t R, int64_t C, void *out, int64_t ldo,
                             hipStream_t s);

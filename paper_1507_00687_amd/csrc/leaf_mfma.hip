@@ -496,7 +496,7 @@ __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_pipelined(PArgs<T>
 // (problems ordered by the host, largest K first, so the longest items are dispatched first).
 // The host launches one such kernel per (scaling, output) mode present in the batch, so each
 // is the single-problem tile code with its register count and occupancy.
-template <typename T, bool SCALED, bool DIRECT>
+template <typename T, bool SCALED, bool DIRECT, bool ONE = false>
 __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_batched(const PArgs<T> *__restrict__ probs,
                                                                      const int64_t *__restrict__ first, int count,
                                                                      int64_t total) {
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(kNT, Core<T>::OCC) void fmm_leaf_batched(const PArg
     const int rem = __builtin_amdgcn_readfirstlane((int)(local - (int64_t)leaf * tiles));
     int64_t tm, tn;
     tile_coords(rem, p.tiles_m, p.tiles_n, tm, tn);
-    leaf_tile<T, SCALED, DIRECT>(p, leaf, tm, tn, sm);
+    leaf_tile<T, SCALED, DIRECT, SCALED, ONE>(p, leaf, tm, tn, sm);
 }
 
 
@@ -584,11 +584,14 @@ int64_t leaf_desc_build(const LeafLaunch &L, void *dst) {
 }
 
 template <typename T>
-hipError_t batched_go(int scaled, int direct, const void *descs, const int64_t *first, int count, int64_t total,
-                      hipStream_t s) {
+hipError_t batched_go(int scaled, int direct, int one, const void *descs, const int64_t *first, int count,
+                      int64_t total, hipStream_t s) {
     const PArgs<T> *d = (const PArgs<T> *)descs;
     const dim3 grid((unsigned)total), block(kNT);
-    if (scaled) {
+    if (one && !scaled) {
+        if (direct) hipLaunchKernelGGL((fmm_leaf_batched<T, false, true, true>), grid, block, 0, s, d, first, count, total);
+        else hipLaunchKernelGGL((fmm_leaf_batched<T, false, false, true>), grid, block, 0, s, d, first, count, total);
+    } else if (scaled) {
         if (direct) hipLaunchKernelGGL((fmm_leaf_batched<T, true, true>), grid, block, 0, s, d, first, count, total);
         else hipLaunchKernelGGL((fmm_leaf_batched<T, true, false>), grid, block, 0, s, d, first, count, total);
     } else {
@@ -598,12 +601,12 @@ hipError_t batched_go(int scaled, int direct, const void *descs, const int64_t *
     return hipGetLastError();
 }
 
-hipError_t launch_leaf_batched(Elem e, int scaled, int direct, const void *descs, const int64_t *first, int count,
-                               int64_t total, hipStream_t s) {
+hipError_t launch_leaf_batched(Elem e, int scaled, int direct, int one, const void *descs, const int64_t *first,
+                               int count, int64_t total, hipStream_t s) {
     if (total <= 0 || count <= 0) return hipSuccess;
     if (total > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (e == Elem::F64) return batched_go<double>(scaled, direct, descs, first, count, total, s);
-    return batched_go<float>(scaled, direct, descs, first, count, total, s);
+    if (e == Elem::F64) return batched_go<double>(scaled, direct, one, descs, first, count, total, s);
+    return batched_go<float>(scaled, direct, one, descs, first, count, total, s);
 }
 
 hipError_t launch_leaf_pipelined(const LeafLaunch &L, hipStream_t s) {
