@@ -187,10 +187,11 @@ typedef enum {
                               outer levels' node operands written out in FP32 level by level
                               (none at depth <= 1), the innermost level's S_r, T_r formed in the
                               limb GEMM's tile loads (no limb planes), then the W-combination */
-    FASTMM_PATH_WRITTEN = 3 /* FP64 / FP32 from depth 2 with a high fan-in (average sources per
-                              leaf operand, (nnz(U)/R)^L and (nnz(V)/R)^L, above 4): every leaf
-                              operand S_r, T_r written out level by level (eq. (1) applied once
-                              per level), one launch over the written-out leaves, then the
+    FASTMM_PATH_WRITTEN = 3 /* FP64 / FP32 from depth 1 where the fused path is not taken (one
+                              rule at every level, every product live): every leaf operand S_r,
+                              T_r written out level by level (eq. (2) applied once per level,
+                              with the scaling factors and transposes at the first), one launch
+                              over the written-out leaves with one source each, then the
                               W-combination */
 } fastmm_path;
 
@@ -199,9 +200,9 @@ typedef enum {
     FASTMM_FUSE_OFF = 0,    /* always the leaf path with composite source lists (neither the
                                fused kernels nor written-out leaf operands; split precisions
                                through limb planes) */
-    FASTMM_FUSE_AUTO = 1,   /* the default: the fused path where it applies and is the faster one
-                               (FP32 from depth 1, FP64 from depth 2), else written-out leaf
-                               operands where FASTMM_PATH_WRITTEN applies, else the leaf path */
+    FASTMM_FUSE_AUTO = 1,   /* the default: the fused path where it applies to an FP32 plan,
+                               else written-out leaf operands where FASTMM_PATH_WRITTEN applies
+                               (every FP64 plan with a level and one rule), else the leaf path */
     FASTMM_FUSE_ALWAYS = 2  /* the fused path wherever it applies; for the split precisions the
                                innermost level formed in the limb GEMM's loads
                                (FASTMM_PATH_FUSED_LOADS) where it applies */

@@ -469,41 +469,35 @@ struct WsLayout {
 };
 
 // Whether a product takes the fused one-level kernel: FP64/FP32, at least one level, row-major
-// operands and a rule with a compiled sign pattern.  FASTMM_FUSE_AUTO leaves FP64 at depth 1
-// on the leaf path, whose 128x128 tiles run faster there (measured on MI355X: 44 against 40
-// effective TFLOP/s for Strassen at n = 8192); from depth 2 on, saving the leaf products'
-// round trip through memory wins.
+// operands and a rule with a compiled sign pattern.  FASTMM_FUSE_AUTO takes it for FP32 only:
+// the FP64 fused kernel (one work-group per CU, source-list loads) runs at 0.45 of the FP64
+// peak, and the written path below beats it at every depth (measured on MI355X, Strassen FP64 at
+// n = 8192: depth 1 56.9 against 45.1 effective TFLOP/s on the composite-list leaf path, depth 2
+// 56.4 against 43.1 fused; classical 55).
 bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, uint32_t masks[6]) {
     if (p->fuse == FASTMM_FUSE_OFF || s.L < 1 || transA || transB) return false;
     if (!p->tree.empty() || !p->levels.empty()) return false;  // the fused kernel: one rule, every level
     if (p->prec != FASTMM_F64 && p->prec != FASTMM_F32) return false;
-    if (p->fuse == FASTMM_FUSE_AUTO && p->prec == FASTMM_F64 && s.L < 2) return false;
+    if (p->fuse == FASTMM_FUSE_AUTO && p->prec == FASTMM_F64) return false;
     return rule_masks_222(plan_algo(p), masks) && node222_supported(masks);
 }
 
-// FP64 / FP32 with a high fan-in: every leaf operand S_r (mb x kb) and T_r (kb x nb) is
-// written out level by level, stacked (leaf r's S_r at rows r mb .. of an R^L mb x xa_ld
-// matrix, T_r likewise at rows r kb of an R^L kb x xb_ld matrix, row strides multiples of 8),
-// and the leaf kernel multiplies the stacked blocks, one source each.  The composite lists
-// would have every work-group re-read (nnz(U)/R)^L source tiles per K stage, ~11 for
-// <4,2,4;26> at depth 2.  Needs every product live (the leaves are then the R^L children, in
-// the composite order) and one rule at every node.
-double plan_fan_in(const fastmm_plan_s *p, int L) {
-    const Algo &a = plan_algo(p);
-    int64_t nu = 0, nv = 0;
-    for (int64_t x : a.U) nu += x != 0;
-    for (int64_t x : a.V) nv += x != 0;
-    return 0.5 * (std::pow((double)nu / a.R, L) + std::pow((double)nv / a.R, L));
-}
-
+// FP64 / FP32 written leaves: every leaf operand S_r (mb x kb) and T_r (kb x nb) is written out
+// level by level, stacked (leaf r's S_r at rows r mb .. of an R^L mb x xa_ld matrix, T_r
+// likewise at rows r kb of an R^L kb x xb_ld matrix, row strides multiples of 8), and the leaf
+// kernel multiplies the stacked blocks in its single-source form.  With the composite lists
+// instead, every work-group re-reads (nnz(U)/R)^L source tiles per K stage and sums them with
+// their coefficients: 1.7-3.3 tiles at depth 1, ~11 for <4,2,4;26> at depth 2.  Measured on
+// MI355X at n = 8192, FP32 depth 1: <4,2,4> 129.9 against 69.7 effective TFLOP/s, <3,2,3>
+// 117.6 against 75.9, Laderman 109.5 against 61.6 (classical 121).  Needs every product live (the
+// leaves are then the R^L children, in the composite order) and one rule at every node.
 bool written_leaves(const fastmm_plan_s *p, const Shape &s) {
-    if (is_split(p->prec) || s.L < 2 || !p->tree.empty() || !p->levels.empty()) return false;
+    if (is_split(p->prec) || s.L < 1 || !p->tree.empty() || !p->levels.empty()) return false;
     if (p->fuse == FASTMM_FUSE_OFF) return false;  // the composite-list leaf path only
     const Algo &a = plan_algo(p);
     int64_t all = 1;
     for (int l = 0; l < s.L; ++l) all *= a.R;
-    if (leaf_count(a, s.L) != all || a.M0 * a.K0 > 16 || a.K0 * a.N0 > 16) return false;
-    return plan_fan_in(p, s.L) > 4.0;
+    return leaf_count(a, s.L) == all && a.M0 * a.K0 <= 16 && a.K0 * a.N0 <= 16;
 }
 
 // The written path is taken where it applies and the fused kernel does not (the fused kernel,

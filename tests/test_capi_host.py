@@ -142,19 +142,22 @@ def _int_rows(M):
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_fused_path_selection(F, precision):
     P = lambda name, depth, cutoff=1, **kw: F.Plan(name, depth, cutoff, precision=precision, **kw)
-    # FP64 at depth 1 stays on the leaf path unless fusion is forced
-    assert P("strassen", 1).path(256, 256, 256) == ("fused" if precision == "f32" else "leaf")
+    # FP32 <2,2,2> rules take the fused kernel; FP64 writes its leaf operands unless fusion is
+    # forced
+    fused = "fused" if precision == "f32" else "written"
+    assert P("strassen", 1).path(256, 256, 256) == fused
     assert P("strassen", 1, fuse="always").path(256, 256, 256) == "fused"
-    assert P("winograd", 3).path(300, 200, 100) == "fused"
-    assert P("strassen", 2).path(17, 300, 41) == "fused"
-    # transposed operands are copied to row-major and take the fused kernel too; no level,
-    # cutoff stopping at depth 0, other rules, fusion off take the leaf path
-    assert P("strassen", 2).path(256, 256, 256, transB=True) == "fused"
-    assert P("strassen", 2).path(256, 256, 256, transA=True) == "fused"
+    assert P("strassen", 2, fuse="always").path(256, 256, 256) == "fused"
+    assert P("winograd", 3).path(300, 200, 100) == fused
+    assert P("strassen", 2).path(17, 300, 41) == fused
+    # transposed operands are copied to row-major and take the fused kernel too; no level and
+    # cutoff stopping at depth 0 take the leaf path; other rules write their leaf operands
+    assert P("strassen", 2).path(256, 256, 256, transB=True) == fused
+    assert P("strassen", 2).path(256, 256, 256, transA=True) == fused
     assert P("strassen", 0).path(256, 256, 256) == "leaf"
     assert P("strassen", 2, 512).path(256, 256, 256) == "leaf"
-    assert P("f323", 1).path(300, 200, 300) == "leaf"
-    assert P("laderman333", 1).path(300, 300, 300) == "leaf"
+    assert P("f323", 1).path(300, 200, 300) == "written"
+    assert P("laderman333", 1).path(300, 300, 300) == "written"
     assert P("strassen", 2, fuse=False).path(256, 256, 256) == "leaf"
     assert P("strassen", 2, fuse="off").path(256, 256, 256) == "leaf"
     plan = P("strassen", 1)
@@ -165,21 +168,24 @@ def test_fused_path_selection(F, precision):
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_written_path_selection(F, precision):
-    """From depth 2, rules whose leaf operands average more than 4 sources (nnz(U)/R)^L,
-    (nnz(V)/R)^L write their leaf operands out level by level; <2,2,2> rules keep the fused
-    kernel; split precisions form limb planes instead; one level, fusion off and trees stay on
-    the leaf path."""
+    """From depth 1, FP32/FP64 plans with one rule write their leaf operands out level by level
+    (FP32 <2,2,2> rules keep the fused kernel); split precisions form limb planes instead;
+    depth 0, fusion off and trees stay on the leaf path."""
     P = lambda name, depth, cutoff=1, **kw: F.Plan(name, depth, cutoff, precision=precision, **kw)
-    assert P("f424", 2).path(256, 128, 256) == "written"          # fan-in 11.0
-    assert P("f323", 2).path(198, 200, 180) == "written"          # 4.55
-    assert P("laderman333", 2).path(135, 100, 81) == "written"    # 4.92
+    assert P("f424", 2).path(256, 128, 256) == "written"
+    assert P("f323", 2).path(198, 200, 180) == "written"
+    assert P("laderman333", 2).path(135, 100, 81) == "written"
     assert P("f424", 2).path(256, 128, 256, transA=True, transB=True) == "written"
-    assert P("f424", 1).path(256, 128, 256) == "leaf"             # one level: 3.31
-    assert P("f424", 2, 200).path(256, 128, 256) == "leaf"        # the cutoff leaves one level
+    assert P("f424", 1).path(256, 128, 256) == "written"
+    assert P("f424", 2, 64).path(256, 128, 256) == "written"      # the cutoff leaves one level
+    assert P("f424", 2, 200).path(256, 128, 256) == "leaf"        # ... or none
     assert P("f424", 2, fuse="off").path(256, 128, 256) == "leaf"  # fusion off: composite lists only
-    assert P("laderman333", 3).path(270, 270, 270) == "written"     # 10.9
-    assert P("strassen", 3).path(256, 256, 256) == "fused"          # 5.04, but <2,2,2> fused first
+    assert P("laderman333", 3).path(270, 270, 270) == "written"
+    assert P("strassen", 3).path(256, 256, 256) == ("fused" if precision == "f32" else "written")
     assert F.Plan("f424", 2, 1, precision="f16x3").path(256, 128, 256) == "leaf"
+    # per-node and per-level rules stay on the leaf path
+    assert P("strassen", 2).set_tree(["strassen"] + ["winograd"] * 7).path(256, 256, 256) == "leaf"
+    assert P("strassen", 2).set_levels(["strassen", "winograd"]).path(256, 256, 256) == "leaf"
 
 
 def test_fused_loads_path_selection(F):
@@ -216,12 +222,12 @@ def test_fused_path_matches_rules_by_coefficients(F):
                 r = C.rotate(r)
             uid = F.fastmm_algo_register(2, 2, 2, 7, _int_rows(r.U), _int_rows(r.V), _int_rows(r.W), 0)
             assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "fused", (name, t)
-            assert F.Plan(uid, 2, 1, precision="f64").path(128, 128, 128) == "fused", (name, t)
+            assert F.Plan(uid, 2, 1, precision="f64", fuse="always").path(128, 128, 128) == "fused", (name, t)
     a = C.strassen()
     perm = [1, 0, 2, 3, 4, 5, 6]
     U, V, W = (_int_rows(M)[:, perm] for M in (a.U, a.V, a.W))
     uid = F.fastmm_algo_register(2, 2, 2, 7, U, V, W, 0)
-    assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "leaf"
+    assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "written"  # no fused kernel
 
 
 def _transpose_rule(a):
@@ -272,7 +278,7 @@ def test_transposed_rotations_are_rules_and_form_the_transpose(F, name):
         assert np.array_equal(got, (A @ B).T)
         if (M0, K0, N0, R) == (2, 2, 2, 7):
             assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "fused", (name, t)
-            assert F.Plan(uid, 2, 1, precision="f64").path(128, 128, 128) == "fused", (name, t)
+            assert F.Plan(uid, 2, 1, precision="f64", fuse="always").path(128, 128, 128) == "fused", (name, t)
 
 
 def test_backward_workspace_and_batched_errors_on_host(F):
