@@ -203,9 +203,12 @@ typedef enum {
     FASTMM_FUSE_AUTO = 1,   /* the default: the fused path where it applies to an FP32 plan,
                                else written-out leaf operands where FASTMM_PATH_WRITTEN applies
                                (every FP64 plan with a level and one rule), else the leaf path */
-    FASTMM_FUSE_ALWAYS = 2  /* the fused path wherever it applies; for the split precisions the
+    FASTMM_FUSE_ALWAYS = 2, /* the fused path wherever it applies; for the split precisions the
                                innermost level formed in the limb GEMM's loads
                                (FASTMM_PATH_FUSED_LOADS) where it applies */
+    FASTMM_FUSE_WRITTEN = 3 /* FP64 / FP32: written-out leaf operands wherever FASTMM_PATH_WRITTEN
+                               applies, never the fused kernel (the path every FP64 / FP32
+                               product of a batched call takes); split precisions as AUTO */
 } fastmm_fusion;
 
 /* Set the fusion mode (fastmm_fusion) of this plan and of the rotated sub-plans of its backward

@@ -475,7 +475,7 @@ struct WsLayout {
 // n = 8192: depth 1 56.9 against 45.1 effective TFLOP/s on the composite-list leaf path, depth 2
 // 56.4 against 43.1 fused; classical 55).
 bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, uint32_t masks[6]) {
-    if (p->fuse == FASTMM_FUSE_OFF || s.L < 1 || transA || transB) return false;
+    if (p->fuse == FASTMM_FUSE_OFF || p->fuse == FASTMM_FUSE_WRITTEN || s.L < 1 || transA || transB) return false;
     if (!p->tree.empty() || !p->levels.empty()) return false;  // the fused kernel: one rule, every level
     if (p->prec != FASTMM_F64 && p->prec != FASTMM_F32) return false;
     if (p->fuse == FASTMM_FUSE_AUTO && p->prec == FASTMM_F64) return false;
@@ -579,8 +579,13 @@ size_t scaling_layout(const fastmm_plan_s *p, int64_t m, int64_t k, int64_t n, W
     return off;
 }
 
-WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n, int bm_force = 0) {
+// batch: the layout of a problem inside a batched call, where FP32/FP64 products take written
+// leaf operands wherever they apply (the batched launch has no fused kernel: the path of
+// FASTMM_FUSE_WRITTEN).
+WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k, int64_t n, int bm_force = 0,
+                   bool batch = false) {
     WsLayout w{};
+    const bool written = batch ? written_leaves(p, s) : written_taken(p, s);
     const size_t es = elem_size(p->prec);
     size_t off = scaling_layout(p, m, k, n, w);
     if (is_split(p->prec) && bm_force == 0 && fused_split(p, s)) {
@@ -603,17 +608,17 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
             w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
             w.ib = off, off = align256(off + inner_levels(p, s, true).back().off);
         }
-    } else if (!is_split(p->prec) && fused_written(p, s)) {
+    } else if (!is_split(p->prec) && !batch && fused_written(p, s)) {
         // FP64 / FP32 fused from depth 2: the outer levels' node operands (the last of them
         // stacked as the fused kernel's operands)
         w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
         w.ib = off, off = align256(off + inner_levels(p, s, true).back().off);
-    } else if (!is_split(p->prec) && !written_taken(p, s)) {
+    } else if (!is_split(p->prec) && !written) {
         // FP64 / FP32: row-major copies of op(A) and op(B), scaled, for scaled plans and for
         // transposed operands (prescale_operands)
         w.xa = off, off = align256(off + es * (size_t)s.Mp * round_up(s.Kp, 8));
         w.xb = off, off = align256(off + es * (size_t)s.Kp * round_up(s.Np, 8));
-    } else if (written_taken(p, s)) {
+    } else if (written) {
         const WrittenDims wd = written_dims(s);
         const size_t nleaves = (size_t)plan_leaf_count(p, s.L);
         w.ia = off, off = align256(off + inner_levels(p, s, false).back().off);
@@ -951,7 +956,7 @@ fastmm_status fastmm_plan_shape(fastmm_plan_t plan, int64_t m, int64_t k, int64_
 
 fastmm_status fastmm_plan_set_fusion(fastmm_plan_t plan, int mode) {
     if (check_plan(plan)) return FASTMM_EINVAL;
-    if (mode < FASTMM_FUSE_OFF || mode > FASTMM_FUSE_ALWAYS) return fail(FASTMM_EINVAL, "unknown fusion mode");
+    if (mode < FASTMM_FUSE_OFF || mode > FASTMM_FUSE_WRITTEN) return fail(FASTMM_EINVAL, "unknown fusion mode");
     std::lock_guard<std::mutex> g(plan->mu);
     plan->fuse = mode;
     for (auto &r : plan->grad)
@@ -1802,7 +1807,7 @@ fastmm_status batch_layout(const fastmm_plan_t *plans, const fastmm_problem_ex *
         const Shape s = shape_of(plans[i], q.m, q.k, q.n);
         if (every_level(plans[i], s))
             return fail(FASTMM_EUNSUPPORTED, "scaling at every level runs through fastmm_gemm_ex, not in a batch");
-        size_t w = ws_layout(plans[i], s, q.m, q.k, q.n, bl.bm).total;
+        size_t w = ws_layout(plans[i], s, q.m, q.k, q.n, bl.bm, true).total;
         size_t ca = 0, cb = 0;
         if (!is_split(prec) && q.transA) ca = align256(w), w = ca + align256(es * (size_t)q.m * q.k);
         if (!is_split(prec) && q.transB) cb = align256(w), w = cb + align256(es * (size_t)q.k * q.n);
@@ -1925,7 +1930,7 @@ fastmm_status fastmm_gemm_batched_ex(const fastmm_plan_t *plans, const fastmm_pr
         fastmm_plan_s *p = plans[i];
         if (q.m == 0 || q.n == 0 || q.k == 0) continue;
         const Shape sh = shape_of(p, q.m, q.k, q.n);
-        const WsLayout w = ws_layout(p, sh, q.m, q.k, q.n, bl.bm);
+        const WsLayout w = ws_layout(p, sh, q.m, q.k, q.n, bl.bm, true);
         if ((st = run_scaling(p, q.A, q.lda, q.transA, q.B, q.ldb, q.transB, q.m, q.k, q.n, ws + bl.ws_off[i], w, s,
                               &exps_all[i])) != FASTMM_OK)
             return st;
@@ -1940,7 +1945,7 @@ fastmm_status fastmm_gemm_batched_ex(const fastmm_plan_t *plans, const fastmm_pr
             continue;
         }
         const Shape sh = shape_of(p, q.m, q.k, q.n);
-        const WsLayout w = ws_layout(p, sh, q.m, q.k, q.n, bl.bm);
+        const WsLayout w = ws_layout(p, sh, q.m, q.k, q.n, bl.bm, true);
         char *pws = ws + bl.ws_off[i];
         Tables *tab = nullptr;
         if ((st = get_tables(p, sh.L, &tab)) != FASTMM_OK) return st;
@@ -1996,6 +2001,19 @@ fastmm_status fastmm_gemm_batched_ex(const fastmm_plan_t *plans, const fastmm_pr
         L.nleaves = tab->nleaves;
         L.leaves = tab->leaves, L.asrc = tab->asrc, L.bsrc = tab->bsrc;
         L.sc = exps;
+        const bool written = sh.L >= 1 && written_leaves(p, sh);
+        if (written) {
+            // leaf operands written out now (with the scaling factors); the batched launch
+            // multiplies the stacked blocks, one source each, as fastmm_gemm_ex does
+            if ((e = form_written(p, sh, qa, qlda, 0, qb, qldb, 0, q.m, q.k, q.n, exps, pws, w, tab, s, sh.L)) !=
+                hipSuccess)
+                return hip_fail(e, "leaf operand formation");
+            const WrittenDims wd = written_dims(sh);
+            L.A = pws + w.xa, L.lda = wd.xa_ld, L.B = pws + w.xb, L.ldb = wd.xb_ld;
+            L.m = (int64_t)tab->nleaves * sh.mb, L.k = (int64_t)tab->nleaves * sh.kb, L.n = sh.nb;
+            L.leaves = tab->wleaves, L.asrc = tab->wsrc, L.bsrc = tab->wsrc;
+            L.sc = ScaleExps{nullptr, nullptr, nullptr};
+        }
         Item it;
         it.idx = i;
         it.kb = sh.kb;
@@ -2012,9 +2030,10 @@ fastmm_status fastmm_gemm_batched_ex(const fastmm_plan_t *plans, const fastmm_pr
             c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
             set_kron(p, sh.L, tab->nleaves, c);
         }
-        // mode bits: one source per leaf (a classical product, unscaled), scaled loads, output to C
-        const bool one = sh.L == 0 && exps.ea == nullptr;
-        it.mode = 4 * (one ? 1 : 0) + 2 * (exps.ea != nullptr ? 1 : 0) + (L.direct ? 1 : 0);
+        // mode bits: one source per leaf (written leaf operands, or a classical product
+        // unscaled), scaled loads, output to C
+        const bool one = written || (sh.L == 0 && exps.ea == nullptr);
+        it.mode = 4 * (one ? 1 : 0) + 2 * (L.sc.ea != nullptr ? 1 : 0) + (L.direct ? 1 : 0);
         it.desc.resize(leaf_desc_bytes(el));
         it.tiles = leaf_desc_build(L, it.desc.data());
         items.push_back(std::move(it));

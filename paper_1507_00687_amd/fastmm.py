@@ -28,7 +28,7 @@ ALGOS = {
     "f244": 8,
     "laderman333": 9,
 }
-FUSION = {"off": 0, "auto": 1, "always": 2}
+FUSION = {"off": 0, "auto": 1, "always": 2, "written": 3}
 SCALE_MODES = {"none": 0, "outside": 1, "inside": 2, "out_in": 3, "in_out": 4, "repeated": 5}
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4, "f16x3": 5, "bf16x6": 6}
 

@@ -160,9 +160,12 @@ def test_fused_path_selection(F, precision):
     assert P("laderman333", 1).path(300, 300, 300) == "written"
     assert P("strassen", 2, fuse=False).path(256, 256, 256) == "leaf"
     assert P("strassen", 2, fuse="off").path(256, 256, 256) == "leaf"
+    # "written": the batched call's path, never the fused kernel
+    assert P("strassen", 1, fuse="written").path(256, 256, 256) == "written"
+    assert P("strassen", 0, fuse="written").path(256, 256, 256) == "leaf"
     plan = P("strassen", 1)
     with pytest.raises(F.FastmmError):
-        F.fastmm._check(F.fastmm.lib().fastmm_plan_set_fusion(plan.handle, 3))
+        F.fastmm._check(F.fastmm.lib().fastmm_plan_set_fusion(plan.handle, 4))
     assert F.Plan("strassen", 1, 1, precision="bf16x3").path(256, 256, 256) == "leaf"
 
 

@@ -122,8 +122,8 @@ def _batch(precision, dist, scaling="none"):
         host.append((A, B, G))
         dev.append(tuple(torch.from_numpy(X).cuda() for X in (A, B, G)))
         plans.append(F.Plan(name, depth, 1, precision=precision, scaling=scaling))
-        # the batched launch runs the leaf path for FP64 / FP32: single launches on the same path
-        leaf_plans.append(F.Plan(name, depth, 1, precision=precision, scaling=scaling, fuse="off"))
+        # the batched launch's path for FP64 / FP32 (no fused kernel): single launches on it
+        leaf_plans.append(F.Plan(name, depth, 1, precision=precision, scaling=scaling, fuse="written"))
     got = F.fastmm_gemm_backward_batched(plans, [d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev])
     singles = [F.fastmm_gemm_backward(p, *d) for p, d in zip(leaf_plans, dev)]
     torch.cuda.synchronize()
@@ -195,7 +195,7 @@ def test_batched_ex_transposed_and_strided_operands(precision):
         tAs.append(ta)
         tBs.append(tb)
         plans.append(F.Plan(name, depth, 1, precision=precision))
-        leaf_plans.append(F.Plan(name, depth, 1, precision=precision, fuse="off"))
+        leaf_plans.append(F.Plan(name, depth, 1, precision=precision, fuse="written"))
     print(f"\n[batched-ex] {precision}", flush=True)
     got = F.fastmm_gemm_batched_ex(plans, As, Bs, tAs, tBs)
     singles = [F.fastmm_gemm_ex(p, a.contiguous(), ta, b.contiguous(), tb)

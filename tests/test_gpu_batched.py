@@ -27,15 +27,16 @@ def _run_batch(precision, dist, scaling="none"):
     import paper_1507_00687_amd as F
 
     dt = np_dtype(precision)
-    # the batched launch runs every problem on the leaf path: compare with single launches on
-    # the same path (fused single launches round differently from depth 2 on)
+    # the batched launch has no fused kernel: FP64 / FP32 problems take written leaf operands
+    # where they apply, else the composite lists, as single launches in fusion mode "written"
+    # do; compare with those (fused single launches round differently from depth 2 on)
     plans, leaf_plans, As, Bs, hostA, hostB = [], [], [], [], [], []
     for i, (name, depth, (m, k, n)) in enumerate(BATCH):
         A, B = make_pair(dist, 100 + i, m, k, n, dtype=dt)
         hostA.append(A)
         hostB.append(B)
         plans.append(F.Plan(name, depth, 1, precision=precision, scaling=scaling))
-        leaf_plans.append(F.Plan(name, depth, 1, precision=precision, scaling=scaling, fuse=False))
+        leaf_plans.append(F.Plan(name, depth, 1, precision=precision, scaling=scaling, fuse="written"))
         As.append(torch.from_numpy(A).cuda())
         Bs.append(torch.from_numpy(B).cuda())
     Cs = F.fastmm_gemm_batched(plans, As, Bs)
