@@ -440,6 +440,7 @@ bool level_formation(const fastmm_plan_s *p, const Shape &s) {
 struct InnerLevel {
     int64_t cb_o, cb_k, y_ld, y_stride, count;
     size_t off;
+    int64_t k_ld, k_stride;  // the same blocks k-major (element (o, kk) at kk k_ld + o)
 };
 std::vector<InnerLevel> inner_levels(const fastmm_plan_s *p, const Shape &s, bool side_b) {
     const Algo &a = plan_algo(p);
@@ -453,11 +454,12 @@ std::vector<InnerLevel> inner_levels(const fastmm_plan_s *p, const Shape &s, boo
         po *= nO, pk *= nK, count *= a.R;
         InnerLevel e;
         e.cb_o = O / po, e.cb_k = K / pk, e.y_ld = (e.cb_k + 7) / 8 * 8, e.y_stride = e.cb_o * e.y_ld;
+        e.k_ld = (e.cb_o + 7) / 8 * 8, e.k_stride = e.cb_k * e.k_ld;
         e.count = count, e.off = off;
-        off = align256(off + es * (size_t)count * e.y_stride);
+        off = align256(off + es * (size_t)count * std::max(e.y_stride, e.k_stride));
         v.push_back(e);
     }
-    v.push_back(InnerLevel{0, 0, 0, 0, 0, off});
+    v.push_back(InnerLevel{0, 0, 0, 0, 0, off, 0, 0});
     return v;
 }
 
@@ -1338,9 +1340,12 @@ hipError_t form_written(fastmm_plan_s *plan, const Shape &s, const void *A, int6
                 }
                 nf.K = k, nf.first = 1, nf.e_k = exps.ep, nf.pre_exp = 0;
             } else {
+                // A side o-major, B side k-major (each in its operand's own orientation, so that
+                // every level is formed without a transpose)
                 const InnerLevel &in = lv[l - 2];
-                nf.X = ibase + in.off, nf.ld_o = in.y_ld, nf.ld_k = 1;
-                nf.node_stride = in.y_stride, nf.first = 0;
+                nf.X = ibase + in.off, nf.first = 0;
+                if (side_b) nf.ld_o = 1, nf.ld_k = in.k_ld, nf.node_stride = in.k_stride;
+                else nf.ld_o = in.y_ld, nf.ld_k = 1, nf.node_stride = in.y_stride;
             }
             nf.nO = side_b ? al.N0 : al.M0, nf.nK = al.K0, nf.side_b = side_b ? 1 : 0, nf.R_ = al.R;
             nf.coef = side_b ? tab->vcoef : tab->ucoef;
@@ -1356,8 +1361,10 @@ hipError_t form_written(fastmm_plan_s *plan, const Shape &s, const void *A, int6
                 const InnerLevel &out = lv[l - 1];
                 nf.cb_o = out.cb_o, nf.cb_k = out.cb_k;
                 nf.Y = ibase + out.off, nf.y_ld = out.y_ld, nf.y_stride = out.y_stride;
-                if (l == upto && side_b) {  // the fused kernel's B operand: k-major, same bytes
+                if (l == upto && side_b) {  // the fused kernel's B operand: k-major, unpadded
                     nf.y_ld = out.cb_o, nf.y_stride = out.cb_k * out.cb_o, nf.kmajor = 1;
+                } else if (side_b) {
+                    nf.y_ld = out.k_ld, nf.y_stride = out.k_stride, nf.kmajor = 1;
                 }
             }
             if (nodes > 65535) return hipErrorInvalidValue;

@@ -1021,6 +1021,88 @@ int limb_gemm_tile(int prec, int64_t mb, int64_t nb) {
     return (limb_count(prec) < 3 && mb >= 256 && nb >= 256) ? 256 : 128;
 }
 
+// form_node without the LDS stage, where the operand's contiguous direction is the output's
+// (k for o-major blocks, o for k-major ones: every level of row-major operands): a thread holds
+// V consecutive elements of one row of each of the nS sub-blocks in registers (one 16-byte load
+// each where aligned and inside the block) and writes V elements of every child, summing the
+// sub-blocks in the same order with the same operations as form_node (bitwise equal results).
+// Rows r and the contiguous position p of the child block: (o, kk) for o-major output, (kk, o)
+// for k-major; p runs over the padded row length y_ld, whose padding is written as zeros.
+template <typename T, int MAXS>
+__global__ __launch_bounds__(256) void form_node_direct(NodeForm a, int64_t rows, int64_t chunks) {
+    constexpr int V = 16 / (int)sizeof(T);
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type vec_t;
+    const int64_t item = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (item >= rows * chunks) return;
+    const int q = blockIdx.z;
+    const int64_t r = item / chunks, p0 = (item - r * chunks) * V;
+    const bool km = a.kmajor != 0;
+    const int64_t oc0 = km ? p0 : r, kc0 = km ? r : p0;  // child block coordinates of element 0
+    const int64_t step_o = km ? 1 : 0, step_k = km ? 0 : 1;
+    const int nS = a.nO * a.nK;
+    const T *X = reinterpret_cast<const T *>(a.X) + (a.first ? 0 : (int64_t)q * a.node_stride);
+    const int64_t ld_p = km ? a.ld_o : a.ld_k;  // 1 here
+    T x[MAXS][V];
+#pragma unroll
+    for (int sb = 0; sb < MAXS; ++sb) {
+        if (sb >= nS) continue;  // (not break: a fully unrolled loop keeps x in registers)
+        const int ob = a.side_b ? sb / a.nK : sb % a.nO, kbk = a.side_b ? sb % a.nK : sb / a.nO;
+        const int64_t o0 = ob * a.cb_o + oc0, k0 = kbk * a.cb_k + kc0;  // inside the node operand
+        const T *src = X + o0 * a.ld_o + k0 * a.ld_k;
+        // all V elements inside the child block and the operand, and 16-byte aligned
+        const bool in_blk = km ? (oc0 + V <= a.cb_o && kc0 < a.cb_k) : (kc0 + V <= a.cb_k && oc0 < a.cb_o);
+        const bool in_op = !a.first || (km ? (o0 + V <= a.R && k0 < a.K) : (k0 + V <= a.K && o0 < a.R));
+        if (in_blk && in_op && ld_p == 1 && ((uintptr_t)src & 15) == 0) {
+            const vec_t w = *reinterpret_cast<const vec_t *>(src);
+            const T *ws = reinterpret_cast<const T *>(&w);
+#pragma unroll
+            for (int j = 0; j < V; ++j) x[sb][j] = ws[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int64_t oc = oc0 + j * step_o, kcn = kc0 + j * step_k;
+                bool ok = oc < a.cb_o && kcn < a.cb_k;
+                const int64_t o = ob * a.cb_o + oc, kk = kbk * a.cb_k + kcn;
+                if (a.first) ok = ok && o < a.R && kk < a.K;
+                const T y = *(ok ? X + o * a.ld_o + kk * a.ld_k : X);
+                x[sb][j] = ok ? y : T(0);
+            }
+        }
+        if (a.first && a.e_o) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int64_t oc = oc0 + j * step_o, kcn = kc0 + j * step_k;
+                const int64_t o = ob * a.cb_o + oc, kk = kbk * a.cb_k + kcn;
+                const bool ok = oc < a.cb_o && kcn < a.cb_k && o < a.R && kk < a.K;
+                x[sb][j] = ldexp(x[sb][j], a.s_o * a.e_o[ok ? o : 0] + a.s_k * a.e_k[ok ? kk : 0] + a.pre_exp);
+            }
+        }
+    }
+    T *Y = reinterpret_cast<T *>(a.Y);
+    for (int c = 0; c < a.R_; ++c) {
+        T v[V];
+        bool first = true;
+#pragma unroll
+        for (int sb = 0; sb < MAXS; ++sb) {
+            const float u = sb < nS ? a.coef[sb * a.R_ + c] : 0.f;
+            if (u == 0.f) continue;
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[j] = first ? (T)u * x[sb][j] : v[j] + (T)u * x[sb][j];
+            first = false;
+        }
+        if (first) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[j] = T(0);
+        }
+        vec_t w;
+        T *ws = reinterpret_cast<T *>(&w);
+#pragma unroll
+        for (int j = 0; j < V; ++j) ws[j] = v[j];
+        const int64_t child = (int64_t)q * a.R_ + c;
+        *reinterpret_cast<vec_t *>(Y + child * a.y_stride + r * a.y_ld + p0) = w;
+    }
+}
+
 hipError_t launch_form_node(int prec, const NodeForm &f, int nodes, hipStream_t s) {
     NodeForm a = f;
     a.nl = limb_count(prec);
@@ -1038,6 +1120,25 @@ hipError_t launch_form_node(int prec, const NodeForm &f, int nodes, hipStream_t 
     if (gx <= 0 || gy <= 0) return hipSuccess;
     if (gx > 0x7fffffffLL || gy > 65535 || nodes > 65535) return hipErrorInvalidValue;
     if (a.kmajor && (a.y_ld % 8 != 0)) return hipErrorInvalidValue;
+    // the operand's contiguous direction is the output's: no LDS transpose needed
+    const bool direct = !a.last && ((a.ld_k == 1 && !a.kmajor) || (a.ld_o == 1 && a.kmajor)) && a.y_ld % 8 == 0 &&
+                        ((uintptr_t)a.Y & 15) == 0 && a.y_stride % 8 == 0;
+    if (direct) {
+        const int64_t rows = a.kmajor ? a.cb_k : a.cb_o, chunks = a.y_ld / (dbl ? 2 : 4);
+        const int64_t blocks = (rows * chunks + 255) / 256;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+        const dim3 g((unsigned)blocks, 1, (unsigned)nodes);
+        if (dbl) {
+            if (nS <= 4) hipLaunchKernelGGL((form_node_direct<double, 4>), g, dim3(256), 0, s, a, rows, chunks);
+            else if (nS <= 8) hipLaunchKernelGGL((form_node_direct<double, 8>), g, dim3(256), 0, s, a, rows, chunks);
+            else hipLaunchKernelGGL((form_node_direct<double, 16>), g, dim3(256), 0, s, a, rows, chunks);
+        } else {
+            if (nS <= 4) hipLaunchKernelGGL((form_node_direct<float, 4>), g, dim3(256), 0, s, a, rows, chunks);
+            else if (nS <= 8) hipLaunchKernelGGL((form_node_direct<float, 8>), g, dim3(256), 0, s, a, rows, chunks);
+            else hipLaunchKernelGGL((form_node_direct<float, 16>), g, dim3(256), 0, s, a, rows, chunks);
+        }
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)nodes);
     const size_t es = dbl ? sizeof(double) : sizeof(float);
     const size_t lds = (size_t)nS * TO * 65 * es + (size_t)nS * a.R_ * sizeof(float);
