@@ -1,6 +1,7 @@
-"""The FP64 / FP32 path with written-out leaf operands (rules with a high fan-in from depth 2):
-every S_r and T_r formed level by level by eq. (1), the first level scaled, then one launch
-over the written-out leaves and the W-combination of the composite destination lists.
+"""The FP64 / FP32 path with written-out leaf operands (from depth 1, every plan with one rule
+that the FP32 fused kernel does not take): every S_r and T_r formed level by level by eq. (2),
+the first level scaled, then one launch over the written-out leaves and the W-combination of
+the composite destination lists.
 
 Integer inputs must be bit-exact (every partial sum is an integer well inside the mantissa);
 floating-point results within Theorem 4.1 and within 4x the oracle's own error for the same
@@ -24,7 +25,10 @@ CASES = [  # rule, depth, shape (ragged: padding on every side)
     ("f323", 2, (200, 150, 220)),
     ("laderman333", 2, (135, 100, 81)),
     ("f424", 3, (260, 70, 300)),
+    ("f424", 1, (200, 40, 180)),
+    ("laderman333", 1, (100, 81, 135)),
 ]
+CASES_F64 = [("strassen", 1, (300, 200, 100)), ("strassen", 2, (257, 300, 129)), ("winograd", 3, (200, 264, 300))]
 
 
 def _plan(name, depth, precision, scaling="none", steps=2):
@@ -94,3 +98,41 @@ def test_written_scaled_against_oracle(precision, scaling, steps):
     Bi = (Bi * np.exp2(-(np.arange(shape[2]) % 7))[None, :]).astype(dt)
     got = run_gpu(p, Ai, Bi)
     assert np.array_equal(got.astype(np.float64), Ai.astype(np.float64) @ Bi.astype(np.float64))
+
+
+@pytest.mark.parametrize("name,depth,shape", CASES_F64)
+def test_written_f64_strassen_exact_and_against_oracle(name, depth, shape):
+    """FP64 <2,2,2> rules take the written path by default: exact on integers, and within
+    Theorem 4.1 and 4x the oracle's own error on N(0,1) inputs."""
+    print(f"\n[written-f64] {name} L={depth} {shape}", flush=True)
+    p = _plan(name, depth, "f64")
+    assert p.path(*shape) == "written"
+    A, B = make_pair("int8", 7, *shape)
+    got = run_gpu(p, A.astype(np.float64), B.astype(np.float64))
+    assert np.array_equal(got, (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64))
+    A, B = make_pair("normal", 8, *shape)
+    got = run_gpu(p, A, B)
+    ref = O.reference_rows(A, B)
+    err = O.normwise_error(got, ref, A, B)
+    assert err <= theorem_bound(name, *shape, depth, 1, UNIT_ROUNDOFF["f64"])
+    err_or = O.normwise_error(oracle_fast(name, A, B, depth, 1), ref, A, B)
+    assert err <= 4 * err_or + 4 * UNIT_ROUNDOFF["f64"]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,depth,shape", [("f424", 2, (200, 40, 180)), ("f323", 1, (150, 100, 120)),
+                                              ("strassen", 2, (130, 200, 90))])
+def test_written_transposed_operands_bitwise_equal(precision, name, depth, shape):
+    """Transposed operands are read through the LDS-staged formation at the first level,
+    row-major ones by the register-only formation; both form every S_r, T_r element with the
+    same operations in the same order, so the products are bitwise equal."""
+    print(f"\n[written-trans] {name} L={depth} {shape} {precision}", flush=True)
+    import paper_1507_00687_amd as F
+
+    p = F.Plan(name, depth, 1, precision=precision, fuse="written")
+    m, k, n = shape
+    assert p.path(m, k, n) == "written" and p.path(m, k, n, True, True) == "written"
+    A, B = make_pair("normal", 9, m, k, n, dtype=np_dtype(precision))
+    plain = run_gpu(p, A, B)
+    trans = run_gpu(p, np.ascontiguousarray(A.T), np.ascontiguousarray(B.T), transA=True, transB=True)
+    assert np.array_equal(plain, trans)
