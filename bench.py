@@ -69,8 +69,9 @@ def parse():
                     help="also time this rule at the same depth, size, scaling and precision (none = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-classical", action="store_true")
-    ap.add_argument("--fuse", default="auto", choices=["auto", "off", "always"],
-                    help="fusion mode of the plan (off: leaf products + W-combination)")
+    ap.add_argument("--fuse", default="auto", choices=["auto", "off", "always", "written"],
+                    help="fusion mode of the plan (off: leaf products from composite source lists; "
+                         "written: written-out leaf operands, never the fused kernel)")
     ap.add_argument("--no-vendor", action="store_true",
                     help="skip timing torch.bmm (hipBLASLt) on the leaf products' shape")
     ap.add_argument("--torch-ref", action="store_true",

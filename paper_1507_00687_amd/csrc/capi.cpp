@@ -471,16 +471,19 @@ struct WsLayout {
 };
 
 // Whether a product takes the fused one-level kernel: FP64/FP32, at least one level, row-major
-// operands and a rule with a compiled sign pattern.  FASTMM_FUSE_AUTO takes it for FP32 only:
-// the FP64 fused kernel (one work-group per CU, source-list loads) runs at 0.45 of the FP64
-// peak, and the written path below beats it at every depth (measured on MI355X, Strassen FP64 at
-// n = 8192: depth 1 56.9 against 45.1 effective TFLOP/s on the composite-list leaf path, depth 2
-// 56.4 against 43.1 fused; classical 55).
+// operands and a rule with a compiled sign pattern.  FASTMM_FUSE_AUTO takes it for FP32 from
+// depth 3 only, where it saves the innermost level's formation and the list-form W-combination
+// of three levels (Strassen n = 16384: 157 against 146 effective TFLOP/s); at depths 1 and 2 the
+// written path below, whose leaf kernel runs at 0.78 of the FP32 peak against the fused
+// kernel's 0.72, is as fast or faster (n = 8192 depth 1: 133 against 129; depth 2: 138 against
+// 137, n = 16384: 151 against 144).  The FP64 fused kernel (one work-group per CU, source-list
+// loads) runs at 0.45 of the FP64 peak; the written path beats it at every depth (n = 8192 depth
+// 2: 63 against 43).
 bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, uint32_t masks[6]) {
     if (p->fuse == FASTMM_FUSE_OFF || p->fuse == FASTMM_FUSE_WRITTEN || s.L < 1 || transA || transB) return false;
     if (!p->tree.empty() || !p->levels.empty()) return false;  // the fused kernel: one rule, every level
     if (p->prec != FASTMM_F64 && p->prec != FASTMM_F32) return false;
-    if (p->fuse == FASTMM_FUSE_AUTO && p->prec == FASTMM_F64) return false;
+    if (p->fuse == FASTMM_FUSE_AUTO && (p->prec == FASTMM_F64 || s.L < 3)) return false;
     return rule_masks_222(plan_algo(p), masks) && node222_supported(masks);
 }
 

@@ -142,18 +142,19 @@ def _int_rows(M):
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_fused_path_selection(F, precision):
     P = lambda name, depth, cutoff=1, **kw: F.Plan(name, depth, cutoff, precision=precision, **kw)
-    # FP32 <2,2,2> rules take the fused kernel; FP64 writes its leaf operands unless fusion is
-    # forced
+    # FP32 <2,2,2> rules take the fused kernel from depth 3; below that, and for FP64, plans
+    # write their leaf operands unless fusion is forced
     fused = "fused" if precision == "f32" else "written"
-    assert P("strassen", 1).path(256, 256, 256) == fused
+    assert P("strassen", 1).path(256, 256, 256) == "written"
+    assert P("strassen", 2).path(256, 256, 256) == "written"
     assert P("strassen", 1, fuse="always").path(256, 256, 256) == "fused"
     assert P("strassen", 2, fuse="always").path(256, 256, 256) == "fused"
     assert P("winograd", 3).path(300, 200, 100) == fused
-    assert P("strassen", 2).path(17, 300, 41) == fused
+    assert P("strassen", 3).path(17, 300, 41) == fused
     # transposed operands are copied to row-major and take the fused kernel too; no level and
     # cutoff stopping at depth 0 take the leaf path; other rules write their leaf operands
-    assert P("strassen", 2).path(256, 256, 256, transB=True) == fused
-    assert P("strassen", 2).path(256, 256, 256, transA=True) == fused
+    assert P("strassen", 3).path(256, 256, 256, transB=True) == fused
+    assert P("strassen", 3).path(256, 256, 256, transA=True) == fused
     assert P("strassen", 0).path(256, 256, 256) == "leaf"
     assert P("strassen", 2, 512).path(256, 256, 256) == "leaf"
     assert P("f323", 1).path(300, 200, 300) == "written"
@@ -224,7 +225,7 @@ def test_fused_path_matches_rules_by_coefficients(F):
             for _ in range(t):
                 r = C.rotate(r)
             uid = F.fastmm_algo_register(2, 2, 2, 7, _int_rows(r.U), _int_rows(r.V), _int_rows(r.W), 0)
-            assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "fused", (name, t)
+            assert F.Plan(uid, 1, 1, precision="f32", fuse="always").path(128, 128, 128) == "fused", (name, t)
             assert F.Plan(uid, 2, 1, precision="f64", fuse="always").path(128, 128, 128) == "fused", (name, t)
     a = C.strassen()
     perm = [1, 0, 2, 3, 4, 5, 6]
@@ -280,7 +281,7 @@ def test_transposed_rotations_are_rules_and_form_the_transpose(F, name):
         got = _eval_tables(tab, np.ascontiguousarray(B.T), np.ascontiguousarray(A.T), M0, K0, N0, 1)
         assert np.array_equal(got, (A @ B).T)
         if (M0, K0, N0, R) == (2, 2, 2, 7):
-            assert F.Plan(uid, 1, 1, precision="f32").path(128, 128, 128) == "fused", (name, t)
+            assert F.Plan(uid, 1, 1, precision="f32", fuse="always").path(128, 128, 128) == "fused", (name, t)
             assert F.Plan(uid, 2, 1, precision="f64", fuse="always").path(128, 128, 128) == "fused", (name, t)
 
 
@@ -413,7 +414,7 @@ def test_tree_argument_errors(F):
     p.set_tree(ids)
     assert p.path(128, 128, 128) == "leaf"  # tree plans take the leaf path
     p.set_tree([])
-    assert F.Plan("strassen", 2, 1, precision="f32").path(128, 128, 128) == "fused"
+    assert F.Plan("strassen", 3, 1, precision="f32").path(128, 128, 128) == "fused"
 
 
 def test_stability_exponent_and_fig2_quantities(F):
@@ -489,10 +490,10 @@ def test_every_level_scaling_plan_rules(F):
     # the nested products' own workspace
     nested = F.Plan("strassen", 1, 1, scaling="out_in", precision="f32").workspace_size(128, 128, 128)
     assert every.workspace_size(m, k, n) >= 7 * 3 * 128 * 128 * 4 + nested
-    # scaling once on the fused path from depth 2: the first level's node operands of both sides
-    # (written before the fused kernel) and the node products, 7 each of 128 x 128
+    # scaling once on the written path at depth 2: the first level's node operands of both
+    # sides and the leaf products, 7 each of 128 x 128 (and the stacked leaf operands)
     assert once.workspace_size(m, k, n) >= 3 * 7 * 128 * 128 * 4
-    assert every.path(m, k, n) == "every_level" and once.path(m, k, n) == "fused"
+    assert every.path(m, k, n) == "every_level" and once.path(m, k, n) == "written"
     # depth <= 1 (or no scaling, or the cutoff stopping at one level): as scaling once
     for depth, mode, cutoff in ((1, "out_in", 1), (2, "none", 1), (2, "outside", 100)):
         a = F.Plan("strassen", depth, cutoff, scaling=mode, per_level=True)
