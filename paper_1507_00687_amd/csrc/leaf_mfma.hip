@@ -406,9 +406,8 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
         // group g = lane / 16, so a lane's operands for the four steps are 4 consecutive k of
         // one tile row: 16-byte LDS reads.
         const int g4 = 4 * (lane >> 4), l16 = lane & 15;
-#pragma unroll
-        for (int h = 0; h < BK / 16; ++h) {
-            T ea[TM][4], eb[TN][4];
+        // the fragments of 16-k chunk h: A rows and B columns of the wave's tile
+        auto read_frag = [&](int h, T (&ea)[TM][4], T (&eb)[TN][4]) {
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -429,6 +428,28 @@ __device__ __forceinline__ void leaf_tile(const PArgs<T> &p, int leaf, int64_t t
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) eb[j][c + e] = xs[e];
                 }
+        };
+        // ONE with two chunks per stage: the second chunk's fragments are read before the
+        // mid-stage stores (the stores go to the other buffer; the compiler cannot tell, and
+        // would otherwise wait for these reads after the first chunk's MFMA work)
+        constexpr bool EARLY = ONE && BK / 16 == 2;
+        T ea1[TM][4], eb1[TN][4];
+        if constexpr (EARLY) read_frag(1, ea1, eb1);
+#pragma unroll
+        for (int h = 0; h < BK / 16; ++h) {
+            T ea[TM][4], eb[TN][4];
+            if (EARLY && h == 1) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) ea[i][c] = ea1[i][c];
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) eb[j][c] = eb1[j][c];
+            } else {
+                read_frag(h, ea, eb);
+            }
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
 #pragma unroll
