@@ -467,7 +467,7 @@ std::vector<InnerLevel> inner_levels(const fastmm_plan_s *p, const Shape &s, boo
 // split precisions: [S limb planes][T^T limb planes] 16-bit | [leaf products nleaves * mb * nb]
 // elems.
 struct WsLayout {
-    size_t ea, ep, eb, flags, maxA, maxB, sp, tp, ia, ib, xa, xb, leaves, total;
+    size_t ea, ep, eb, flags, maxA, maxB, sp, tp, ia, ib, xa, xb, leaves, nodes, total;
 };
 
 // Whether a product takes the fused one-level kernel: FP64/FP32, at least one level, row-major
@@ -584,6 +584,8 @@ size_t scaling_layout(const fastmm_plan_s *p, int64_t m, int64_t k, int64_t n, W
     return off;
 }
 
+bool two_pass_combine(const fastmm_plan_s *p, const Shape &s);
+
 // batch: the layout of a problem inside a batched call, where FP32/FP64 products take written
 // leaf operands wherever they apply (the batched launch has no fused kernel: the path of
 // FASTMM_FUSE_WRITTEN).
@@ -633,6 +635,10 @@ WsLayout ws_layout(const fastmm_plan_s *p, const Shape &s, int64_t m, int64_t k,
     }
     w.leaves = off;
     if (s.L > 0) off = align256(off + es * (size_t)plan_leaf_count(p, s.L) * s.mb * s.nb);
+    if (two_pass_combine(p, s)) {  // the first-level node products of the two-pass combination
+        const Algo &a = plan_algo(p);
+        w.nodes = off, off = align256(off + es * (size_t)a.R * (a.M0 * s.mb) * (a.N0 * s.nb));
+    }
     w.total = off;
     return w;
 }
@@ -683,6 +689,18 @@ void set_kron(const fastmm_plan_s *p, int levels, int nleaves, CombineLaunch &Cb
     Cb.R2 = a2.R, Cb.kron = 2;
 }
 
+// Two levels of one rule with 16 output blocks per level (<4,2,4> and its rotations): combined
+// level by level, each level from the one-level lists (CombineLaunch::kron = 4) through the R
+// first-level node products.  The composite-list form re-reads each output block's ~100
+// contributing products from cache (FETCH about 10x the products' bytes); measured at
+// n = 8192 FP32: 1.02 -> 0.54 ms, F16X3 n = 16384: 5.2 -> 2.5 ms.  With 9 output blocks the
+// lists stay (<3,2,3> depth 2: 0.44 against 0.76 ms two-pass; Laderman 1.26 against 1.14).
+bool two_pass_combine(const fastmm_plan_s *p, const Shape &s) {
+    if (s.L != 2 || !p->tree.empty() || !p->levels.empty()) return false;
+    const Algo &a = plan_algo(p);
+    return a.M0 * a.N0 == 16 && a.R <= 64 && leaf_count(a, 2) == (int64_t)a.R * a.R;
+}
+
 fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -730,6 +748,21 @@ fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
     }
     *out = t.get();
     p->tables[key] = std::move(t);
+    return FASTMM_OK;
+}
+
+// The W-combination of a product's leaves: the register forms of set_kron, else two levels of
+// one rule level by level (two_pass_combine, through w.nodes), else the composite lists.
+fastmm_status set_combine(fastmm_plan_s *p, const Shape &s, const Tables *tab, char *ws, const WsLayout &w,
+                          CombineLaunch &Cb) {
+    set_kron(p, s.L, tab->nleaves, Cb);
+    if (Cb.kron != 0 || !two_pass_combine(p, s)) return FASTMM_OK;
+    Tables *t1 = nullptr;
+    const fastmm_status st = get_tables(p, 1, &t1);
+    if (st != FASTMM_OK) return st;
+    const Algo &a = plan_algo(p);
+    Cb.kron = 4, Cb.R1 = a.R, Cb.M0 = a.M0, Cb.N0 = a.N0;
+    Cb.bdest1 = t1->bdest, Cb.dest1 = t1->dest, Cb.nodes = ws + w.nodes;
     return FASTMM_OK;
 }
 
@@ -1579,7 +1612,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         Cb.NB = tab->NB;
         Cb.bdest = tab->bdest, Cb.dest = tab->dest;
         Cb.sc = exps;
-        set_kron(plan, s.L, tab->nleaves, Cb);
+        if (const fastmm_status cs = set_combine(plan, s, tab, ws, w, Cb)) return cs;
         if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
         return FASTMM_OK;
     }
@@ -1608,7 +1641,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         Cb.NB = tab->NB;
         Cb.bdest = tab->bdest, Cb.dest = tab->dest;
         Cb.sc = exps;
-        set_kron(plan, s.L, tab->nleaves, Cb);
+        if (const fastmm_status cs = set_combine(plan, s, tab, ws, w, Cb)) return cs;
         if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
         return FASTMM_OK;
     }
@@ -1663,7 +1696,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
         Cb.NB = tab->NB;
         Cb.bdest = tab->bdest, Cb.dest = tab->dest;
         Cb.sc = exps;
-        set_kron(plan, s.L, tab->nleaves, Cb);
+        if (const fastmm_status cs = set_combine(plan, s, tab, ws, w, Cb)) return cs;
         if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
         return FASTMM_OK;
     }
@@ -1735,7 +1768,7 @@ fastmm_status fastmm_gemm_ex(fastmm_plan_t plan, const void *A, int64_t lda, int
     Cb.NB = tab->NB;
     Cb.bdest = tab->bdest, Cb.dest = tab->dest;
     Cb.sc = exps;
-    set_kron(plan, s.L, tab->nleaves, Cb);
+    if (const fastmm_status cs = set_combine(plan, s, tab, ws, w, Cb)) return cs;
     if ((e = launch_combine(Cb, st)) != hipSuccess) return hip_fail(e, "combine kernel");
     return FASTMM_OK;
 }
@@ -1981,7 +2014,7 @@ fastmm_status fastmm_gemm_batched_ex(const fastmm_plan_t *plans, const fastmm_pr
                 c.leaf_stride = sh.mb * sh.nb;
                 c.C = q.C, c.ldc = q.ldc, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
                 c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
-                set_kron(p, sh.L, tab->nleaves, c);
+                if (const fastmm_status cs = set_combine(p, sh, tab, pws, w, c)) return cs;
             }
             it.mode = 0;
             it.desc.resize(sizeof(LimbGemm));
@@ -2038,7 +2071,7 @@ fastmm_status fastmm_gemm_batched_ex(const fastmm_plan_t *plans, const fastmm_pr
             c.leaf_stride = sh.mb * sh.nb;
             c.C = q.C, c.ldc = q.ldc, c.m = q.m, c.n = q.n, c.mb = sh.mb, c.nb = sh.nb;
             c.NB = tab->NB, c.bdest = tab->bdest, c.dest = tab->dest, c.sc = exps;
-            set_kron(p, sh.L, tab->nleaves, c);
+            if (const fastmm_status cs = set_combine(p, sh, tab, pws, w, c)) return cs;
         }
         // mode bits: one source per leaf (written leaf operands, or a classical product
         // unscaled), scaled loads, output to C

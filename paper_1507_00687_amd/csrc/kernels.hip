@@ -205,6 +205,7 @@ struct CombineArgs {
     const BlockDests *bdest;
     const DestEntry *dest;
     ScaleExps sc;
+    int64_t zM = 0, zC = 0;  // combine_level_kernel: offsets of work-group layer z in M and C
 };
 
 // C(i, j) = 2^(ea_i + eb_j) * sum_q coef_q * M_{leaf_q}(i mod mb, j mod nb), summed in list
@@ -504,6 +505,8 @@ __global__ __launch_bounds__(kThreads) void combine_level_kernel(CombineArgs<T> 
     __syncthreads();
     const int64_t y = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * VEC;
     if (y >= p.nb) return;
+    const T *M = p.M + (int64_t)blockIdx.z * p.zM;
+    T *C = p.C + (int64_t)blockIdx.z * p.zC;
     for (int64_t x = blockIdx.y; x < p.mb; x += gridDim.y) {
         T acc[kCombineMaxBlocks][VEC];
         bool seen[kCombineMaxBlocks];
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(kThreads) void combine_level_kernel(CombineArgs<T> 
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (r0 + u < nprod) {
-                    const T *src = p.M + (int64_t)(r0 + u) * p.leaf_stride + x * p.nb + y;
+                    const T *src = M + (int64_t)(r0 + u) * p.leaf_stride + x * p.nb + y;
                     if constexpr (VEC == 1) {
                         mv[u][0] = *src;
                     } else {
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void combine_level_kernel(CombineArgs<T> 
                 out[e] = seen[b] ? acc[b][e] : T(0);
                 if (SCALED) out[e] = ldexp_t(out[e], ea + eb[e]);
             }
-            T *dst = p.C + row * p.ldc + col;
+            T *dst = C + row * p.ldc + col;
             if constexpr (VEC == 1) {
                 *dst = out[0];
             } else {
@@ -997,25 +1000,20 @@ hipError_t combine2_go(const CombineLaunch &L, hipStream_t s) {
     return hipGetLastError();
 }
 
+// One level of the lists in `a` over nz layers (layer z reads M + z zM, writes C + z zC), with
+// 8-byte vectors where the shapes allow (16 output blocks' sums are live per thread).
 template <typename T>
-hipError_t combine_level_go(const CombineLaunch &L, hipStream_t s) {
-    CombineArgs<T> a;
-    a.M = (const T *)L.M;
-    a.leaf_stride = L.leaf_stride;
-    a.C = (T *)L.C;
-    a.ldc = L.ldc, a.m = L.m, a.n = L.n, a.mb = L.mb, a.nb = L.nb;
-    a.NB = L.NB;
-    a.bdest = L.bdest, a.dest = L.dest, a.sc = L.sc;
-    const int nblocks = L.R2, nprod = L.R1;  // output blocks, products
-    if (nblocks < 1 || nblocks > kCombineMaxBlocks || nprod < 1 || nprod > kCombineMaxProducts || L.NB < 1)
+hipError_t combine_level_launch(const CombineArgs<T> &a, int nblocks, int nprod, int nz, hipStream_t s) {
+    if (nblocks < 1 || nblocks > kCombineMaxBlocks || nprod < 1 || nprod > kCombineMaxProducts || a.NB < 1 ||
+        nz < 1 || nz > 65535)
         return hipErrorInvalidValue;
-    constexpr int VEC = 16 / (int)sizeof(T);
-    const bool vec = L.nb % VEC == 0 && L.n % VEC == 0 && L.ldc % VEC == 0 && (uintptr_t)L.C % 16 == 0 &&
-                     (uintptr_t)L.M % 16 == 0 && L.leaf_stride % VEC == 0;
+    constexpr int VEC = 8 / (int)sizeof(T);
+    const bool vec = VEC > 1 && a.nb % VEC == 0 && a.n % VEC == 0 && a.ldc % VEC == 0 && (uintptr_t)a.C % 8 == 0 &&
+                     (uintptr_t)a.M % 8 == 0 && a.leaf_stride % VEC == 0 && a.zM % VEC == 0 && a.zC % VEC == 0;
     const int per = vec ? VEC : 1;
-    const int64_t cols = (L.nb + per - 1) / per;
-    dim3 grid((unsigned)((cols + kThreads - 1) / kThreads), (unsigned)(L.mb < 65535 ? L.mb : 65535));
-    const bool sc = L.sc.ea != nullptr;
+    const int64_t cols = (a.nb + per - 1) / per;
+    dim3 grid((unsigned)((cols + kThreads - 1) / kThreads), (unsigned)(a.mb < 65535 ? a.mb : 65535), (unsigned)nz);
+    const bool sc = a.sc.ea != nullptr;
     if (vec) {
         if (sc) hipLaunchKernelGGL((combine_level_kernel<T, true, VEC>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
         else hipLaunchKernelGGL((combine_level_kernel<T, false, VEC>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
@@ -1027,11 +1025,49 @@ hipError_t combine_level_go(const CombineLaunch &L, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t combine_level_go(const CombineLaunch &L, hipStream_t s) {
+    CombineArgs<T> a;
+    a.M = (const T *)L.M;
+    a.leaf_stride = L.leaf_stride;
+    a.C = (T *)L.C;
+    a.ldc = L.ldc, a.m = L.m, a.n = L.n, a.mb = L.mb, a.nb = L.nb;
+    a.NB = L.NB;
+    a.bdest = L.bdest, a.dest = L.dest, a.sc = L.sc;
+    return combine_level_launch<T>(a, L.R2, L.R1, 1, s);  // R2 output blocks, R1 products
+}
+
+// Two levels of one rule, level by level (kron = 4): the R children of every first-level node
+// summed into the node's product (M0 mb x N0 nb, in L.nodes), then the R node products into C
+// with the scaling factors; each product element is read once per level.
+template <typename T>
+hipError_t combine_two_go(const CombineLaunch &L, hipStream_t s) {
+    const int R = L.R1, nblocks = L.M0 * L.N0;
+    const int64_t nm = (int64_t)L.M0 * L.mb, nn = (int64_t)L.N0 * L.nb, node = nm * nn;
+    CombineArgs<T> a;
+    a.M = (const T *)L.M, a.leaf_stride = L.leaf_stride;
+    a.C = (T *)L.nodes, a.ldc = nn, a.m = nm, a.n = nn, a.mb = L.mb, a.nb = L.nb;
+    a.NB = L.N0, a.bdest = L.bdest1, a.dest = L.dest1, a.sc = ScaleExps{nullptr, nullptr, nullptr};
+    a.zM = (int64_t)R * L.leaf_stride, a.zC = node;
+    hipError_t e = combine_level_launch<T>(a, nblocks, R, R, s);
+    if (e != hipSuccess) return e;
+    CombineArgs<T> b;
+    b.M = (const T *)L.nodes, b.leaf_stride = node;
+    b.C = (T *)L.C, b.ldc = L.ldc, b.m = L.m, b.n = L.n, b.mb = nm, b.nb = nn;
+    b.NB = L.N0, b.bdest = L.bdest1, b.dest = L.dest1, b.sc = L.sc;
+    return combine_level_launch<T>(b, nblocks, R, 1, s);
+}
+
+template <typename T>
 hipError_t combine_go(const CombineLaunch &L, hipStream_t s) {
     if (L.kron == 3) {
         if (L.m <= 0 || L.n <= 0) return hipSuccess;
         if (L.mb <= 0 || L.nb <= 0) return hipErrorInvalidValue;
         return combine_level_go<T>(L, s);
+    }
+    if (L.kron == 4) {
+        if (L.m <= 0 || L.n <= 0) return hipSuccess;
+        if (L.mb <= 0 || L.nb <= 0 || !L.nodes || !L.bdest1 || !L.dest1) return hipErrorInvalidValue;
+        return combine_two_go<T>(L, s);
     }
     if (L.kron) {
         if (L.m <= 0 || L.n <= 0) return hipSuccess;

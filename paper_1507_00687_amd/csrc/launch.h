@@ -59,9 +59,17 @@ struct CombineLaunch {
     // kron = 3: one level of any rule with at most 16 output blocks (R2 of them, NB per row)
     // and at most 64 products (R1), every product live: the lists, expanded in LDS, are
     // summed from registers with each product read once.
+    // kron = 4: two levels of one rule with at most 16 output blocks (M0 N0) and at most 64
+    // products (R1 = R) that kron = 2 does not cover, level by level: the children of each
+    // first-level node into its product (nodes: R blocks of M0 mb x N0 nb), then those into C,
+    // both from the one-level lists bdest1 / dest1.
     int kron = 0;
     int R1 = 0, R2 = 0;
     float w1[4][8] = {}, w2[4][8] = {};
+    const BlockDests *bdest1 = nullptr;
+    const DestEntry *dest1 = nullptr;
+    void *nodes = nullptr;
+    int M0 = 0, N0 = 0;
 };
 
 // Node operands of the first recursion level, written out: node q (q < nodes) of op(X)
