@@ -78,6 +78,8 @@ struct Tables {
     SrcEntry *bsrc = nullptr;
     BlockDests *bdest = nullptr;
     float *ucoef = nullptr, *vcoef = nullptr;  // the rule's U (M0K0 x R) and V (K0N0 x R), row-major
+    // per-level rules (fastmm_plan_set_levels): level l's U and V, same layout (else empty)
+    std::vector<float *> lucoef, lvcoef;
     DestEntry *dest = nullptr;
     // Leaf r's operands written out as block r of a stacked operand: one source each, (r, 0)
     // with coefficient 1 (the FP64 / FP32 paths with written-out leaf operands).
@@ -97,6 +99,8 @@ struct Tables {
             (void)hipFree(dest);
             (void)hipFree(ucoef);
             (void)hipFree(vcoef);
+            for (float *x : lucoef) (void)hipFree(x);
+            for (float *x : lvcoef) (void)hipFree(x);
             (void)hipFree(wleaves);
             (void)hipFree(wsrc);
             (void)hipFree(unit);
@@ -443,15 +447,14 @@ struct InnerLevel {
     int64_t k_ld, k_stride;  // the same blocks k-major (element (o, kk) at kk k_ld + o)
 };
 std::vector<InnerLevel> inner_levels(const fastmm_plan_s *p, const Shape &s, bool side_b) {
-    const Algo &a = plan_algo(p);
     const size_t es = p->prec == FASTMM_F64 ? 8 : 4;
-    const int nO = side_b ? a.N0 : a.M0, nK = a.K0;
     const int64_t O = side_b ? s.Np : s.Mp, K = s.Kp;
     std::vector<InnerLevel> v;
     int64_t po = 1, pk = 1, count = 1;
     size_t off = 0;
     for (int l = 1; l < s.L; ++l) {
-        po *= nO, pk *= nK, count *= a.R;
+        const Algo &a = level_algo(p, l - 1);  // the rule that forms level l's nodes
+        po *= side_b ? a.N0 : a.M0, pk *= a.K0, count *= a.R;
         InnerLevel e;
         e.cb_o = O / po, e.cb_k = K / pk, e.y_ld = (e.cb_k + 7) / 8 * 8, e.y_stride = e.cb_o * e.y_ld;
         e.k_ld = (e.cb_o + 7) / 8 * 8, e.k_stride = e.cb_k * e.k_ld;
@@ -497,12 +500,13 @@ bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, 
 // 117.6 against 75.9, Laderman 109.5 against 61.6 (classical 121).  Needs every product live (the
 // leaves are then the R^L children, in the composite order) and one rule at every node.
 bool written_leaves(const fastmm_plan_s *p, const Shape &s) {
-    if (is_split(p->prec) || s.L < 1 || !p->tree.empty() || !p->levels.empty()) return false;
+    if (is_split(p->prec) || s.L < 1 || !p->tree.empty()) return false;
     if (p->fuse == FASTMM_FUSE_OFF) return false;  // the composite-list leaf path only
-    const Algo &a = plan_algo(p);
-    int64_t all = 1;
-    for (int l = 0; l < s.L; ++l) all *= a.R;
-    return leaf_count(a, s.L) == all && a.M0 * a.K0 <= 16 && a.K0 * a.N0 <= 16;
+    for (int l = 0; l < s.L; ++l) {  // one rule per level (per-level rules included)
+        const Algo &a = level_algo(p, l);
+        if (leaf_count(a, 1) != a.R || a.M0 * a.K0 > 16 || a.K0 * a.N0 > 16) return false;
+    }
+    return true;
 }
 
 // The written path is taken where it applies and the fused kernel does not (the fused kernel,
@@ -729,14 +733,26 @@ fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
         (e = upload(&t->dest, ht.dest)) != hipSuccess)
         return hip_fail(e, "uploading task tables");
     {
-        const Algo &a = plan_algo(p);
-        std::vector<float> u((size_t)a.M0 * a.K0 * a.R), v((size_t)a.K0 * a.N0 * a.R);
-        for (int i = 0; i < a.M0 * a.K0; ++i)
-            for (int r = 0; r < a.R; ++r) u[(size_t)i * a.R + r] = (float)a.u(i, r);
-        for (int j = 0; j < a.K0 * a.N0; ++j)
-            for (int r = 0; r < a.R; ++r) v[(size_t)j * a.R + r] = (float)a.v(j, r);
+        auto coefs = [](const Algo &a, std::vector<float> &u, std::vector<float> &v) {
+            u.assign((size_t)a.M0 * a.K0 * a.R, 0.f), v.assign((size_t)a.K0 * a.N0 * a.R, 0.f);
+            for (int i = 0; i < a.M0 * a.K0; ++i)
+                for (int r = 0; r < a.R; ++r) u[(size_t)i * a.R + r] = (float)a.u(i, r);
+            for (int j = 0; j < a.K0 * a.N0; ++j)
+                for (int r = 0; r < a.R; ++r) v[(size_t)j * a.R + r] = (float)a.v(j, r);
+        };
+        std::vector<float> u, v;
+        coefs(plan_algo(p), u, v);
         if ((e = upload(&t->ucoef, u)) != hipSuccess || (e = upload(&t->vcoef, v)) != hipSuccess)
             return hip_fail(e, "uploading coefficients");
+        if (!p->levels.empty()) {
+            t->lucoef.assign((size_t)L, nullptr), t->lvcoef.assign((size_t)L, nullptr);
+            for (int l = 0; l < L; ++l) {
+                coefs(level_algo(p, l), u, v);
+                if ((e = upload(&t->lucoef[(size_t)l], u)) != hipSuccess ||
+                    (e = upload(&t->lvcoef[(size_t)l], v)) != hipSuccess)
+                    return hip_fail(e, "uploading coefficients");
+            }
+        }
     }
     {
         std::vector<LeafEntry> wl((size_t)t->nleaves);
@@ -1358,7 +1374,6 @@ hipError_t prescale_operands(fastmm_plan_s *plan, const Shape &s, const void *A,
 hipError_t form_written(fastmm_plan_s *plan, const Shape &s, const void *A, int64_t lda, int transA, const void *B,
                         int64_t ldb, int transB, int64_t m, int64_t k, int64_t n, const ScaleExps &exps, char *ws,
                         const WsLayout &w, const Tables *tab, hipStream_t st, int upto) {
-    const Algo &al = plan_algo(plan);
     const WrittenDims wd = written_dims(s);
     auto form_side = [&](bool side_b) -> hipError_t {
         const std::vector<InnerLevel> lv = inner_levels(plan, s, side_b);
@@ -1383,8 +1398,11 @@ hipError_t form_written(fastmm_plan_s *plan, const Shape &s, const void *A, int6
                 if (side_b) nf.ld_o = 1, nf.ld_k = in.k_ld, nf.node_stride = in.k_stride;
                 else nf.ld_o = in.y_ld, nf.ld_k = 1, nf.node_stride = in.y_stride;
             }
+            // level l's rule (per-level rules: each level its own U, V)
+            const Algo &al = level_algo(plan, l - 1);
+            const bool per = !tab->lucoef.empty();
             nf.nO = side_b ? al.N0 : al.M0, nf.nK = al.K0, nf.side_b = side_b ? 1 : 0, nf.R_ = al.R;
-            nf.coef = side_b ? tab->vcoef : tab->ucoef;
+            nf.coef = side_b ? (per ? tab->lvcoef[(size_t)l - 1] : tab->vcoef) : (per ? tab->lucoef[(size_t)l - 1] : tab->ucoef);
             nf.last = 0;
             if (l == s.L) {
                 nf.cb_o = side_b ? s.nb : s.mb, nf.cb_k = s.kb;

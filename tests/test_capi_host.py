@@ -187,9 +187,11 @@ def test_written_path_selection(F, precision):
     assert P("laderman333", 3).path(270, 270, 270) == "written"
     assert P("strassen", 3).path(256, 256, 256) == ("fused" if precision == "f32" else "written")
     assert F.Plan("f424", 2, 1, precision="f16x3").path(256, 128, 256) == "leaf"
-    # per-node and per-level rules stay on the leaf path
+    # per-level rules write their leaf operands (each level with its own rule); per-node rules
+    # stay on the leaf path
     assert P("strassen", 2).set_tree(["strassen"] + ["winograd"] * 7).path(256, 256, 256) == "leaf"
-    assert P("strassen", 2).set_levels(["strassen", "winograd"]).path(256, 256, 256) == "leaf"
+    assert P("strassen", 2).set_levels(["strassen", "winograd"]).path(256, 256, 256) == "written"
+    assert P("f424", 2).set_levels(["f424", "strassen"]).path(256, 128, 256) == "written"
 
 
 def test_fused_loads_path_selection(F):
@@ -473,7 +475,8 @@ def test_levels_argument_errors(F):
     with pytest.raises(F.FastmmError):
         p.set_levels(["strassen", 10 ** 6])
     p.set_levels(["f323", "strassen"])
-    assert p.path(256, 256, 256) == "leaf"
+    assert p.path(256, 256, 256) == "written"  # leaf operands written level by level, each level's rule
+    assert F.Plan("strassen", 2, 1, fuse="off").set_levels(["f323", "strassen"]).path(256, 256, 256) == "leaf"
     p.set_levels([])
     assert p.shape(32, 32, 32) == (2, 32, 32, 32)
 

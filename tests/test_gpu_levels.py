@@ -1,7 +1,8 @@
 """GPU tests of uniform non-stationary recursion (section 3.3, Theorem 4.2): a rule per level,
-with different base shapes, on the leaf path (FP64, FP32) and the split-precision path, single,
-batched and through the backward pass (every level's rule rotated), against the oracle's
-level-by-level recursion and Theorem 4.2."""
+with different base shapes, on the written path (FP64, FP32: each level's node operands formed
+with that level's rule), the composite-list leaf path (fusion off) and the split-precision path,
+single, batched and through the backward pass (every level's rule rotated), against the
+oracle's level-by-level recursion and Theorem 4.2."""
 import numpy as np
 import pytest
 
@@ -84,3 +85,22 @@ def test_levels_batched_and_backward():
         torch.cuda.synchronize()
         assert np.array_equal(dA.cpu().numpy(), _exact(G, B.T))
         assert np.array_equal(dB.cpu().numpy(), _exact(A.T, G))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("key,shape", [("323-222", (200, 130, 190)), ("222-424", (260, 100, 240)),
+                                       ("332-233-323", (150, 120, 170))])
+def test_levels_written_path_equals_leaf_path_on_integers(precision, key, shape):
+    """Per-level rules take the written path by default (each level's node operands formed with
+    its own U, V); on integers it is exact, like the composite-list leaf path."""
+    import paper_1507_00687_amd as F
+
+    print(f"\n[levels-written] {key} {shape} {precision}", flush=True)
+    lv = LEVELS[key]
+    written = _plan(F, key, precision)
+    listed = F.Plan(lv[0], len(lv), 1, precision=precision, fuse="off").set_levels(lv)
+    assert written.path(*shape) == "written" and listed.path(*shape) == "leaf"
+    A, B = make_pair("int8", 63, *shape, dtype=np_dtype(precision))
+    exact = _exact(A, B)
+    assert np.array_equal(run_gpu(written, A, B).astype(np.float64), exact)
+    assert np.array_equal(run_gpu(listed, A, B).astype(np.float64), exact)
