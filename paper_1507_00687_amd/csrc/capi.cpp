@@ -78,7 +78,8 @@ struct Tables {
     SrcEntry *bsrc = nullptr;
     BlockDests *bdest = nullptr;
     float *ucoef = nullptr, *vcoef = nullptr;  // the rule's U (M0K0 x R) and V (K0N0 x R), row-major
-    // per-level rules (fastmm_plan_set_levels): level l's U and V, same layout (else empty)
+    // per-level rules (fastmm_plan_set_levels): level l's U and V, same layout (else empty);
+    // tree plans: level l's nodes' U and V one after another, node q at q M0K0 R (resp. K0N0 R)
     std::vector<float *> lucoef, lvcoef;
     DestEntry *dest = nullptr;
     // Leaf r's operands written out as block r of a stacked operand: one source each, (r, 0)
@@ -500,7 +501,7 @@ bool fused_path(const fastmm_plan_s *p, const Shape &s, int transA, int transB, 
 // 117.6 against 75.9, Laderman 109.5 against 61.6 (classical 121).  Needs every product live (the
 // leaves are then the R^L children, in the composite order) and one rule at every node.
 bool written_leaves(const fastmm_plan_s *p, const Shape &s) {
-    if (is_split(p->prec) || s.L < 1 || !p->tree.empty()) return false;
+    if (is_split(p->prec) || s.L < 1) return false;
     if (p->fuse == FASTMM_FUSE_OFF) return false;  // the composite-list leaf path only
     for (int l = 0; l < s.L; ++l) {  // one rule per level (per-level rules included)
         const Algo &a = level_algo(p, l);
@@ -744,12 +745,17 @@ fastmm_status get_tables(fastmm_plan_s *p, int L, Tables **out) {
         coefs(plan_algo(p), u, v);
         if ((e = upload(&t->ucoef, u)) != hipSuccess || (e = upload(&t->vcoef, v)) != hipSuccess)
             return hip_fail(e, "uploading coefficients");
-        if (!p->levels.empty()) {
+        if (!p->levels.empty() || !p->tree.empty()) {
             t->lucoef.assign((size_t)L, nullptr), t->lvcoef.assign((size_t)L, nullptr);
-            for (int l = 0; l < L; ++l) {
-                coefs(level_algo(p, l), u, v);
-                if ((e = upload(&t->lucoef[(size_t)l], u)) != hipSuccess ||
-                    (e = upload(&t->lvcoef[(size_t)l], v)) != hipSuccess)
+            int64_t off = 0, nodes = 1;  // breadth-first index of the level's first tree node
+            for (int l = 0; l < L; ++l, off += nodes, nodes *= plan_algo(p).R) {
+                std::vector<float> ul, vl;
+                for (int64_t q = 0; q < (p->tree.empty() ? 1 : nodes); ++q) {
+                    coefs(p->tree.empty() ? level_algo(p, l) : *algo_get(p->tree[(size_t)(off + q)]), u, v);
+                    ul.insert(ul.end(), u.begin(), u.end()), vl.insert(vl.end(), v.begin(), v.end());
+                }
+                if ((e = upload(&t->lucoef[(size_t)l], ul)) != hipSuccess ||
+                    (e = upload(&t->lvcoef[(size_t)l], vl)) != hipSuccess)
                     return hip_fail(e, "uploading coefficients");
             }
         }
@@ -1398,11 +1404,13 @@ hipError_t form_written(fastmm_plan_s *plan, const Shape &s, const void *A, int6
                 if (side_b) nf.ld_o = 1, nf.ld_k = in.k_ld, nf.node_stride = in.k_stride;
                 else nf.ld_o = in.y_ld, nf.ld_k = 1, nf.node_stride = in.y_stride;
             }
-            // level l's rule (per-level rules: each level its own U, V)
+            // level l's rule (per-level rules: each level its own U, V; trees: each parent node
+            // its own, coef_stride apart)
             const Algo &al = level_algo(plan, l - 1);
             const bool per = !tab->lucoef.empty();
             nf.nO = side_b ? al.N0 : al.M0, nf.nK = al.K0, nf.side_b = side_b ? 1 : 0, nf.R_ = al.R;
             nf.coef = side_b ? (per ? tab->lvcoef[(size_t)l - 1] : tab->vcoef) : (per ? tab->lucoef[(size_t)l - 1] : tab->ucoef);
+            nf.coef_stride = plan->tree.empty() ? 0 : (int64_t)nf.nO * nf.nK * al.R;
             nf.last = 0;
             if (l == s.L) {
                 nf.cb_o = side_b ? s.nb : s.mb, nf.cb_k = s.kb;

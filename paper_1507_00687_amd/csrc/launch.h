@@ -229,6 +229,7 @@ struct NodeForm {
     int first;
     int nO, nK, side_b, R_;
     const float *coef;
+    int64_t coef_stride;  // node q's coefficients at coef + q coef_stride (0: one table for all)
     int64_t cb_o, cb_k;
     const int32_t *e_o, *e_k;
     int s_o, s_k, pre_exp;

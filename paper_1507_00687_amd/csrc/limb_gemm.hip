@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void form_node(NodeForm a) {
     const bool kc = a.ld_k == 1;
     const T *X = reinterpret_cast<const T *>(a.X) + (a.first ? 0 : (int64_t)q * a.node_stride);
     float *coef = reinterpret_cast<float *>(ntile + nS * TO * 65);
-    for (int i = t; i < nS * a.R_; i += 256) coef[i] = a.coef[i];
+    for (int i = t; i < nS * a.R_; i += 256) coef[i] = a.coef[(int64_t)q * a.coef_stride + i];
     for (int sb = 0; sb < nS; ++sb) {
         const int ob = a.side_b ? sb / a.nK : sb % a.nO, kbk = a.side_b ? sb % a.nK : sb / a.nO;
         for (int e = t; e < TO * 64; e += 256) {
@@ -1084,7 +1084,7 @@ __global__ __launch_bounds__(256) void form_node_direct(NodeForm a, int64_t rows
         bool first = true;
 #pragma unroll
         for (int sb = 0; sb < MAXS; ++sb) {
-            const float u = sb < nS ? a.coef[sb * a.R_ + c] : 0.f;
+            const float u = sb < nS ? a.coef[(int64_t)q * a.coef_stride + sb * a.R_ + c] : 0.f;
             if (u == 0.f) continue;
 #pragma unroll
             for (int j = 0; j < V; ++j) v[j] = first ? (T)u * x[sb][j] : v[j] + (T)u * x[sb][j];

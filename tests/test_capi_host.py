@@ -187,9 +187,8 @@ def test_written_path_selection(F, precision):
     assert P("laderman333", 3).path(270, 270, 270) == "written"
     assert P("strassen", 3).path(256, 256, 256) == ("fused" if precision == "f32" else "written")
     assert F.Plan("f424", 2, 1, precision="f16x3").path(256, 128, 256) == "leaf"
-    # per-level rules write their leaf operands (each level with its own rule); per-node rules
-    # stay on the leaf path
-    assert P("strassen", 2).set_tree(["strassen"] + ["winograd"] * 7).path(256, 256, 256) == "leaf"
+    # per-level and per-node rules write their leaf operands (each level or node with its own rule)
+    assert P("strassen", 2).set_tree(["strassen"] + ["winograd"] * 7).path(256, 256, 256) == "written"
     assert P("strassen", 2).set_levels(["strassen", "winograd"]).path(256, 256, 256) == "written"
     assert P("f424", 2).set_levels(["f424", "strassen"]).path(256, 128, 256) == "written"
 
@@ -414,7 +413,8 @@ def test_tree_argument_errors(F):
     with pytest.raises(F.FastmmError):
         p.set_tree([10 ** 6] * 8)  # unknown id
     p.set_tree(ids)
-    assert p.path(128, 128, 128) == "leaf"  # tree plans take the leaf path
+    assert p.path(128, 128, 128) == "written"  # each parent node's operands formed with its own rule
+    assert F.Plan("strassen", 2, 1, fuse="off").set_tree(ids).path(128, 128, 128) == "leaf"
     p.set_tree([])
     assert F.Plan("strassen", 3, 1, precision="f32").path(128, 128, 128) == "fused"
 

@@ -1,7 +1,7 @@
 """GPU tests of non-uniform recursion (section 3.4): the trees of the two non-uniform examples of section 5.2
-(Examples 4.2 and 4.3 here) on the
-leaf path (FP64, FP32) and the split-precision path, single and batched, against the oracle's
-per-node recursion."""
+(Examples 4.2 and 4.3 here) on the written path (FP64, FP32: each parent node's operands
+formed with its own rule), the composite-list leaf path (fusion off) and the split-precision
+path, single and batched, against the oracle's per-node recursion."""
 import numpy as np
 import pytest
 
@@ -86,3 +86,22 @@ def test_tree_in_a_batch_and_backward():
     for (a, b), g, (ga, gb) in zip(host, Gs, batched):
         assert np.array_equal(ga.cpu().numpy().astype(np.float64), (i64(g) @ i64(b).T).astype(np.float64))
         assert np.array_equal(gb.cpu().numpy().astype(np.float64), (i64(a).T @ i64(g)).astype(np.float64))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("tree,shape", [("dalberto", (130, 70, 190)), ("f323", (200, 150, 220))])
+def test_tree_written_and_list_paths_exact(precision, tree, shape):
+    """Tree plans write their leaf operands by default, each parent node's children formed with
+    that node's rule; on integers both that path and the composite-list path are exact."""
+    import paper_1507_00687_amd as F
+
+    print(f"\n[tree-written] {tree} {shape} {precision}", flush=True)
+    build, base, _ = TREES[tree]
+    ids, _ = build(F)
+    written = F.Plan(base, 2, 1, precision=precision).set_tree(ids)
+    listed = F.Plan(base, 2, 1, precision=precision, fuse="off").set_tree(ids)
+    assert written.path(*shape) == "written" and listed.path(*shape) == "leaf"
+    A, B = make_pair("int8", 42, *shape, dtype=np_dtype(precision))
+    exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+    assert np.array_equal(run_gpu(written, A, B).astype(np.float64), exact)
+    assert np.array_equal(run_gpu(listed, A, B).astype(np.float64), exact)
