@@ -234,6 +234,83 @@ __global__ __launch_bounds__(256) void form_node_direct(NodeForm a, int64_t rows
     }
 }
 
+// The last level of form_node (limb planes) without the LDS stage, for inner node operands whose
+// k is contiguous (o-major blocks): a thread owns one 8-element chunk of a leaf plane (rows o of
+// a bt x 32 piece, k in steps of 8), numbered in the planes' memory order, so that consecutive
+// threads write consecutive 16 bytes and four threads read one 128-byte row segment of each
+// sub-block.  It holds the 8 elements of each of the nS sub-blocks in registers and writes that
+// chunk of every child's limb planes, with the same sums and splits as form_node (bitwise equal
+// planes).  Elements outside the child block (the planes' padding) are zeros.
+template <int MAXS>
+__global__ __launch_bounds__(256) void form_planes_direct(NodeForm a, int64_t chunks) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= chunks) return;
+    const int q = blockIdx.z;
+    const int64_t per_piece = a.bt * 4, kpieces = a.kp / 32;
+    const int64_t piece = g / per_piece, w = g - piece * per_piece;
+    const int64_t oc = (piece / kpieces) * a.bt + w / 4, kc0 = (piece % kpieces) * 32 + (w % 4) * 8;
+    const int nS = a.nO * a.nK;
+    const float *X = reinterpret_cast<const float *>(a.X) + (int64_t)q * a.node_stride;
+    float x[MAXS][8];
+#pragma unroll
+    for (int sb = 0; sb < MAXS; ++sb) {
+        if (sb >= nS) continue;  // (not break: a fully unrolled loop keeps x in registers)
+        const int ob = a.side_b ? sb / a.nK : sb % a.nO, kbk = a.side_b ? sb % a.nK : sb / a.nO;
+        const float *src = X + (ob * a.cb_o + oc) * a.ld_o + kbk * a.cb_k + kc0;
+        if (oc < a.cb_o && kc0 + 8 <= a.cb_k && ((uintptr_t)src & 15) == 0) {
+            const float4 u0 = *reinterpret_cast<const float4 *>(src);
+            const float4 u1 = *reinterpret_cast<const float4 *>(src + 4);
+            x[sb][0] = u0.x, x[sb][1] = u0.y, x[sb][2] = u0.z, x[sb][3] = u0.w;
+            x[sb][4] = u1.x, x[sb][5] = u1.y, x[sb][6] = u1.z, x[sb][7] = u1.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bool ok = oc < a.cb_o && kc0 + j < a.cb_k;
+                const float y = *(ok ? src + j : X);
+                x[sb][j] = ok ? y : 0.f;
+            }
+        }
+    }
+    for (int c = 0; c < a.R_; ++c) {
+        float v[8];
+        bool first = true;
+#pragma unroll
+        for (int sb = 0; sb < MAXS; ++sb) {
+            const float u = sb < nS ? a.coef[(int64_t)q * a.coef_stride + sb * a.R_ + c] : 0.f;
+            if (u == 0.f) continue;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = first ? u * x[sb][j] : v[j] + u * x[sb][j];
+            first = false;
+        }
+        if (first) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = 0.f;
+        }
+        unsigned short h[3][8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float r = v[j];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                float back;
+                h[l][j] = a.half ? LimbT<true>::split(r, back) : LimbT<false>::split(r, back);
+                r = r - back;
+            }
+        }
+        unsigned short *dst = a.planes + ((int64_t)q * a.R_ + c) * a.leaf_stride + g * 8;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (l >= a.nl) break;
+            uint4 wv;
+            wv.x = (uint32_t)h[l][0] | ((uint32_t)h[l][1] << 16);
+            wv.y = (uint32_t)h[l][2] | ((uint32_t)h[l][3] << 16);
+            wv.z = (uint32_t)h[l][4] | ((uint32_t)h[l][5] << 16);
+            wv.w = (uint32_t)h[l][6] | ((uint32_t)h[l][7] << 16);
+            *reinterpret_cast<uint4 *>(dst + l * a.plane_stride) = wv;
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_form_node(int prec, const NodeForm &f, int nodes, hipStream_t s) {
@@ -253,6 +330,17 @@ hipError_t launch_form_node(int prec, const NodeForm &f, int nodes, hipStream_t 
     if (gx <= 0 || gy <= 0) return hipSuccess;
     if (gx > 0x7fffffffLL || gy > 65535 || nodes > 65535) return hipErrorInvalidValue;
     if (a.kmajor && (a.y_ld % 8 != 0)) return hipErrorInvalidValue;
+    // limb planes from k-contiguous inner node operands: no LDS transpose needed
+    if (a.last && !a.first && a.ld_k == 1 && a.bt > 0 && a.rowsp % a.bt == 0 && a.kp % 32 == 0 &&
+        ((uintptr_t)a.planes & 15) == 0 && a.plane_stride % 8 == 0 && a.leaf_stride % 8 == 0) {
+        const int64_t chunks = a.rowsp * a.kp / 8, blocks = (chunks + 255) / 256;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+        const dim3 g((unsigned)blocks, 1, (unsigned)nodes);
+        if (nS <= 4) hipLaunchKernelGGL((form_planes_direct<4>), g, dim3(256), 0, s, a, chunks);
+        else if (nS <= 8) hipLaunchKernelGGL((form_planes_direct<8>), g, dim3(256), 0, s, a, chunks);
+        else hipLaunchKernelGGL((form_planes_direct<16>), g, dim3(256), 0, s, a, chunks);
+        return hipGetLastError();
+    }
     // the operand's contiguous direction is the output's: no LDS transpose needed
     const bool direct = !a.last && ((a.ld_k == 1 && !a.kmajor) || (a.ld_o == 1 && a.kmajor)) && a.y_ld % 8 == 0 &&
                         ((uintptr_t)a.Y & 15) == 0 && a.y_stride % 8 == 0;
