@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfastmm.so")
 SOURCES = ["algos.cpp", "capi.cpp", "kernels.hip", "leaf_mfma.hip", "transpose.hip", "node_fused.hip",
-           "node_fused_t.hip", "limb_gemm.hip", "node_form.hip", "noalloc.hip"]
+           "node_fused_t.hip", "limb_gemm.hip", "plane_form.hip", "node_form.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 (v_pk_*_f32) instructions.

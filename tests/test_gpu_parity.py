@@ -348,6 +348,28 @@ def test_transposed_split_depths(name, depth):
         assert np.array_equal(got.astype(np.float64), _exact(A, B))
 
 
+@pytest.mark.parametrize("precision,scaling", [("f16x3", "outside"), ("bf16x3", "none"), ("bf16x6", "repeated")])
+@pytest.mark.parametrize("name,depth,shape", [("strassen", 2, (256, 320, 192)), ("strassen", 2, (203, 130, 157)),
+                                              ("winograd", 1, (96, 129, 70))])
+def test_split_plane_layouts_bitwise_equal(precision, scaling, name, depth, shape):
+    # A source whose rows run along k is read straight into registers; one whose rows run along
+    # o (B as stored, a transposed A) goes through an LDS transpose first.  Both write the same
+    # planes, so the four storage orders give bitwise equal products on float data.
+    print(f"\n[split-layouts] {name} L={depth} {shape} {precision} {scaling}", flush=True)
+    A, B = make_pair("normal", 11, *shape, dtype=np.float32)
+    kw = {"scaling": scaling, "steps": 4} if scaling == "repeated" else {"scaling": scaling}
+    ref = None
+    for ta, tb in [(False, False), (True, False), (False, True), (True, True)]:
+        As = np.ascontiguousarray(A.T) if ta else A
+        Bs = np.ascontiguousarray(B.T) if tb else B
+        got = run_gpu(_plan(name, depth, 1, precision, **kw), As, Bs, ta, tb)
+        if ref is None:
+            ref = got
+            assert np.all(np.isfinite(ref))
+        else:
+            assert np.array_equal(got, ref), (ta, tb)
+
+
 @pytest.mark.parametrize("precision", ["bf16x3", "f32", "f64"])
 def test_transposed_split_and_mfma(precision):
     m, k, n = 96, 130, 72
