@@ -165,8 +165,7 @@ constexpr int kAllMaxCoef = 4096;  // leaves x blocks entries of the coefficient
 // the rule's single block index at depth 1 (column-major for A, row-major over (n-block,
 // k-block) for B), which is the order of the source lists there.  Thread layout: k-contiguous
 // operands (KCONTIG): eight consecutive lanes take the eight chunks of one row; otherwise (B, n
-// contiguous) 32 consecutive lanes take 32 consecutive rows of one chunk, so loads read whole
-// 128-byte lines.  Small work-groups (TR = 16 or 32 rows) let several run per CU out of phase
+// contiguous) 16 consecutive lanes take 16 consecutive rows of one chunk.  Small work-groups (TR = 16 or 32 rows) let several run per CU out of phase
 // (one loading while another writes); a 512-thread version with one 64 x 64 tile per
 // work-group, and the earlier LDS-transposing version with a barrier per leaf, both ran 5 %
 // slower.  For o-contiguous operands, passing the 32 x 32 source tiles of all blocks through
@@ -180,16 +179,19 @@ __global__ __launch_bounds__(TR * 8) void form_regs(PlaneForm a, int nleaves) {
     const int t = threadIdx.x;
     const int nbo = a.nbo, nbk = a.nbk, nblk = nbo * nbk;
     leaf_coef_table<NT>(a, nleaves, rcoef);
-    static_assert(TR % 16 == 0 && TR <= 64 && (KCONTIG || TR % 32 == 0), "tile rows");
+    static_assert(TR % 16 == 0 && TR <= 64, "tile rows");
     static_assert(KW == 8 || KW == 4, "chunk width");
     int ol, kc;  // the thread's row and KW-wide k chunk in the TR x 8 KW tile
     if (KCONTIG) {
         ol = t >> 3, kc = t & 7;
     } else {
-        // 32 consecutive lanes on 32 consecutive rows (o contiguous in op(X)): every load reads
-        // whole 128-byte lines; a wave writes 32 bytes of 32 rows, its neighbour the rest
+        // o contiguous in op(X): a wave takes 16 consecutive rows by four chunks (16 k), so each
+        // load reads 64-byte runs of four k rows and each limb store writes 32-byte runs of 16
+        // plane rows.  Measured on this side: 32 rows by two chunks (whole 128-byte lines read,
+        // 16-byte runs written) 15 % slower, 8 rows by eight chunks 3 %, work-groups of 16 or 64
+        // rows 3-5 %.
         const int wave = t >> 6, lane = t & 63;
-        ol = (lane & 31) + 32 * (wave % (TR / 32)), kc = (lane >> 5) + 2 * (wave / (TR / 32));
+        ol = (lane & 15) + 16 * (wave % (TR / 16)), kc = (lane >> 4) + 4 * (wave / (TR / 16));
     }
     // work-group (row tile x, k tile y): consecutive work-groups take consecutive TR-row slices
     // of the same 32-k plane pieces, so the work-groups in flight write whole pieces together
