@@ -20,8 +20,10 @@ namespace {
 // blocks of the element type T (inner levels, and every level of the FP64 / FP32 paths) or as
 // limb planes (last level of the split precisions, T = float).  Each work-group handles a
 // TO x 64 tile position (o, kk) of the child blocks: it stages the nS sub-block tiles in LDS,
-// then forms every child tile from them.  Children of node q are numbered q R + c, the order of
-// the composite leaves (first level most significant).  Blocks are written o-major (element
+// then forms every child tile from them (for an operand with o contiguous written o-major, a
+// register-only form with 16-row x 16-k waves, 64-byte runs both ways, ran 12 % slower than
+// this staged one, whose stores write whole 256-byte rows).  Children of node q are numbered
+// q R + c, the order of the composite leaves (first level most significant).  Blocks are written o-major (element
 // (o, kk) at o * y_ld + kk) or, with kmajor, k-major (element (o, kk) at kk * y_ld + o: a
 // B-side operand written back in its own row-major k x n orientation).
 template <typename T, int TO>
