@@ -23,9 +23,9 @@ namespace {
 // then forms every child tile from them (for an operand with o contiguous written o-major, a
 // register-only form with 16-row x 16-k waves, 64-byte runs both ways, ran 12 % slower than
 // this staged one, whose stores write whole 256-byte rows).  Children of node q are numbered
-// q R + c, the order of the composite leaves (first level most significant).  Blocks are written o-major (element
-// (o, kk) at o * y_ld + kk) or, with kmajor, k-major (element (o, kk) at kk * y_ld + o: a
-// B-side operand written back in its own row-major k x n orientation).
+// q R + c, the order of the composite leaves (first level most significant).  Blocks are
+// written o-major (element (o, kk) at o * y_ld + kk) or, with kmajor, k-major (element (o, kk)
+// at kk * y_ld + o: a B-side operand written back in its own row-major k x n orientation).
 template <typename T, int TO>
 __global__ __launch_bounds__(256) void form_node(NodeForm a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char node_lds[];
