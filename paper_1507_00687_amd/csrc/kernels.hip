@@ -489,7 +489,7 @@ __global__ __launch_bounds__(kThreads) void combine1_kernel(Combine2Args<T> p) {
 // keeps in registers.
 constexpr int kCombineMaxBlocks = 16, kCombineMaxProducts = 64;
 
-template <typename T, bool SCALED, int VEC>
+template <typename T, bool SCALED, int VEC, int NBT>
 __global__ __launch_bounds__(kThreads) void combine_level_kernel(CombineArgs<T> p, int nblocks, int nprod) {
     __shared__ float wt[kCombineMaxProducts][kCombineMaxBlocks];
     for (int i = threadIdx.x; i < kCombineMaxProducts * kCombineMaxBlocks; i += kThreads)
@@ -544,13 +544,44 @@ __global__ __launch_bounds__(kThreads) void combine_level_kernel(CombineArgs<T> 
                 }
             }
         }
+        // With the block-grid width NBT known at compile time, the scaling exponents of the
+        // thread's NBT columns and 16 / NBT rows are loaded once, not once per output block
+        // (per-block loads doubled the time of the scaled second level of <4,2,4>).
+        constexpr int NR = NBT > 0 ? (kCombineMaxBlocks + NBT - 1) / NBT : 1, NC = NBT > 0 ? NBT : 1;
+        int ea_r[NR], eb_c[NC][VEC];
+        if constexpr (SCALED && NBT > 0) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int64_t row = r * p.mb + x;
+                ea_r[r] = (r * NBT < nblocks && row < p.m) ? p.sc.ea[row] : 0;
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int64_t col = c * p.nb + y;
+                if (col < p.n) {
+                    load_exps<VEC>(p.sc.eb + col, eb_c[c]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) eb_c[c][e] = 0;
+                }
+            }
+        }
+        const int nbw = NBT > 0 ? NBT : p.NB;
 #pragma unroll
         for (int b = 0; b < kCombineMaxBlocks; ++b) {
-            const int64_t row = (b / p.NB) * p.mb + x, col = (b % p.NB) * p.nb + y;
+            const int64_t row = (b / nbw) * p.mb + x, col = (b % nbw) * p.nb + y;
             if (b >= nblocks || row >= p.m || col >= p.n) continue;
-            int eb[VEC];
-            if (SCALED) load_exps<VEC>(p.sc.eb + col, eb);
-            const int ea = SCALED ? p.sc.ea[row] : 0;
+            int eb[VEC], ea = 0;
+            if constexpr (SCALED) {
+                if constexpr (NBT > 0) {
+                    ea = ea_r[b / NBT];
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) eb[e] = eb_c[b % NBT][e];
+                } else {
+                    load_exps<VEC>(p.sc.eb + col, eb);
+                    ea = p.sc.ea[row];
+                }
+            }
             T out[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
@@ -1016,12 +1047,14 @@ hipError_t combine_level_launch(const CombineArgs<T> &a, int nblocks, int nprod,
     const int64_t cols = (a.nb + per - 1) / per;
     dim3 grid((unsigned)((cols + kThreads - 1) / kThreads), (unsigned)(a.mb < 65535 ? a.mb : 65535), (unsigned)nz);
     const bool sc = a.sc.ea != nullptr;
-    if (vec) {
-        if (sc) hipLaunchKernelGGL((combine_level_kernel<T, true, VEC>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
-        else hipLaunchKernelGGL((combine_level_kernel<T, false, VEC>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
+    if (vec && sc && a.NB == 4) {
+        hipLaunchKernelGGL((combine_level_kernel<T, true, VEC, 4>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
+    } else if (vec) {
+        if (sc) hipLaunchKernelGGL((combine_level_kernel<T, true, VEC, 0>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
+        else hipLaunchKernelGGL((combine_level_kernel<T, false, VEC, 0>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
     } else {
-        if (sc) hipLaunchKernelGGL((combine_level_kernel<T, true, 1>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
-        else hipLaunchKernelGGL((combine_level_kernel<T, false, 1>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
+        if (sc) hipLaunchKernelGGL((combine_level_kernel<T, true, 1, 0>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
+        else hipLaunchKernelGGL((combine_level_kernel<T, false, 1, 0>), grid, dim3(kThreads), 0, s, a, nblocks, nprod);
     }
     return hipGetLastError();
 }
